@@ -1,0 +1,190 @@
+#!/usr/bin/env python3
+"""SPSTD throughput on one MI355X: grid-point stage updates per second.
+
+Workload: the 3D isotropic harmonic oscillator on a 256^3 periodic grid over
+[-12, 12)^3 (hbar = m* = 1, omega = 1), seeded off-centre Gaussian start,
+Yoshida sixth-order 8-stage symplectic set (15 non-zero substeps per step),
+dt = 0.5 x the stability limit, 3 probes.  One "step" is one full time step
+of the hot path (every directional pass of every stage plus the probe
+sample).  A stage update is one A plus one B substep at one grid point, so a
+step is 7.5 stage updates per point.
+
+The timed region runs with per-pass HIP events on the plan's stream; the
+dominant kernel's average duration gives the roofline entry.  The CPU oracle
+is timed on a bounded sample of the same workload (rank 0, N = 1 only).
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "grid-point stage updates/s (3D HO 256³, FP64 vs FP32); p50/p99 solve latency"
+HBM_PEAK_GBS = 8000.0
+KERNEL_SOURCES = ["paper_1805_03155_amd/csrc/kernels.hip", "paper_1805_03155_amd/csrc/fft_core.hpp"]
+KERNEL_NAMES = {"y": "k_axis_acc (y pass)", "z": "k_axis_acc (z pass)",
+                "xab": "k_x_ab (fused A+B x pass)", "x": "k_x_acc (x half-stage)"}
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_for(kind, prec):
+    """HBM bytes per launch from the committed rocprofv3 PMC summary, if it
+    was taken on the current kernel sources."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        data = json.load(open(path))
+    except ValueError:
+        return None
+    if data.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    ent = data.get("entries", {}).get(f"{prec}:{kind}")
+    return None if ent is None else ent.get("hbm_bytes_per_launch")
+
+
+def run_precision(w, prec, steps, warmup):
+    import torch
+    from paper_1805_03155_amd import spstd
+    code = spstd.FP64 if prec == "fp64" else spstd.FP32
+    p = spstd.plan_from_workload(w, precision=code, nsteps_max=steps + warmup,
+                                 flags=spstd.TIMING)
+    st = p.info()
+    npts = w.npoints
+    su_per_step = npts * st.substeps_per_step / 2.0
+    p.step(warmup)
+    p.pass_times()                       # synchronises; discards warm-up timings
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    p.step(steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    times = p.pass_times()
+    el = t1 - t0
+    info = p.info()
+    _, st2 = p.run(0)                    # norm check (raises on NaN/Inf)
+    log(f"{prec}: {steps} steps in {el:.3f} s, norm drift {st2.norm / st2.norm0 - 1:.2e}")
+    kinds = {k: v for k, v in times.items() if v[0] > 0}
+    dom = max(kinds, key=lambda k: kinds[k][1])
+    n, ms, by = kinds[dom]
+    avg_s = ms / n / 1e3
+    achieved = by / avg_s / 1e9
+    roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_for(dom, prec),
+            "kernel": KERNEL_NAMES[dom], "avg_launch_us": avg_s * 1e6,
+            "algorithmic_bytes_per_launch": by}
+    per_kernel = {KERNEL_NAMES[k]: {"launches": v[0], "avg_us": v[1] / v[0] * 1e3,
+                                    "GBps": v[2] / (v[1] / v[0] / 1e3) / 1e9,
+                                    "share_of_pass_time": v[1] / sum(x[1] for x in kinds.values())}
+                  for k, v in kinds.items()}
+    # graph-replayed steps (the default execution mode) for reference
+    q = spstd.plan_from_workload(w, precision=code, nsteps_max=steps + warmup)
+    q.step(warmup)
+    torch.cuda.synchronize()
+    g0 = time.perf_counter()
+    q.step(steps)
+    torch.cuda.synchronize()
+    g1 = time.perf_counter()
+    del q
+    return {"value": su_per_step * steps / el, "ms_per_step": el / steps * 1e3,
+            "roofline": roof, "kernels": per_kernel, "dt": info.dt,
+            "graph_mode": {"value": su_per_step * steps / (g1 - g0),
+                           "ms_per_step": (g1 - g0) / steps * 1e3},
+            "stage_updates_per_step": su_per_step}
+
+
+def cpu_baseline(w, steps):
+    import oracle
+    c, d = w.coeffs
+    dt = oracle.stable_dt(c, d, w.V, w.n, w.dx)
+    nsub = sum(1 for x in c if x != 0.0) + sum(1 for x in d if x != 0.0)
+    t0 = time.perf_counter()
+    oracle.run(w.psiR, w.psiI, w.V, w.n, w.dx, c, d, dt, steps, w.probes)
+    el = time.perf_counter() - t0
+    su = w.npoints * nsub / 2.0 * steps
+    return {"value": su / el, "unit": "stage updates/s", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": f"{steps} full time step(s) ({nsub} substeps each) of the 256^3 FP64 "
+                      f"oracle run, {el:.1f} s wall"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--n", type=int, default=256, help="grid points per axis")
+    ap.add_argument("--cpu-baseline", choices=["on", "off"], default="on")
+    ap.add_argument("--cpu-steps", type=int, default=1)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on exactly one GPU: this engine has no multi-GPU path "
+              "(one MI355X per run); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1805_03155_amd import workloads as W
+    assert torch.cuda.is_available(), "bench.py needs a HIP device"
+    log(f"building the {args.n}^3 oscillator workload")
+    w = W.harmonic_3d(seed=0, n=args.n, half_box=12.0, omega=1.0, steps=100000,
+                      coeffs=W.YOSHIDA6, nprobes=3)
+    res = {}
+    for prec in ("fp64", "fp32"):
+        log(f"{prec}: warmup {args.warmup}, timed {args.steps} steps")
+        res[prec] = run_precision(w, prec, args.steps, args.warmup)
+    cpu = None
+    if args.cpu_baseline == "on":
+        log("timing the CPU oracle on a bounded sample")
+        cpu = cpu_baseline(w, args.cpu_steps)
+    r64, r32 = res["fp64"], res["fp32"]
+    line = {
+        "metric": METRIC,
+        "value": r64["value"],
+        "unit": "stage updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": r64["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"3D harmonic oscillator {args.n}^3 on [-12,12)^3, "
+                               "Yoshida-6 8-stage symplectic set, dt = 0.5 x stability limit, "
+                               "3 probes",
+                   "grid": [args.n] * 3, "stage_updates_per_step": r64["stage_updates_per_step"],
+                   "dt": r64["dt"], "execution": "eager launches with per-pass HIP events"},
+        "roofline": r64["roofline"],
+        "cpu_baseline": cpu,
+        "kernels": r64["kernels"],
+        "graph_mode": r64["graph_mode"],
+        "fp32": {"value": r32["value"], "ms_per_step": r32["ms_per_step"], "dtype": "f32",
+                 "roofline": r32["roofline"], "kernels": r32["kernels"],
+                 "graph_mode": r32["graph_mode"],
+                 "speedup_vs_fp64": r32["value"] / r64["value"]},
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,236 @@
+/*
+ * spstd.h -- C ABI of the MI355X SPSTD engine.
+ *
+ * The engine advances the time-dependent Schroedinger equation
+ *     i hbar d(psi)/dt = -(hbar^2 / 2 m*) Laplacian psi + V(r) psi      (Eq. 1)
+ * on a periodic, collocated grid (Eq. 5-6) with psi = psi_R + i psi_I
+ * (Eq. 2-4), the Fourier pseudospectral second derivative (Eq. 7-10) and the
+ * partitioned symplectic stage update (Eq. 13-18) of Shen, Sha, Kuang, Hu,
+ * Huang and Wu, "Symplectic Pseudospectral Time-Domain Scheme for Solving
+ * Time-Dependent Schroedinger Equation" (arXiv:1805.03155).  Eigenvalues are
+ * read from the time spectrum of probe-point series (Sec. 3, Tables 2-4).
+ *
+ * Conventions shared by every call:
+ *   - Every call returns spstd_status; 0 is success.  Nothing aborts or
+ *     throws across the ABI.
+ *   - Grids are row-major with x fastest: index = (z * ny + y) * nx + x.
+ *   - "host" pointers are ordinary CPU memory; "device" pointers are HIP
+ *     device memory on the current device.  The library never allocates
+ *     device memory: the caller passes one device workspace per plan
+ *     (size from spstd_workspace_size) and owns it.
+ *   - A plan is not thread-safe; distinct plans are independent.
+ *   - Stage l of a step applies first  psi_R += c_l dt K psi_I  and then
+ *     psi_I -= d_l dt K psi_R  (Eq. 17-18 with K of Eq. 16); stages whose
+ *     coefficient is 0 are skipped.
+ */
+#ifndef SPSTD_H
+#define SPSTD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum spstd_status {
+    SPSTD_OK = 0,
+    SPSTD_ERR_ARG = 1,        /* an argument is out of range or malformed */
+    SPSTD_ERR_UNSTABLE = 2,   /* dt * rho >= x_max (Eq. 24-30) without SPSTD_ALLOW_UNSTABLE */
+    SPSTD_ERR_WORKSPACE = 3,  /* workspace missing, too small or misaligned */
+    SPSTD_ERR_DEVICE = 4,     /* a HIP runtime call failed */
+    SPSTD_ERR_NONFINITE = 5,  /* the state holds NaN or Inf after a run */
+    SPSTD_ERR_CAPACITY = 6    /* more steps than the probe buffer holds */
+} spstd_status;
+
+enum { SPSTD_FP64 = 0, SPSTD_FP32 = 1 };            /* storage and arithmetic of fields */
+enum { SPSTD_NYQ_FULL = 0, SPSTD_NYQ_ZERO = 1 };    /* Nyquist bin convention, see below */
+enum { SPSTD_SYMPLECTIC = 0, SPSTD_RK4 = 1 };        /* time integrator */
+
+#define SPSTD_ALLOW_UNSTABLE 0x1u                    /* flags: accept dt beyond the edge */
+#define SPSTD_EAGER 0x2u                             /* flags: launch kernels one by one
+                                                        instead of replaying step-chunk graphs */
+#define SPSTD_TIMING 0x4u                            /* flags: eager launches, each pass kernel
+                                                        bracketed by HIP events (spstd_pass_times) */
+#define SPSTD_MAX_STAGES 16
+#define SPSTD_MAX_PROBES 64
+
+/*
+ * Problem descriptor (caller-owned; copied by spstd_plan).
+ *   ndim         1, 2 or 3.
+ *   n[3]         points per axis (unused axes must be 1).  Powers of two;
+ *                x: 16..16384; y, z: 16..1024.  Periodic boundaries (Sec. 2.2,
+ *                last paragraph: periodic conditions use the DFT).
+ *   dx[3]        grid spacing per axis (> 0), so L_d = n_d * dx_d.
+ *   hbar, mass   hbar and m* (> 0); the configs use 1 and 1.
+ *   precision    SPSTD_FP64 or SPSTD_FP32 (fields, potential and transforms
+ *                stored and computed in that type; probes, norms and the
+ *                spectrum are always FP64).
+ *   method       SPSTD_SYMPLECTIC (Eq. 17-18) or SPSTD_RK4 (classical
+ *                fourth-order Runge-Kutta on d/dt(psi_R, psi_I) =
+ *                (K psi_I, -K psi_R), the non-symplectic comparison of Sec. 3.1).
+ *   m, c, d      stage count (1..16) and coefficients (host, length m) of
+ *                Eq. (17); ignored for RK4.  The paper's set is
+ *                c = (0.26833010, -0.18799162, 0.91966152), d_l = c_{m-l+1}.
+ *   dt           time step; 0 selects dt = cfl_fraction * x_max / rho with
+ *                x_max the first x where |tr L^d(x)| = 2 (Eq. 23-25) and
+ *                rho = (hbar/2m*) sum_d (pi/dx_d)^2 + max|V|/hbar.
+ *   cfl_fraction used when dt == 0 (0 < f < 1).
+ *   nyquist      SPSTD_NYQ_FULL: symbol -k^2 with |k| = pi/dx at the Nyquist
+ *                bin (direct second derivative); SPSTD_NYQ_ZERO: the Nyquist
+ *                term removed, as Eq. (10) read literally (two first
+ *                derivatives, real part kept after each inverse transform).
+ *   nprobes      0..64 probe points; probe_idx (host) their linear indices.
+ *   flags        SPSTD_ALLOW_UNSTABLE, SPSTD_EAGER, SPSTD_TIMING (OR-ed), or 0.
+ */
+typedef struct spstd_desc {
+    int ndim;
+    int64_t n[3];
+    double dx[3];
+    double hbar, mass;
+    int precision;
+    int method;
+    int m;
+    const double *c, *d;
+    double dt;
+    double cfl_fraction;
+    int nyquist;
+    int nprobes;
+    const int64_t *probe_idx;
+    uint32_t flags;
+} spstd_desc;
+
+typedef struct spstd_plan_s *spstd_plan_t;
+
+/* Run statistics (host, filled by spstd_run and spstd_plan_info). */
+typedef struct spstd_stats {
+    int64_t steps_done;    /* steps taken since the plan was made */
+    double dt;             /* time step in use */
+    double xmax;           /* stability edge x_max of the coefficient set */
+    double rho;            /* the spectral-radius bound used for dt */
+    double norm0;          /* sum |psi|^2 * cell volume at plan time */
+    double norm;           /* the same after the last spstd_run */
+    double substeps_per_step; /* non-zero A and B substeps per step (RK4: 8) */
+} spstd_stats;
+
+/*
+ * Stability edge of a coefficient set: the smallest x > 0 beyond which
+ * |tr L^d(x)| > 2, L^d the per-mode evolution matrix of Eq. (23)
+ * (Eq. 24-25).  c, d: host arrays of length m.  Pure host computation.
+ * Errors: SPSTD_ERR_ARG for m outside 1..16, null pointers or no edge below 1e3.
+ */
+spstd_status spstd_xmax(int m, const double *c, const double *d, double *xmax_out);
+
+/*
+ * The time step spstd_plan would choose: cfl_fraction * x_max / rho with
+ * rho as described for spstd_desc.dt (Eq. 24-30 extended by max|V|/hbar).
+ * V: host array of the grid's size.  Pure host computation.
+ */
+spstd_status spstd_stable_dt(const spstd_desc *desc, const double *V, double *dt_out);
+
+/*
+ * Exact device workspace size, in bytes, of a plan for desc that can record
+ * up to nsteps_max steps of probe samples.  Pure host computation.
+ */
+spstd_status spstd_workspace_size(const spstd_desc *desc, int64_t nsteps_max, size_t *bytes);
+
+/*
+ * Create a plan: validate desc, fix dt, build the FP64 twiddle tables and
+ * copy V, psi_R(0), psi_I(0) (host FP64 arrays of the grid's size; psi_I may
+ * be NULL for zero) into d_workspace (device, ws_bytes >= the size returned
+ * by spstd_workspace_size for the same nsteps_max, 256-byte aligned).
+ * stream: a hipStream_t (NULL for the null stream) on which every kernel of
+ * the plan runs.  Records probe sample 0 (the initial state).  Synchronises
+ * the stream before returning.  *out receives the plan; release it with
+ * spstd_destroy (the workspace stays the caller's).
+ * Errors: SPSTD_ERR_ARG, SPSTD_ERR_UNSTABLE, SPSTD_ERR_WORKSPACE,
+ * SPSTD_ERR_DEVICE.
+ */
+spstd_status spstd_plan(const spstd_desc *desc, const double *V, const double *psiR0,
+                        const double *psiI0, void *d_workspace, size_t ws_bytes,
+                        int64_t nsteps_max, void *stream, spstd_plan_t *out);
+
+/*
+ * Enqueue nsteps time steps (Eq. 17-18 per step, or RK4) on the plan's stream
+ * and record one probe sample after each.  Asynchronous: returns once the
+ * work is queued.  SPSTD_ERR_CAPACITY if the probe buffer would overflow
+ * (nothing is queued then).
+ */
+spstd_status spstd_step(spstd_plan_t plan, int64_t nsteps);
+
+/*
+ * spstd_step(nsteps), then synchronise, check the state for NaN/Inf
+ * (SPSTD_ERR_NONFINITE), update stats and copy the whole probe series
+ * recorded so far to probe_out (host, [(steps_done + 1) * nprobes * 2]
+ * doubles as (psi_R, psi_I) per probe per sample; may be NULL).
+ * stats_out may be NULL.
+ */
+spstd_status spstd_run(spstd_plan_t plan, int64_t nsteps, double *probe_out,
+                       spstd_stats *stats_out);
+
+/* Statistics without running (steps_done, dt, x_max, rho, norm0). */
+spstd_status spstd_plan_info(spstd_plan_t plan, spstd_stats *stats_out);
+
+/*
+ * Device pointers of the plan's fields (psi_R, psi_I, V) and of its FP64
+ * probe buffer, for callers that read them in place (e.g. as tensors).
+ * The element type of the fields follows desc.precision.
+ */
+spstd_status spstd_device_fields(spstd_plan_t plan, void **psiR, void **psiI, void **V,
+                                 double **probes);
+
+/*
+ * Checkpoint: copy the state to host FP64 arrays (synchronising), with the
+ * step count; and restore it (the probe series restarts at the given step
+ * count: samples beyond it are discarded).  psiI may be NULL on get.
+ */
+spstd_status spstd_get_state(spstd_plan_t plan, double *psiR, double *psiI, int64_t *step);
+spstd_status spstd_set_state(spstd_plan_t plan, const double *psiR, const double *psiI,
+                             int64_t step);
+
+/*
+ * Eigenvalues from probe time series (Sec. 3: time-FFT of the recorded wave
+ * function; Tables 2-4).  series: host [nsamples][nprobes][2] (psi_R, psi_I)
+ * sampled every dt.  Reading of the unstated details: the conjugated complex
+ * series per probe, a symmetric 4-term Blackman-Harris window, zero padding
+ * to 2^ceil(log2(8 nsamples)), power summed over probes, local maxima above
+ * 1e-8 of the largest, each refined to the zero of the derivative of the
+ * windowed DTFT power; E = hbar * omega ascending.  Writes up to nlevels
+ * energies to E_out and amplitudes to amp_out (may be NULL), the count to
+ * *nfound (fewer than nlevels is not an error).  Pure host FP64.
+ */
+spstd_status spstd_spectrum(const double *series, int64_t nsamples, int nprobes, double dt,
+                            double hbar, int nlevels, double *E_out, double *amp_out,
+                            int *nfound);
+
+/*
+ * Kinds of pass kernels, for spstd_pass_times.  Y and Z: one directional
+ * second-derivative pass along y or z added into a field; XAB: the fused A
+ * and B halves along x of one stage (Eq. 18 and its psi_I mirror); X: one
+ * half-stage along x.
+ */
+enum { SPSTD_PASS_Y = 0, SPSTD_PASS_Z = 1, SPSTD_PASS_XAB = 2, SPSTD_PASS_X = 3,
+       SPSTD_NPASS_KINDS = 4 };
+
+/*
+ * Per-kind kernel timing of a plan made with SPSTD_TIMING: synchronises the
+ * plan's stream and returns, for each kind k < SPSTD_NPASS_KINDS, the number
+ * of launches since the previous call (launches[k]), their summed duration
+ * in milliseconds measured with HIP events recorded on the plan's stream
+ * around each launch (total_ms[k]), and the algorithmic HBM bytes of one
+ * launch (bytes_per_launch[k]: every field read once and every field written
+ * once).  Host arrays of SPSTD_NPASS_KINDS entries; any may be NULL.
+ * SPSTD_ERR_ARG if the plan was made without SPSTD_TIMING.
+ */
+spstd_status spstd_pass_times(spstd_plan_t plan, int64_t *launches, double *total_ms,
+                              double *bytes_per_launch);
+
+spstd_status spstd_destroy(spstd_plan_t plan);
+const char *spstd_strerror(spstd_status status);
+/* Text of the last error recorded on the plan (never NULL). */
+const char *spstd_last_error(spstd_plan_t plan);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SPSTD_H */

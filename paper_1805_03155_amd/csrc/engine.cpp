@@ -1,0 +1,739 @@
+// Host engine behind the C ABI: plan validation, time step, workspace
+// layout, stage sequencing of the directional passes, step-chunk HIP graphs,
+// probe recording, norms, checkpoints and the RK4 comparison integrator.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/spstd.h"
+#include "kernels.hpp"
+
+namespace spstd {
+
+static const double kPi = 3.14159265358979323846264338327950288;
+
+// ---------------------------------------------------------------------------
+// Stability edge from the trace polynomial of the per-mode matrix.
+// The matrix of one step (Eq. 23) is the time-ordered product of the stage
+// shears A(c_l x) = [[1, c_l x], [0, 1]] and B(d_l x) = [[1, 0], [-d_l x, 1]];
+// its entries are polynomials in x of degree <= 2m.  tr = 2 + sum_l (-1)^l
+// g_l x^(2l) (Eq. 26-28); the edge is the first x > 0 with |tr| > 2.
+// ---------------------------------------------------------------------------
+struct Poly {
+    double a[2 * SPSTD_MAX_STAGES + 2];
+    int deg;
+};
+
+static Poly pmul_x(const Poly& p, double s) {  // s * x * p(x)
+    Poly r{};
+    r.deg = p.deg + 1;
+    for (int i = 0; i <= p.deg; ++i) r.a[i + 1] = s * p.a[i];
+    return r;
+}
+static Poly padd(const Poly& p, const Poly& q) {
+    Poly r{};
+    r.deg = p.deg > q.deg ? p.deg : q.deg;
+    for (int i = 0; i <= r.deg; ++i) r.a[i] = (i <= p.deg ? p.a[i] : 0.0) + (i <= q.deg ? q.a[i] : 0.0);
+    return r;
+}
+static double peval(const Poly& p, double x) {
+    double s = 0.0;
+    for (int i = p.deg; i >= 0; --i) s = s * x + p.a[i];
+    return s;
+}
+
+static bool trace_poly(int m, const double* c, const double* d, Poly* tr) {
+    Poly m00{}, m01{}, m10{}, m11{};
+    m00.a[0] = 1.0; m11.a[0] = 1.0;
+    for (int l = 0; l < m; ++l) {
+        // rows: A multiplies from the left: row0 += c x * row1
+        Poly n00 = padd(m00, pmul_x(m10, c[l]));
+        Poly n01 = padd(m01, pmul_x(m11, c[l]));
+        // B: row1 -= d x * row0 (new row0)
+        Poly n10 = padd(m10, pmul_x(n00, -d[l]));
+        Poly n11 = padd(m11, pmul_x(n01, -d[l]));
+        m00 = n00; m01 = n01; m10 = n10; m11 = n11;
+    }
+    *tr = padd(m00, m11);
+    return true;
+}
+
+static bool xmax_symplectic(int m, const double* c, const double* d, double* out) {
+    Poly tr;
+    trace_poly(m, c, d, &tr);
+    auto beyond = [&](double x) { return std::fabs(peval(tr, x)) > 2.0; };
+    // scan in steps of 1/256 of a unit, then bisect the bracketing step
+    const double h = 1.0 / 256.0;
+    double lo = 0.0;
+    for (int i = 1; i <= 256 * 1000; ++i) {
+        double x = i * h;
+        if (beyond(x)) {
+            double hi = x;
+            for (int it = 0; it < 200; ++it) {
+                double mid = 0.5 * (lo + hi);
+                if (mid <= lo || mid >= hi) break;
+                (beyond(mid) ? hi : lo) = mid;
+            }
+            *out = lo;
+            return true;
+        }
+        lo = x;
+    }
+    return false;
+}
+
+// classical RK4 on an oscillation: stable while |x| <= 2 sqrt(2)
+static const double kRK4Edge = 2.8284271247461900976;
+
+// ---------------------------------------------------------------------------
+// plan
+// ---------------------------------------------------------------------------
+struct Layout {
+    size_t psiR, psiI, V, rk[6], tw[3], pidx, probes, counter, partials, total;
+};
+
+static const int kNormBlocks = 256;
+static const int kGraphChunk = 16;
+
+struct Plan {
+    spstd_desc d;
+    double c[SPSTD_MAX_STAGES], dd[SPSTD_MAX_STAGES];
+    int64_t probe_idx[SPSTD_MAX_PROBES];
+    double dt, xmax, rho, norm0, norm, cellvol;
+    int64_t N, nsteps_max, steps_done;
+    size_t esz;
+    char* ws;
+    Layout L;
+    hipStream_t st;
+    int64_t twlen[3];
+    hipGraphExec_t graph;
+    bool graph_ready;
+    std::string err;
+    // SPSTD_TIMING: event pairs around pass launches, their kinds
+    std::vector<hipEvent_t> ev_pool;
+    std::vector<int> ev_kind;
+    size_t ev_used = 0;
+};
+
+// Brackets one pass launch with HIP events on the plan's stream when the
+// plan times its passes.
+struct PassTimer {
+    Plan* p;
+    int slot;
+    PassTimer(Plan* pl, int kind) : p(pl), slot(-1) {
+        if (!(p->d.flags & SPSTD_TIMING)) return;
+        if (p->ev_used + 2 > p->ev_pool.size()) {
+            hipEvent_t a, b;
+            if (hipEventCreate(&a) != hipSuccess) return;
+            if (hipEventCreate(&b) != hipSuccess) { (void)hipEventDestroy(a); return; }
+            p->ev_pool.push_back(a);
+            p->ev_pool.push_back(b);
+        }
+        slot = (int)p->ev_used;
+        p->ev_used += 2;
+        p->ev_kind.push_back(kind);
+        (void)hipEventRecord(p->ev_pool[slot], p->st);
+    }
+    ~PassTimer() {
+        if (slot >= 0) (void)hipEventRecord(p->ev_pool[slot + 1], p->st);
+    }
+};
+
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+static bool pow2(int64_t n) { return n > 0 && (n & (n - 1)) == 0; }
+
+static spstd_status validate(const spstd_desc* d, std::string* why) {
+    if (!d) { *why = "null descriptor"; return SPSTD_ERR_ARG; }
+    if (d->ndim < 1 || d->ndim > 3) { *why = "ndim must be 1, 2 or 3"; return SPSTD_ERR_ARG; }
+    for (int a = 0; a < 3; ++a) {
+        if (a < d->ndim) {
+            bool ok = (a == 0) ? row_len_ok(d->n[a]) : axis_len_ok(d->n[a]);
+            if (!ok) { *why = "axis length must be a power of two (x: 16..16384, y/z: 16..1024)"; return SPSTD_ERR_ARG; }
+            if (!(d->dx[a] > 0.0) || !std::isfinite(d->dx[a])) { *why = "dx must be positive"; return SPSTD_ERR_ARG; }
+        } else if (d->n[a] != 1) {
+            *why = "unused axes must have length 1";
+            return SPSTD_ERR_ARG;
+        }
+    }
+    if (!(d->hbar > 0.0) || !(d->mass > 0.0) || !std::isfinite(d->hbar) || !std::isfinite(d->mass)) {
+        *why = "hbar and mass must be positive"; return SPSTD_ERR_ARG;
+    }
+    if (d->precision != SPSTD_FP64 && d->precision != SPSTD_FP32) { *why = "bad precision"; return SPSTD_ERR_ARG; }
+    if (d->method != SPSTD_SYMPLECTIC && d->method != SPSTD_RK4) { *why = "bad method"; return SPSTD_ERR_ARG; }
+    if (d->method == SPSTD_SYMPLECTIC) {
+        if (d->m < 1 || d->m > SPSTD_MAX_STAGES || !d->c || !d->d) { *why = "m must be 1..16 with c, d"; return SPSTD_ERR_ARG; }
+        for (int l = 0; l < d->m; ++l)
+            if (!std::isfinite(d->c[l]) || !std::isfinite(d->d[l])) { *why = "non-finite coefficient"; return SPSTD_ERR_ARG; }
+    }
+    if (d->nyquist != SPSTD_NYQ_FULL && d->nyquist != SPSTD_NYQ_ZERO) { *why = "bad nyquist"; return SPSTD_ERR_ARG; }
+    if (!(d->dt >= 0.0) || !std::isfinite(d->dt)) { *why = "dt must be >= 0"; return SPSTD_ERR_ARG; }
+    if (d->dt == 0.0 && !(d->cfl_fraction > 0.0 && std::isfinite(d->cfl_fraction))) {
+        *why = "cfl_fraction must be positive when dt is 0"; return SPSTD_ERR_ARG;
+    }
+    if (d->nprobes < 0 || d->nprobes > SPSTD_MAX_PROBES || (d->nprobes > 0 && !d->probe_idx)) {
+        *why = "nprobes must be 0..64"; return SPSTD_ERR_ARG;
+    }
+    const int64_t N = d->n[0] * d->n[1] * d->n[2];
+    for (int p = 0; p < d->nprobes; ++p)
+        if (d->probe_idx[p] < 0 || d->probe_idx[p] >= N) { *why = "probe index out of range"; return SPSTD_ERR_ARG; }
+    return SPSTD_OK;
+}
+
+static double rho_of(const spstd_desc* d, const double* V, int64_t N) {
+    double r = 0.0;
+    for (int a = 0; a < d->ndim; ++a) r += (kPi / d->dx[a]) * (kPi / d->dx[a]);
+    r *= d->hbar / (2.0 * d->mass);
+    double vm = 0.0;
+    for (int64_t i = 0; i < N; ++i) vm = std::fmax(vm, std::fabs(V[i]));
+    return r + vm / d->hbar;
+}
+
+static spstd_status edge_of(const spstd_desc* d, double* x) {
+    if (d->method == SPSTD_RK4) { *x = kRK4Edge; return SPSTD_OK; }
+    return xmax_symplectic(d->m, d->c, d->d, x) ? SPSTD_OK : SPSTD_ERR_ARG;
+}
+
+static Layout layout_of(const spstd_desc* d, int64_t nsteps_max) {
+    Layout L{};
+    const int64_t N = d->n[0] * d->n[1] * d->n[2];
+    const size_t esz = d->precision == SPSTD_FP64 ? 8 : 4;
+    const size_t fb = align256((size_t)N * esz);
+    size_t off = 0;
+    L.psiR = off; off += fb;
+    L.psiI = off; off += fb;
+    L.V = off; off += fb;
+    for (int k = 0; k < 6; ++k) {
+        L.rk[k] = off;
+        if (d->method == SPSTD_RK4) off += fb;
+    }
+    for (int a = 0; a < 3; ++a) {
+        L.tw[a] = off;
+        if (a < d->ndim) off += align256((size_t)d->n[a] * 2 * esz);
+    }
+    L.pidx = off; off += align256(sizeof(int64_t) * (size_t)(d->nprobes > 0 ? d->nprobes : 1));
+    L.probes = off;
+    off += align256(sizeof(double) * 2 * (size_t)(d->nprobes > 0 ? d->nprobes : 1) * (size_t)(nsteps_max + 1));
+    L.counter = off; off += 256;
+    L.partials = off; off += align256(sizeof(double) * kNormBlocks);
+    L.total = off;
+    return L;
+}
+
+template <typename R>
+static R* F(Plan* p, size_t off) { return reinterpret_cast<R*>(p->ws + off); }
+
+// FP64 twiddles w_n^t = exp(-2 pi i t / n), from long-double cos/sin.
+static std::vector<double> twiddles(int64_t n) {
+    std::vector<double> t(2 * n);
+    for (int64_t k = 0; k < n; ++k) {
+        long double ang = -2.0L * 3.14159265358979323846264338327950288L * (long double)k / (long double)n;
+        t[2 * k] = (double)cosl(ang);
+        t[2 * k + 1] = (double)sinl(ang);
+    }
+    return t;
+}
+
+#define HIPCHK(x)                                                   \
+    do {                                                            \
+        hipError_t e_ = (x);                                        \
+        if (e_ != hipSuccess) {                                     \
+            p->err = std::string(#x) + ": " + hipGetErrorString(e_); \
+            return SPSTD_ERR_DEVICE;                                \
+        }                                                           \
+    } while (0)
+
+template <typename R>
+static spstd_status upload(Plan* p, size_t off, const double* src) {
+    const int64_t N = p->N;
+    if (sizeof(R) == 8) {
+        if (src) HIPCHK(hipMemcpyAsync(p->ws + off, src, N * 8, hipMemcpyHostToDevice, p->st));
+        else HIPCHK(launch_fill0<R>(N, F<R>(p, off), p->st));
+    } else {
+        if (src) {
+            std::vector<float> tmp(N);
+            for (int64_t i = 0; i < N; ++i) tmp[i] = (float)src[i];
+            HIPCHK(hipMemcpyAsync(p->ws + off, tmp.data(), N * 4, hipMemcpyHostToDevice, p->st));
+            HIPCHK(hipStreamSynchronize(p->st));   // tmp goes out of scope
+        } else {
+            HIPCHK(launch_fill0<R>(N, F<R>(p, off), p->st));
+        }
+    }
+    return SPSTD_OK;
+}
+
+// symbol scale of axis a for substep coefficient coef: coef (hbar/2m) (2 pi/L)^2 / n
+static double sym_scale(const Plan* p, int a, double coef) {
+    const double L = (double)p->d.n[a] * p->d.dx[a];
+    const double k1 = 2.0 * kPi / L;
+    return coef * p->d.hbar / (2.0 * p->d.mass) * k1 * k1 / (double)p->d.n[a];
+}
+
+static AxisGeom axis_geom(const Plan* p, int a) {
+    AxisGeom g;
+    const int64_t nx = p->d.n[0], ny = p->d.n[1], nz = p->d.n[2];
+    g.half_x = nx / 2;
+    if (a == 1) { g.n_outer = nz; g.outer_stride = nx * ny; g.stride = nx; }
+    else { g.n_outer = ny; g.outer_stride = nx; g.stride = nx * ny; }
+    return g;
+}
+
+// dst += coef * T_{y,z} src for every axis beyond x
+template <typename R>
+static hipError_t yz_passes(Plan* p, const R* src, R* dst, double coef) {
+    for (int a = 1; a < p->d.ndim; ++a) {
+        PassTimer tm(p, a == 1 ? SPSTD_PASS_Y : SPSTD_PASS_Z);
+        hipError_t e = launch_axis_acc<R>(p->d.n[a], src, dst, p->ws + p->L.tw[a], axis_geom(p, a),
+                                          sym_scale(p, a, coef), p->d.nyquist, p->st);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+template <typename R>
+static hipError_t enqueue_symplectic_step(Plan* p) {
+    R* pr = F<R>(p, p->L.psiR);
+    R* pi = F<R>(p, p->L.psiI);
+    const R* V = F<R>(p, p->L.V);
+    const RowGeom rg{p->N / p->d.n[0]};
+    const int64_t nx = p->d.n[0];
+    const void* twx = p->ws + p->L.tw[0];
+    const double dt = p->dt, hb = p->d.hbar;
+    hipError_t e = hipSuccess;
+    for (int l = 0; l < p->d.m && e == hipSuccess; ++l) {
+        const double a = p->c[l] * dt, b = -p->dd[l] * dt;
+        if (a != 0.0) e = yz_passes<R>(p, pi, pr, a);
+        if (e != hipSuccess) break;
+        if (a != 0.0 || b != 0.0) {
+            PassTimer tm(p, (a != 0.0 && b != 0.0) ? SPSTD_PASS_XAB : SPSTD_PASS_X);
+            if (a != 0.0 && b != 0.0)
+                e = launch_x_ab<R>(nx, pr, pi, V, twx, rg, sym_scale(p, 0, a), a / hb,
+                                   sym_scale(p, 0, b), b / hb, p->d.nyquist, p->st);
+            else if (a != 0.0)
+                e = launch_x_acc<R>(nx, pi, pr, V, twx, rg, sym_scale(p, 0, a), a / hb,
+                                    p->d.nyquist, p->st);
+            else
+                e = launch_x_acc<R>(nx, pr, pi, V, twx, rg, sym_scale(p, 0, b), b / hb,
+                                    p->d.nyquist, p->st);
+        }
+        if (e != hipSuccess) break;
+        if (b != 0.0) e = yz_passes<R>(p, pr, pi, b);
+    }
+    return e;
+}
+
+// kout = coef * K src  (K of Eq. 16), into a cleared buffer
+template <typename R>
+static hipError_t apply_K(Plan* p, const R* src, R* kout, double coef) {
+    const R* V = F<R>(p, p->L.V);
+    hipError_t e = launch_fill0<R>(p->N, kout, p->st);
+    if (e == hipSuccess) e = yz_passes<R>(p, src, kout, coef);
+    PassTimer tm(p, SPSTD_PASS_X);
+    if (e == hipSuccess)
+        e = launch_x_acc<R>(p->d.n[0], src, kout, V, p->ws + p->L.tw[0], RowGeom{p->N / p->d.n[0]},
+                            sym_scale(p, 0, coef), coef / p->d.hbar, p->d.nyquist, p->st);
+    return e;
+}
+
+template <typename R>
+static hipError_t enqueue_rk4_step(Plan* p) {
+    R* pr = F<R>(p, p->L.psiR);
+    R* pi = F<R>(p, p->L.psiI);
+    R* kR = F<R>(p, p->L.rk[0]);
+    R* kI = F<R>(p, p->L.rk[1]);
+    R* yR = F<R>(p, p->L.rk[2]);
+    R* yI = F<R>(p, p->L.rk[3]);
+    R* aR = F<R>(p, p->L.rk[4]);
+    R* aI = F<R>(p, p->L.rk[5]);
+    const int64_t N = p->N;
+    const double dt = p->dt;
+    static const double wgt[4] = {1.0, 2.0, 2.0, 1.0};
+    static const double nxt[3] = {0.5, 0.5, 1.0};
+    hipError_t e = launch_fill0<R>(N, aR, p->st);
+    if (e == hipSuccess) e = launch_fill0<R>(N, aI, p->st);
+    for (int s = 0; s < 4 && e == hipSuccess; ++s) {
+        const R* inR = s ? yR : pr;
+        const R* inI = s ? yI : pi;
+        e = apply_K<R>(p, inI, kR, 1.0);                 // d psi_R / dt =  K psi_I
+        if (e == hipSuccess) e = apply_K<R>(p, inR, kI, -1.0);   // d psi_I / dt = -K psi_R
+        if (e == hipSuccess) e = launch_axpby<R>(N, wgt[s], kR, 1.0, aR, p->st);
+        if (e == hipSuccess) e = launch_axpby<R>(N, wgt[s], kI, 1.0, aI, p->st);
+        if (s < 3) {
+            if (e == hipSuccess) e = launch_xpay<R>(N, pr, nxt[s] * dt, kR, yR, p->st);
+            if (e == hipSuccess) e = launch_xpay<R>(N, pi, nxt[s] * dt, kI, yI, p->st);
+        }
+    }
+    if (e == hipSuccess) e = launch_axpby<R>(N, dt / 6.0, aR, 1.0, pr, p->st);
+    if (e == hipSuccess) e = launch_axpby<R>(N, dt / 6.0, aI, 1.0, pi, p->st);
+    return e;
+}
+
+template <typename R>
+static hipError_t enqueue_steps_eager(Plan* p, int64_t n) {
+    hipError_t e = hipSuccess;
+    for (int64_t s = 0; s < n && e == hipSuccess; ++s) {
+        e = (p->d.method == SPSTD_RK4) ? enqueue_rk4_step<R>(p) : enqueue_symplectic_step<R>(p);
+        if (e == hipSuccess && p->d.nprobes > 0)
+            e = launch_probe<R>(F<R>(p, p->L.psiR), F<R>(p, p->L.psiI),
+                                reinterpret_cast<const int64_t*>(p->ws + p->L.pidx), p->d.nprobes,
+                                reinterpret_cast<double*>(p->ws + p->L.probes),
+                                reinterpret_cast<int64_t*>(p->ws + p->L.counter), p->nsteps_max + 1,
+                                p->st);
+    }
+    return e;
+}
+
+template <typename R>
+static spstd_status build_graph(Plan* p) {
+    hipStream_t cap;
+    HIPCHK(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+    hipStream_t user = p->st;
+    p->st = cap;
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        hipError_t e2 = enqueue_steps_eager<R>(p, kGraphChunk);
+        e = hipStreamEndCapture(cap, &g);
+        if (e == hipSuccess) e = e2;
+    }
+    p->st = user;
+    if (e == hipSuccess) e = hipGraphInstantiate(&p->graph, g, nullptr, nullptr, 0);
+    if (g) (void)hipGraphDestroy(g);
+    (void)hipStreamDestroy(cap);
+    if (e != hipSuccess) {
+        p->err = std::string("graph capture: ") + hipGetErrorString(e);
+        return SPSTD_ERR_DEVICE;
+    }
+    p->graph_ready = true;
+    return SPSTD_OK;
+}
+
+template <typename R>
+static spstd_status enqueue_steps(Plan* p, int64_t n) {
+    const bool use_graph = !(p->d.flags & (SPSTD_EAGER | SPSTD_TIMING)) && n >= kGraphChunk;
+    if (use_graph && !p->graph_ready) {
+        spstd_status s = build_graph<R>(p);
+        if (s != SPSTD_OK) return s;
+    }
+    int64_t left = n;
+    if (use_graph) {
+        for (; left >= kGraphChunk; left -= kGraphChunk) HIPCHK(hipGraphLaunch(p->graph, p->st));
+    }
+    HIPCHK(enqueue_steps_eager<R>(p, left));
+    return SPSTD_OK;
+}
+
+template <typename R>
+static spstd_status compute_norm(Plan* p, double* out) {
+    HIPCHK(launch_norm_partials<R>(F<R>(p, p->L.psiR), F<R>(p, p->L.psiI), p->N,
+                                   reinterpret_cast<double*>(p->ws + p->L.partials), kNormBlocks, p->st));
+    double part[kNormBlocks];
+    HIPCHK(hipMemcpyAsync(part, p->ws + p->L.partials, sizeof(part), hipMemcpyDeviceToHost, p->st));
+    HIPCHK(hipStreamSynchronize(p->st));
+    double s = 0.0;
+    for (int i = 0; i < kNormBlocks; ++i) s += part[i];
+    *out = s * p->cellvol;
+    return SPSTD_OK;
+}
+
+template <typename R>
+static spstd_status plan_init(Plan* p, const double* V, const double* psiR0, const double* psiI0) {
+    spstd_status s;
+    if ((s = upload<R>(p, p->L.psiR, psiR0)) != SPSTD_OK) return s;
+    if ((s = upload<R>(p, p->L.psiI, psiI0)) != SPSTD_OK) return s;
+    if ((s = upload<R>(p, p->L.V, V)) != SPSTD_OK) return s;
+    for (int a = 0; a < p->d.ndim; ++a) {
+        std::vector<double> t = twiddles(p->d.n[a]);
+        if (sizeof(R) == 8) {
+            HIPCHK(hipMemcpyAsync(p->ws + p->L.tw[a], t.data(), t.size() * 8, hipMemcpyHostToDevice, p->st));
+            HIPCHK(hipStreamSynchronize(p->st));
+        } else {
+            std::vector<float> f(t.size());
+            for (size_t i = 0; i < t.size(); ++i) f[i] = (float)t[i];
+            HIPCHK(hipMemcpyAsync(p->ws + p->L.tw[a], f.data(), f.size() * 4, hipMemcpyHostToDevice, p->st));
+            HIPCHK(hipStreamSynchronize(p->st));
+        }
+    }
+    if (p->d.nprobes > 0)
+        HIPCHK(hipMemcpyAsync(p->ws + p->L.pidx, p->probe_idx, sizeof(int64_t) * p->d.nprobes,
+                              hipMemcpyHostToDevice, p->st));
+    int64_t zero = 0;
+    HIPCHK(hipMemcpyAsync(p->ws + p->L.counter, &zero, sizeof(zero), hipMemcpyHostToDevice, p->st));
+    if (p->d.nprobes > 0)
+        HIPCHK(launch_probe<R>(F<R>(p, p->L.psiR), F<R>(p, p->L.psiI),
+                               reinterpret_cast<const int64_t*>(p->ws + p->L.pidx), p->d.nprobes,
+                               reinterpret_cast<double*>(p->ws + p->L.probes),
+                               reinterpret_cast<int64_t*>(p->ws + p->L.counter), p->nsteps_max + 1, p->st));
+    HIPCHK(hipStreamSynchronize(p->st));
+    return compute_norm<R>(p, &p->norm0);
+}
+
+template <typename R>
+static spstd_status get_state_t(Plan* p, double* psiR, double* psiI) {
+    const int64_t N = p->N;
+    std::vector<R> tmp(N);
+    double* outs[2] = {psiR, psiI};
+    size_t offs[2] = {p->L.psiR, p->L.psiI};
+    for (int k = 0; k < 2; ++k) {
+        if (!outs[k]) continue;
+        HIPCHK(hipMemcpyAsync(tmp.data(), p->ws + offs[k], N * sizeof(R), hipMemcpyDeviceToHost, p->st));
+        HIPCHK(hipStreamSynchronize(p->st));
+        for (int64_t i = 0; i < N; ++i) outs[k][i] = (double)tmp[i];
+    }
+    return SPSTD_OK;
+}
+
+}  // namespace spstd
+
+using namespace spstd;
+
+struct spstd_plan_s : Plan {};
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+spstd_status spstd_xmax(int m, const double* c, const double* d, double* xmax_out) {
+    if (m < 1 || m > SPSTD_MAX_STAGES || !c || !d || !xmax_out) return SPSTD_ERR_ARG;
+    for (int l = 0; l < m; ++l)
+        if (!std::isfinite(c[l]) || !std::isfinite(d[l])) return SPSTD_ERR_ARG;
+    return xmax_symplectic(m, c, d, xmax_out) ? SPSTD_OK : SPSTD_ERR_ARG;
+}
+
+spstd_status spstd_stable_dt(const spstd_desc* desc, const double* V, double* dt_out) {
+    std::string why;
+    spstd_status s = validate(desc, &why);
+    if (s != SPSTD_OK) return s;
+    if (!V || !dt_out) return SPSTD_ERR_ARG;
+    double x;
+    if ((s = edge_of(desc, &x)) != SPSTD_OK) return s;
+    const int64_t N = desc->n[0] * desc->n[1] * desc->n[2];
+    const double f = desc->cfl_fraction > 0.0 ? desc->cfl_fraction : 1.0;
+    *dt_out = f * x / rho_of(desc, V, N);
+    return SPSTD_OK;
+}
+
+spstd_status spstd_workspace_size(const spstd_desc* desc, int64_t nsteps_max, size_t* bytes) {
+    std::string why;
+    spstd_status s = validate(desc, &why);
+    if (s != SPSTD_OK) return s;
+    if (nsteps_max < 0 || !bytes) return SPSTD_ERR_ARG;
+    *bytes = layout_of(desc, nsteps_max).total;
+    return SPSTD_OK;
+}
+
+spstd_status spstd_plan(const spstd_desc* desc, const double* V, const double* psiR0, const double* psiI0,
+                        void* d_workspace, size_t ws_bytes, int64_t nsteps_max, void* stream,
+                        spstd_plan_t* out) {
+    if (!out) return SPSTD_ERR_ARG;
+    *out = nullptr;
+    std::string why;
+    spstd_status s = validate(desc, &why);
+    if (s != SPSTD_OK) return s;
+    if (!V || !psiR0 || nsteps_max < 0) return SPSTD_ERR_ARG;
+    const int64_t N = desc->n[0] * desc->n[1] * desc->n[2];
+    for (int64_t i = 0; i < N; ++i)
+        if (!std::isfinite(V[i]) || !std::isfinite(psiR0[i]) || (psiI0 && !std::isfinite(psiI0[i])))
+            return SPSTD_ERR_ARG;
+    Layout L = layout_of(desc, nsteps_max);
+    if (!d_workspace || ws_bytes < L.total || ((uintptr_t)d_workspace & 255)) return SPSTD_ERR_WORKSPACE;
+    double x;
+    if ((s = edge_of(desc, &x)) != SPSTD_OK) return s;
+    const double rho = rho_of(desc, V, N);
+    double dt = desc->dt > 0.0 ? desc->dt : desc->cfl_fraction * x / rho;
+    if (!(desc->flags & SPSTD_ALLOW_UNSTABLE) && dt * rho >= x) return SPSTD_ERR_UNSTABLE;
+
+    spstd_plan_s* p = new (std::nothrow) spstd_plan_s();
+    if (!p) return SPSTD_ERR_DEVICE;
+    p->d = *desc;
+    for (int l = 0; l < desc->m && desc->method == SPSTD_SYMPLECTIC; ++l) {
+        p->c[l] = desc->c[l];
+        p->dd[l] = desc->d[l];
+    }
+    p->d.c = p->c;
+    p->d.d = p->dd;
+    for (int q = 0; q < desc->nprobes; ++q) p->probe_idx[q] = desc->probe_idx[q];
+    p->d.probe_idx = p->probe_idx;
+    p->dt = dt;
+    p->xmax = x;
+    p->rho = rho;
+    p->N = N;
+    p->nsteps_max = nsteps_max;
+    p->steps_done = 0;
+    p->esz = desc->precision == SPSTD_FP64 ? 8 : 4;
+    p->ws = (char*)d_workspace;
+    p->L = L;
+    p->st = (hipStream_t)stream;
+    p->graph_ready = false;
+    p->cellvol = 1.0;
+    for (int a = 0; a < desc->ndim; ++a) p->cellvol *= desc->dx[a];
+    s = (desc->precision == SPSTD_FP64) ? plan_init<double>(p, V, psiR0, psiI0)
+                                        : plan_init<float>(p, V, psiR0, psiI0);
+    if (s != SPSTD_OK) {
+        delete p;
+        return s;
+    }
+    p->norm = p->norm0;
+    *out = p;
+    return SPSTD_OK;
+}
+
+spstd_status spstd_step(spstd_plan_t p, int64_t nsteps) {
+    if (!p || nsteps < 0) return SPSTD_ERR_ARG;
+    if (p->steps_done + nsteps > p->nsteps_max) {
+        p->err = "probe buffer capacity exceeded";
+        return SPSTD_ERR_CAPACITY;
+    }
+    spstd_status s = (p->esz == 8) ? enqueue_steps<double>(p, nsteps) : enqueue_steps<float>(p, nsteps);
+    if (s == SPSTD_OK) p->steps_done += nsteps;
+    return s;
+}
+
+spstd_status spstd_run(spstd_plan_t p, int64_t nsteps, double* probe_out, spstd_stats* stats) {
+    spstd_status s = spstd_step(p, nsteps);
+    if (s != SPSTD_OK) return s;
+    s = (p->esz == 8) ? compute_norm<double>(p, &p->norm) : compute_norm<float>(p, &p->norm);
+    if (s != SPSTD_OK) return s;
+    if (probe_out && p->d.nprobes > 0) {
+        const size_t bytes = sizeof(double) * 2 * p->d.nprobes * (size_t)(p->steps_done + 1);
+        hipError_t e = hipMemcpyAsync(probe_out, p->ws + p->L.probes, bytes, hipMemcpyDeviceToHost, p->st);
+        if (e == hipSuccess) e = hipStreamSynchronize(p->st);
+        if (e != hipSuccess) {
+            p->err = hipGetErrorString(e);
+            return SPSTD_ERR_DEVICE;
+        }
+    }
+    if (stats) spstd_plan_info(p, stats);
+    if (!std::isfinite(p->norm)) {
+        p->err = "state is not finite";
+        return SPSTD_ERR_NONFINITE;
+    }
+    return SPSTD_OK;
+}
+
+spstd_status spstd_plan_info(spstd_plan_t p, spstd_stats* st) {
+    if (!p || !st) return SPSTD_ERR_ARG;
+    st->steps_done = p->steps_done;
+    st->dt = p->dt;
+    st->xmax = p->xmax;
+    st->rho = p->rho;
+    st->norm0 = p->norm0;
+    st->norm = p->norm;
+    double subs = 0.0;
+    if (p->d.method == SPSTD_RK4) subs = 8.0;
+    else
+        for (int l = 0; l < p->d.m; ++l) subs += (p->c[l] != 0.0) + (p->dd[l] != 0.0);
+    st->substeps_per_step = subs;
+    return SPSTD_OK;
+}
+
+spstd_status spstd_device_fields(spstd_plan_t p, void** psiR, void** psiI, void** V, double** probes) {
+    if (!p) return SPSTD_ERR_ARG;
+    if (psiR) *psiR = p->ws + p->L.psiR;
+    if (psiI) *psiI = p->ws + p->L.psiI;
+    if (V) *V = p->ws + p->L.V;
+    if (probes) *probes = reinterpret_cast<double*>(p->ws + p->L.probes);
+    return SPSTD_OK;
+}
+
+spstd_status spstd_get_state(spstd_plan_t p, double* psiR, double* psiI, int64_t* step) {
+    if (!p || !psiR) return SPSTD_ERR_ARG;
+    spstd_status s = (p->esz == 8) ? get_state_t<double>(p, psiR, psiI) : get_state_t<float>(p, psiR, psiI);
+    if (s == SPSTD_OK && step) *step = p->steps_done;
+    return s;
+}
+
+spstd_status spstd_set_state(spstd_plan_t p, const double* psiR, const double* psiI, int64_t step) {
+    if (!p || !psiR || step < 0 || step > p->nsteps_max) return SPSTD_ERR_ARG;
+    for (int64_t i = 0; i < p->N; ++i)
+        if (!std::isfinite(psiR[i]) || (psiI && !std::isfinite(psiI[i]))) return SPSTD_ERR_ARG;
+    spstd_status s = (p->esz == 8) ? upload<double>(p, p->L.psiR, psiR) : upload<float>(p, p->L.psiR, psiR);
+    if (s == SPSTD_OK)
+        s = (p->esz == 8) ? upload<double>(p, p->L.psiI, psiI) : upload<float>(p, p->L.psiI, psiI);
+    if (s != SPSTD_OK) return s;
+    // the next sample goes to slot step + 1; slot `step` holds this state
+    int64_t next = step;
+    hipError_t e = hipMemcpyAsync(p->ws + p->L.counter, &next, sizeof(next), hipMemcpyHostToDevice, p->st);
+    if (e == hipSuccess && p->d.nprobes > 0) {
+        e = (p->esz == 8)
+                ? launch_probe<double>(F<double>(p, p->L.psiR), F<double>(p, p->L.psiI),
+                                       reinterpret_cast<const int64_t*>(p->ws + p->L.pidx), p->d.nprobes,
+                                       reinterpret_cast<double*>(p->ws + p->L.probes),
+                                       reinterpret_cast<int64_t*>(p->ws + p->L.counter), p->nsteps_max + 1, p->st)
+                : launch_probe<float>(F<float>(p, p->L.psiR), F<float>(p, p->L.psiI),
+                                      reinterpret_cast<const int64_t*>(p->ws + p->L.pidx), p->d.nprobes,
+                                      reinterpret_cast<double*>(p->ws + p->L.probes),
+                                      reinterpret_cast<int64_t*>(p->ws + p->L.counter), p->nsteps_max + 1, p->st);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(p->st);
+    if (e != hipSuccess) {
+        p->err = hipGetErrorString(e);
+        return SPSTD_ERR_DEVICE;
+    }
+    p->steps_done = step;
+    return SPSTD_OK;
+}
+
+spstd_status spstd_destroy(spstd_plan_t p) {
+    if (!p) return SPSTD_ERR_ARG;
+    if (p->graph_ready) (void)hipGraphExecDestroy(p->graph);
+    for (hipEvent_t e : p->ev_pool) (void)hipEventDestroy(e);
+    delete p;
+    return SPSTD_OK;
+}
+
+spstd_status spstd_pass_times(spstd_plan_t p, int64_t* launches, double* total_ms,
+                              double* bytes_per_launch) {
+    if (!p || !(p->d.flags & SPSTD_TIMING)) return SPSTD_ERR_ARG;
+    const double fb = (double)p->N * (double)p->esz;
+    // fields read + fields written once per launch
+    const double per[SPSTD_NPASS_KINDS] = {3.0 * fb, 3.0 * fb, 5.0 * fb, 4.0 * fb};
+    int64_t cnt[SPSTD_NPASS_KINDS] = {0};
+    double ms[SPSTD_NPASS_KINDS] = {0.0};
+    hipError_t e = hipStreamSynchronize(p->st);
+    if (e != hipSuccess) {
+        p->err = hipGetErrorString(e);
+        return SPSTD_ERR_DEVICE;
+    }
+    for (size_t i = 0; i < p->ev_kind.size(); ++i) {
+        float t = 0.0f;
+        e = hipEventElapsedTime(&t, p->ev_pool[2 * i], p->ev_pool[2 * i + 1]);
+        if (e != hipSuccess) {
+            p->err = hipGetErrorString(e);
+            return SPSTD_ERR_DEVICE;
+        }
+        cnt[p->ev_kind[i]] += 1;
+        ms[p->ev_kind[i]] += t;
+    }
+    p->ev_kind.clear();
+    p->ev_used = 0;
+    for (int k = 0; k < SPSTD_NPASS_KINDS; ++k) {
+        if (launches) launches[k] = cnt[k];
+        if (total_ms) total_ms[k] = ms[k];
+        if (bytes_per_launch) bytes_per_launch[k] = per[k];
+    }
+    return SPSTD_OK;
+}
+
+const char* spstd_strerror(spstd_status s) {
+    switch (s) {
+        case SPSTD_OK: return "ok";
+        case SPSTD_ERR_ARG: return "invalid argument";
+        case SPSTD_ERR_UNSTABLE: return "time step beyond the stability edge";
+        case SPSTD_ERR_WORKSPACE: return "workspace missing, too small or misaligned";
+        case SPSTD_ERR_DEVICE: return "HIP runtime error";
+        case SPSTD_ERR_NONFINITE: return "state is not finite";
+        case SPSTD_ERR_CAPACITY: return "probe buffer capacity exceeded";
+    }
+    return "unknown status";
+}
+
+const char* spstd_last_error(spstd_plan_t p) { return p ? p->err.c_str() : "null plan"; }
+
+}  // extern "C"

@@ -1,0 +1,266 @@
+// Device building blocks of the spectral operator: complex arithmetic,
+// register DFTs of length 2/4/8/16, and a Stockham FFT of one pencil of
+// length N (a power of two, 16 <= N <= 16384) spread over T = N/16 lanes.
+//
+// Layout contract ("strided layout"): lane j of a pencil (0 <= j < T) holds
+// in its 16 registers v[e] the elements j + T*e, e = 0..15.  The forward
+// transform takes samples in this layout and leaves DFT bins in the same
+// layout; the inverse transform does the converse.  Between radix passes the
+// data goes through LDS; the last pass ends in registers.
+//
+// Passes: floor(log2 N / 4) radix-16 passes, then one radix-2/4/8 pass when
+// log2 N is not a multiple of 4.  Pass p with radix R and running size Ns
+// (product of the previous radices) maps butterfly b (inputs b + r*N/R) to
+// outputs (b/Ns)*Ns*R + (b mod Ns) + r*Ns after the twiddles
+// w_{Ns*R}^{r*(b mod Ns)} -- the self-sorting (Stockham) form, so no
+// bit-reversal pass exists.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace spstd {
+
+template <typename R>
+struct cpx {
+    R x, y;
+};
+
+template <typename R>
+__device__ __forceinline__ cpx<R> operator+(cpx<R> a, cpx<R> b) { return {a.x + b.x, a.y + b.y}; }
+template <typename R>
+__device__ __forceinline__ cpx<R> operator-(cpx<R> a, cpx<R> b) { return {a.x - b.x, a.y - b.y}; }
+template <typename R>
+__device__ __forceinline__ cpx<R> cmul(cpx<R> a, cpx<R> b) {
+    return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+// a * conj(b)
+template <typename R>
+__device__ __forceinline__ cpx<R> cmulc(cpx<R> a, cpx<R> b) {
+    return {a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y};
+}
+// multiply by -i (forward) or +i (inverse)
+template <typename R, bool INV>
+__device__ __forceinline__ cpx<R> rot90(cpx<R> a) {
+    return INV ? cpx<R>{-a.y, a.x} : cpx<R>{a.y, -a.x};
+}
+
+// exp(-+ 2 pi i m / 16) for the internal twiddles of the 16-point DFT;
+// cos(pi/8), sin(pi/8) and sqrt(1/2) to 20 digits.
+template <typename R, bool INV, int M>
+__device__ __forceinline__ cpx<R> w16mul(cpx<R> a) {
+    constexpr double C1 = 0.92387953251128675613;  // cos(pi/8)
+    constexpr double S1 = 0.38268343236508977173;  // sin(pi/8)
+    constexpr double H = 0.70710678118654752440;   // sqrt(1/2)
+    constexpr int m = M % 16;
+    if constexpr (m == 0) return a;
+    // angle theta = 2 pi m / 16; forward multiplies by cos - i sin
+    constexpr double cs = (m == 1) ? C1 : (m == 2) ? H : (m == 3) ? S1 : (m == 4) ? 0.0
+                        : (m == 6) ? -H : (m == 9) ? -C1 : 0.0;
+    constexpr double sn = (m == 1) ? S1 : (m == 2) ? H : (m == 3) ? C1 : (m == 4) ? 1.0
+                        : (m == 6) ? H : (m == 9) ? -S1 : 0.0;
+    static_assert(m == 1 || m == 2 || m == 3 || m == 4 || m == 6 || m == 9, "unused");
+    if constexpr (m == 4) return rot90<R, INV>(a);
+    const R c = (R)cs;
+    const R s = INV ? (R)sn : (R)(-sn);
+    return {a.x * c - a.y * s, a.x * s + a.y * c};
+}
+
+template <typename R, bool INV>
+__device__ __forceinline__ void dft2(cpx<R>& a, cpx<R>& b) {
+    cpx<R> t = a - b;
+    a = a + b;
+    b = t;
+}
+
+template <typename R, bool INV>
+__device__ __forceinline__ void dft4(cpx<R>& a, cpx<R>& b, cpx<R>& c, cpx<R>& d) {
+    cpx<R> s0 = a + c, d0 = a - c, s1 = b + d, d1 = rot90<R, INV>(b - d);
+    a = s0 + s1;
+    c = s0 - s1;
+    b = d0 + d1;
+    d = d0 - d1;
+}
+
+// natural order in, natural order out
+template <typename R, bool INV>
+__device__ __forceinline__ void dft8(cpx<R>& x0, cpx<R>& x1, cpx<R>& x2, cpx<R>& x3,
+                                     cpx<R>& x4, cpx<R>& x5, cpx<R>& x6, cpx<R>& x7) {
+    constexpr double H = 0.70710678118654752440;
+    dft4<R, INV>(x0, x2, x4, x6);  // E[k] at x0,x2,x4,x6
+    dft4<R, INV>(x1, x3, x5, x7);  // O[k] at x1,x3,x5,x7
+    // O[k] *= w8^k
+    const R h = (R)H;
+    cpx<R> o1 = INV ? cpx<R>{(x3.x - x3.y) * h, (x3.x + x3.y) * h}
+                    : cpx<R>{(x3.x + x3.y) * h, (x3.y - x3.x) * h};
+    cpx<R> o2 = rot90<R, INV>(x5);
+    cpx<R> o3 = INV ? cpx<R>{-(x7.x + x7.y) * h, (x7.x - x7.y) * h}
+                    : cpx<R>{(x7.y - x7.x) * h, -(x7.x + x7.y) * h};
+    cpx<R> e0 = x0, e1 = x2, e2 = x4, e3 = x6, o0 = x1;
+    x0 = e0 + o0; x4 = e0 - o0;
+    x1 = e1 + o1; x5 = e1 - o1;
+    x2 = e2 + o2; x6 = e2 - o2;
+    x3 = e3 + o3; x7 = e3 - o3;
+}
+
+// 16-point DFT as 4 x 4: natural order in v[0..15], natural order out.
+template <typename R, bool INV, int S = 1>
+__device__ __forceinline__ void dft16(cpx<R>* v) {
+#define V_(i) v[(i) * S]
+    dft4<R, INV>(V_(0), V_(4), V_(8), V_(12));
+    dft4<R, INV>(V_(1), V_(5), V_(9), V_(13));
+    dft4<R, INV>(V_(2), V_(6), V_(10), V_(14));
+    dft4<R, INV>(V_(3), V_(7), V_(11), V_(15));
+    // element r1 + 4 k1 holds A[r1][k1]; multiply by w16^(r1 k1)
+    V_(5) = w16mul<R, INV, 1>(V_(5));
+    V_(9) = w16mul<R, INV, 2>(V_(9));
+    V_(13) = w16mul<R, INV, 3>(V_(13));
+    V_(6) = w16mul<R, INV, 2>(V_(6));
+    V_(10) = w16mul<R, INV, 4>(V_(10));
+    V_(14) = w16mul<R, INV, 6>(V_(14));
+    V_(7) = w16mul<R, INV, 3>(V_(7));
+    V_(11) = w16mul<R, INV, 6>(V_(11));
+    V_(15) = w16mul<R, INV, 9>(V_(15));
+    dft4<R, INV>(V_(0), V_(1), V_(2), V_(3));
+    dft4<R, INV>(V_(4), V_(5), V_(6), V_(7));
+    dft4<R, INV>(V_(8), V_(9), V_(10), V_(11));
+    dft4<R, INV>(V_(12), V_(13), V_(14), V_(15));
+    // now element k2 + 4 k1 holds X[k1 + 4 k2]: transpose the 4x4 index
+    cpx<R> t;
+    t = V_(1); V_(1) = V_(4); V_(4) = t;
+    t = V_(2); V_(2) = V_(8); V_(8) = t;
+    t = V_(3); V_(3) = V_(12); V_(12) = t;
+    t = V_(6); V_(6) = V_(9); V_(9) = t;
+    t = V_(7); V_(7) = V_(13); V_(13) = t;
+    t = V_(11); V_(11) = V_(14); V_(14) = t;
+#undef V_
+}
+
+template <int N>
+struct fft_shape {
+    static constexpr int LOG = (N <= 1) ? 0 : 1 + fft_shape<N / 2>::LOG;
+};
+template <>
+struct fft_shape<1> {
+    static constexpr int LOG = 0;
+};
+
+// LDS index padding: one spare slot every 16 keeps the radix-16 scatter
+// (stride-16 writes) off a single bank.
+__device__ __forceinline__ int lpad(int i) { return i + (i >> 4); }
+template <int N>
+struct lds_size {
+    static constexpr int value = N + N / 16;
+};
+
+// Wave-local or workgroup-wide LDS barrier.
+template <bool WAVE>
+__device__ __forceinline__ void lds_sync() {
+    if constexpr (WAVE) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    } else {
+        __syncthreads();
+    }
+}
+
+// One pencil transform, forward (INV = false) or inverse (unnormalised).
+// v: the lane's 16 values in strided layout; j: lane position in the pencil;
+// lre/lim: this pencil's LDS slices (lds_size<N> reals each);
+// tw: table of w_N^t = exp(-2 pi i t / N), t = 0..N-1.
+// WAVE: the pencil lies inside one wavefront (T <= 64).
+// SPLIT: exchange the real parts, then the imaginary parts, through lre
+// alone (half the LDS, twice the barriers); lim is then unused.
+template <typename R, int N, bool INV, bool WAVE, bool SPLIT = false>
+__device__ __forceinline__ void fft_pencil(cpx<R> (&v)[16], int j, R* lre, R* lim,
+                                           const cpx<R>* __restrict__ tw) {
+    constexpr int LOG = fft_shape<N>::LOG;
+    constexpr int T = N / 16;
+    constexpr int NP16 = LOG / 4;            // radix-16 passes
+    constexpr int RL = 1 << (LOG % 4);       // radix of the tail pass (1: none)
+    constexpr int NPASS = NP16 + (RL > 1 ? 1 : 0);
+    static_assert(N >= 16 && (N & (N - 1)) == 0, "N must be a power of two >= 16");
+
+    // pass 0: radix 16, Ns = 1, no twiddles
+    dft16<R, INV>(v);
+    if constexpr (NPASS == 1) return;
+
+    int Ns = 1;
+#pragma unroll
+    for (int p = 1; p < NPASS; ++p) {
+        // scatter the previous radix-16 pass outputs (Ns = 16^(p-1))
+        {
+            const int k = j % Ns;
+            const int base = (j / Ns) * Ns * 16 + k;
+            lds_sync<WAVE>();   // previous reads of this slice are complete
+            if constexpr (!SPLIT) {
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    const int q = lpad(base + r * Ns);
+                    lre[q] = v[r].x;
+                    lim[q] = v[r].y;
+                }
+                lds_sync<WAVE>();
+#pragma unroll
+                for (int e = 0; e < 16; ++e) {
+                    const int q = lpad(j + T * e);
+                    v[e].x = lre[q];
+                    v[e].y = lim[q];
+                }
+            } else {
+                R keep[16];
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    lre[lpad(base + r * Ns)] = v[r].x;
+                    keep[r] = v[r].y;
+                }
+                lds_sync<WAVE>();
+#pragma unroll
+                for (int e = 0; e < 16; ++e) v[e].x = lre[lpad(j + T * e)];
+                lds_sync<WAVE>();
+#pragma unroll
+                for (int r = 0; r < 16; ++r) lre[lpad(base + r * Ns)] = keep[r];
+                lds_sync<WAVE>();
+#pragma unroll
+                for (int e = 0; e < 16; ++e) v[e].y = lre[lpad(j + T * e)];
+            }
+        }
+        Ns *= 16;
+        const bool last = (p == NPASS - 1);
+        if (!last || RL == 1) {
+            // radix-16 pass: butterfly b = j, k = j mod Ns,
+            // twiddle w_{16 Ns}^{r k} = w_N^{r k N / (16 Ns)}
+            const int k = j % Ns;
+            const int step = k * (N / (16 * Ns));
+#pragma unroll
+            for (int r = 1; r < 16; ++r) {
+                const cpx<R> w = tw[r * step];
+                v[r] = INV ? cmulc(v[r], w) : cmul(v[r], w);
+            }
+            dft16<R, INV>(v);
+        } else {
+            // tail pass of radix RL: butterflies b = j + T u, u < 16/RL,
+            // Ns * RL = N so the twiddle is w_N^{r b}
+            constexpr int U = 16 / RL;
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int b = j + T * u;
+#pragma unroll
+                for (int r = 1; r < RL; ++r) {
+                    const cpx<R> w = tw[r * b];
+                    v[u + U * r] = INV ? cmulc(v[u + U * r], w) : cmul(v[u + U * r], w);
+                }
+                if constexpr (RL == 2) {
+                    dft2<R, INV>(v[u], v[u + U]);
+                } else if constexpr (RL == 4) {
+                    dft4<R, INV>(v[u], v[u + U], v[u + 2 * U], v[u + 3 * U]);
+                } else {
+                    dft8<R, INV>(v[u], v[u + U], v[u + 2 * U], v[u + 3 * U],
+                                 v[u + 4 * U], v[u + 5 * U], v[u + 6 * U], v[u + 7 * U]);
+                }
+            }
+        }
+    }
+}
+
+}  // namespace spstd
