@@ -127,6 +127,27 @@ def cpu_baseline(w, steps):
                       f"oracle run, {el:.1f} s wall"}
 
 
+def pmc_sample(w, steps):
+    """Short run for hardware-counter passes: a plain device copy of a known
+    size (the calibration of FETCH_SIZE / WRITE_SIZE), then a few eager
+    steps of the hot path in each precision."""
+    import torch
+    from paper_1805_03155_amd import spstd
+    nbytes = 256 << 20
+    a = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    del a, b
+    for code in (spstd.FP64, spstd.FP32):
+        p = spstd.plan_from_workload(w, precision=code, nsteps_max=steps, flags=spstd.EAGER)
+        p.step(steps)
+        torch.cuda.synchronize()
+        del p
+    print(json.dumps({"pmc_sample": True, "copy_bytes_each_way": nbytes, "steps": steps}))
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -135,6 +156,8 @@ def main():
     ap.add_argument("--n", type=int, default=256, help="grid points per axis")
     ap.add_argument("--cpu-baseline", choices=["on", "off"], default="on")
     ap.add_argument("--cpu-steps", type=int, default=5)
+    ap.add_argument("--pmc-sample", action="store_true",
+                    help="short run for rocprofv3 counter passes (no timing output)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: this engine has no multi-GPU path "
@@ -147,6 +170,9 @@ def main():
     log(f"building the {args.n}^3 oscillator workload")
     w = W.harmonic_3d(seed=0, n=args.n, half_box=12.0, omega=1.0, steps=100000,
                       coeffs=W.YOSHIDA6, nprobes=3)
+    if args.pmc_sample:
+        pmc_sample(w, 2)
+        return
     res = {}
     for prec in ("fp64", "fp32"):
         log(f"{prec}: warmup {args.warmup}, timed {args.steps} steps")

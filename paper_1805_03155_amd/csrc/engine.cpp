@@ -114,19 +114,38 @@ struct Plan {
     hipGraphExec_t graph;
     bool graph_ready;
     std::string err;
-    // SPSTD_TIMING: event pairs around pass launches, their kinds
+    // SPSTD_TIMING: event pairs around pass launches and their kinds, for
+    // eager launches (ev_*) and for the ones captured in the step graph (gev*)
     std::vector<hipEvent_t> ev_pool;
     std::vector<int> ev_kind;
     size_t ev_used = 0;
+    std::vector<hipEvent_t> gev;
+    std::vector<int> gev_kind;
+    bool capturing = false;
+    int64_t acc_n[SPSTD_NPASS_KINDS] = {0};
+    double acc_ms[SPSTD_NPASS_KINDS] = {0.0};
 };
 
 // Brackets one pass launch with HIP events on the plan's stream when the
-// plan times its passes.
+// plan times its passes.  Under graph capture the records become external
+// event nodes of the graph, re-recorded at every replay.
 struct PassTimer {
     Plan* p;
     int slot;
-    PassTimer(Plan* pl, int kind) : p(pl), slot(-1) {
+    bool graph;
+    PassTimer(Plan* pl, int kind) : p(pl), slot(-1), graph(pl->capturing) {
         if (!(p->d.flags & SPSTD_TIMING)) return;
+        if (graph) {
+            hipEvent_t a, b;
+            if (hipEventCreate(&a) != hipSuccess) return;
+            if (hipEventCreate(&b) != hipSuccess) { (void)hipEventDestroy(a); return; }
+            slot = (int)p->gev.size();
+            p->gev.push_back(a);
+            p->gev.push_back(b);
+            p->gev_kind.push_back(kind);
+            (void)hipEventRecordWithFlags(a, p->st, hipEventRecordExternal);
+            return;
+        }
         if (p->ev_used + 2 > p->ev_pool.size()) {
             hipEvent_t a, b;
             if (hipEventCreate(&a) != hipSuccess) return;
@@ -140,9 +159,23 @@ struct PassTimer {
         (void)hipEventRecord(p->ev_pool[slot], p->st);
     }
     ~PassTimer() {
-        if (slot >= 0) (void)hipEventRecord(p->ev_pool[slot + 1], p->st);
+        if (slot < 0) return;
+        if (graph) (void)hipEventRecordWithFlags(p->gev[slot + 1], p->st, hipEventRecordExternal);
+        else (void)hipEventRecord(p->ev_pool[slot + 1], p->st);
     }
 };
+
+// Add the durations of completed event pairs to the per-kind totals.
+static hipError_t harvest(Plan* p, const std::vector<hipEvent_t>& ev, const std::vector<int>& kind) {
+    for (size_t i = 0; i < kind.size(); ++i) {
+        float t = 0.0f;
+        hipError_t e = hipEventElapsedTime(&t, ev[2 * i], ev[2 * i + 1]);
+        if (e != hipSuccess) return e;
+        p->acc_n[kind[i]] += 1;
+        p->acc_ms[kind[i]] += t;
+    }
+    return hipSuccess;
+}
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
@@ -397,7 +430,9 @@ static spstd_status build_graph(Plan* p) {
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
+        p->capturing = true;
         hipError_t e2 = enqueue_steps_eager<R>(p, kGraphChunk);
+        p->capturing = false;
         e = hipStreamEndCapture(cap, &g);
         if (e == hipSuccess) e = e2;
     }
@@ -415,14 +450,22 @@ static spstd_status build_graph(Plan* p) {
 
 template <typename R>
 static spstd_status enqueue_steps(Plan* p, int64_t n) {
-    const bool use_graph = !(p->d.flags & (SPSTD_EAGER | SPSTD_TIMING)) && n >= kGraphChunk;
+    const bool use_graph = !(p->d.flags & SPSTD_EAGER) && n >= kGraphChunk;
+    const bool timing = (p->d.flags & SPSTD_TIMING) != 0;
     if (use_graph && !p->graph_ready) {
         spstd_status s = build_graph<R>(p);
         if (s != SPSTD_OK) return s;
     }
     int64_t left = n;
     if (use_graph) {
-        for (; left >= kGraphChunk; left -= kGraphChunk) HIPCHK(hipGraphLaunch(p->graph, p->st));
+        for (; left >= kGraphChunk; left -= kGraphChunk) {
+            HIPCHK(hipGraphLaunch(p->graph, p->st));
+            if (timing) {
+                // the graph's events are re-recorded at every replay: read them now
+                HIPCHK(hipStreamSynchronize(p->st));
+                HIPCHK(harvest(p, p->gev, p->gev_kind));
+            }
+        }
     }
     HIPCHK(enqueue_steps_eager<R>(p, left));
     return SPSTD_OK;
@@ -684,6 +727,7 @@ spstd_status spstd_destroy(spstd_plan_t p) {
     if (!p) return SPSTD_ERR_ARG;
     if (p->graph_ready) (void)hipGraphExecDestroy(p->graph);
     for (hipEvent_t e : p->ev_pool) (void)hipEventDestroy(e);
+    for (hipEvent_t e : p->gev) (void)hipEventDestroy(e);
     delete p;
     return SPSTD_OK;
 }
@@ -694,29 +738,24 @@ spstd_status spstd_pass_times(spstd_plan_t p, int64_t* launches, double* total_m
     const double fb = (double)p->N * (double)p->esz;
     // fields read + fields written once per launch
     const double per[SPSTD_NPASS_KINDS] = {3.0 * fb, 3.0 * fb, 5.0 * fb, 4.0 * fb};
-    int64_t cnt[SPSTD_NPASS_KINDS] = {0};
-    double ms[SPSTD_NPASS_KINDS] = {0.0};
     hipError_t e = hipStreamSynchronize(p->st);
     if (e != hipSuccess) {
         p->err = hipGetErrorString(e);
         return SPSTD_ERR_DEVICE;
     }
-    for (size_t i = 0; i < p->ev_kind.size(); ++i) {
-        float t = 0.0f;
-        e = hipEventElapsedTime(&t, p->ev_pool[2 * i], p->ev_pool[2 * i + 1]);
-        if (e != hipSuccess) {
-            p->err = hipGetErrorString(e);
-            return SPSTD_ERR_DEVICE;
-        }
-        cnt[p->ev_kind[i]] += 1;
-        ms[p->ev_kind[i]] += t;
+    e = harvest(p, p->ev_pool, p->ev_kind);
+    if (e != hipSuccess) {
+        p->err = hipGetErrorString(e);
+        return SPSTD_ERR_DEVICE;
     }
     p->ev_kind.clear();
     p->ev_used = 0;
     for (int k = 0; k < SPSTD_NPASS_KINDS; ++k) {
-        if (launches) launches[k] = cnt[k];
-        if (total_ms) total_ms[k] = ms[k];
+        if (launches) launches[k] = p->acc_n[k];
+        if (total_ms) total_ms[k] = p->acc_ms[k];
         if (bytes_per_launch) bytes_per_launch[k] = per[k];
+        p->acc_n[k] = 0;
+        p->acc_ms[k] = 0.0;
     }
     return SPSTD_OK;
 }

@@ -164,80 +164,156 @@ __device__ __forceinline__ void lds_sync() {
     }
 }
 
-// One pencil transform, forward (INV = false) or inverse (unnormalised).
-// v: the lane's 16 values in strided layout; j: lane position in the pencil;
-// lre/lim: this pencil's LDS slices (lds_size<N> reals each);
+// Twiddles w_N^{r*step}, r = 0..15, of one radix-16 pass.  Either 15
+// table reads, or (PRODUCTS) two reads, w^step and w^{4 step}, and the other
+// powers as products w^{a step} * w^{4 b step} (r = a + 4b, a, b < 4): at
+// most four roundings on top of the tabulated values.
+template <typename R, bool PRODUCTS>
+__device__ __forceinline__ void twiddles16(const cpx<R>* __restrict__ tw, int step, cpx<R> (&w)[16]) {
+    w[0] = cpx<R>{(R)1, (R)0};
+    if constexpr (!PRODUCTS) {
+#pragma unroll
+        for (int r = 1; r < 16; ++r) w[r] = tw[r * step];
+    } else {
+        const cpx<R> t1 = tw[step], t4 = tw[4 * step];
+        const cpx<R> t2 = cmul(t1, t1), t3 = cmul(t2, t1);
+        const cpx<R> t8 = cmul(t4, t4), t12 = cmul(t8, t4);
+        const cpx<R> lo[4] = {w[0], t1, t2, t3};
+        const cpx<R> hi[4] = {w[0], t4, t8, t12};
+#pragma unroll
+        for (int r = 1; r < 16; ++r) w[r] = (r >> 2) == 0 ? lo[r & 3] : (r & 3) == 0 ? hi[r >> 2] : cmul(lo[r & 3], hi[r >> 2]);
+    }
+}
+
+// Twiddles w_N^{r*b}, r < RL, of the tail pass (RL = 2, 4, 8).
+template <typename R, int RL, bool PRODUCTS>
+__device__ __forceinline__ void twiddles_tail(const cpx<R>* __restrict__ tw, int b, cpx<R> (&w)[8]) {
+    w[0] = cpx<R>{(R)1, (R)0};
+    if constexpr (!PRODUCTS || RL == 2) {
+#pragma unroll
+        for (int r = 1; r < RL; ++r) w[r] = tw[r * b];
+    } else {
+        const cpx<R> t1 = tw[b];
+        w[1] = t1;
+        w[2] = cmul(t1, t1);
+        w[3] = cmul(w[2], t1);
+        if constexpr (RL == 8) {
+            const cpx<R> t4 = tw[4 * b];
+            w[4] = t4;
+            w[5] = cmul(t1, t4);
+            w[6] = cmul(w[2], t4);
+            w[7] = cmul(w[3], t4);
+        }
+    }
+}
+
+// Transform of P pencils per lane group, forward (INV = false) or inverse
+// (unnormalised).
+// v[p]: the lane's 16 values of pencil p in strided layout; j: lane position
+// in the pencil; lds: LDS of pencil 0, pencil p at lds + p * lds_stride;
+// a pencil slice holds lds_size<N> reals (SPLIT) or twice that (re, im).
 // tw: table of w_N^t = exp(-2 pi i t / N), t = 0..N-1.
-// WAVE: the pencil lies inside one wavefront (T <= 64).
-// SPLIT: exchange the real parts, then the imaginary parts, through lre
-// alone (half the LDS, twice the barriers); lim is then unused.
-template <typename R, int N, bool INV, bool WAVE, bool SPLIT = false>
-__device__ __forceinline__ void fft_pencil(cpx<R> (&v)[16], int j, R* lre, R* lim,
-                                           const cpx<R>* __restrict__ tw) {
+// WAVE: the pencils lie inside one wavefront (T <= 64).
+// SPLIT: exchange the real parts, then the imaginary parts (half the LDS,
+// twice the barriers).
+// PRODUCTS: build the twiddles of a pass from two table reads.
+template <typename R, int N, bool INV, bool WAVE, bool SPLIT, bool PRODUCTS, int P>
+__device__ __forceinline__ void fft_pencils(cpx<R> (&v)[P][16], int j, R* lds, int lds_stride,
+                                            const cpx<R>* __restrict__ tw) {
     constexpr int LOG = fft_shape<N>::LOG;
     constexpr int T = N / 16;
     constexpr int NP16 = LOG / 4;            // radix-16 passes
     constexpr int RL = 1 << (LOG % 4);       // radix of the tail pass (1: none)
     constexpr int NPASS = NP16 + (RL > 1 ? 1 : 0);
+    constexpr int LS = lds_size<N>::value;
     static_assert(N >= 16 && (N & (N - 1)) == 0, "N must be a power of two >= 16");
 
     // pass 0: radix 16, Ns = 1, no twiddles
-    dft16<R, INV>(v);
+#pragma unroll
+    for (int p = 0; p < P; ++p) dft16<R, INV>(v[p]);
     if constexpr (NPASS == 1) return;
 
     int Ns = 1;
 #pragma unroll
-    for (int p = 1; p < NPASS; ++p) {
-        // scatter the previous radix-16 pass outputs (Ns = 16^(p-1))
+    for (int ps = 1; ps < NPASS; ++ps) {
+        // scatter the previous radix-16 pass outputs (Ns = 16^(ps-1)),
+        // gather the strided layout
         {
             const int k = j % Ns;
             const int base = (j / Ns) * Ns * 16 + k;
-            lds_sync<WAVE>();   // previous reads of this slice are complete
+            lds_sync<WAVE>();   // earlier reads of these slices are complete
             if constexpr (!SPLIT) {
 #pragma unroll
-                for (int r = 0; r < 16; ++r) {
-                    const int q = lpad(base + r * Ns);
-                    lre[q] = v[r].x;
-                    lim[q] = v[r].y;
+                for (int p = 0; p < P; ++p) {
+                    R* lre = lds + p * lds_stride;
+                    R* lim = lre + LS;
+#pragma unroll
+                    for (int r = 0; r < 16; ++r) {
+                        const int q = lpad(base + r * Ns);
+                        lre[q] = v[p][r].x;
+                        lim[q] = v[p][r].y;
+                    }
                 }
                 lds_sync<WAVE>();
 #pragma unroll
-                for (int e = 0; e < 16; ++e) {
-                    const int q = lpad(j + T * e);
-                    v[e].x = lre[q];
-                    v[e].y = lim[q];
+                for (int p = 0; p < P; ++p) {
+                    R* lre = lds + p * lds_stride;
+                    R* lim = lre + LS;
+#pragma unroll
+                    for (int e = 0; e < 16; ++e) {
+                        const int q = lpad(j + T * e);
+                        v[p][e].x = lre[q];
+                        v[p][e].y = lim[q];
+                    }
                 }
             } else {
-                R keep[16];
 #pragma unroll
-                for (int r = 0; r < 16; ++r) {
-                    lre[lpad(base + r * Ns)] = v[r].x;
-                    keep[r] = v[r].y;
+                for (int p = 0; p < P; ++p) {
+                    R* lre = lds + p * lds_stride;
+#pragma unroll
+                    for (int r = 0; r < 16; ++r) lre[lpad(base + r * Ns)] = v[p][r].x;
                 }
                 lds_sync<WAVE>();
 #pragma unroll
-                for (int e = 0; e < 16; ++e) v[e].x = lre[lpad(j + T * e)];
+                for (int p = 0; p < P; ++p) {
+                    R* lre = lds + p * lds_stride;
+                    R keep[16];
+#pragma unroll
+                    for (int e = 0; e < 16; ++e) keep[e] = lre[lpad(j + T * e)];
+#pragma unroll
+                    for (int e = 0; e < 16; ++e) v[p][e].x = keep[e];
+                }
+                // the imaginary parts still sit in v[p][r].y in scatter order
                 lds_sync<WAVE>();
 #pragma unroll
-                for (int r = 0; r < 16; ++r) lre[lpad(base + r * Ns)] = keep[r];
+                for (int p = 0; p < P; ++p) {
+                    R* lre = lds + p * lds_stride;
+#pragma unroll
+                    for (int r = 0; r < 16; ++r) lre[lpad(base + r * Ns)] = v[p][r].y;
+                }
                 lds_sync<WAVE>();
 #pragma unroll
-                for (int e = 0; e < 16; ++e) v[e].y = lre[lpad(j + T * e)];
+                for (int p = 0; p < P; ++p) {
+                    R* lre = lds + p * lds_stride;
+#pragma unroll
+                    for (int e = 0; e < 16; ++e) v[p][e].y = lre[lpad(j + T * e)];
+                }
             }
         }
         Ns *= 16;
-        const bool last = (p == NPASS - 1);
+        const bool last = (ps == NPASS - 1);
         if (!last || RL == 1) {
             // radix-16 pass: butterfly b = j, k = j mod Ns,
             // twiddle w_{16 Ns}^{r k} = w_N^{r k N / (16 Ns)}
             const int k = j % Ns;
-            const int step = k * (N / (16 * Ns));
+            cpx<R> w[16];
+            twiddles16<R, PRODUCTS>(tw, k * (N / (16 * Ns)), w);
 #pragma unroll
-            for (int r = 1; r < 16; ++r) {
-                const cpx<R> w = tw[r * step];
-                v[r] = INV ? cmulc(v[r], w) : cmul(v[r], w);
+            for (int p = 0; p < P; ++p) {
+#pragma unroll
+                for (int r = 1; r < 16; ++r) v[p][r] = INV ? cmulc(v[p][r], w[r]) : cmul(v[p][r], w[r]);
+                dft16<R, INV>(v[p]);
             }
-            dft16<R, INV>(v);
         } else {
             // tail pass of radix RL: butterflies b = j + T u, u < 16/RL,
             // Ns * RL = N so the twiddle is w_N^{r b}
@@ -245,18 +321,21 @@ __device__ __forceinline__ void fft_pencil(cpx<R> (&v)[16], int j, R* lre, R* li
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 const int b = j + T * u;
+                cpx<R> w[8];
+                twiddles_tail<R, RL, PRODUCTS>(tw, b, w);
 #pragma unroll
-                for (int r = 1; r < RL; ++r) {
-                    const cpx<R> w = tw[r * b];
-                    v[u + U * r] = INV ? cmulc(v[u + U * r], w) : cmul(v[u + U * r], w);
-                }
-                if constexpr (RL == 2) {
-                    dft2<R, INV>(v[u], v[u + U]);
-                } else if constexpr (RL == 4) {
-                    dft4<R, INV>(v[u], v[u + U], v[u + 2 * U], v[u + 3 * U]);
-                } else {
-                    dft8<R, INV>(v[u], v[u + U], v[u + 2 * U], v[u + 3 * U],
-                                 v[u + 4 * U], v[u + 5 * U], v[u + 6 * U], v[u + 7 * U]);
+                for (int p = 0; p < P; ++p) {
+#pragma unroll
+                    for (int r = 1; r < RL; ++r)
+                        v[p][u + U * r] = INV ? cmulc(v[p][u + U * r], w[r]) : cmul(v[p][u + U * r], w[r]);
+                    if constexpr (RL == 2) {
+                        dft2<R, INV>(v[p][u], v[p][u + U]);
+                    } else if constexpr (RL == 4) {
+                        dft4<R, INV>(v[p][u], v[p][u + U], v[p][u + 2 * U], v[p][u + 3 * U]);
+                    } else {
+                        dft8<R, INV>(v[p][u], v[p][u + U], v[p][u + 2 * U], v[p][u + 3 * U],
+                                     v[p][u + 4 * U], v[p][u + 5 * U], v[p][u + 6 * U], v[p][u + 7 * U]);
+                    }
                 }
             }
         }

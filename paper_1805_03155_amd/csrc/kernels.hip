@@ -22,6 +22,93 @@ namespace spstd {
 bool axis_len_ok(int64_t n) { return n >= 16 && n <= 1024 && (n & (n - 1)) == 0; }
 bool row_len_ok(int64_t n) { return n >= 16 && n <= 16384 && (n & (n - 1)) == 0; }
 
+// Build-time tuning switches (defaults are the measured choices):
+//   TW_PRODUCTS_*  twiddles of a pass from two table reads and products
+//   SPLIT_*        real-then-imaginary LDS exchange (half the LDS per wave)
+//   X_RELOAD       x passes re-read their inputs in the epilogue instead of
+//                  keeping them in registers through the transforms
+//   MIN_WAVES      minimum waves per SIMD requested for the pass kernels
+//   YZ_PPL_F32     complex pencils per lane group in FP32 y/z passes
+//   EPI_CHUNK      epilogue elements scheduled together (caps the loads in
+//                  flight, and with them the registers)
+//   EPI_FENCE      keep epilogue loads from being hoisted into the inverse
+//                  transform
+//   YZ_ORDER       0: consecutive blocks take neighbouring x column groups of
+//                  one (z or y) plane; 1: consecutive blocks take the same
+//                  column groups of neighbouring planes (spreads the
+//                  concurrently running blocks over more memory channels)
+#ifndef SPSTD_TW_PRODUCTS_F64
+#define SPSTD_TW_PRODUCTS_F64 1
+#endif
+#ifndef SPSTD_TW_PRODUCTS_F32
+#define SPSTD_TW_PRODUCTS_F32 0
+#endif
+#ifndef SPSTD_SPLIT_F64
+#define SPSTD_SPLIT_F64 1
+#endif
+#ifndef SPSTD_SPLIT_F32
+#define SPSTD_SPLIT_F32 0
+#endif
+#ifndef SPSTD_X_RELOAD
+#define SPSTD_X_RELOAD 0
+#endif
+#ifndef SPSTD_MIN_WAVES
+#define SPSTD_MIN_WAVES 0
+#endif
+#ifndef SPSTD_YZ_PPL_F32
+#define SPSTD_YZ_PPL_F32 2
+#endif
+#ifndef SPSTD_WPB
+#define SPSTD_WPB 4
+#endif
+#ifndef SPSTD_EPI_CHUNK
+#define SPSTD_EPI_CHUNK 4
+#endif
+#ifndef SPSTD_EPI_FENCE
+#define SPSTD_EPI_FENCE 1
+#endif
+#ifndef SPSTD_YZ_ORDER
+#define SPSTD_YZ_ORDER 1
+#endif
+
+#if SPSTD_MIN_WAVES > 0
+#define SPSTD_WAVES_ATTR __attribute__((amdgpu_waves_per_eu(SPSTD_MIN_WAVES)))
+#else
+#define SPSTD_WAVES_ATTR
+#endif
+
+template <typename R>
+struct tuning;
+template <>
+struct tuning<double> {
+    static constexpr bool PRODUCTS = SPSTD_TW_PRODUCTS_F64;
+    static constexpr bool SPLIT = SPSTD_SPLIT_F64;
+    static constexpr int YZ_PPL = 1;
+};
+template <>
+struct tuning<float> {
+    static constexpr bool PRODUCTS = SPSTD_TW_PRODUCTS_F32;
+    static constexpr bool SPLIT = SPSTD_SPLIT_F32;
+    static constexpr int YZ_PPL = SPSTD_YZ_PPL_F32;
+};
+
+// Compiler-only memory barrier: values loaded before it are not reused
+// after it (the epilogues re-read their inputs rather than keep them live
+// in registers through the transforms).
+__device__ __forceinline__ void reload_fence() { asm volatile("" ::: "memory"); }
+
+// Start of an epilogue: its loads stay below the inverse transform.
+__device__ __forceinline__ void epi_begin() {
+    if constexpr (SPSTD_EPI_FENCE) asm volatile("" ::: "memory");
+}
+
+// Scheduling fence after every EPI_CHUNK-th epilogue element.
+__device__ __forceinline__ void epi_fence(int e) {
+    if constexpr (SPSTD_EPI_CHUNK < 16) {
+        if ((e + 1) % SPSTD_EPI_CHUNK == 0) __builtin_amdgcn_sched_barrier(0);
+    }
+}
+
 // Multiply bins kk = j + T*e by scale * ks^2 (ks the signed bin index);
 // under the ZERO convention the Nyquist bin kk = N/2 is removed.
 template <typename R, int N>
@@ -38,7 +125,7 @@ __device__ __forceinline__ void apply_symbol(cpx<R> (&v)[16], int j, R scale, in
     }
 }
 
-// Lanes per pencil T = N/16; pencils per wave for N <= 1024.
+// Lanes per pencil T = N/16; lane groups per wave for N <= 1024.
 template <int N>
 struct pencil_cfg {
     static constexpr int T = N / 16;
@@ -46,43 +133,98 @@ struct pencil_cfg {
     static constexpr int PPW = WAVE ? 64 / T : 1;
 };
 
+// Vector of 2*P reals: P complex pencils of a lane group.
+template <typename R, int P>
+struct vec_of;
+template <>
+struct vec_of<double, 1> { using type = double2; };
+template <>
+struct vec_of<float, 1> { using type = float2; };
+template <>
+struct vec_of<double, 2> { using type = double4; };
+template <>
+struct vec_of<float, 2> { using type = float4; };
+
+template <typename R, int P>
+__device__ __forceinline__ void load_group(const R* src, cpx<R> (&v)[P][16], int e) {
+    using V = typename vec_of<R, P>::type;
+    const V a = *reinterpret_cast<const V*>(src);
+    if constexpr (P == 1) {
+        v[0][e] = cpx<R>{a.x, a.y};
+    } else {
+        v[0][e] = cpx<R>{a.x, a.y};
+        v[1][e] = cpx<R>{a.z, a.w};
+    }
+}
+
+template <typename R, int P>
+__device__ __forceinline__ void add_group(R* dst, const cpx<R> (&v)[P][16], int e) {
+    using V = typename vec_of<R, P>::type;
+    V* q = reinterpret_cast<V*>(dst);
+    V a = *q;
+    if constexpr (P == 1) {
+        a.x += v[0][e].x; a.y += v[0][e].y;
+    } else {
+        a.x += v[0][e].x; a.y += v[0][e].y;
+        a.z += v[1][e].x; a.w += v[1][e].y;
+    }
+    *q = a;
+}
+
 // ---------------------------------------------------------------------------
-// y / z pass: dst += T_axis src.  Lane l of a wave: pencil p = l % PPW (the
-// fast index, so neighbouring lanes read neighbouring x pairs), position
-// j = l / PPW.
+// y / z pass: dst += T_axis src.  A lane group carries P complex pencils
+// (2P neighbouring x columns, one vector load per element).  Lane l of a
+// wave: group g = l % PPW (the fast index, so neighbouring lanes read
+// neighbouring columns), position j = l / PPW.
 // ---------------------------------------------------------------------------
-template <typename R, int N, int WPB>
-__global__ __launch_bounds__(64 * WPB) void k_axis_acc(const R* __restrict__ src, R* __restrict__ dst,
-                                                       const cpx<R>* __restrict__ tw, AxisGeom g,
-                                                       R scale, int nyq_zero) {
+template <typename R, int N, int WPB, int P>
+__global__ __launch_bounds__(64 * WPB) SPSTD_WAVES_ATTR void k_axis_acc(
+    const R* __restrict__ src, R* __restrict__ dst, const cpx<R>* __restrict__ tw, AxisGeom g,
+    R scale, int nyq_zero) {
     using C = pencil_cfg<N>;
+    using TU = tuning<R>;
     static_assert(C::WAVE, "y/z pencils must fit in one wavefront");
     constexpr int LS = lds_size<N>::value;
-    __shared__ R lds[N == 16 ? 1 : WPB * C::PPW * 2 * LS];
+    constexpr int SL = (TU::SPLIT ? 1 : 2) * LS;
+    __shared__ R lds[N == 16 ? 1 : WPB * C::PPW * P * SL];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int p = lane % C::PPW, j = lane / C::PPW;
-    const int64_t npen = g.half_x * g.n_outer;
-    const int64_t pencil = ((int64_t)blockIdx.x * WPB + wave) * C::PPW + p;
-    const bool valid = pencil < npen;
-    const int64_t px = valid ? pencil % g.half_x : 0, outer = valid ? pencil / g.half_x : 0;
-    const int64_t base = outer * g.outer_stride + 2 * px;
+    const int64_t groups_x = g.half_x / P;
+    const int64_t ngroups = groups_x * g.n_outer;
+    constexpr int GPB = WPB * C::PPW;                 // lane groups per block
+    int64_t group;
+    if (SPSTD_YZ_ORDER == 1 && groups_x % GPB == 0) {
+        // block b: plane b mod n_outer, column block b / n_outer
+        const int64_t b = blockIdx.x;
+        group = ((b % g.n_outer) * (groups_x / GPB) + b / g.n_outer) * GPB + wave * C::PPW + p;
+    } else {
+        group = ((int64_t)blockIdx.x * WPB + wave) * C::PPW + p;
+    }
+    const bool valid = group < ngroups;
+    const int64_t gx = valid ? group % groups_x : 0, outer = valid ? group / groups_x : 0;
+    const int64_t base = outer * g.outer_stride + 2 * P * gx;
 
-    cpx<R> v[16];
+    cpx<R> v[P][16];
 #pragma unroll
     for (int e = 0; e < 16; ++e) {
-        v[e] = valid ? *reinterpret_cast<const cpx<R>*>(src + base + (int64_t)(j + C::T * e) * g.stride)
-                     : cpx<R>{(R)0, (R)0};
+        if (valid) {
+            load_group<R, P>(src + base + (int64_t)(j + C::T * e) * g.stride, v, e);
+        } else {
+#pragma unroll
+            for (int q = 0; q < P; ++q) v[q][e] = cpx<R>{(R)0, (R)0};
+        }
     }
-    R* lre = lds + (wave * C::PPW + p) * 2 * LS;
-    fft_pencil<R, N, false, true>(v, j, lre, lre + LS, tw);
-    apply_symbol<R, N>(v, j, scale, nyq_zero);
-    fft_pencil<R, N, true, true>(v, j, lre, lre + LS, tw);
+    R* l0 = lds + (wave * C::PPW + p) * P * SL;
+    fft_pencils<R, N, false, true, TU::SPLIT, TU::PRODUCTS, P>(v, j, l0, SL, tw);
+#pragma unroll
+    for (int q = 0; q < P; ++q) apply_symbol<R, N>(v[q], j, scale, nyq_zero);
+    fft_pencils<R, N, true, true, TU::SPLIT, TU::PRODUCTS, P>(v, j, l0, SL, tw);
+    epi_begin();
     if (valid) {
 #pragma unroll
         for (int e = 0; e < 16; ++e) {
-            cpx<R>* q = reinterpret_cast<cpx<R>*>(dst + base + (int64_t)(j + C::T * e) * g.stride);
-            cpx<R> o = *q;
-            *q = cpx<R>{o.x + v[e].x, o.y + v[e].y};
+            add_group<R, P>(dst + base + (int64_t)(j + C::T * e) * g.stride, v, e);
+            epi_fence(e);
         }
     }
 }
@@ -92,122 +234,183 @@ __global__ __launch_bounds__(64 * WPB) void k_axis_acc(const R* __restrict__ src
 // (neighbouring lanes read neighbouring x), or one pencil per block for
 // N > 1024.
 // ---------------------------------------------------------------------------
-template <int N, int WPB>
+template <typename R, int N, int WPB>
 struct row_map {
     using C = pencil_cfg<N>;
     static constexpr int PPB = C::WAVE ? WPB * C::PPW : 1;   // pencils per block
     static constexpr int THREADS = C::WAVE ? 64 * WPB : C::T;
     static constexpr int LS = lds_size<N>::value;
-    // large pencils exchange re and im in turn to stay within 160 KB of LDS
-    static constexpr bool SPLIT = !C::WAVE;
+    // large pencils always exchange re and im in turn to stay within LDS
+    static constexpr bool SPLIT = C::WAVE ? tuning<R>::SPLIT : true;
+    static constexpr int SL = (SPLIT ? 1 : 2) * LS;
     // a 16-point pencil is one radix-16 pass in registers: no LDS at all
-    static constexpr int LDS_REALS = N == 16 ? 1 : PPB * (SPLIT ? 1 : 2) * LS;
+    static constexpr int LDS_REALS = N == 16 ? 1 : PPB * SL;
+};
+
+// Row pair of this lane: rows 2q and 2q + 1 with q = block_pair0 + pin_block.
+// Fields are addressed as (block-uniform pointer) + (32-bit lane offset) +
+// (compile-time element offset), so one VGPR holds a lane's address.
+template <typename R, int N, int WPB>
+struct row_lane {
+    int j;            // position in the pencil
+    int pin_block;    // pencil index within the block
+    int64_t q;        // global pencil (row pair) index
+    int64_t row0;     // first row of the block (uniform)
+    int off;          // lane offset of row 2q, element j, from row0
 };
 
 template <typename R, int N, int WPB>
-__device__ __forceinline__ void row_coords(int& j, int& pin_block, int64_t& q) {
+__device__ __forceinline__ row_lane<R, N, WPB> row_coords() {
     using C = pencil_cfg<N>;
+    row_lane<R, N, WPB> L;
     if constexpr (C::WAVE) {
         const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-        j = lane % C::T;
-        pin_block = wave * C::PPW + lane / C::T;
+        L.j = lane % C::T;
+        L.pin_block = wave * C::PPW + lane / C::T;
     } else {
-        j = threadIdx.x;
-        pin_block = 0;
+        L.j = threadIdx.x;
+        L.pin_block = 0;
     }
-    q = (int64_t)blockIdx.x * row_map<N, WPB>::PPB + pin_block;
+    L.q = (int64_t)blockIdx.x * row_map<R, N, WPB>::PPB + L.pin_block;
+    L.row0 = (int64_t)blockIdx.x * row_map<R, N, WPB>::PPB * 2;
+    L.off = 2 * L.pin_block * N + L.j;
+    return L;
 }
 
-template <typename R, int N, int WPB>
-__global__ __launch_bounds__((row_map<N, WPB>::THREADS)) void k_x_acc(
+// FULL: every row pair of every block exists (no per-lane guards, so the
+// epilogue's loads can be batched); otherwise rows past nrows are skipped.
+template <typename R, int N, int WPB, bool FULL>
+__global__ __launch_bounds__((row_map<R, N, WPB>::THREADS)) SPSTD_WAVES_ATTR void k_x_acc(
     const R* __restrict__ src, R* __restrict__ dst, const R* __restrict__ V,
     const cpx<R>* __restrict__ tw, int64_t nrows, R scale, R vscale, int nyq_zero) {
     using C = pencil_cfg<N>;
-    using M = row_map<N, WPB>;
+    using M = row_map<R, N, WPB>;
+    using TU = tuning<R>;
     __shared__ R lds[M::LDS_REALS];
-    int j, pb;
-    int64_t q;
-    row_coords<R, N, WPB>(j, pb, q);
-    const int64_t r0 = 2 * q, r1 = 2 * q + 1;
-    const bool v0 = r0 < nrows, v1 = r1 < nrows;
-    const R* s0 = src + r0 * N;
-    const R* s1 = src + r1 * N;
-    cpx<R> v[16];
+    const row_lane<R, N, WPB> L = row_coords<R, N, WPB>();
+    const int j = L.j;
+    const bool v0 = FULL || 2 * L.q < nrows, v1 = FULL || 2 * L.q + 1 < nrows;
+    const int64_t b = L.row0 * N;
+    const R* __restrict__ sb = src + b;
+    R* __restrict__ db = dst + b;
+    const R* __restrict__ Vb = V + b;
+    const int o0 = L.off, o1 = L.off + N;
+    cpx<R> v[1][16];
+#if !SPSTD_X_RELOAD
     R f0[16], f1[16];
+#endif
 #pragma unroll
     for (int e = 0; e < 16; ++e) {
-        const int x = j + C::T * e;
-        f0[e] = v0 ? s0[x] : (R)0;
-        f1[e] = v1 ? s1[x] : (R)0;
-        v[e] = cpx<R>{f0[e], f1[e]};
+        const R a = v0 ? sb[o0 + C::T * e] : (R)0;
+        const R c = v1 ? sb[o1 + C::T * e] : (R)0;
+        v[0][e] = cpx<R>{a, c};
+#if !SPSTD_X_RELOAD
+        f0[e] = a;
+        f1[e] = c;
+#endif
     }
-    R* lre = lds + pb * (M::SPLIT ? 1 : 2) * M::LS;
-    fft_pencil<R, N, false, C::WAVE, M::SPLIT>(v, j, lre, lre + M::LS, tw);
-    apply_symbol<R, N>(v, j, scale, nyq_zero);
-    fft_pencil<R, N, true, C::WAVE, M::SPLIT>(v, j, lre, lre + M::LS, tw);
+#if SPSTD_X_RELOAD
+    reload_fence();
+#endif
+    R* l0 = lds + L.pin_block * M::SL;
+    fft_pencils<R, N, false, C::WAVE, M::SPLIT, TU::PRODUCTS, 1>(v, j, l0, M::SL, tw);
+    apply_symbol<R, N>(v[0], j, scale, nyq_zero);
+    fft_pencils<R, N, true, C::WAVE, M::SPLIT, TU::PRODUCTS, 1>(v, j, l0, M::SL, tw);
+    epi_begin();
 #pragma unroll
     for (int e = 0; e < 16; ++e) {
-        const int x = j + C::T * e;
-        if (v0) {
-            const int64_t a = r0 * N + x;
-            dst[a] = dst[a] + v[e].x + vscale * V[a] * f0[e];
-        }
-        if (v1) {
-            const int64_t a = r1 * N + x;
-            dst[a] = dst[a] + v[e].y + vscale * V[a] * f1[e];
-        }
+        const int i0 = o0 + C::T * e, i1 = o1 + C::T * e;
+#if SPSTD_X_RELOAD
+        const R a = v0 ? sb[i0] : (R)0;
+        const R c = v1 ? sb[i1] : (R)0;
+#else
+        const R a = f0[e], c = f1[e];
+#endif
+        if (v0) db[i0] = db[i0] + v[0][e].x + vscale * Vb[i0] * a;
+        if (v1) db[i1] = db[i1] + v[0][e].y + vscale * Vb[i1] * c;
+        epi_fence(e);
     }
 }
 
-template <typename R, int N, int WPB>
-__global__ __launch_bounds__((row_map<N, WPB>::THREADS)) void k_x_ab(
+template <typename R, int N, int WPB, bool FULL>
+__global__ __launch_bounds__((row_map<R, N, WPB>::THREADS)) SPSTD_WAVES_ATTR void k_x_ab(
     R* __restrict__ psiR, R* __restrict__ psiI, const R* __restrict__ V,
     const cpx<R>* __restrict__ tw, int64_t nrows, R sa, R va, R sb, R vb, int nyq_zero) {
     using C = pencil_cfg<N>;
-    using M = row_map<N, WPB>;
+    using M = row_map<R, N, WPB>;
+    using TU = tuning<R>;
     __shared__ R lds[M::LDS_REALS];
-    int j, pb;
-    int64_t q;
-    row_coords<R, N, WPB>(j, pb, q);
-    const int64_t r0 = 2 * q, r1 = 2 * q + 1;
-    const bool v0 = r0 < nrows, v1 = r1 < nrows;
-    cpx<R> v[16];
+    const row_lane<R, N, WPB> L = row_coords<R, N, WPB>();
+    const int j = L.j;
+    const bool v0 = FULL || 2 * L.q < nrows, v1 = FULL || 2 * L.q + 1 < nrows;
+    const int64_t b = L.row0 * N;
+    R* __restrict__ Rb = psiR + b;
+    R* __restrict__ Ib = psiI + b;
+    const R* __restrict__ Vb = V + b;
+    const int o0 = L.off, o1 = L.off + N;
+    cpx<R> v[1][16];
+#if !SPSTD_X_RELOAD
     cpx<R> f[16];   // psi_I on entry; later psi_I + vb * V * psi_R(new)
+#endif
 #pragma unroll
     for (int e = 0; e < 16; ++e) {
-        const int x = j + C::T * e;
-        f[e].x = v0 ? psiI[r0 * N + x] : (R)0;
-        f[e].y = v1 ? psiI[r1 * N + x] : (R)0;
-        v[e] = f[e];
+        v[0][e].x = v0 ? Ib[o0 + C::T * e] : (R)0;
+        v[0][e].y = v1 ? Ib[o1 + C::T * e] : (R)0;
+#if !SPSTD_X_RELOAD
+        f[e] = v[0][e];
+#endif
     }
-    R* lre = lds + pb * (M::SPLIT ? 1 : 2) * M::LS;
+#if SPSTD_X_RELOAD
+    reload_fence();
+#endif
+    R* l0 = lds + L.pin_block * M::SL;
     // A half: psi_R += T_x^a psi_I + va V psi_I
-    fft_pencil<R, N, false, C::WAVE, M::SPLIT>(v, j, lre, lre + M::LS, tw);
-    apply_symbol<R, N>(v, j, sa, nyq_zero);
-    fft_pencil<R, N, true, C::WAVE, M::SPLIT>(v, j, lre, lre + M::LS, tw);
+    fft_pencils<R, N, false, C::WAVE, M::SPLIT, TU::PRODUCTS, 1>(v, j, l0, M::SL, tw);
+    apply_symbol<R, N>(v[0], j, sa, nyq_zero);
+    fft_pencils<R, N, true, C::WAVE, M::SPLIT, TU::PRODUCTS, 1>(v, j, l0, M::SL, tw);
+    epi_begin();
 #pragma unroll
     for (int e = 0; e < 16; ++e) {
-        const int x = j + C::T * e;
-        cpx<R> vv = {(R)0, (R)0}, g = {(R)0, (R)0};
-        if (v0) { vv.x = V[r0 * N + x]; g.x = psiR[r0 * N + x]; }
-        if (v1) { vv.y = V[r1 * N + x]; g.y = psiR[r1 * N + x]; }
-        g.x = g.x + v[e].x + va * vv.x * f[e].x;
-        g.y = g.y + v[e].y + va * vv.y * f[e].y;
-        if (v0) psiR[r0 * N + x] = g.x;
-        if (v1) psiR[r1 * N + x] = g.y;
-        v[e] = g;
-        f[e].x = f[e].x + vb * vv.x * g.x;
-        f[e].y = f[e].y + vb * vv.y * g.y;
+        const int i0 = o0 + C::T * e, i1 = o1 + C::T * e;
+        cpx<R> vv = {(R)0, (R)0}, g = {(R)0, (R)0}, fe;
+#if SPSTD_X_RELOAD
+        fe = cpx<R>{v0 ? Ib[i0] : (R)0, v1 ? Ib[i1] : (R)0};
+#else
+        fe = f[e];
+#endif
+        if (v0) { vv.x = Vb[i0]; g.x = Rb[i0]; }
+        if (v1) { vv.y = Vb[i1]; g.y = Rb[i1]; }
+        g.x = g.x + v[0][e].x + va * vv.x * fe.x;
+        g.y = g.y + v[0][e].y + va * vv.y * fe.y;
+        if (v0) Rb[i0] = g.x;
+        if (v1) Rb[i1] = g.y;
+        v[0][e] = g;
+#if !SPSTD_X_RELOAD
+        f[e].x = fe.x + vb * vv.x * g.x;
+        f[e].y = fe.y + vb * vv.y * g.y;
+#endif
+        epi_fence(e);
     }
+#if SPSTD_X_RELOAD
+    reload_fence();
+#endif
     // B half: psi_I += T_x^b psi_R(new) + vb V psi_R(new)
-    fft_pencil<R, N, false, C::WAVE, M::SPLIT>(v, j, lre, lre + M::LS, tw);
-    apply_symbol<R, N>(v, j, sb, nyq_zero);
-    fft_pencil<R, N, true, C::WAVE, M::SPLIT>(v, j, lre, lre + M::LS, tw);
+    fft_pencils<R, N, false, C::WAVE, M::SPLIT, TU::PRODUCTS, 1>(v, j, l0, M::SL, tw);
+    apply_symbol<R, N>(v[0], j, sb, nyq_zero);
+    fft_pencils<R, N, true, C::WAVE, M::SPLIT, TU::PRODUCTS, 1>(v, j, l0, M::SL, tw);
+    epi_begin();
 #pragma unroll
     for (int e = 0; e < 16; ++e) {
-        const int x = j + C::T * e;
-        if (v0) psiI[r0 * N + x] = f[e].x + v[e].x;
-        if (v1) psiI[r1 * N + x] = f[e].y + v[e].y;
+        const int i0 = o0 + C::T * e, i1 = o1 + C::T * e;
+#if SPSTD_X_RELOAD
+        // psi_R here is the value this lane stored in the A epilogue
+        if (v0) Ib[i0] = Ib[i0] + vb * Vb[i0] * Rb[i0] + v[0][e].x;
+        if (v1) Ib[i1] = Ib[i1] + vb * Vb[i1] * Rb[i1] + v[0][e].y;
+#else
+        if (v0) Ib[i0] = f[e].x + v[0][e].x;
+        if (v1) Ib[i1] = f[e].y + v[0][e].y;
+#endif
+        epi_fence(e);
     }
 }
 
@@ -274,16 +477,18 @@ __global__ void k_fill0(int64_t n, R* __restrict__ y) {
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
-constexpr int kWPB = 2;   // waves per block of the wave-local passes
+constexpr int kWPB = SPSTD_WPB;   // waves per block of the wave-local passes
 
 template <typename R, int N>
 static hipError_t axis_acc_n(const R* src, R* dst, const void* tw, const AxisGeom& g, double scale,
                              int nyq_zero, hipStream_t st) {
     using C = pencil_cfg<N>;
-    const int64_t npen = g.half_x * g.n_outer;
-    const int64_t waves = (npen + C::PPW - 1) / C::PPW;
+    constexpr int P = tuning<R>::YZ_PPL;
+    if (g.half_x % P) return hipErrorInvalidValue;
+    const int64_t ngroups = g.half_x / P * g.n_outer;
+    const int64_t waves = (ngroups + C::PPW - 1) / C::PPW;
     const int64_t blocks = (waves + kWPB - 1) / kWPB;
-    hipLaunchKernelGGL((k_axis_acc<R, N, kWPB>), dim3((unsigned)blocks), dim3(64 * kWPB), 0, st,
+    hipLaunchKernelGGL((k_axis_acc<R, N, kWPB, P>), dim3((unsigned)blocks), dim3(64 * kWPB), 0, st,
                        src, dst, (const cpx<R>*)tw, g, (R)scale, nyq_zero);
     return hipGetLastError();
 }
@@ -306,23 +511,32 @@ hipError_t launch_axis_acc(int64_t n, const R* src, R* dst, const void* tw, cons
 template <typename R, int N>
 static hipError_t x_acc_n(const R* src, R* dst, const R* V, const void* tw, const RowGeom& g,
                           double scale, double vscale, int nyq_zero, hipStream_t st) {
-    using M = row_map<N, kWPB>;
+    using M = row_map<R, N, kWPB>;
     const int64_t npen = (g.nrows + 1) / 2;
     const int64_t blocks = (npen + M::PPB - 1) / M::PPB;
-    hipLaunchKernelGGL((k_x_acc<R, N, kWPB>), dim3((unsigned)blocks), dim3(M::THREADS), 0, st,
-                       src, dst, V, (const cpx<R>*)tw, g.nrows, (R)scale, (R)vscale, nyq_zero);
+    if (g.nrows % (2 * M::PPB) == 0)
+        hipLaunchKernelGGL((k_x_acc<R, N, kWPB, true>), dim3((unsigned)blocks), dim3(M::THREADS), 0, st,
+                           src, dst, V, (const cpx<R>*)tw, g.nrows, (R)scale, (R)vscale, nyq_zero);
+    else
+        hipLaunchKernelGGL((k_x_acc<R, N, kWPB, false>), dim3((unsigned)blocks), dim3(M::THREADS), 0, st,
+                           src, dst, V, (const cpx<R>*)tw, g.nrows, (R)scale, (R)vscale, nyq_zero);
     return hipGetLastError();
 }
 
 template <typename R, int N>
 static hipError_t x_ab_n(R* psiR, R* psiI, const R* V, const void* tw, const RowGeom& g, double sa,
                          double va, double sb, double vb, int nyq_zero, hipStream_t st) {
-    using M = row_map<N, kWPB>;
+    using M = row_map<R, N, kWPB>;
     const int64_t npen = (g.nrows + 1) / 2;
     const int64_t blocks = (npen + M::PPB - 1) / M::PPB;
-    hipLaunchKernelGGL((k_x_ab<R, N, kWPB>), dim3((unsigned)blocks), dim3(M::THREADS), 0, st,
-                       psiR, psiI, V, (const cpx<R>*)tw, g.nrows, (R)sa, (R)va, (R)sb, (R)vb,
-                       nyq_zero);
+    if (g.nrows % (2 * M::PPB) == 0)
+        hipLaunchKernelGGL((k_x_ab<R, N, kWPB, true>), dim3((unsigned)blocks), dim3(M::THREADS), 0, st,
+                           psiR, psiI, V, (const cpx<R>*)tw, g.nrows, (R)sa, (R)va, (R)sb, (R)vb,
+                           nyq_zero);
+    else
+        hipLaunchKernelGGL((k_x_ab<R, N, kWPB, false>), dim3((unsigned)blocks), dim3(M::THREADS), 0, st,
+                           psiR, psiI, V, (const cpx<R>*)tw, g.nrows, (R)sa, (R)va, (R)sb, (R)vb,
+                           nyq_zero);
     return hipGetLastError();
 }
 
