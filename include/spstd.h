@@ -52,6 +52,8 @@ enum { SPSTD_SYMPLECTIC = 0, SPSTD_RK4 = 1 };        /* time integrator */
                                                         instead of replaying step-chunk graphs */
 #define SPSTD_TIMING 0x4u                            /* flags: each pass kernel (eager or in the
                                                         step graph) bracketed by HIP events */
+#define SPSTD_NO_RESIDENT 0x8u                       /* flags: 1D plans use the pass kernels
+                                                        even where the resident kernel applies */
 #define SPSTD_MAX_STAGES 16
 #define SPSTD_MAX_PROBES 64
 
@@ -81,7 +83,10 @@ enum { SPSTD_SYMPLECTIC = 0, SPSTD_RK4 = 1 };        /* time integrator */
  *                term removed, as Eq. (10) read literally (two first
  *                derivatives, real part kept after each inverse transform).
  *   nprobes      0..64 probe points; probe_idx (host) their linear indices.
- *   flags        SPSTD_ALLOW_UNSTABLE, SPSTD_EAGER, SPSTD_TIMING (OR-ed), or 0.
+ *   flags        SPSTD_ALLOW_UNSTABLE, SPSTD_EAGER, SPSTD_TIMING, SPSTD_NO_RESIDENT
+ *                (OR-ed), or 0.  1D symplectic plans with n <= 4096 and at most
+ *                8 probes (and no SPSTD_TIMING) run each spstd_step call as one
+ *                launch of a kernel that keeps the grid in registers.
  */
 typedef struct spstd_desc {
     int ndim;
@@ -228,6 +233,91 @@ spstd_status spstd_pass_times(spstd_plan_t plan, int64_t *launches, double *tota
 
 spstd_status spstd_destroy(spstd_plan_t plan);
 const char *spstd_strerror(spstd_status status);
+
+/* ------------------------------------------------------------------------
+ * Batches: many independent instances of one grid shape advanced together
+ * (each with its own spacing, hbar, m*, V, initial state, dt and probes; the
+ * coefficient set is shared).  Instances live in slots of one stacked
+ * buffer; every pass of a stage is one launch over all slots, so a step of
+ * the whole batch costs what one large grid costs.  Slots are loaded and
+ * released while others keep running, which is what the serving loop uses.
+ * ------------------------------------------------------------------------ */
+typedef struct spstd_batch_s *spstd_batch_t;
+
+/*
+ * Batch descriptor (caller-owned; copied by spstd_batch_create).
+ *   ndim, n[3]    shape of every instance (as spstd_desc).
+ *   precision     SPSTD_FP64 or SPSTD_FP32.
+ *   m, c, d       stage coefficients of Eq. (17), shared by all slots.
+ *   nyquist       as spstd_desc.
+ *   capacity      number of slots (>= 1).
+ *   nprobes       probe points per slot, 0..8.
+ *   nsteps_max    probe samples kept per slot after sample 0.
+ *   flags         SPSTD_ALLOW_UNSTABLE, SPSTD_NO_RESIDENT.
+ */
+typedef struct spstd_batch_desc {
+    int ndim;
+    int64_t n[3];
+    int precision;
+    int m;
+    const double *c, *d;
+    int nyquist;
+    int capacity;
+    int nprobes;
+    int64_t nsteps_max;
+    uint32_t flags;
+} spstd_batch_desc;
+
+/* Exact device workspace size of a batch.  Pure host computation. */
+spstd_status spstd_batch_workspace_size(const spstd_batch_desc *desc, size_t *bytes);
+
+/*
+ * Create a batch over the caller's device workspace (256-byte aligned,
+ * ws_bytes >= spstd_batch_workspace_size); all slots start free.  stream: a
+ * hipStream_t (NULL for the null stream) for every kernel of the batch.
+ * Synchronises the stream.  Errors: SPSTD_ERR_ARG, SPSTD_ERR_WORKSPACE,
+ * SPSTD_ERR_DEVICE.
+ */
+spstd_status spstd_batch_create(const spstd_batch_desc *desc, void *d_workspace, size_t ws_bytes,
+                                void *stream, spstd_batch_t *out);
+
+/*
+ * Load an instance into a free slot: spacing dx[ndim], hbar, m*, the time
+ * step (dt > 0, or dt == 0 for cfl_fraction * x_max / rho of this instance,
+ * as in spstd_desc), host FP64 arrays V, psi_R(0), psi_I(0) (NULL for zero)
+ * of the shape's size, and nprobes linear probe indices.  Records sample 0,
+ * marks the slot active and writes the time step used to *dt_out (may be
+ * NULL).  Synchronises the batch stream.  Errors: SPSTD_ERR_ARG (slot busy or
+ * out of range, bad values), SPSTD_ERR_UNSTABLE, SPSTD_ERR_DEVICE.
+ */
+spstd_status spstd_batch_load(spstd_batch_t batch, int slot, const double *dx, double hbar, double mass,
+                              double dt, double cfl_fraction, const double *V, const double *psiR0,
+                              const double *psiI0, const int64_t *probe_idx, double *dt_out);
+
+/*
+ * Enqueue nsteps steps of every active slot (asynchronous).  Each active
+ * slot records one probe sample per step.  SPSTD_ERR_CAPACITY (nothing
+ * queued) if a slot would pass nsteps_max.
+ */
+spstd_status spstd_batch_step(spstd_batch_t batch, int64_t nsteps);
+
+/*
+ * Synchronise and copy a slot's probe series ([(steps_done + 1) * nprobes * 2]
+ * doubles) and state (host FP64, N values each); any output may be NULL.
+ * SPSTD_ERR_NONFINITE if a copied state holds NaN or Inf.
+ */
+spstd_status spstd_batch_read(spstd_batch_t batch, int slot, double *probes_out, double *psiR,
+                              double *psiI, int64_t *steps_done);
+
+/* Free a slot (its fields and scales are cleared).  Synchronises. */
+spstd_status spstd_batch_release(spstd_batch_t batch, int slot);
+
+/* Slot state: active flag, steps since its load, time step. */
+spstd_status spstd_batch_slot_info(spstd_batch_t batch, int slot, int *active, int64_t *steps_done,
+                                   double *dt);
+
+spstd_status spstd_batch_destroy(spstd_batch_t batch);
+const char *spstd_batch_last_error(spstd_batch_t batch);
 /* Text of the last error recorded on the plan (never NULL). */
 const char *spstd_last_error(spstd_plan_t plan);
 

@@ -11,81 +11,11 @@
 #include <vector>
 
 #include "../../include/spstd.h"
+#include "host_common.hpp"
 #include "kernels.hpp"
+#include "resident.hpp"
 
 namespace spstd {
-
-static const double kPi = 3.14159265358979323846264338327950288;
-
-// ---------------------------------------------------------------------------
-// Stability edge from the trace polynomial of the per-mode matrix.
-// The matrix of one step (Eq. 23) is the time-ordered product of the stage
-// shears A(c_l x) = [[1, c_l x], [0, 1]] and B(d_l x) = [[1, 0], [-d_l x, 1]];
-// its entries are polynomials in x of degree <= 2m.  tr = 2 + sum_l (-1)^l
-// g_l x^(2l) (Eq. 26-28); the edge is the first x > 0 with |tr| > 2.
-// ---------------------------------------------------------------------------
-struct Poly {
-    double a[2 * SPSTD_MAX_STAGES + 2];
-    int deg;
-};
-
-static Poly pmul_x(const Poly& p, double s) {  // s * x * p(x)
-    Poly r{};
-    r.deg = p.deg + 1;
-    for (int i = 0; i <= p.deg; ++i) r.a[i + 1] = s * p.a[i];
-    return r;
-}
-static Poly padd(const Poly& p, const Poly& q) {
-    Poly r{};
-    r.deg = p.deg > q.deg ? p.deg : q.deg;
-    for (int i = 0; i <= r.deg; ++i) r.a[i] = (i <= p.deg ? p.a[i] : 0.0) + (i <= q.deg ? q.a[i] : 0.0);
-    return r;
-}
-static double peval(const Poly& p, double x) {
-    double s = 0.0;
-    for (int i = p.deg; i >= 0; --i) s = s * x + p.a[i];
-    return s;
-}
-
-static bool trace_poly(int m, const double* c, const double* d, Poly* tr) {
-    Poly m00{}, m01{}, m10{}, m11{};
-    m00.a[0] = 1.0; m11.a[0] = 1.0;
-    for (int l = 0; l < m; ++l) {
-        // rows: A multiplies from the left: row0 += c x * row1
-        Poly n00 = padd(m00, pmul_x(m10, c[l]));
-        Poly n01 = padd(m01, pmul_x(m11, c[l]));
-        // B: row1 -= d x * row0 (new row0)
-        Poly n10 = padd(m10, pmul_x(n00, -d[l]));
-        Poly n11 = padd(m11, pmul_x(n01, -d[l]));
-        m00 = n00; m01 = n01; m10 = n10; m11 = n11;
-    }
-    *tr = padd(m00, m11);
-    return true;
-}
-
-static bool xmax_symplectic(int m, const double* c, const double* d, double* out) {
-    Poly tr;
-    trace_poly(m, c, d, &tr);
-    auto beyond = [&](double x) { return std::fabs(peval(tr, x)) > 2.0; };
-    // scan in steps of 1/256 of a unit, then bisect the bracketing step
-    const double h = 1.0 / 256.0;
-    double lo = 0.0;
-    for (int i = 1; i <= 256 * 1000; ++i) {
-        double x = i * h;
-        if (beyond(x)) {
-            double hi = x;
-            for (int it = 0; it < 200; ++it) {
-                double mid = 0.5 * (lo + hi);
-                if (mid <= lo || mid >= hi) break;
-                (beyond(mid) ? hi : lo) = mid;
-            }
-            *out = lo;
-            return true;
-        }
-        lo = x;
-    }
-    return false;
-}
 
 // classical RK4 on an oscillation: stable while |x| <= 2 sqrt(2)
 static const double kRK4Edge = 2.8284271247461900976;
@@ -94,7 +24,7 @@ static const double kRK4Edge = 2.8284271247461900976;
 // plan
 // ---------------------------------------------------------------------------
 struct Layout {
-    size_t psiR, psiI, V, rk[6], tw[3], pidx, probes, counter, partials, total;
+    size_t psiR, psiI, V, rk[6], tw[3], pidx, probes, counter, partials, rinst, scales, total;
 };
 
 static const int kNormBlocks = 256;
@@ -177,7 +107,6 @@ static hipError_t harvest(Plan* p, const std::vector<hipEvent_t>& ev, const std:
     return hipSuccess;
 }
 
-static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 static bool pow2(int64_t n) { return n > 0 && (n & (n - 1)) == 0; }
 
@@ -199,6 +128,7 @@ static spstd_status validate(const spstd_desc* d, std::string* why) {
     }
     if (d->precision != SPSTD_FP64 && d->precision != SPSTD_FP32) { *why = "bad precision"; return SPSTD_ERR_ARG; }
     if (d->method != SPSTD_SYMPLECTIC && d->method != SPSTD_RK4) { *why = "bad method"; return SPSTD_ERR_ARG; }
+    if (d->m < 0 || d->m > SPSTD_MAX_STAGES) { *why = "m must be 0..16"; return SPSTD_ERR_ARG; }
     if (d->method == SPSTD_SYMPLECTIC) {
         if (d->m < 1 || d->m > SPSTD_MAX_STAGES || !d->c || !d->d) { *why = "m must be 1..16 with c, d"; return SPSTD_ERR_ARG; }
         for (int l = 0; l < d->m; ++l)
@@ -219,12 +149,7 @@ static spstd_status validate(const spstd_desc* d, std::string* why) {
 }
 
 static double rho_of(const spstd_desc* d, const double* V, int64_t N) {
-    double r = 0.0;
-    for (int a = 0; a < d->ndim; ++a) r += (kPi / d->dx[a]) * (kPi / d->dx[a]);
-    r *= d->hbar / (2.0 * d->mass);
-    double vm = 0.0;
-    for (int64_t i = 0; i < N; ++i) vm = std::fmax(vm, std::fabs(V[i]));
-    return r + vm / d->hbar;
+    return rho_bound_of(d->ndim, d->dx, d->hbar, d->mass, V, N);
 }
 
 static spstd_status edge_of(const spstd_desc* d, double* x) {
@@ -254,23 +179,15 @@ static Layout layout_of(const spstd_desc* d, int64_t nsteps_max) {
     off += align256(sizeof(double) * 2 * (size_t)(d->nprobes > 0 ? d->nprobes : 1) * (size_t)(nsteps_max + 1));
     L.counter = off; off += 256;
     L.partials = off; off += align256(sizeof(double) * kNormBlocks);
+    L.rinst = off; off += align256(sizeof(ResidentInst<double>));
+    // per-stage pass scales, then one row for the RK4 operator applications
+    L.scales = off; off += align256((size_t)(d->m + 1) * SC_COLS * esz);
     L.total = off;
     return L;
 }
 
 template <typename R>
 static R* F(Plan* p, size_t off) { return reinterpret_cast<R*>(p->ws + off); }
-
-// FP64 twiddles w_n^t = exp(-2 pi i t / n), from long-double cos/sin.
-static std::vector<double> twiddles(int64_t n) {
-    std::vector<double> t(2 * n);
-    for (int64_t k = 0; k < n; ++k) {
-        long double ang = -2.0L * 3.14159265358979323846264338327950288L * (long double)k / (long double)n;
-        t[2 * k] = (double)cosl(ang);
-        t[2 * k + 1] = (double)sinl(ang);
-    }
-    return t;
-}
 
 #define HIPCHK(x)                                                   \
     do {                                                            \
@@ -300,29 +217,15 @@ static spstd_status upload(Plan* p, size_t off, const double* src) {
     return SPSTD_OK;
 }
 
-// symbol scale of axis a for substep coefficient coef: coef (hbar/2m) (2 pi/L)^2 / n
-static double sym_scale(const Plan* p, int a, double coef) {
-    const double L = (double)p->d.n[a] * p->d.dx[a];
-    const double k1 = 2.0 * kPi / L;
-    return coef * p->d.hbar / (2.0 * p->d.mass) * k1 * k1 / (double)p->d.n[a];
-}
-
-static AxisGeom axis_geom(const Plan* p, int a) {
-    AxisGeom g;
-    const int64_t nx = p->d.n[0], ny = p->d.n[1], nz = p->d.n[2];
-    g.half_x = nx / 2;
-    if (a == 1) { g.n_outer = nz; g.outer_stride = nx * ny; g.stride = nx; }
-    else { g.n_outer = ny; g.outer_stride = nx; g.stride = nx * ny; }
-    return g;
-}
-
-// dst += coef * T_{y,z} src for every axis beyond x
+// dst += T_{y,z} src for every axis beyond x, with the scale columns of the
+// A (ab = 0) or B (ab = 1) substep
 template <typename R>
-static hipError_t yz_passes(Plan* p, const R* src, R* dst, double coef) {
+static hipError_t yz_passes(Plan* p, const R* src, R* dst, const ScaleRef& sc, int ab) {
     for (int a = 1; a < p->d.ndim; ++a) {
         PassTimer tm(p, a == 1 ? SPSTD_PASS_Y : SPSTD_PASS_Z);
-        hipError_t e = launch_axis_acc<R>(p->d.n[a], src, dst, p->ws + p->L.tw[a], axis_geom(p, a),
-                                          sym_scale(p, a, coef), p->d.nyquist, p->st);
+        const int col = (ab ? SC_KXB : SC_KXA) + a;
+        hipError_t e = launch_axis_acc<R>(p->d.n[a], src, dst, p->ws + p->L.tw[a], axis_geom_of(p->d, a, 1),
+                                          sc, col, p->d.nyquist, p->st);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
@@ -333,43 +236,43 @@ static hipError_t enqueue_symplectic_step(Plan* p) {
     R* pr = F<R>(p, p->L.psiR);
     R* pi = F<R>(p, p->L.psiI);
     const R* V = F<R>(p, p->L.V);
-    const RowGeom rg{p->N / p->d.n[0]};
+    const RowGeom rg{p->N / p->d.n[0], p->N / p->d.n[0]};
     const int64_t nx = p->d.n[0];
     const void* twx = p->ws + p->L.tw[0];
-    const double dt = p->dt, hb = p->d.hbar;
     hipError_t e = hipSuccess;
     for (int l = 0; l < p->d.m && e == hipSuccess; ++l) {
-        const double a = p->c[l] * dt, b = -p->dd[l] * dt;
-        if (a != 0.0) e = yz_passes<R>(p, pi, pr, a);
+        const bool a = p->c[l] != 0.0, b = p->dd[l] != 0.0;
+        const ScaleRef sc{p->ws + p->L.scales, p->d.m + 1, l};
+        if (a) e = yz_passes<R>(p, pi, pr, sc, 0);
         if (e != hipSuccess) break;
-        if (a != 0.0 || b != 0.0) {
-            PassTimer tm(p, (a != 0.0 && b != 0.0) ? SPSTD_PASS_XAB : SPSTD_PASS_X);
-            if (a != 0.0 && b != 0.0)
-                e = launch_x_ab<R>(nx, pr, pi, V, twx, rg, sym_scale(p, 0, a), a / hb,
-                                   sym_scale(p, 0, b), b / hb, p->d.nyquist, p->st);
-            else if (a != 0.0)
-                e = launch_x_acc<R>(nx, pi, pr, V, twx, rg, sym_scale(p, 0, a), a / hb,
-                                    p->d.nyquist, p->st);
+        if (a || b) {
+            PassTimer tm(p, (a && b) ? SPSTD_PASS_XAB : SPSTD_PASS_X);
+            if (a && b)
+                e = launch_x_ab<R>(nx, pr, pi, V, twx, rg, sc, p->d.nyquist, p->st);
+            else if (a)
+                e = launch_x_acc<R>(nx, pi, pr, V, twx, rg, sc, SC_KXA, SC_PA, p->d.nyquist, p->st);
             else
-                e = launch_x_acc<R>(nx, pr, pi, V, twx, rg, sym_scale(p, 0, b), b / hb,
-                                    p->d.nyquist, p->st);
+                e = launch_x_acc<R>(nx, pr, pi, V, twx, rg, sc, SC_KXB, SC_PB, p->d.nyquist, p->st);
         }
         if (e != hipSuccess) break;
-        if (b != 0.0) e = yz_passes<R>(p, pr, pi, b);
+        if (b) e = yz_passes<R>(p, pr, pi, sc, 1);
     }
     return e;
 }
 
-// kout = coef * K src  (K of Eq. 16), into a cleared buffer
+// kout = (+K or -K) src  (K of Eq. 16), into a cleared buffer; the RK4 row of
+// the scale table holds coefficient +1 in its A columns and -1 in its B columns
 template <typename R>
 static hipError_t apply_K(Plan* p, const R* src, R* kout, double coef) {
     const R* V = F<R>(p, p->L.V);
+    const ScaleRef sc{p->ws + p->L.scales, p->d.m + 1, p->d.m};
+    const int ab = coef > 0.0 ? 0 : 1;
     hipError_t e = launch_fill0<R>(p->N, kout, p->st);
-    if (e == hipSuccess) e = yz_passes<R>(p, src, kout, coef);
+    if (e == hipSuccess) e = yz_passes<R>(p, src, kout, sc, ab);
     PassTimer tm(p, SPSTD_PASS_X);
     if (e == hipSuccess)
-        e = launch_x_acc<R>(p->d.n[0], src, kout, V, p->ws + p->L.tw[0], RowGeom{p->N / p->d.n[0]},
-                            sym_scale(p, 0, coef), coef / p->d.hbar, p->d.nyquist, p->st);
+        e = launch_x_acc<R>(p->d.n[0], src, kout, V, p->ws + p->L.tw[0], RowGeom{p->N / p->d.n[0], p->N / p->d.n[0]},
+                            sc, ab ? SC_KXB : SC_KXA, ab ? SC_PB : SC_PA, p->d.nyquist, p->st);
     return e;
 }
 
@@ -404,6 +307,40 @@ static hipError_t enqueue_rk4_step(Plan* p) {
     if (e == hipSuccess) e = launch_axpby<R>(N, dt / 6.0, aR, 1.0, pr, p->st);
     if (e == hipSuccess) e = launch_axpby<R>(N, dt / 6.0, aI, 1.0, pi, p->st);
     return e;
+}
+
+static bool uses_resident(const Plan* p) {
+    const spstd_desc& d = p->d;
+    return d.ndim == 1 && d.method == SPSTD_SYMPLECTIC && resident_len_ok(d.n[0]) &&
+           d.nprobes <= kResMaxProbes && d.m <= SPSTD_MAX_STAGES &&
+           !(d.flags & (SPSTD_NO_RESIDENT | SPSTD_TIMING));
+}
+
+// The resident kernel's one-entry instance table for a 1D plan.
+template <typename R>
+static spstd_status upload_resident_inst(Plan* p) {
+    ResidentInst<R> I{};
+    I.V = F<R>(p, p->L.V);
+    I.psiR = F<R>(p, p->L.psiR);
+    I.psiI = F<R>(p, p->L.psiI);
+    I.probes = reinterpret_cast<double*>(p->ws + p->L.probes);
+    I.counter = reinterpret_cast<int64_t*>(p->ws + p->L.counter);
+    I.capacity = p->nsteps_max + 1;
+    I.nprobes = p->d.nprobes;
+    for (int q = 0; q < p->d.nprobes; ++q) I.probe_idx[q] = p->probe_idx[q];
+    const double L = (double)p->d.n[0] * p->d.dx[0];
+    const double k1 = 2.0 * kPi / L;
+    const double kin = p->d.hbar / (2.0 * p->d.mass) * k1 * k1 / (double)p->d.n[0];
+    for (int l = 0; l < p->d.m; ++l) {
+        const double a = p->c[l] * p->dt, b = -p->dd[l] * p->dt;
+        I.kin[2 * l] = (R)(a * kin);
+        I.kin[2 * l + 1] = (R)(b * kin);
+        I.pot[2 * l] = (R)(a / p->d.hbar);
+        I.pot[2 * l + 1] = (R)(b / p->d.hbar);
+    }
+    HIPCHK(hipMemcpyAsync(p->ws + p->L.rinst, &I, sizeof(I), hipMemcpyHostToDevice, p->st));
+    HIPCHK(hipStreamSynchronize(p->st));
+    return SPSTD_OK;
 }
 
 template <typename R>
@@ -450,6 +387,12 @@ static spstd_status build_graph(Plan* p) {
 
 template <typename R>
 static spstd_status enqueue_steps(Plan* p, int64_t n) {
+    if (uses_resident(p)) {
+        if (n > 0)
+            HIPCHK(launch_resident_1d<R>(p->d.n[0], reinterpret_cast<const ResidentInst<R>*>(p->ws + p->L.rinst),
+                                         1, p->d.m, n, p->d.nyquist, p->ws + p->L.tw[0], p->st));
+        return SPSTD_OK;
+    }
     const bool use_graph = !(p->d.flags & SPSTD_EAGER) && n >= kGraphChunk;
     const bool timing = (p->d.flags & SPSTD_TIMING) != 0;
     if (use_graph && !p->graph_ready) {
@@ -502,6 +445,18 @@ static spstd_status plan_init(Plan* p, const double* V, const double* psiR0, con
             HIPCHK(hipStreamSynchronize(p->st));
         }
     }
+    {
+        // stage rows (A coefficient c_l dt, B coefficient -d_l dt), then the RK4 row (+1, -1)
+        const int rows = p->d.m + 1;
+        std::vector<double> tab((size_t)rows * SC_COLS, 0.0);
+        for (int l = 0; l < p->d.m && p->d.method == SPSTD_SYMPLECTIC; ++l)
+            scale_row(p->d, p->c[l] * p->dt, -p->dd[l] * p->dt, &tab[(size_t)l * SC_COLS]);
+        scale_row(p->d, 1.0, -1.0, &tab[(size_t)p->d.m * SC_COLS]);
+        std::vector<R> tr(tab.size());
+        for (size_t i = 0; i < tab.size(); ++i) tr[i] = (R)tab[i];
+        HIPCHK(hipMemcpyAsync(p->ws + p->L.scales, tr.data(), tr.size() * sizeof(R), hipMemcpyHostToDevice, p->st));
+        HIPCHK(hipStreamSynchronize(p->st));
+    }
     if (p->d.nprobes > 0)
         HIPCHK(hipMemcpyAsync(p->ws + p->L.pidx, p->probe_idx, sizeof(int64_t) * p->d.nprobes,
                               hipMemcpyHostToDevice, p->st));
@@ -513,6 +468,10 @@ static spstd_status plan_init(Plan* p, const double* V, const double* psiR0, con
                                reinterpret_cast<double*>(p->ws + p->L.probes),
                                reinterpret_cast<int64_t*>(p->ws + p->L.counter), p->nsteps_max + 1, p->st));
     HIPCHK(hipStreamSynchronize(p->st));
+    if (uses_resident(p)) {
+        spstd_status s2 = upload_resident_inst<R>(p);
+        if (s2 != SPSTD_OK) return s2;
+    }
     return compute_norm<R>(p, &p->norm0);
 }
 

@@ -109,20 +109,26 @@ __device__ __forceinline__ void epi_fence(int e) {
     }
 }
 
-// Multiply bins kk = j + T*e by scale * ks^2 (ks the signed bin index);
-// under the ZERO convention the Nyquist bin kk = N/2 is removed.
+// Multiply bins kk = j + T*e by ks^2 (ks the signed bin index); under the
+// ZERO convention the Nyquist bin kk = N/2 is removed.  The instance's
+// scale is applied after the inverse transform.
 template <typename R, int N>
-__device__ __forceinline__ void apply_symbol(cpx<R> (&v)[16], int j, R scale, int nyq_zero) {
+__device__ __forceinline__ void apply_k2(cpx<R> (&v)[16], int j, int nyq_zero) {
     constexpr int T = N / 16;
 #pragma unroll
     for (int e = 0; e < 16; ++e) {
         const int kk = j + T * e;
         const int ks = (kk <= N / 2) ? kk : kk - N;
-        R s = scale * (R)(ks * ks);
+        R s = (R)(ks * ks);
         if (nyq_zero && kk == N / 2) s = (R)0;
         v[e].x *= s;
         v[e].y *= s;
     }
+}
+
+template <typename R>
+__device__ __forceinline__ R scale_of(const ScaleRef& sc, int64_t inst, int col) {
+    return reinterpret_cast<const R*>(sc.tab)[(inst * sc.m + sc.l) * SC_COLS + col];
 }
 
 // Lanes per pencil T = N/16; lane groups per wave for N <= 1024.
@@ -180,7 +186,7 @@ __device__ __forceinline__ void add_group(R* dst, const cpx<R> (&v)[P][16], int 
 template <typename R, int N, int WPB, int P>
 __global__ __launch_bounds__(64 * WPB) SPSTD_WAVES_ATTR void k_axis_acc(
     const R* __restrict__ src, R* __restrict__ dst, const cpx<R>* __restrict__ tw, AxisGeom g,
-    R scale, int nyq_zero) {
+    ScaleRef sc, int col, int nyq_zero) {
     using C = pencil_cfg<N>;
     using TU = tuning<R>;
     static_assert(C::WAVE, "y/z pencils must fit in one wavefront");
@@ -202,7 +208,8 @@ __global__ __launch_bounds__(64 * WPB) SPSTD_WAVES_ATTR void k_axis_acc(
     }
     const bool valid = group < ngroups;
     const int64_t gx = valid ? group % groups_x : 0, outer = valid ? group / groups_x : 0;
-    const int64_t base = outer * g.outer_stride + 2 * P * gx;
+    const int64_t inst = outer / g.n_in;
+    const int64_t base = inst * g.stride_hi + (outer - inst * g.n_in) * g.stride_lo + 2 * P * gx;
 
     cpx<R> v[P][16];
 #pragma unroll
@@ -217,10 +224,19 @@ __global__ __launch_bounds__(64 * WPB) SPSTD_WAVES_ATTR void k_axis_acc(
     R* l0 = lds + (wave * C::PPW + p) * P * SL;
     fft_pencils<R, N, false, true, TU::SPLIT, TU::PRODUCTS, P>(v, j, l0, SL, tw);
 #pragma unroll
-    for (int q = 0; q < P; ++q) apply_symbol<R, N>(v[q], j, scale, nyq_zero);
+    for (int q = 0; q < P; ++q) apply_k2<R, N>(v[q], j, nyq_zero);
     fft_pencils<R, N, true, true, TU::SPLIT, TU::PRODUCTS, P>(v, j, l0, SL, tw);
     epi_begin();
     if (valid) {
+        const R scale = scale_of<R>(sc, inst, col);
+#pragma unroll
+        for (int q = 0; q < P; ++q) {
+#pragma unroll
+            for (int e = 0; e < 16; ++e) {
+                v[q][e].x *= scale;
+                v[q][e].y *= scale;
+            }
+        }
 #pragma unroll
         for (int e = 0; e < 16; ++e) {
             add_group<R, P>(dst + base + (int64_t)(j + C::T * e) * g.stride, v, e);
@@ -282,14 +298,17 @@ __device__ __forceinline__ row_lane<R, N, WPB> row_coords() {
 template <typename R, int N, int WPB, bool FULL>
 __global__ __launch_bounds__((row_map<R, N, WPB>::THREADS)) SPSTD_WAVES_ATTR void k_x_acc(
     const R* __restrict__ src, R* __restrict__ dst, const R* __restrict__ V,
-    const cpx<R>* __restrict__ tw, int64_t nrows, R scale, R vscale, int nyq_zero) {
+    const cpx<R>* __restrict__ tw, RowGeom rg, ScaleRef sc, int kcol, int pcol, int nyq_zero) {
     using C = pencil_cfg<N>;
     using M = row_map<R, N, WPB>;
     using TU = tuning<R>;
     __shared__ R lds[M::LDS_REALS];
     const row_lane<R, N, WPB> L = row_coords<R, N, WPB>();
     const int j = L.j;
+    const int64_t nrows = rg.nrows;
     const bool v0 = FULL || 2 * L.q < nrows, v1 = FULL || 2 * L.q + 1 < nrows;
+    const int64_t inst0 = v0 ? (2 * L.q) / rg.rows_per_inst : 0;
+    const int64_t inst1 = v1 ? (2 * L.q + 1) / rg.rows_per_inst : inst0;
     const int64_t b = L.row0 * N;
     const R* __restrict__ sb = src + b;
     R* __restrict__ db = dst + b;
@@ -314,9 +333,11 @@ __global__ __launch_bounds__((row_map<R, N, WPB>::THREADS)) SPSTD_WAVES_ATTR voi
 #endif
     R* l0 = lds + L.pin_block * M::SL;
     fft_pencils<R, N, false, C::WAVE, M::SPLIT, TU::PRODUCTS, 1>(v, j, l0, M::SL, tw);
-    apply_symbol<R, N>(v[0], j, scale, nyq_zero);
+    apply_k2<R, N>(v[0], j, nyq_zero);
     fft_pencils<R, N, true, C::WAVE, M::SPLIT, TU::PRODUCTS, 1>(v, j, l0, M::SL, tw);
     epi_begin();
+    const R k0 = scale_of<R>(sc, inst0, kcol), p0 = scale_of<R>(sc, inst0, pcol);
+    const R k1 = scale_of<R>(sc, inst1, kcol), p1 = scale_of<R>(sc, inst1, pcol);
 #pragma unroll
     for (int e = 0; e < 16; ++e) {
         const int i0 = o0 + C::T * e, i1 = o1 + C::T * e;
@@ -326,8 +347,8 @@ __global__ __launch_bounds__((row_map<R, N, WPB>::THREADS)) SPSTD_WAVES_ATTR voi
 #else
         const R a = f0[e], c = f1[e];
 #endif
-        if (v0) db[i0] = db[i0] + v[0][e].x + vscale * Vb[i0] * a;
-        if (v1) db[i1] = db[i1] + v[0][e].y + vscale * Vb[i1] * c;
+        if (v0) db[i0] = db[i0] + k0 * v[0][e].x + p0 * Vb[i0] * a;
+        if (v1) db[i1] = db[i1] + k1 * v[0][e].y + p1 * Vb[i1] * c;
         epi_fence(e);
     }
 }
@@ -335,14 +356,17 @@ __global__ __launch_bounds__((row_map<R, N, WPB>::THREADS)) SPSTD_WAVES_ATTR voi
 template <typename R, int N, int WPB, bool FULL>
 __global__ __launch_bounds__((row_map<R, N, WPB>::THREADS)) SPSTD_WAVES_ATTR void k_x_ab(
     R* __restrict__ psiR, R* __restrict__ psiI, const R* __restrict__ V,
-    const cpx<R>* __restrict__ tw, int64_t nrows, R sa, R va, R sb, R vb, int nyq_zero) {
+    const cpx<R>* __restrict__ tw, RowGeom rg, ScaleRef sc, int nyq_zero) {
     using C = pencil_cfg<N>;
     using M = row_map<R, N, WPB>;
     using TU = tuning<R>;
     __shared__ R lds[M::LDS_REALS];
     const row_lane<R, N, WPB> L = row_coords<R, N, WPB>();
     const int j = L.j;
+    const int64_t nrows = rg.nrows;
     const bool v0 = FULL || 2 * L.q < nrows, v1 = FULL || 2 * L.q + 1 < nrows;
+    const int64_t inst0 = v0 ? (2 * L.q) / rg.rows_per_inst : 0;
+    const int64_t inst1 = v1 ? (2 * L.q + 1) / rg.rows_per_inst : inst0;
     const int64_t b = L.row0 * N;
     R* __restrict__ Rb = psiR + b;
     R* __restrict__ Ib = psiI + b;
@@ -364,11 +388,15 @@ __global__ __launch_bounds__((row_map<R, N, WPB>::THREADS)) SPSTD_WAVES_ATTR voi
     reload_fence();
 #endif
     R* l0 = lds + L.pin_block * M::SL;
-    // A half: psi_R += T_x^a psi_I + va V psi_I
+    // A half: psi_R += T_x^A psi_I + p_A V psi_I
     fft_pencils<R, N, false, C::WAVE, M::SPLIT, TU::PRODUCTS, 1>(v, j, l0, M::SL, tw);
-    apply_symbol<R, N>(v[0], j, sa, nyq_zero);
+    apply_k2<R, N>(v[0], j, nyq_zero);
     fft_pencils<R, N, true, C::WAVE, M::SPLIT, TU::PRODUCTS, 1>(v, j, l0, M::SL, tw);
     epi_begin();
+    const cpx<R> sa = {scale_of<R>(sc, inst0, SC_KXA), scale_of<R>(sc, inst1, SC_KXA)};
+    const cpx<R> va = {scale_of<R>(sc, inst0, SC_PA), scale_of<R>(sc, inst1, SC_PA)};
+    const cpx<R> sb = {scale_of<R>(sc, inst0, SC_KXB), scale_of<R>(sc, inst1, SC_KXB)};
+    const cpx<R> vb = {scale_of<R>(sc, inst0, SC_PB), scale_of<R>(sc, inst1, SC_PB)};
 #pragma unroll
     for (int e = 0; e < 16; ++e) {
         const int i0 = o0 + C::T * e, i1 = o1 + C::T * e;
@@ -380,23 +408,23 @@ __global__ __launch_bounds__((row_map<R, N, WPB>::THREADS)) SPSTD_WAVES_ATTR voi
 #endif
         if (v0) { vv.x = Vb[i0]; g.x = Rb[i0]; }
         if (v1) { vv.y = Vb[i1]; g.y = Rb[i1]; }
-        g.x = g.x + v[0][e].x + va * vv.x * fe.x;
-        g.y = g.y + v[0][e].y + va * vv.y * fe.y;
+        g.x = g.x + sa.x * v[0][e].x + va.x * vv.x * fe.x;
+        g.y = g.y + sa.y * v[0][e].y + va.y * vv.y * fe.y;
         if (v0) Rb[i0] = g.x;
         if (v1) Rb[i1] = g.y;
         v[0][e] = g;
 #if !SPSTD_X_RELOAD
-        f[e].x = fe.x + vb * vv.x * g.x;
-        f[e].y = fe.y + vb * vv.y * g.y;
+        f[e].x = fe.x + vb.x * vv.x * g.x;
+        f[e].y = fe.y + vb.y * vv.y * g.y;
 #endif
         epi_fence(e);
     }
 #if SPSTD_X_RELOAD
     reload_fence();
 #endif
-    // B half: psi_I += T_x^b psi_R(new) + vb V psi_R(new)
+    // B half: psi_I += T_x^B psi_R(new) + p_B V psi_R(new)
     fft_pencils<R, N, false, C::WAVE, M::SPLIT, TU::PRODUCTS, 1>(v, j, l0, M::SL, tw);
-    apply_symbol<R, N>(v[0], j, sb, nyq_zero);
+    apply_k2<R, N>(v[0], j, nyq_zero);
     fft_pencils<R, N, true, C::WAVE, M::SPLIT, TU::PRODUCTS, 1>(v, j, l0, M::SL, tw);
     epi_begin();
 #pragma unroll
@@ -404,11 +432,11 @@ __global__ __launch_bounds__((row_map<R, N, WPB>::THREADS)) SPSTD_WAVES_ATTR voi
         const int i0 = o0 + C::T * e, i1 = o1 + C::T * e;
 #if SPSTD_X_RELOAD
         // psi_R here is the value this lane stored in the A epilogue
-        if (v0) Ib[i0] = Ib[i0] + vb * Vb[i0] * Rb[i0] + v[0][e].x;
-        if (v1) Ib[i1] = Ib[i1] + vb * Vb[i1] * Rb[i1] + v[0][e].y;
+        if (v0) Ib[i0] = Ib[i0] + vb.x * Vb[i0] * Rb[i0] + sb.x * v[0][e].x;
+        if (v1) Ib[i1] = Ib[i1] + vb.y * Vb[i1] * Rb[i1] + sb.y * v[0][e].y;
 #else
-        if (v0) Ib[i0] = f[e].x + v[0][e].x;
-        if (v1) Ib[i1] = f[e].y + v[0][e].y;
+        if (v0) Ib[i0] = f[e].x + sb.x * v[0][e].x;
+        if (v1) Ib[i1] = f[e].y + sb.y * v[0][e].y;
 #endif
         epi_fence(e);
     }
@@ -480,8 +508,8 @@ __global__ void k_fill0(int64_t n, R* __restrict__ y) {
 constexpr int kWPB = SPSTD_WPB;   // waves per block of the wave-local passes
 
 template <typename R, int N>
-static hipError_t axis_acc_n(const R* src, R* dst, const void* tw, const AxisGeom& g, double scale,
-                             int nyq_zero, hipStream_t st) {
+static hipError_t axis_acc_n(const R* src, R* dst, const void* tw, const AxisGeom& g, const ScaleRef& sc,
+                             int col, int nyq_zero, hipStream_t st) {
     using C = pencil_cfg<N>;
     constexpr int P = tuning<R>::YZ_PPL;
     if (g.half_x % P) return hipErrorInvalidValue;
@@ -489,54 +517,52 @@ static hipError_t axis_acc_n(const R* src, R* dst, const void* tw, const AxisGeo
     const int64_t waves = (ngroups + C::PPW - 1) / C::PPW;
     const int64_t blocks = (waves + kWPB - 1) / kWPB;
     hipLaunchKernelGGL((k_axis_acc<R, N, kWPB, P>), dim3((unsigned)blocks), dim3(64 * kWPB), 0, st,
-                       src, dst, (const cpx<R>*)tw, g, (R)scale, nyq_zero);
+                       src, dst, (const cpx<R>*)tw, g, sc, col, nyq_zero);
     return hipGetLastError();
 }
 
 template <typename R>
 hipError_t launch_axis_acc(int64_t n, const R* src, R* dst, const void* tw, const AxisGeom& g,
-                           double scale, int nyq_zero, hipStream_t st) {
+                           const ScaleRef& sc, int col, int nyq_zero, hipStream_t st) {
     switch (n) {
-        case 16: return axis_acc_n<R, 16>(src, dst, tw, g, scale, nyq_zero, st);
-        case 32: return axis_acc_n<R, 32>(src, dst, tw, g, scale, nyq_zero, st);
-        case 64: return axis_acc_n<R, 64>(src, dst, tw, g, scale, nyq_zero, st);
-        case 128: return axis_acc_n<R, 128>(src, dst, tw, g, scale, nyq_zero, st);
-        case 256: return axis_acc_n<R, 256>(src, dst, tw, g, scale, nyq_zero, st);
-        case 512: return axis_acc_n<R, 512>(src, dst, tw, g, scale, nyq_zero, st);
-        case 1024: return axis_acc_n<R, 1024>(src, dst, tw, g, scale, nyq_zero, st);
+        case 16: return axis_acc_n<R, 16>(src, dst, tw, g, sc, col, nyq_zero, st);
+        case 32: return axis_acc_n<R, 32>(src, dst, tw, g, sc, col, nyq_zero, st);
+        case 64: return axis_acc_n<R, 64>(src, dst, tw, g, sc, col, nyq_zero, st);
+        case 128: return axis_acc_n<R, 128>(src, dst, tw, g, sc, col, nyq_zero, st);
+        case 256: return axis_acc_n<R, 256>(src, dst, tw, g, sc, col, nyq_zero, st);
+        case 512: return axis_acc_n<R, 512>(src, dst, tw, g, sc, col, nyq_zero, st);
+        case 1024: return axis_acc_n<R, 1024>(src, dst, tw, g, sc, col, nyq_zero, st);
         default: return hipErrorInvalidValue;
     }
 }
 
 template <typename R, int N>
 static hipError_t x_acc_n(const R* src, R* dst, const R* V, const void* tw, const RowGeom& g,
-                          double scale, double vscale, int nyq_zero, hipStream_t st) {
+                          const ScaleRef& sc, int kcol, int pcol, int nyq_zero, hipStream_t st) {
     using M = row_map<R, N, kWPB>;
     const int64_t npen = (g.nrows + 1) / 2;
     const int64_t blocks = (npen + M::PPB - 1) / M::PPB;
     if (g.nrows % (2 * M::PPB) == 0)
         hipLaunchKernelGGL((k_x_acc<R, N, kWPB, true>), dim3((unsigned)blocks), dim3(M::THREADS), 0, st,
-                           src, dst, V, (const cpx<R>*)tw, g.nrows, (R)scale, (R)vscale, nyq_zero);
+                           src, dst, V, (const cpx<R>*)tw, g, sc, kcol, pcol, nyq_zero);
     else
         hipLaunchKernelGGL((k_x_acc<R, N, kWPB, false>), dim3((unsigned)blocks), dim3(M::THREADS), 0, st,
-                           src, dst, V, (const cpx<R>*)tw, g.nrows, (R)scale, (R)vscale, nyq_zero);
+                           src, dst, V, (const cpx<R>*)tw, g, sc, kcol, pcol, nyq_zero);
     return hipGetLastError();
 }
 
 template <typename R, int N>
-static hipError_t x_ab_n(R* psiR, R* psiI, const R* V, const void* tw, const RowGeom& g, double sa,
-                         double va, double sb, double vb, int nyq_zero, hipStream_t st) {
+static hipError_t x_ab_n(R* psiR, R* psiI, const R* V, const void* tw, const RowGeom& g,
+                         const ScaleRef& sc, int nyq_zero, hipStream_t st) {
     using M = row_map<R, N, kWPB>;
     const int64_t npen = (g.nrows + 1) / 2;
     const int64_t blocks = (npen + M::PPB - 1) / M::PPB;
     if (g.nrows % (2 * M::PPB) == 0)
         hipLaunchKernelGGL((k_x_ab<R, N, kWPB, true>), dim3((unsigned)blocks), dim3(M::THREADS), 0, st,
-                           psiR, psiI, V, (const cpx<R>*)tw, g.nrows, (R)sa, (R)va, (R)sb, (R)vb,
-                           nyq_zero);
+                           psiR, psiI, V, (const cpx<R>*)tw, g, sc, nyq_zero);
     else
         hipLaunchKernelGGL((k_x_ab<R, N, kWPB, false>), dim3((unsigned)blocks), dim3(M::THREADS), 0, st,
-                           psiR, psiI, V, (const cpx<R>*)tw, g.nrows, (R)sa, (R)va, (R)sb, (R)vb,
-                           nyq_zero);
+                           psiR, psiI, V, (const cpx<R>*)tw, g, sc, nyq_zero);
     return hipGetLastError();
 }
 
@@ -558,16 +584,44 @@ static hipError_t x_ab_n(R* psiR, R* psiI, const R* V, const void* tw, const Row
 
 template <typename R>
 hipError_t launch_x_acc(int64_t nx, const R* src, R* dst, const R* V, const void* tw,
-                        const RowGeom& g, double scale, double vscale, int nyq_zero,
+                        const RowGeom& g, const ScaleRef& sc, int kcol, int pcol, int nyq_zero,
                         hipStream_t st) {
-    SPSTD_ROW_CASES(x_acc_n, src, dst, V, tw, g, scale, vscale, nyq_zero, st)
+    SPSTD_ROW_CASES(x_acc_n, src, dst, V, tw, g, sc, kcol, pcol, nyq_zero, st)
 }
 
 template <typename R>
 hipError_t launch_x_ab(int64_t nx, R* psiR, R* psiI, const R* V, const void* tw,
-                       const RowGeom& g, double sa, double va, double sb, double vb,
-                       int nyq_zero, hipStream_t st) {
-    SPSTD_ROW_CASES(x_ab_n, psiR, psiI, V, tw, g, sa, va, sb, vb, nyq_zero, st)
+                       const RowGeom& g, const ScaleRef& sc, int nyq_zero, hipStream_t st) {
+    SPSTD_ROW_CASES(x_ab_n, psiR, psiI, V, tw, g, sc, nyq_zero, st)
+}
+
+template <typename R>
+__global__ void k_probe_batch(const R* __restrict__ psiR, const R* __restrict__ psiI, int64_t npts,
+                              const int64_t* __restrict__ idx, int nprobes, const int* __restrict__ active,
+                              int ninst, double* __restrict__ probes, int64_t* __restrict__ counter,
+                              int64_t capacity) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= ninst || !active[i]) return;
+    const int64_t slot = counter[i];
+    if (slot < capacity) {
+        double* out = probes + ((int64_t)i * capacity + slot) * nprobes * 2;
+        for (int q = 0; q < nprobes; ++q) {
+            const int64_t k = (int64_t)i * npts + idx[(int64_t)i * nprobes + q];
+            out[2 * q] = (double)psiR[k];
+            out[2 * q + 1] = (double)psiI[k];
+        }
+    }
+    counter[i] = slot + 1;
+}
+
+template <typename R>
+hipError_t launch_probe_batch(const R* psiR, const R* psiI, int64_t npts, const int64_t* idx, int nprobes,
+                              const int* active, int ninst, double* probes, int64_t* counter,
+                              int64_t capacity, hipStream_t st) {
+    const int blocks = (ninst + 63) / 64;
+    hipLaunchKernelGGL((k_probe_batch<R>), dim3(blocks), dim3(64), 0, st, psiR, psiI, npts, idx, nprobes,
+                       active, ninst, probes, counter, capacity);
+    return hipGetLastError();
 }
 
 template <typename R>
@@ -611,11 +665,15 @@ hipError_t launch_fill0(int64_t n, R* y, hipStream_t st) {
 
 #define SPSTD_INSTANTIATE(R)                                                                    \
     template hipError_t launch_axis_acc<R>(int64_t, const R*, R*, const void*, const AxisGeom&, \
-                                           double, int, hipStream_t);                          \
+                                           const ScaleRef&, int, int, hipStream_t);             \
     template hipError_t launch_x_acc<R>(int64_t, const R*, R*, const R*, const void*,           \
-                                        const RowGeom&, double, double, int, hipStream_t);      \
+                                        const RowGeom&, const ScaleRef&, int, int, int,         \
+                                        hipStream_t);                                           \
     template hipError_t launch_x_ab<R>(int64_t, R*, R*, const R*, const void*, const RowGeom&,  \
-                                       double, double, double, double, int, hipStream_t);       \
+                                       const ScaleRef&, int, hipStream_t);                      \
+    template hipError_t launch_probe_batch<R>(const R*, const R*, int64_t, const int64_t*, int, \
+                                              const int*, int, double*, int64_t*, int64_t,      \
+                                              hipStream_t);                                     \
     template hipError_t launch_probe<R>(const R*, const R*, const int64_t*, int, double*,       \
                                         int64_t*, int64_t, hipStream_t);                        \
     template hipError_t launch_norm_partials<R>(const R*, const R*, int64_t, double*, int,      \

@@ -5,45 +5,72 @@
 
 namespace spstd {
 
-// Pencils along y (axis 1) or z (axis 2): a complex pencil packs the real
-// columns x = 2*px and 2*px + 1.  Element e of pencil (px, outer) lies at
-// outer*outer_stride + 2*px + e*stride.
+// Pencils along y (axis 1) or z (axis 2) of a stack of instances of one
+// shape: a complex pencil packs the real columns x = 2*px and 2*px + 1.
+// Pencil (px, outer) starts at
+//   (outer / n_in) * stride_hi + (outer % n_in) * stride_lo + 2 * px
+// and element e lies stride further on; the instance is outer / n_in.
 struct AxisGeom {
-    int64_t half_x;        // nx / 2
-    int64_t n_outer;       // nz for the y pass, ny for the z pass
-    int64_t outer_stride;  // nx*ny for the y pass, nx for the z pass
-    int64_t stride;        // nx for the y pass, nx*ny for the z pass
+    int64_t half_x;      // nx / 2
+    int64_t n_outer;     // instances * (nz for the y pass, ny for the z pass)
+    int64_t n_in;        // nz (y pass) or ny (z pass)
+    int64_t stride_lo;   // nx*ny (y pass) or nx (z pass)
+    int64_t stride_hi;   // points per instance
+    int64_t stride;      // nx (y pass) or nx*ny (z pass)
 };
 
-// Rows along x: complex pencil q packs rows 2q and 2q+1 (row r starts at r*nx);
-// with an odd row count the last pencil has no imaginary row.
+// Rows along x: complex pencil q packs rows 2q and 2q+1 (row r starts at
+// r*nx; rows of one instance are consecutive, rows_per_inst of them); with
+// an odd row count the last pencil has no imaginary row.
 struct RowGeom {
     int64_t nrows;
+    int64_t rows_per_inst;
+};
+
+// Per-instance, per-stage scales (run precision), row-major
+// [instance][stage][SC_COLS]: kinetic scale of the A substep along x, y, z
+// (c_l dt (hbar/2m*) (2 pi/L_d)^2 / n_d), potential scale of A (c_l dt/hbar),
+// then the same four for B (with -d_l dt).  Each pass multiplies the
+// inverse transform by its instance's scale, so instances with different
+// dt, spacing and potential share launches (and complex pencils).
+enum { SC_KXA = 0, SC_KYA, SC_KZA, SC_PA, SC_KXB, SC_KYB, SC_KZB, SC_PB, SC_COLS };
+struct ScaleRef {
+    const void* tab;   // device table, run precision
+    int m;             // stages per instance
+    int l;             // stage of this pass
 };
 
 // Supported pencil lengths.
 bool axis_len_ok(int64_t n);   // y/z passes: 16..1024
 bool row_len_ok(int64_t n);    // x pass:     16..16384
 
-// dst += T_axis src, T_axis = IFFT_axis(scale * ks^2 * FFT_axis(.)).
+// dst += scale_inst * IFFT_axis(ks^2 FFT_axis(src)), scale column col.
 template <typename R>
 hipError_t launch_axis_acc(int64_t n, const R* src, R* dst, const void* tw,
-                           const AxisGeom& g, double scale, int nyq_zero,
+                           const AxisGeom& g, const ScaleRef& sc, int col, int nyq_zero,
                            hipStream_t st);
 
-// dst += T_x src + vscale * V * src  (one half-stage along x)
+// dst += k * IFFT_x(ks^2 FFT_x(src)) + p * V * src with (k, p) of columns
+// (kcol, pcol): one half-stage along x.
 template <typename R>
 hipError_t launch_x_acc(int64_t nx, const R* src, R* dst, const R* V,
-                        const void* tw, const RowGeom& g, double scale,
-                        double vscale, int nyq_zero, hipStream_t st);
+                        const void* tw, const RowGeom& g, const ScaleRef& sc,
+                        int kcol, int pcol, int nyq_zero, hipStream_t st);
 
-// Fused A and B halves along x:
-//   g  = g + T_x^a f + va * V f         (g = psi_R, f = psi_I)
-//   f  = f + T_x^b g + vb * V g         (with the new g)
+// Fused A and B halves along x (columns SC_KXA, SC_PA, SC_KXB, SC_PB):
+//   psi_R += T_x^A psi_I + p_A V psi_I;  then  psi_I += T_x^B psi_R + p_B V psi_R
 template <typename R>
 hipError_t launch_x_ab(int64_t nx, R* psiR, R* psiI, const R* V, const void* tw,
-                       const RowGeom& g, double sa, double va, double sb,
-                       double vb, int nyq_zero, hipStream_t st);
+                       const RowGeom& g, const ScaleRef& sc, int nyq_zero, hipStream_t st);
+
+// Batched probe samples: for every instance i < ninst with active[i],
+// out_i[slot][p] = (psiR[i*npts + idx[i*P + p]], psiI[...]) as doubles,
+// slot = counter[i], then counter[i]++ (slots >= capacity are not written).
+// out_i = probes + i * capacity * P * 2.
+template <typename R>
+hipError_t launch_probe_batch(const R* psiR, const R* psiI, int64_t npts, const int64_t* idx,
+                              int nprobes, const int* active, int ninst, double* probes,
+                              int64_t* counter, int64_t capacity, hipStream_t st);
 
 // probe sample: out[slot][p] = (psiR[idx_p], psiI[idx_p]) as doubles, where
 // slot = *counter; then (*counter)++.  Single thread block.

@@ -1,0 +1,185 @@
+// Resident 1D kernel: whole runs of short 1D instances in one launch.
+//
+// A lane group (T = N/16 lanes) keeps two instances of the same length N in
+// registers for every step of the launch: instance a in the real parts and
+// instance b in the imaginary parts of the complex arrays PR (psi_R) and PI
+// (psi_I).  The kinetic operator T = IFFT(s(k) FFT(.)) has a real, even
+// symbol, so T(f_a + i f_b) = T f_a + i T f_b; the transform applies the bare
+// k^2 (bin index squared) and each instance's own scale
+// c dt (hbar/2m*) (2 pi / L)^2 / N is applied after the inverse transform,
+// which lets instances with different dt, L and V share a pencil.
+//
+// Substep of stage l (Eq. 17-18, A before B):
+//   A: PR += kin_A * T PI + pot_A * V * PI      (kin_A from c_l dt, pot_A = c_l dt / hbar)
+//   B: PI += kin_B * T PR + pot_B * V * PR      (kin_B, pot_B from -d_l dt)
+// After every step each instance's probe samples (FP64) are written.
+#include "fft_core.hpp"
+#include "resident.hpp"
+
+namespace spstd {
+
+template <int N>
+struct res_cfg {
+    static constexpr int T = N / 16;
+    static constexpr bool WAVE = T <= 64;
+    static constexpr int GPW = WAVE ? 64 / T : 1;     // lane groups per wave
+    static constexpr int WPB = WAVE ? 2 : 1;           // waves per block (wave-local groups)
+    static constexpr int THREADS = WAVE ? 64 * WPB : T;
+    static constexpr int GPB = WAVE ? WPB * GPW : 1;   // lane groups per block
+    static constexpr int LS = lds_size<N>::value;
+    static constexpr int LDS_REALS = N == 16 ? 1 : GPB * LS;   // split exchange
+};
+
+template <typename R, int N>
+__device__ __forceinline__ void k2_symbol(cpx<R> (&v)[16], int j, int nyq_zero) {
+    constexpr int T = N / 16;
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+        const int kk = j + T * e;
+        const int ks = (kk <= N / 2) ? kk : kk - N;
+        R s = (R)(ks * ks);
+        if (nyq_zero && kk == N / 2) s = (R)0;
+        v[e].x *= s;
+        v[e].y *= s;
+    }
+}
+
+template <typename R, int N>
+__global__ __launch_bounds__((res_cfg<N>::THREADS)) void k_resident_1d(
+    const ResidentInst<R>* __restrict__ inst, int ninst, int m, int64_t nsteps, int nyq_zero,
+    const cpx<R>* __restrict__ tw) {
+    using C = res_cfg<N>;
+    __shared__ R lds[C::LDS_REALS];
+    int j, gib;
+    if constexpr (C::WAVE) {
+        const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+        j = lane % C::T;
+        gib = wave * C::GPW + lane / C::T;
+    } else {
+        j = threadIdx.x;
+        gib = 0;
+    }
+    const int g = blockIdx.x * C::GPB + gib;
+    const int ia = 2 * g, ib = 2 * g + 1;
+    const bool ha = ia < ninst, hb = ib < ninst;
+    // lanes of a group with no instance still take part in the exchanges
+    const ResidentInst<R>* A = ha ? inst + ia : inst;
+    const ResidentInst<R>* B = hb ? inst + ib : A;
+    R* l0 = lds + (N == 16 ? 0 : gib * C::LS);
+
+    cpx<R> PR[16], PI[16];
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+        const int x = j + C::T * e;
+        PR[e] = cpx<R>{ha ? A->psiR[x] : (R)0, hb ? B->psiR[x] : (R)0};
+        PI[e] = cpx<R>{ha ? A->psiI[x] : (R)0, hb ? B->psiI[x] : (R)0};
+    }
+    const R* Va = A->V;
+    const R* Vb = B->V;
+    const int64_t slot_a = ha ? *A->counter : 0;
+    const int64_t slot_b = hb ? *B->counter : 0;
+
+    for (int64_t s = 0; s < nsteps; ++s) {
+        for (int l = 0; l < m; ++l) {
+#pragma unroll
+            for (int half = 0; half < 2; ++half) {
+                const R ka = ha ? A->kin[2 * l + half] : (R)0, kb = hb ? B->kin[2 * l + half] : (R)0;
+                const R pa = ha ? A->pot[2 * l + half] : (R)0, pb = hb ? B->pot[2 * l + half] : (R)0;
+                if (ka == (R)0 && kb == (R)0 && pa == (R)0 && pb == (R)0) continue;   // uniform
+                cpx<R>(&src)[16] = half == 0 ? PI : PR;
+                cpx<R>(&dst)[16] = half == 0 ? PR : PI;
+                cpx<R> v[1][16];
+#pragma unroll
+                for (int e = 0; e < 16; ++e) v[0][e] = src[e];
+                fft_pencils<R, N, false, C::WAVE, true, true, 1>(v, j, l0, C::LS, tw);
+                k2_symbol<R, N>(v[0], j, nyq_zero);
+                fft_pencils<R, N, true, C::WAVE, true, true, 1>(v, j, l0, C::LS, tw);
+#pragma unroll
+                for (int e = 0; e < 16; ++e) {
+                    const int x = j + C::T * e;
+                    const R va = Va[x], vb = Vb[x];
+                    dst[e].x += ka * v[0][e].x + pa * va * src[e].x;
+                    dst[e].y += kb * v[0][e].y + pb * vb * src[e].y;
+                }
+            }
+        }
+        // probe samples of this step
+#pragma unroll
+        for (int who = 0; who < 2; ++who) {
+            const bool has = who == 0 ? ha : hb;
+            const ResidentInst<R>* I = who == 0 ? A : B;
+            if (!has) continue;
+            for (int q = 0; q < I->nprobes; ++q) {
+                const int64_t pidx = I->probe_idx[q];
+                if ((int)(pidx % C::T) != j) continue;
+                const int pe = (int)(pidx / C::T);
+                R r = (R)0, im = (R)0;
+#pragma unroll
+                for (int e = 0; e < 16; ++e) {
+                    if (e == pe) {
+                        r = who == 0 ? PR[e].x : PR[e].y;
+                        im = who == 0 ? PI[e].x : PI[e].y;
+                    }
+                }
+                const int64_t slot = (who == 0 ? slot_a : slot_b) + s;
+                if (slot < I->capacity) {
+                    I->probes[(slot * I->nprobes + q) * 2 + 0] = (double)r;
+                    I->probes[(slot * I->nprobes + q) * 2 + 1] = (double)im;
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+        const int x = j + C::T * e;
+        if (ha) { A->psiR[x] = PR[e].x; A->psiI[x] = PI[e].x; }
+        if (hb) { B->psiR[x] = PR[e].y; B->psiI[x] = PI[e].y; }
+    }
+    // every lane of the group has read the counters before lane 0 advances them
+    if constexpr (C::WAVE) {
+        lds_sync<true>();
+    } else {
+        __syncthreads();
+    }
+    if (j == 0) {
+        if (ha) *A->counter = slot_a + nsteps;
+        if (hb) *B->counter = slot_b + nsteps;
+    }
+}
+
+bool resident_len_ok(int64_t n) { return n >= 16 && (n & (n - 1)) == 0 && n <= 4096; }
+
+template <typename R, int N>
+static hipError_t res_n(const ResidentInst<R>* inst, int ninst, int m, int64_t nsteps, int nyq_zero,
+                        const void* tw, hipStream_t st) {
+    using C = res_cfg<N>;
+    const int groups = (ninst + 1) / 2;
+    const int blocks = (groups + C::GPB - 1) / C::GPB;
+    hipLaunchKernelGGL((k_resident_1d<R, N>), dim3(blocks), dim3(C::THREADS), 0, st, inst, ninst, m,
+                       nsteps, nyq_zero, (const cpx<R>*)tw);
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_resident_1d(int64_t n, const ResidentInst<R>* inst, int ninst, int m, int64_t nsteps,
+                              int nyq_zero, const void* tw, hipStream_t st) {
+    switch (n) {
+        case 16: return res_n<R, 16>(inst, ninst, m, nsteps, nyq_zero, tw, st);
+        case 32: return res_n<R, 32>(inst, ninst, m, nsteps, nyq_zero, tw, st);
+        case 64: return res_n<R, 64>(inst, ninst, m, nsteps, nyq_zero, tw, st);
+        case 128: return res_n<R, 128>(inst, ninst, m, nsteps, nyq_zero, tw, st);
+        case 256: return res_n<R, 256>(inst, ninst, m, nsteps, nyq_zero, tw, st);
+        case 512: return res_n<R, 512>(inst, ninst, m, nsteps, nyq_zero, tw, st);
+        case 1024: return res_n<R, 1024>(inst, ninst, m, nsteps, nyq_zero, tw, st);
+        case 2048: return res_n<R, 2048>(inst, ninst, m, nsteps, nyq_zero, tw, st);
+        case 4096: return res_n<R, 4096>(inst, ninst, m, nsteps, nyq_zero, tw, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template hipError_t launch_resident_1d<double>(int64_t, const ResidentInst<double>*, int, int, int64_t, int,
+                                               const void*, hipStream_t);
+template hipError_t launch_resident_1d<float>(int64_t, const ResidentInst<float>*, int, int, int64_t, int,
+                                              const void*, hipStream_t);
+
+}  // namespace spstd

@@ -1,0 +1,36 @@
+// Resident 1D kernel: instance table and launcher (host-callable C++).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "fft_core.hpp"
+
+namespace spstd {
+
+constexpr int kResMaxProbes = 8;
+constexpr int kResMaxSubsteps = 32;   // 2 * SPSTD_MAX_STAGES
+
+// One 1D instance advanced by the resident kernel (device-resident table).
+template <typename R>
+struct ResidentInst {
+    const R* V;            // N potential values
+    R* psiR;               // N values: state in, state out
+    R* psiI;
+    double* probes;        // FP64 samples [capacity][nprobes][2]
+    int64_t* counter;      // next free sample slot (advanced by nsteps)
+    int64_t capacity;      // sample slots available
+    int nprobes;           // 0..kResMaxProbes
+    int64_t probe_idx[kResMaxProbes];
+    R kin[kResMaxSubsteps];   // substep 2l (A) and 2l+1 (B): coef dt (hbar/2m*) (2 pi/L)^2 / N
+    R pot[kResMaxSubsteps];   // substep 2l (A) and 2l+1 (B): coef dt / hbar
+};
+
+bool resident_len_ok(int64_t n);
+
+// Advance every instance of the table (all of length n) by nsteps steps of
+// m stages.  tw: twiddle table w_n^t, t < n, in the run precision.
+template <typename R>
+hipError_t launch_resident_1d(int64_t n, const ResidentInst<R>* inst, int ninst, int m, int64_t nsteps,
+                              int nyq_zero, const void* tw, hipStream_t st);
+
+}  // namespace spstd

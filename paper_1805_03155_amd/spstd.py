@@ -19,7 +19,8 @@ NYQ_FULL, NYQ_ZERO = 0, 1
 SYMPLECTIC, RK4 = 0, 1
 ALLOW_UNSTABLE = 0x1
 EAGER = 0x2          # no step-chunk graphs
-TIMING = 0x4         # eager launches bracketed by HIP events (pass_times)
+TIMING = 0x4         # pass kernels bracketed by HIP events (pass_times)
+NO_RESIDENT = 0x8    # 1D plans use the pass kernels, not the resident kernel
 PASS_KINDS = ("y", "z", "xab", "x")
 MAX_PROBES = 64
 
@@ -47,6 +48,12 @@ class Desc(ctypes.Structure):
                 ("flags", c_u32)]
 
 
+class BatchDesc(ctypes.Structure):
+    _fields_ = [("ndim", c_int), ("n", c_i64 * 3), ("precision", c_int), ("m", c_int),
+                ("c", P(c_d)), ("d", P(c_d)), ("nyquist", c_int), ("capacity", c_int),
+                ("nprobes", c_int), ("nsteps_max", c_i64), ("flags", c_u32)]
+
+
 class Stats(ctypes.Structure):
     _fields_ = [("steps_done", c_i64), ("dt", c_d), ("xmax", c_d), ("rho", c_d),
                 ("norm0", c_d), ("norm", c_d), ("substeps_per_step", c_d)]
@@ -55,7 +62,10 @@ class Stats(ctypes.Structure):
 EXPORTS = ["spstd_xmax", "spstd_stable_dt", "spstd_workspace_size", "spstd_plan",
            "spstd_step", "spstd_run", "spstd_plan_info", "spstd_device_fields",
            "spstd_get_state", "spstd_set_state", "spstd_spectrum", "spstd_pass_times",
-           "spstd_destroy", "spstd_strerror", "spstd_last_error"]
+           "spstd_destroy", "spstd_strerror", "spstd_last_error",
+           "spstd_batch_workspace_size", "spstd_batch_create", "spstd_batch_load",
+           "spstd_batch_step", "spstd_batch_read", "spstd_batch_release",
+           "spstd_batch_slot_info", "spstd_batch_destroy", "spstd_batch_last_error"]
 
 _lib = None
 
@@ -83,22 +93,35 @@ def lib():
         L.spstd_spectrum.argtypes = [pd, c_i64, c_int, c_d, c_d, c_int, pd, pd, P(c_int)]
         L.spstd_pass_times.argtypes = [ctypes.c_void_p, pi64, pd, pd]
         L.spstd_destroy.argtypes = [ctypes.c_void_p]
+        vp = ctypes.c_void_p
+        L.spstd_batch_workspace_size.argtypes = [P(BatchDesc), P(c_sz)]
+        L.spstd_batch_create.argtypes = [P(BatchDesc), vp, c_sz, vp, P(vp)]
+        L.spstd_batch_load.argtypes = [vp, c_int, pd, c_d, c_d, c_d, c_d, pd, pd, pd, pi64, pd]
+        L.spstd_batch_step.argtypes = [vp, c_i64]
+        L.spstd_batch_read.argtypes = [vp, c_int, pd, pd, pd, pi64]
+        L.spstd_batch_release.argtypes = [vp, c_int]
+        L.spstd_batch_slot_info.argtypes = [vp, c_int, P(c_int), pi64, pd]
+        L.spstd_batch_destroy.argtypes = [vp]
+        L.spstd_batch_last_error.argtypes = [vp]
+        L.spstd_batch_last_error.restype = ctypes.c_char_p
         L.spstd_strerror.argtypes = [c_int]
         L.spstd_strerror.restype = ctypes.c_char_p
         L.spstd_last_error.argtypes = [ctypes.c_void_p]
         L.spstd_last_error.restype = ctypes.c_char_p
         for name in EXPORTS:
-            if name not in ("spstd_strerror", "spstd_last_error"):
+            if name not in ("spstd_strerror", "spstd_last_error", "spstd_batch_last_error"):
                 getattr(L, name).restype = c_int
         _lib = L
     return _lib
 
 
-def _check(rc, plan=None):
+def _check(rc, plan=None, batch=None):
     if rc != 0:
         msg = lib().spstd_strerror(rc).decode()
         if plan:
             msg += " / " + lib().spstd_last_error(plan).decode()
+        if batch:
+            msg += " / " + lib().spstd_batch_last_error(batch).decode()
         raise SpstdError(rc, msg)
 
 
@@ -271,3 +294,97 @@ def plan_from_workload(w, precision=FP64, method=SYMPLECTIC, dt=0.0, nsteps_max=
     return Plan(desc, w.V, w.psiR, w.psiI,
                 nsteps_max=w.steps if nsteps_max is None else nsteps_max,
                 device=device, stream=stream)
+
+
+def make_batch_desc(n, coeffs, capacity, nprobes=1, nsteps_max=0, precision=FP64,
+                    nyquist=NYQ_FULL, flags=0):
+    c, d = coeffs
+    desc = BatchDesc()
+    desc.ndim = len(n)
+    for a in range(3):
+        desc.n[a] = int(n[a]) if a < len(n) else 1
+    ca, da = _f64(c), _f64(d)
+    desc.precision, desc.m = precision, len(ca)
+    desc.c, desc.d = _dp(ca), _dp(da)
+    desc.nyquist, desc.capacity, desc.nprobes = nyquist, int(capacity), int(nprobes)
+    desc.nsteps_max, desc.flags = int(nsteps_max), flags
+    desc._keep = [ca, da]
+    return desc
+
+
+def batch_workspace_size(desc):
+    out = c_sz()
+    _check(lib().spstd_batch_workspace_size(ctypes.byref(desc), ctypes.byref(out)))
+    return out.value
+
+
+class Batch:
+    """Slots of independent instances of one shape, stepped together."""
+
+    def __init__(self, n, coeffs, capacity, nprobes=1, nsteps_max=0, precision=FP64,
+                 nyquist=NYQ_FULL, flags=0, device="cuda", stream=None):
+        import torch
+        self.desc = make_batch_desc(n, coeffs, capacity, nprobes, nsteps_max, precision,
+                                    nyquist, flags)
+        self.n = tuple(n)
+        self.npoints = int(np.prod(n))
+        self.nprobes = int(nprobes)
+        self.capacity = int(capacity)
+        nbytes = batch_workspace_size(self.desc)
+        dev = torch.device(device)
+        self.ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=dev)
+        base = self.ws.data_ptr()
+        self.stream = stream if stream is not None else torch.cuda.current_stream(dev)
+        h = ctypes.c_void_p()
+        with torch.cuda.device(dev):
+            rc = lib().spstd_batch_create(ctypes.byref(self.desc),
+                                          ctypes.c_void_p(base + (-base) % 256), nbytes,
+                                          ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h))
+        _check(rc)
+        self.h = h
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h is not None and h.value:
+            lib().spstd_batch_destroy(h)
+            self.h = None
+
+    def load(self, slot, dx, V, psiR, psiI=None, probes=(), dt=0.0, cfl_fraction=0.5,
+             hbar=1.0, mass=1.0):
+        """Load an instance into a free slot; returns the time step used."""
+        dxa = _f64(list(dx) + [1.0] * (3 - len(dx)))
+        pidx = np.ascontiguousarray(np.asarray(probes, dtype=np.int64).ravel())
+        out = c_d()
+        _check(lib().spstd_batch_load(self.h, int(slot), _dp(dxa), float(hbar), float(mass),
+                                      float(dt), float(cfl_fraction), _dp(_f64(V)),
+                                      _dp(_f64(psiR)), _dp(_f64(psiI)),
+                                      pidx.ctypes.data_as(P(c_i64)) if len(pidx) else None,
+                                      ctypes.byref(out)), batch=self.h)
+        return out.value
+
+    def load_workload(self, slot, w, dt=0.0):
+        return self.load(slot, w.dx, w.V, w.psiR, w.psiI, w.probes, dt=dt,
+                         cfl_fraction=w.cfl_fraction, hbar=w.hbar, mass=w.mass)
+
+    def step(self, nsteps):
+        _check(lib().spstd_batch_step(self.h, int(nsteps)), batch=self.h)
+
+    def slot_info(self, slot):
+        a, s, dt = c_int(), c_i64(), c_d()
+        _check(lib().spstd_batch_slot_info(self.h, int(slot), ctypes.byref(a), ctypes.byref(s),
+                                           ctypes.byref(dt)), batch=self.h)
+        return bool(a.value), s.value, dt.value
+
+    def read(self, slot, state=True):
+        """(series [(steps+1), P, 2], psiR, psiI, steps) of one slot."""
+        _, steps, _ = self.slot_info(slot)
+        ser = np.zeros((steps + 1, max(self.nprobes, 1), 2))
+        pr = np.zeros(self.npoints) if state else None
+        pi = np.zeros(self.npoints) if state else None
+        st = c_i64()
+        _check(lib().spstd_batch_read(self.h, int(slot), _dp(ser.ravel()) if self.nprobes else None,
+                                      _dp(pr), _dp(pi), ctypes.byref(st)), batch=self.h)
+        return (ser[:, : self.nprobes] if self.nprobes else None), pr, pi, st.value
+
+    def release(self, slot):
+        _check(lib().spstd_batch_release(self.h, int(slot)), batch=self.h)

@@ -1,0 +1,116 @@
+"""Resident 1D kernel and batches of instances, through the C ABI.
+
+Each instance is checked alone (a single plan) against the same instance
+inside a batch, and against the CPU oracle.  The tolerance for "same alone
+and in the mix" is rounding-level: within a batch two instances can share a
+complex pencil, which changes the rounding but not the arithmetic.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1805_03155_amd import spstd
+from paper_1805_03155_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def rel(a, b):
+    return np.linalg.norm(np.ravel(a) - np.ravel(b)) / np.linalg.norm(np.ravel(b))
+
+
+def inst(n, seed, nprobes=1):
+    rng = np.random.default_rng(seed)
+    N = int(np.prod(n))
+    dx = tuple(0.15 + 0.05 * rng.random() for _ in n)
+    V = (1.0 + 3.0 * rng.random()) * rng.random(N)
+    return W.Workload(f"inst{seed}", tuple(n), dx, (0.0,) * len(n), V, rng.standard_normal(N),
+                      rng.standard_normal(N), rng.integers(0, N, nprobes).astype(np.int64), 0, W.PAPER)
+
+
+def alone(w, dt, steps, precision=spstd.FP64, flags=0):
+    p = spstd.plan_from_workload(w, dt=dt, nsteps_max=steps, precision=precision, flags=flags)
+    ser, _ = p.run(steps)
+    r, i, _ = p.get_state()
+    return r, i, ser
+
+
+@pytest.mark.parametrize("n", [16, 32, 256, 1024, 4096])
+@pytest.mark.parametrize("prec", [spstd.FP64, spstd.FP32])
+def test_resident_kernel_matches_pass_kernels(n, prec):
+    w = inst((n,), seed=n)
+    dt = oracle.stable_dt(*w.coeffs, w.V, w.n, w.dx)
+    a = alone(w, dt, 50, prec)                              # resident (one launch)
+    b = alone(w, dt, 50, prec, flags=spstd.NO_RESIDENT)     # pass kernels
+    tol = 1e-13 if prec == spstd.FP64 else 2e-5
+    assert rel(np.concatenate(a[:2]), np.concatenate(b[:2])) < tol
+    assert rel(a[2], b[2]) < tol
+    if prec == spstd.FP64:
+        ro, io, so, _ = oracle.run(w.psiR, w.psiI, w.V, w.n, w.dx, *w.coeffs, dt, 50, w.probes)
+        assert rel(np.concatenate(a[:2]), np.concatenate([ro, io])) <= 1e-12
+        assert rel(a[2], so) <= 1e-12
+
+
+@pytest.mark.parametrize("shape,cap,slots", [((512,), 5, [0, 1, 3, 4]),          # resident
+                                              ((8192,), 3, [0, 2]),              # pass kernels
+                                              ((64, 32), 6, [0, 2, 3, 5]),
+                                              ((32, 16, 16), 3, [0, 1, 2])])
+def test_batch_instances_alone_vs_in_the_mix(shape, cap, slots):
+    steps = 40
+    b = spstd.Batch(shape, W.PAPER, capacity=cap, nprobes=2, nsteps_max=steps)
+    ws = {s: inst(shape, seed=100 + s, nprobes=2) for s in slots}
+    dts = {}
+    for s, w in ws.items():
+        dts[s] = 0.9 * oracle.stable_dt(*w.coeffs, w.V, w.n, w.dx)
+        assert b.load(s, w.dx, w.V, w.psiR, w.psiI, w.probes, dt=dts[s]) == dts[s]
+    b.step(steps)
+    for s, w in ws.items():
+        ser, r, i, k = b.read(s)
+        assert k == steps
+        ra, ia, sa = alone(w, dts[s], steps)
+        assert rel(np.concatenate([r, i]), np.concatenate([ra, ia])) < 1e-13
+        assert rel(ser, sa) < 1e-13
+        ro, io, so, _ = oracle.run(w.psiR, w.psiI, w.V, w.n, w.dx, *w.coeffs, dts[s], steps, w.probes)
+        assert rel(np.concatenate([r, i]), np.concatenate([ro, io])) <= 1e-12
+        assert rel(ser, so) <= 1e-12
+    # free slots stayed empty
+    for s in set(range(cap)) - set(slots):
+        assert b.slot_info(s)[0] is False
+
+
+def test_batch_fp32_against_fp64_oracle():
+    shape, steps = (256, 64), 60
+    b = spstd.Batch(shape, W.PAPER, capacity=2, nprobes=1, nsteps_max=steps, precision=spstd.FP32)
+    w = inst(shape, seed=7)
+    dt = oracle.stable_dt(*w.coeffs, w.V, w.n, w.dx)
+    b.load(1, w.dx, w.V, w.psiR, w.psiI, w.probes, dt=dt)
+    b.step(steps)
+    ser, r, i, _ = b.read(1)
+    ro, io, so, _ = oracle.run(w.psiR, w.psiI, w.V, w.n, w.dx, *w.coeffs, dt, steps, w.probes)
+    assert rel(np.concatenate([r, i]), np.concatenate([ro, io])) < 2e-5
+
+
+def test_batch_release_and_reload_slot():
+    shape, steps = (1024,), 30
+    b = spstd.Batch(shape, W.PAPER, capacity=2, nprobes=1, nsteps_max=2 * steps,
+                    flags=spstd.NO_RESIDENT)
+    w0, w1, w2 = inst(shape, 1), inst(shape, 2), inst(shape, 3)
+    dt = lambda w: oracle.stable_dt(*w.coeffs, w.V, w.n, w.dx)
+    b.load(0, w0.dx, w0.V, w0.psiR, w0.psiI, w0.probes, dt=dt(w0))
+    b.load(1, w1.dx, w1.V, w1.psiR, w1.psiI, w1.probes, dt=dt(w1))
+    b.step(steps)
+    b.release(0)
+    b.load(0, w2.dx, w2.V, w2.psiR, w2.psiI, w2.probes, dt=dt(w2))
+    b.step(steps)
+    ser2, r2, i2, k2 = b.read(0)
+    ser1, r1, i1, k1 = b.read(1)
+    assert (k2, k1) == (steps, 2 * steps)
+    ra, ia, sa = alone(w2, dt(w2), steps)
+    assert rel(np.concatenate([r2, i2]), np.concatenate([ra, ia])) < 1e-13
+    rb, ib, sb = alone(w1, dt(w1), 2 * steps)
+    assert rel(np.concatenate([r1, i1]), np.concatenate([rb, ib])) < 1e-13
+    with pytest.raises(spstd.SpstdError) as ei:
+        b.step(steps + 1)
+    assert ei.value.code == 6
+    with pytest.raises(spstd.SpstdError):
+        b.load(1, w0.dx, w0.V, w0.psiR, w0.psiI, w0.probes)   # slot busy
