@@ -26,6 +26,9 @@ import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
+# the serving leg runs one stream per request class; give HIP enough hardware
+# queues that classes do not wait behind each other (set before HIP starts)
+os.environ.setdefault("GPU_MAX_HW_QUEUES", "16")
 
 METRIC = "grid-point stage updates/s (3D HO 256³, FP64 vs FP32); p50/p99 solve latency"
 HBM_PEAK_GBS = 8000.0
@@ -127,6 +130,36 @@ def cpu_baseline(w, steps):
                       f"oracle run, {el:.1f} s wall"}
 
 
+def batching_leg(count, steps, seed=0):
+    """The batching workload: `count` seeded 1D/2D instances of uneven sizes
+    (1D 2^7..2^14, 2D 32^2..512^2, square or harmonic wells), FP32 fields
+    with FP64 probes, paper coefficient set; one batch per shape."""
+    from paper_1805_03155_amd import batching, spstd
+    from paper_1805_03155_amd import workloads as W
+    inst = W.batch_instances(count=count, seed=seed, steps=steps)
+    _, st = batching.run_instances(inst, steps, precision=spstd.FP32)
+    return {"value": st["stage_updates_per_s"], "unit": "stage updates/s", "instances": count,
+            "steps": steps, "points": st["points"], "elapsed_s": st["elapsed_s"],
+            "shape_groups": len(st["groups"]), "dtype": "f32 fields, f64 probes"}
+
+
+def serving_leg(count, rate, steps, seed=0, budget_gb=64):
+    """Poisson arrivals of eigenvalue-solve requests (1D 1024..16384 points
+    or 3D 32^3..128^3, 80/20; FP32 or FP64; square or harmonic wells), served
+    with continuous batching under an HBM budget."""
+    from paper_1805_03155_amd import serve
+    reqs = serve.request_mix(count, rate, seed=seed, steps=steps)
+    srv = serve.Server(hbm_budget=budget_gb << 30, chunk=512, max_slots=64,
+                       max_steps=steps[1], keep_series=False)
+    t0 = time.perf_counter()
+    srv.run(reqs)
+    el = time.perf_counter() - t0
+    out = serve.latency_summary(reqs, el, srv.stage_updates)
+    out.update({"rate_per_s": rate, "steps_range": list(steps), "budget_GB": budget_gb,
+                "peak_workspace_GB": srv.peak_used / 2 ** 30, "elapsed_s": el})
+    return out
+
+
 def pmc_sample(w, steps):
     """Short run for hardware-counter passes: a plain device copy of a known
     size (the calibration of FETCH_SIZE / WRITE_SIZE), then a few eager
@@ -156,6 +189,11 @@ def main():
     ap.add_argument("--n", type=int, default=256, help="grid points per axis")
     ap.add_argument("--cpu-baseline", choices=["on", "off"], default="on")
     ap.add_argument("--cpu-steps", type=int, default=5)
+    ap.add_argument("--batch-steps", type=int, default=500,
+                    help="steps of the 512-instance batching leg (0: skip)")
+    ap.add_argument("--serve-requests", type=int, default=40,
+                    help="requests of the serving leg (0: skip)")
+    ap.add_argument("--serve-rate", type=float, default=10.0)
     ap.add_argument("--pmc-sample", action="store_true",
                     help="short run for rocprofv3 counter passes (no timing output)")
     args = ap.parse_args()
@@ -177,6 +215,15 @@ def main():
     for prec in ("fp64", "fp32"):
         log(f"{prec}: warmup {args.warmup}, timed {args.steps} steps")
         res[prec] = run_precision(w, prec, args.steps, args.warmup)
+    batch = serving = None
+    if args.batch_steps > 0:
+        log(f"batching leg: 512 instances, {args.batch_steps} steps")
+        batch = batching_leg(512, args.batch_steps)
+        log(f"batching: {batch['value']:.3e} stage updates/s")
+    if args.serve_requests > 0:
+        log(f"serving leg: {args.serve_requests} requests at {args.serve_rate}/s")
+        serving = serving_leg(args.serve_requests, args.serve_rate, (2000, 20000))
+        log(f"serving: p50 {serving['p50_s']:.2f} s, p99 {serving['p99_s']:.2f} s")
     cpu = None
     if args.cpu_baseline == "on":
         log("timing the CPU oracle on a bounded sample")
@@ -204,6 +251,8 @@ def main():
         "cpu_baseline": cpu,
         "kernels": r64["kernels"],
         "graph_mode": r64["graph_mode"],
+        "batching": batch,
+        "serving": serving,
         "fp32": {"value": r32["value"], "ms_per_step": r32["ms_per_step"], "dtype": "f32",
                  "roofline": r32["roofline"], "kernels": r32["kernels"],
                  "graph_mode": r32["graph_mode"],

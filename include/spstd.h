@@ -50,8 +50,8 @@ enum { SPSTD_SYMPLECTIC = 0, SPSTD_RK4 = 1 };        /* time integrator */
 #define SPSTD_ALLOW_UNSTABLE 0x1u                    /* flags: accept dt beyond the edge */
 #define SPSTD_EAGER 0x2u                             /* flags: launch kernels one by one
                                                         instead of replaying step-chunk graphs */
-#define SPSTD_TIMING 0x4u                            /* flags: each pass kernel (eager or in the
-                                                        step graph) bracketed by HIP events */
+#define SPSTD_TIMING 0x4u                            /* flags: eager launches, each pass kernel
+                                                        bracketed by HIP events (spstd_pass_times) */
 #define SPSTD_NO_RESIDENT 0x8u                       /* flags: 1D plans use the pass kernels
                                                         even where the resident kernel applies */
 #define SPSTD_MAX_STAGES 16
@@ -222,8 +222,7 @@ enum { SPSTD_PASS_Y = 0, SPSTD_PASS_Z = 1, SPSTD_PASS_XAB = 2, SPSTD_PASS_X = 3,
  * plan's stream and returns, for each kind k < SPSTD_NPASS_KINDS, the number
  * of launches since the previous call (launches[k]), their summed duration
  * in milliseconds measured with HIP events recorded on the plan's stream
- * around each launch (total_ms[k]; when steps replay graphs the records are
- * event nodes of the graph, read after each replay), and the algorithmic HBM bytes of one
+ * around each launch (total_ms[k]), and the algorithmic HBM bytes of one
  * launch (bytes_per_launch[k]: every field read once and every field written
  * once).  Host arrays of SPSTD_NPASS_KINDS entries; any may be NULL.
  * SPSTD_ERR_ARG if the plan was made without SPSTD_TIMING.

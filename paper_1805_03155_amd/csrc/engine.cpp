@@ -44,38 +44,21 @@ struct Plan {
     hipGraphExec_t graph;
     bool graph_ready;
     std::string err;
-    // SPSTD_TIMING: event pairs around pass launches and their kinds, for
-    // eager launches (ev_*) and for the ones captured in the step graph (gev*)
+    // SPSTD_TIMING: event pairs around pass launches and their kinds
     std::vector<hipEvent_t> ev_pool;
     std::vector<int> ev_kind;
     size_t ev_used = 0;
-    std::vector<hipEvent_t> gev;
-    std::vector<int> gev_kind;
-    bool capturing = false;
     int64_t acc_n[SPSTD_NPASS_KINDS] = {0};
     double acc_ms[SPSTD_NPASS_KINDS] = {0.0};
 };
 
 // Brackets one pass launch with HIP events on the plan's stream when the
-// plan times its passes.  Under graph capture the records become external
-// event nodes of the graph, re-recorded at every replay.
+// plan times its passes (timing plans launch eagerly, never from a graph).
 struct PassTimer {
     Plan* p;
     int slot;
-    bool graph;
-    PassTimer(Plan* pl, int kind) : p(pl), slot(-1), graph(pl->capturing) {
+    PassTimer(Plan* pl, int kind) : p(pl), slot(-1) {
         if (!(p->d.flags & SPSTD_TIMING)) return;
-        if (graph) {
-            hipEvent_t a, b;
-            if (hipEventCreate(&a) != hipSuccess) return;
-            if (hipEventCreate(&b) != hipSuccess) { (void)hipEventDestroy(a); return; }
-            slot = (int)p->gev.size();
-            p->gev.push_back(a);
-            p->gev.push_back(b);
-            p->gev_kind.push_back(kind);
-            (void)hipEventRecordWithFlags(a, p->st, hipEventRecordExternal);
-            return;
-        }
         if (p->ev_used + 2 > p->ev_pool.size()) {
             hipEvent_t a, b;
             if (hipEventCreate(&a) != hipSuccess) return;
@@ -89,9 +72,7 @@ struct PassTimer {
         (void)hipEventRecord(p->ev_pool[slot], p->st);
     }
     ~PassTimer() {
-        if (slot < 0) return;
-        if (graph) (void)hipEventRecordWithFlags(p->gev[slot + 1], p->st, hipEventRecordExternal);
-        else (void)hipEventRecord(p->ev_pool[slot + 1], p->st);
+        if (slot >= 0) (void)hipEventRecord(p->ev_pool[slot + 1], p->st);
     }
 };
 
@@ -367,9 +348,7 @@ static spstd_status build_graph(Plan* p) {
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
-        p->capturing = true;
         hipError_t e2 = enqueue_steps_eager<R>(p, kGraphChunk);
-        p->capturing = false;
         e = hipStreamEndCapture(cap, &g);
         if (e == hipSuccess) e = e2;
     }
@@ -393,22 +372,14 @@ static spstd_status enqueue_steps(Plan* p, int64_t n) {
                                          1, p->d.m, n, p->d.nyquist, p->ws + p->L.tw[0], p->st));
         return SPSTD_OK;
     }
-    const bool use_graph = !(p->d.flags & SPSTD_EAGER) && n >= kGraphChunk;
-    const bool timing = (p->d.flags & SPSTD_TIMING) != 0;
+    const bool use_graph = !(p->d.flags & (SPSTD_EAGER | SPSTD_TIMING)) && n >= kGraphChunk;
     if (use_graph && !p->graph_ready) {
         spstd_status s = build_graph<R>(p);
         if (s != SPSTD_OK) return s;
     }
     int64_t left = n;
     if (use_graph) {
-        for (; left >= kGraphChunk; left -= kGraphChunk) {
-            HIPCHK(hipGraphLaunch(p->graph, p->st));
-            if (timing) {
-                // the graph's events are re-recorded at every replay: read them now
-                HIPCHK(hipStreamSynchronize(p->st));
-                HIPCHK(harvest(p, p->gev, p->gev_kind));
-            }
-        }
+        for (; left >= kGraphChunk; left -= kGraphChunk) HIPCHK(hipGraphLaunch(p->graph, p->st));
     }
     HIPCHK(enqueue_steps_eager<R>(p, left));
     return SPSTD_OK;
@@ -686,7 +657,6 @@ spstd_status spstd_destroy(spstd_plan_t p) {
     if (!p) return SPSTD_ERR_ARG;
     if (p->graph_ready) (void)hipGraphExecDestroy(p->graph);
     for (hipEvent_t e : p->ev_pool) (void)hipEventDestroy(e);
-    for (hipEvent_t e : p->gev) (void)hipEventDestroy(e);
     delete p;
     return SPSTD_OK;
 }

@@ -306,14 +306,31 @@ __device__ __forceinline__ void fft_pencils(cpx<R> (&v)[P][16], int j, R* lds, i
             // radix-16 pass: butterfly b = j, k = j mod Ns,
             // twiddle w_{16 Ns}^{r k} = w_N^{r k N / (16 Ns)}
             const int k = j % Ns;
-            cpx<R> w[16];
-            twiddles16<R, PRODUCTS>(tw, k * (N / (16 * Ns)), w);
+            const int step = k * (N / (16 * Ns));
+            if constexpr (PRODUCTS) {
+                // w^{a step} w^{4 b step}, r = a + 4b, formed where used
+                const cpx<R> t1 = tw[step], t4 = tw[4 * step];
+                const cpx<R> t2 = cmul(t1, t1), t3 = cmul(t2, t1);
+                const cpx<R> t8 = cmul(t4, t4), t12 = cmul(t8, t4);
 #pragma unroll
-            for (int p = 0; p < P; ++p) {
+                for (int r = 1; r < 16; ++r) {
+                    const int a = r & 3, b = r >> 2;
+                    const cpx<R> lo = a == 1 ? t1 : a == 2 ? t2 : t3;
+                    const cpx<R> hi = b == 1 ? t4 : b == 2 ? t8 : t12;
+                    const cpx<R> w = b == 0 ? lo : a == 0 ? hi : cmul(lo, hi);
 #pragma unroll
-                for (int r = 1; r < 16; ++r) v[p][r] = INV ? cmulc(v[p][r], w[r]) : cmul(v[p][r], w[r]);
-                dft16<R, INV>(v[p]);
+                    for (int p = 0; p < P; ++p) v[p][r] = INV ? cmulc(v[p][r], w) : cmul(v[p][r], w);
+                }
+            } else {
+#pragma unroll
+                for (int r = 1; r < 16; ++r) {
+                    const cpx<R> w = tw[r * step];
+#pragma unroll
+                    for (int p = 0; p < P; ++p) v[p][r] = INV ? cmulc(v[p][r], w) : cmul(v[p][r], w);
+                }
             }
+#pragma unroll
+            for (int p = 0; p < P; ++p) dft16<R, INV>(v[p]);
         } else {
             // tail pass of radix RL: butterflies b = j + T u, u < 16/RL,
             // Ns * RL = N so the twiddle is w_N^{r b}

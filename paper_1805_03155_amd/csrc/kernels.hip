@@ -210,6 +210,10 @@ __global__ __launch_bounds__(64 * WPB) SPSTD_WAVES_ATTR void k_axis_acc(
     const int64_t gx = valid ? group % groups_x : 0, outer = valid ? group / groups_x : 0;
     const int64_t inst = outer / g.n_in;
     const int64_t base = inst * g.stride_hi + (outer - inst * g.n_in) * g.stride_lo + 2 * P * gx;
+    const R scale = scale_of<R>(sc, inst, col);
+    // a free batch slot has zero scales: a wave with nothing to update leaves
+    // (its LDS barriers are wave-local)
+    if (__all(!valid || scale == (R)0)) return;
 
     cpx<R> v[P][16];
 #pragma unroll
@@ -228,7 +232,6 @@ __global__ __launch_bounds__(64 * WPB) SPSTD_WAVES_ATTR void k_axis_acc(
     fft_pencils<R, N, true, true, TU::SPLIT, TU::PRODUCTS, P>(v, j, l0, SL, tw);
     epi_begin();
     if (valid) {
-        const R scale = scale_of<R>(sc, inst, col);
 #pragma unroll
         for (int q = 0; q < P; ++q) {
 #pragma unroll
@@ -309,6 +312,13 @@ __global__ __launch_bounds__((row_map<R, N, WPB>::THREADS)) SPSTD_WAVES_ATTR voi
     const bool v0 = FULL || 2 * L.q < nrows, v1 = FULL || 2 * L.q + 1 < nrows;
     const int64_t inst0 = v0 ? (2 * L.q) / rg.rows_per_inst : 0;
     const int64_t inst1 = v1 ? (2 * L.q + 1) / rg.rows_per_inst : inst0;
+    {
+        // rows of free batch slots (zero scales) need no work; the test is
+        // uniform over the wave, or over the workgroup for one-pencil blocks
+        const bool idle = scale_of<R>(sc, inst0, kcol) == (R)0 && scale_of<R>(sc, inst1, kcol) == (R)0 &&
+                          scale_of<R>(sc, inst0, pcol) == (R)0 && scale_of<R>(sc, inst1, pcol) == (R)0;
+        if (__all(idle)) return;
+    }
     const int64_t b = L.row0 * N;
     const R* __restrict__ sb = src + b;
     R* __restrict__ db = dst + b;
@@ -367,6 +377,11 @@ __global__ __launch_bounds__((row_map<R, N, WPB>::THREADS)) SPSTD_WAVES_ATTR voi
     const bool v0 = FULL || 2 * L.q < nrows, v1 = FULL || 2 * L.q + 1 < nrows;
     const int64_t inst0 = v0 ? (2 * L.q) / rg.rows_per_inst : 0;
     const int64_t inst1 = v1 ? (2 * L.q + 1) / rg.rows_per_inst : inst0;
+    {
+        const bool idle = scale_of<R>(sc, inst0, SC_KXA) == (R)0 && scale_of<R>(sc, inst1, SC_KXA) == (R)0 &&
+                          scale_of<R>(sc, inst0, SC_KXB) == (R)0 && scale_of<R>(sc, inst1, SC_KXB) == (R)0;
+        if (__all(idle)) return;
+    }
     const int64_t b = L.row0 * N;
     R* __restrict__ Rb = psiR + b;
     R* __restrict__ Ib = psiI + b;

@@ -13,6 +13,12 @@
 //   A: PR += kin_A * T PI + pot_A * V * PI      (kin_A from c_l dt, pot_A = c_l dt / hbar)
 //   B: PI += kin_B * T PR + pot_B * V * PR      (kin_B, pot_B from -d_l dt)
 // After every step each instance's probe samples (FP64) are written.
+//
+// Up to N = 4096 the state lives in registers.  Longer grids (GS: global
+// state) keep psi_R and psi_I in the instances' own arrays -- each row is
+// touched only by its own workgroup, so it stays in cache -- and read and
+// write them around every substep, ordered by workgroup barriers; the step
+// loop still runs inside one launch.
 #include "fft_core.hpp"
 #include "resident.hpp"
 
@@ -44,7 +50,7 @@ __device__ __forceinline__ void k2_symbol(cpx<R> (&v)[16], int j, int nyq_zero) 
     }
 }
 
-template <typename R, int N>
+template <typename R, int N, bool GS>
 __global__ __launch_bounds__((res_cfg<N>::THREADS)) void k_resident_1d(
     const ResidentInst<R>* __restrict__ inst, int ninst, int m, int64_t nsteps, int nyq_zero,
     const cpx<R>* __restrict__ tw) {
@@ -66,74 +72,120 @@ __global__ __launch_bounds__((res_cfg<N>::THREADS)) void k_resident_1d(
     const ResidentInst<R>* A = ha ? inst + ia : inst;
     const ResidentInst<R>* B = hb ? inst + ib : A;
     R* l0 = lds + (N == 16 ? 0 : gib * C::LS);
-
-    cpx<R> PR[16], PI[16];
-#pragma unroll
-    for (int e = 0; e < 16; ++e) {
-        const int x = j + C::T * e;
-        PR[e] = cpx<R>{ha ? A->psiR[x] : (R)0, hb ? B->psiR[x] : (R)0};
-        PI[e] = cpx<R>{ha ? A->psiI[x] : (R)0, hb ? B->psiI[x] : (R)0};
-    }
     const R* Va = A->V;
     const R* Vb = B->V;
     const int64_t slot_a = ha ? *A->counter : 0;
     const int64_t slot_b = hb ? *B->counter : 0;
 
-    for (int64_t s = 0; s < nsteps; ++s) {
-        for (int l = 0; l < m; ++l) {
+    if constexpr (!GS) {
+        cpx<R> PR[16], PI[16];
 #pragma unroll
-            for (int half = 0; half < 2; ++half) {
-                const R ka = ha ? A->kin[2 * l + half] : (R)0, kb = hb ? B->kin[2 * l + half] : (R)0;
-                const R pa = ha ? A->pot[2 * l + half] : (R)0, pb = hb ? B->pot[2 * l + half] : (R)0;
-                if (ka == (R)0 && kb == (R)0 && pa == (R)0 && pb == (R)0) continue;   // uniform
-                cpx<R>(&src)[16] = half == 0 ? PI : PR;
-                cpx<R>(&dst)[16] = half == 0 ? PR : PI;
-                cpx<R> v[1][16];
-#pragma unroll
-                for (int e = 0; e < 16; ++e) v[0][e] = src[e];
-                fft_pencils<R, N, false, C::WAVE, true, true, 1>(v, j, l0, C::LS, tw);
-                k2_symbol<R, N>(v[0], j, nyq_zero);
-                fft_pencils<R, N, true, C::WAVE, true, true, 1>(v, j, l0, C::LS, tw);
-#pragma unroll
-                for (int e = 0; e < 16; ++e) {
-                    const int x = j + C::T * e;
-                    const R va = Va[x], vb = Vb[x];
-                    dst[e].x += ka * v[0][e].x + pa * va * src[e].x;
-                    dst[e].y += kb * v[0][e].y + pb * vb * src[e].y;
-                }
-            }
+        for (int e = 0; e < 16; ++e) {
+            const int x = j + C::T * e;
+            PR[e] = cpx<R>{ha ? A->psiR[x] : (R)0, hb ? B->psiR[x] : (R)0};
+            PI[e] = cpx<R>{ha ? A->psiI[x] : (R)0, hb ? B->psiI[x] : (R)0};
         }
-        // probe samples of this step
+        for (int64_t s = 0; s < nsteps; ++s) {
+            for (int l = 0; l < m; ++l) {
 #pragma unroll
-        for (int who = 0; who < 2; ++who) {
-            const bool has = who == 0 ? ha : hb;
-            const ResidentInst<R>* I = who == 0 ? A : B;
-            if (!has) continue;
-            for (int q = 0; q < I->nprobes; ++q) {
-                const int64_t pidx = I->probe_idx[q];
-                if ((int)(pidx % C::T) != j) continue;
-                const int pe = (int)(pidx / C::T);
-                R r = (R)0, im = (R)0;
+                for (int half = 0; half < 2; ++half) {
+                    const R ka = ha ? A->kin[2 * l + half] : (R)0, kb = hb ? B->kin[2 * l + half] : (R)0;
+                    const R pa = ha ? A->pot[2 * l + half] : (R)0, pb = hb ? B->pot[2 * l + half] : (R)0;
+                    if (ka == (R)0 && kb == (R)0 && pa == (R)0 && pb == (R)0) continue;   // uniform
+                    cpx<R>(&src)[16] = half == 0 ? PI : PR;
+                    cpx<R>(&dst)[16] = half == 0 ? PR : PI;
+                    cpx<R> v[1][16];
 #pragma unroll
-                for (int e = 0; e < 16; ++e) {
-                    if (e == pe) {
-                        r = who == 0 ? PR[e].x : PR[e].y;
-                        im = who == 0 ? PI[e].x : PI[e].y;
+                    for (int e = 0; e < 16; ++e) v[0][e] = src[e];
+                    fft_pencils<R, N, false, C::WAVE, true, true, 1>(v, j, l0, C::LS, tw);
+                    k2_symbol<R, N>(v[0], j, nyq_zero);
+                    fft_pencils<R, N, true, C::WAVE, true, true, 1>(v, j, l0, C::LS, tw);
+#pragma unroll
+                    for (int e = 0; e < 16; ++e) {
+                        const int x = j + C::T * e;
+                        const R va = Va[x], vb = Vb[x];
+                        dst[e].x += ka * v[0][e].x + pa * va * src[e].x;
+                        dst[e].y += kb * v[0][e].y + pb * vb * src[e].y;
                     }
                 }
-                const int64_t slot = (who == 0 ? slot_a : slot_b) + s;
-                if (slot < I->capacity) {
-                    I->probes[(slot * I->nprobes + q) * 2 + 0] = (double)r;
-                    I->probes[(slot * I->nprobes + q) * 2 + 1] = (double)im;
+            }
+            // probe samples of this step
+#pragma unroll
+            for (int who = 0; who < 2; ++who) {
+                const bool has = who == 0 ? ha : hb;
+                const ResidentInst<R>* I = who == 0 ? A : B;
+                if (!has) continue;
+                for (int q = 0; q < I->nprobes; ++q) {
+                    const int64_t pidx = I->probe_idx[q];
+                    if ((int)(pidx % C::T) != j) continue;
+                    const int pe = (int)(pidx / C::T);
+                    R r = (R)0, im = (R)0;
+#pragma unroll
+                    for (int e = 0; e < 16; ++e) {
+                        if (e == pe) {
+                            r = who == 0 ? PR[e].x : PR[e].y;
+                            im = who == 0 ? PI[e].x : PI[e].y;
+                        }
+                    }
+                    const int64_t slot = (who == 0 ? slot_a : slot_b) + s;
+                    if (slot < I->capacity) {
+                        I->probes[(slot * I->nprobes + q) * 2 + 0] = (double)r;
+                        I->probes[(slot * I->nprobes + q) * 2 + 1] = (double)im;
+                    }
                 }
             }
         }
-    }
 #pragma unroll
-    for (int e = 0; e < 16; ++e) {
-        const int x = j + C::T * e;
-        if (ha) { A->psiR[x] = PR[e].x; A->psiI[x] = PI[e].x; }
-        if (hb) { B->psiR[x] = PR[e].y; B->psiI[x] = PI[e].y; }
+        for (int e = 0; e < 16; ++e) {
+            const int x = j + C::T * e;
+            if (ha) { A->psiR[x] = PR[e].x; A->psiI[x] = PI[e].x; }
+            if (hb) { B->psiR[x] = PR[e].y; B->psiI[x] = PI[e].y; }
+        }
+    } else {
+        // global state: every substep reads its source and destination rows
+        for (int64_t s = 0; s < nsteps; ++s) {
+            for (int l = 0; l < m; ++l) {
+                for (int half = 0; half < 2; ++half) {
+                    const R ka = ha ? A->kin[2 * l + half] : (R)0, kb = hb ? B->kin[2 * l + half] : (R)0;
+                    const R pa = ha ? A->pot[2 * l + half] : (R)0, pb = hb ? B->pot[2 * l + half] : (R)0;
+                    if (ka == (R)0 && kb == (R)0 && pa == (R)0 && pb == (R)0) continue;   // uniform
+                    const R* sa = half == 0 ? A->psiI : A->psiR;
+                    const R* sb = half == 0 ? B->psiI : B->psiR;
+                    R* da = half == 0 ? A->psiR : A->psiI;
+                    R* db = half == 0 ? B->psiR : B->psiI;
+                    cpx<R> v[1][16];
+#pragma unroll
+                    for (int e = 0; e < 16; ++e) {
+                        const int x = j + C::T * e;
+                        v[0][e] = cpx<R>{ha ? sa[x] : (R)0, hb ? sb[x] : (R)0};
+                    }
+                    fft_pencils<R, N, false, C::WAVE, true, true, 1>(v, j, l0, C::LS, tw);
+                    k2_symbol<R, N>(v[0], j, nyq_zero);
+                    fft_pencils<R, N, true, C::WAVE, true, true, 1>(v, j, l0, C::LS, tw);
+#pragma unroll
+                    for (int e = 0; e < 16; ++e) {
+                        const int x = j + C::T * e;
+                        if (ha) da[x] = da[x] + ka * v[0][e].x + pa * Va[x] * sa[x];
+                        if (hb) db[x] = db[x] + kb * v[0][e].y + pb * Vb[x] * sb[x];
+                    }
+                    // the next substep reads what other lanes of the group wrote
+                    __threadfence_block();
+                    if constexpr (C::WAVE) lds_sync<true>(); else __syncthreads();
+                }
+            }
+#pragma unroll
+            for (int who = 0; who < 2; ++who) {
+                const bool has = who == 0 ? ha : hb;
+                const ResidentInst<R>* I = who == 0 ? A : B;
+                if (!has || j != 0) continue;
+                const int64_t slot = (who == 0 ? slot_a : slot_b) + s;
+                for (int q = 0; q < I->nprobes && slot < I->capacity; ++q) {
+                    const int64_t pidx = I->probe_idx[q];
+                    I->probes[(slot * I->nprobes + q) * 2 + 0] = (double)I->psiR[pidx];
+                    I->probes[(slot * I->nprobes + q) * 2 + 1] = (double)I->psiI[pidx];
+                }
+            }
+        }
     }
     // every lane of the group has read the counters before lane 0 advances them
     if constexpr (C::WAVE) {
@@ -147,7 +199,7 @@ __global__ __launch_bounds__((res_cfg<N>::THREADS)) void k_resident_1d(
     }
 }
 
-bool resident_len_ok(int64_t n) { return n >= 16 && (n & (n - 1)) == 0 && n <= 4096; }
+bool resident_len_ok(int64_t n) { return n >= 16 && (n & (n - 1)) == 0 && n <= 16384; }
 
 template <typename R, int N>
 static hipError_t res_n(const ResidentInst<R>* inst, int ninst, int m, int64_t nsteps, int nyq_zero,
@@ -155,8 +207,8 @@ static hipError_t res_n(const ResidentInst<R>* inst, int ninst, int m, int64_t n
     using C = res_cfg<N>;
     const int groups = (ninst + 1) / 2;
     const int blocks = (groups + C::GPB - 1) / C::GPB;
-    hipLaunchKernelGGL((k_resident_1d<R, N>), dim3(blocks), dim3(C::THREADS), 0, st, inst, ninst, m,
-                       nsteps, nyq_zero, (const cpx<R>*)tw);
+    hipLaunchKernelGGL((k_resident_1d<R, N, (N > 4096)>), dim3(blocks), dim3(C::THREADS), 0, st, inst,
+                       ninst, m, nsteps, nyq_zero, (const cpx<R>*)tw);
     return hipGetLastError();
 }
 
@@ -173,6 +225,8 @@ hipError_t launch_resident_1d(int64_t n, const ResidentInst<R>* inst, int ninst,
         case 1024: return res_n<R, 1024>(inst, ninst, m, nsteps, nyq_zero, tw, st);
         case 2048: return res_n<R, 2048>(inst, ninst, m, nsteps, nyq_zero, tw, st);
         case 4096: return res_n<R, 4096>(inst, ninst, m, nsteps, nyq_zero, tw, st);
+        case 8192: return res_n<R, 8192>(inst, ninst, m, nsteps, nyq_zero, tw, st);
+        case 16384: return res_n<R, 16384>(inst, ninst, m, nsteps, nyq_zero, tw, st);
         default: return hipErrorInvalidValue;
     }
 }

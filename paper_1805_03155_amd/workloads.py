@@ -154,7 +154,7 @@ def batch_instances(count=512, seed=0, steps=5000, box=20.0, max_1d_log2=14,
     probability p2d), sizes 2^U{...}, square wells (width U[2,20], depth
     U[1,50]) or harmonic wells (omega U[0.5,2]) with probability 1/2 each;
     psi_R = 8 seeded Gaussians (sigma 0.5) inside the well, psi_I = 0; one
-    probe at a seeded point near the well centre."""
+    probe next to the first Gaussian."""
     rng = np.random.default_rng(seed)
     out = []
     for i in range(count):
@@ -183,13 +183,16 @@ def batch_instances(count=512, seed=0, steps=5000, box=20.0, max_1d_log2=14,
             spread = min(box / 2, 2.0 / np.sqrt(om))
             kind = ("harmonic", om)
         psi = np.zeros_like(V, dtype=np.float64)
+        centres = []
         for _ in range(8):
             ctr = rng.uniform(-spread, spread, dim) * 0.8
+            centres.append(ctr)
             a = rng.normal()
             r2 = sum((g - cc) ** 2 for g, cc in zip(grids, ctr))
             psi += a * np.exp(-r2 / (2 * 0.25))
-        pc = rng.uniform(-spread, spread, dim) * 0.5
-        idx = [snap(v, -box, d) for v in pc]
+        # the probe sits half a width from the first Gaussian, where the state has weight
+        pc = centres[0] + 0.25
+        idx = [min(n - 1, max(0, snap(v, -box, d))) for v in pc]
         lin = idx[0] if dim == 1 else idx[1] * n + idx[0]
         out.append(Workload(f"batch_{i}", shape, (d,) * dim, (-box,) * dim,
                             np.ascontiguousarray(V.ravel(), np.float64),
