@@ -142,6 +142,23 @@ def apply_K(f, V, n, dx, hbar=1.0, mass=1.0, nyquist=NYQ_FULL,
     return out
 
 
+def energy(psiR, psiI, V, n, dx, hbar=1.0, mass=1.0, nyquist=NYQ_FULL):
+    """Energy diagnostics of psi = psiR + i psiI as plain sums over the grid
+    (Sec. 2.2, Eq. 16, times hbar), each times the cell volume:
+    kinetic = sum psi* (-(hbar^2/2m*) Laplacian) psi, potential =
+    sum V |psi|^2, norm = sum |psi|^2.  <H> = (kinetic + potential) / norm.
+    The Laplacian is the oracle's own K with V = 0."""
+    _, d3 = _grid(n, dx)
+    cell = float(np.prod(d3[: len(n)]))
+    r, i = _f64(psiR).ravel(), _f64(psiI).ravel()
+    kr = apply_K(r, None, n, dx, hbar, mass, nyquist)
+    ki = apply_K(i, None, n, dx, hbar, mass, nyquist)
+    kin = hbar * float(np.dot(r, kr) + np.dot(i, ki)) * cell
+    rho = r * r + i * i
+    pot = float(np.dot(_f64(V).ravel(), rho)) * cell
+    return kin, pot, float(rho.sum()) * cell
+
+
 def mode_matrix(c, d, x):
     """One step's 2x2 evolution matrix for a mode with omega*dt = x (Eq. 23)."""
     c, d = _f64(c), _f64(d)

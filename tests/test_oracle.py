@@ -390,6 +390,64 @@ def test_norm_bounded_for_spstd_and_decays_for_rk4():
             assert slope_T < 0 and abs(slope_T) > 0.5 * np.abs(dev).max()
 
 
+# ------------------------------------------ energy diagnostics
+@pytest.mark.parametrize("nz", [oracle.NYQ_FULL, oracle.NYQ_ZERO])
+def test_energy_of_dense_eigenvectors_is_the_eigenvalue(nz):
+    # <phi|H|phi> = hbar * lambda for an eigenvector of the dense K, built
+    # from its definition (modal.hamiltonian_1d), not from the oracle's FFT
+    rng = np.random.default_rng(3)
+    n, dx, hb, m = 64, 0.3, 0.7, 1.3
+    V = 2.0 * rng.random(n)
+    lam, phi = np.linalg.eigh(modal.hamiltonian_1d(V, dx, hb, m, nz == oracle.NYQ_ZERO))
+    for j in (0, 5, 63):
+        kin, pot, nrm = oracle.energy(0.6 * phi[:, j], 0.8 * phi[:, j], V, (n,), (dx,), hb, m, nz)
+        assert abs(nrm / dx - 1.0) < 1e-13
+        assert abs((kin + pot) / nrm / (hb * lam[j]) - 1.0) < 1e-13
+        assert abs(pot / nrm - float(np.dot(V, phi[:, j] ** 2))) < 1e-13
+
+
+def test_energy_of_a_plane_wave():
+    # e^{i k.r}: kinetic hbar^2 |k|^2 / 2m* per unit |psi|^2, exactly
+    n, dx, hb, m = (16, 8, 32), (0.2, 0.35, 0.1), 0.9, 1.7
+    kv = [2 * np.pi * a / (nn * d) for a, nn, d in zip((3, -2, 5), n, dx)]
+    c = W.plane_wave_field(n, dx, kv)
+    s = W.plane_wave_field(n, dx, kv, phase=-np.pi / 2)
+    kin, pot, nrm = oracle.energy(c, s, np.full(int(np.prod(n)), 1.5), n, dx, hb, m)
+    vol = np.prod(n) * np.prod(dx)
+    assert abs(nrm / vol - 1.0) < 1e-13
+    assert abs(kin / (hb ** 2 * sum(k * k for k in kv) / (2 * m) * vol) - 1.0) < 1e-13
+    assert abs(pot / (1.5 * vol) - 1.0) < 1e-13
+
+
+def test_energy_of_the_oscillator_ground_state():
+    # exp(-r^2/2) with omega = 1: kinetic = potential = 3/4, total 3/2 (virial)
+    w = W.harmonic_3d(seed=0, n=32, half_box=8.0)
+    x = W.axis_coords(32, -8.0, 8.0)
+    Z, Y, X = np.meshgrid(x, x, x, indexing="ij")
+    g = np.exp(-(X ** 2 + Y ** 2 + Z ** 2) / 2).ravel()
+    kin, pot, nrm = oracle.energy(g, 0 * g, w.V, w.n, w.dx)
+    assert abs(kin / nrm - 0.75) < 1e-12 and abs(pot / nrm - 0.75) < 1e-12
+
+
+def test_energy_bounded_for_spstd_and_decays_for_rk4():
+    # as for the norm: the symplectic run keeps <H> within a small band, the
+    # RK4 run at the same dt loses energy steadily
+    w = W.finite_well_1d(seed=0, steps=20000)
+    c, d = w.coeffs
+    dt = oracle.stable_dt(c, d, w.V, w.n, w.dx)
+    for method in (oracle.METHOD_SYMPLECTIC, oracle.METHOD_RK4):
+        r, i, E = w.psiR, w.psiI, []
+        for _ in range(6):
+            kin, pot, _ = oracle.energy(r, i, w.V, w.n, w.dx)
+            E.append(kin + pot)
+            r, i, _, _ = oracle.run(r, i, w.V, w.n, w.dx, c, d, dt, 4000, method=method)
+        dev = np.array(E) / E[0] - 1.0
+        if method == oracle.METHOD_SYMPLECTIC:
+            assert np.abs(dev).max() < 1e-5
+        else:
+            assert np.all(np.diff(dev) < 0) and dev[-1] < -1e-3
+
+
 # ------------------------------------- T10: the paper's printed tables
 def _bins(table, c, d, dims):
     si = GOLD["si_constants"]
