@@ -181,6 +181,66 @@ def pmc_sample(w, steps):
     print(json.dumps({"pmc_sample": True, "copy_bytes_each_way": nbytes, "steps": steps}))
 
 
+def _advance(p, steps, chunk, label):
+    """Queue steps in chunks, waiting for each so progress can be printed."""
+    import torch
+    done = 0
+    t0 = time.perf_counter()
+    while done < steps:
+        k = min(chunk, steps - done)
+        p.step(k)
+        torch.cuda.synchronize()
+        done += k
+        log(f"{label}: {done}/{steps} steps, {time.perf_counter() - t0:.1f} s")
+    return time.perf_counter() - t0
+
+
+def precision_study(w, which, steps, nlevels=8):
+    """Long runs of the 256^3 oscillator: FP64 and FP32 symplectic runs, or
+    the RK4 run at the FP64 run's dt.  Reports rate, norm and energy drift,
+    eigenvalues against the oscillator ladder (n + 3/2) hbar omega, and
+    FP32 against FP64 (state and eigenvalues)."""
+    import numpy as np
+    from paper_1805_03155_amd import spstd
+    exact = np.arange(nlevels) + 1.5
+    out = {"workload": f"{w.n[0]}^3 oscillator, Yoshida-6, dt = 0.5 x limit", "steps": steps}
+    runs = [("fp64", spstd.FP64, spstd.SYMPLECTIC), ("fp32", spstd.FP32, spstd.SYMPLECTIC)] \
+        if which == "precision" else [("rk4", spstd.FP64, spstd.RK4)]
+    dt64 = spstd.plan_from_workload(w, nsteps_max=1).dt
+    states = {}
+    for name, prec, method in runs:
+        p = spstd.plan_from_workload(w, precision=prec, method=method, dt=dt64, nsteps_max=steps)
+        st0 = p.info()
+        kin0, pot0, nrm0 = p.energy()
+        el = _advance(p, steps, 5000, name)
+        series, st = p.run(0)
+        kin1, pot1, nrm1 = p.energy()
+        E, _ = spstd.spectrum(series, st.dt, nlevels=nlevels)
+        r, i, _ = p.get_state()
+        states[name] = (r, i, E)
+        subs = st0.substeps_per_step
+        res = {"seconds": el, "ms_per_step": el / steps * 1e3,
+               "stage_updates_per_s": w.npoints * subs / 2.0 * steps / el,
+               "dt": st.dt, "norm_drift": nrm1 / nrm0 - 1.0,
+               "energy_drift": ((kin1 + pot1) / nrm1) / ((kin0 + pot0) / nrm0) - 1.0,
+               "energy0": (kin0 + pot0) / nrm0,
+               "levels": [float(x) for x in E]}
+        k = min(len(E), nlevels)
+        res["level_rel_err_vs_ladder"] = [float(abs(E[j] - exact[j]) / exact[j]) for j in range(k)]
+        out[name] = res
+        log(f"{name}: levels {np.round(E, 7).tolist()}, norm drift {res['norm_drift']:.2e}")
+        del p
+    if "fp32" in states:
+        r64, i64, E64 = states["fp64"]
+        r32, i32, E32 = states["fp32"]
+        a, b = np.concatenate([r32, i32]), np.concatenate([r64, i64])
+        k = min(len(E64), len(E32))
+        out["fp32_vs_fp64"] = {
+            "psi_rel_l2": float(np.linalg.norm(a - b) / np.linalg.norm(b)),
+            "level_rel_err": [float(abs(E32[j] - E64[j]) / abs(E64[j])) for j in range(k)]}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -196,6 +256,9 @@ def main():
     ap.add_argument("--serve-rate", type=float, default=10.0)
     ap.add_argument("--pmc-sample", action="store_true",
                     help="short run for rocprofv3 counter passes (no timing output)")
+    ap.add_argument("--study", choices=["precision", "rk4"],
+                    help="long-run accuracy study instead of the timing line")
+    ap.add_argument("--study-steps", type=int, default=100000)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: this engine has no multi-GPU path "
@@ -210,6 +273,9 @@ def main():
                       coeffs=W.YOSHIDA6, nprobes=3)
     if args.pmc_sample:
         pmc_sample(w, 2)
+        return
+    if args.study:
+        print(json.dumps(precision_study(w, args.study, args.study_steps)), flush=True)
         return
     res = {}
     for prec in ("fp64", "fp32"):

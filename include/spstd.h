@@ -173,6 +173,22 @@ spstd_status spstd_step(spstd_plan_t plan, int64_t nsteps);
 spstd_status spstd_run(spstd_plan_t plan, int64_t nsteps, double *probe_out,
                        spstd_stats *stats_out);
 
+/*
+ * Energy diagnostics of the current state psi = psi_R + i psi_I, the pieces
+ * of <H> with H = hbar K (Sec. 2.2, Eq. 16), each summed over the grid and
+ * multiplied by the cell volume:
+ *   out[0] kinetic   sum psi* (-(hbar^2/2m*) Laplacian) psi, with the
+ *                    plan's spectral second derivative (Eq. 9-10 and the
+ *                    plan's Nyquist convention), by Parseval per axis;
+ *   out[1] potential sum V |psi|^2;
+ *   out[2] norm      sum |psi|^2.
+ * <H> = (out[0] + out[1]) / out[2].  out: host array of 3 doubles.  Sums are
+ * FP64 in a fixed order (deterministic).  Runs on the plan's stream after
+ * the steps already queued and synchronises it.  Errors: SPSTD_ERR_ARG (null
+ * pointers), SPSTD_ERR_NONFINITE (state not finite), SPSTD_ERR_DEVICE.
+ */
+spstd_status spstd_energy(spstd_plan_t plan, double *out);
+
 /* Statistics without running (steps_done, dt, x_max, rho, norm0). */
 spstd_status spstd_plan_info(spstd_plan_t plan, spstd_stats *stats_out);
 

@@ -159,7 +159,8 @@ static Layout layout_of(const spstd_desc* d, int64_t nsteps_max) {
     L.probes = off;
     off += align256(sizeof(double) * 2 * (size_t)(d->nprobes > 0 ? d->nprobes : 1) * (size_t)(nsteps_max + 1));
     L.counter = off; off += 256;
-    L.partials = off; off += align256(sizeof(double) * kNormBlocks);
+    // norm partials, then the energy sums: kinetic per axis, potential, norm
+    L.partials = off; off += align256(sizeof(double) * kNormBlocks * 6);
     L.rinst = off; off += align256(sizeof(ResidentInst<double>));
     // per-stage pass scales, then one row for the RK4 operator applications
     L.scales = off; off += align256((size_t)(d->m + 1) * SC_COLS * esz);
@@ -398,6 +399,45 @@ static spstd_status compute_norm(Plan* p, double* out) {
     return SPSTD_OK;
 }
 
+// <H> pieces (Sec. 2.2, Eq. 16 times hbar), each times the cell volume:
+// out[0] kinetic, out[1] potential, out[2] norm.  Synchronises the stream.
+template <typename R>
+static spstd_status compute_energy(Plan* p, double* out) {
+    double* part = reinterpret_cast<double*>(p->ws + p->L.partials) + kNormBlocks;
+    const int64_t nx = p->d.n[0], ny = p->d.ndim > 1 ? p->d.n[1] : 1, nz = p->d.ndim > 2 ? p->d.n[2] : 1;
+    const EnergyGeom geo[3] = {{ny * nz, 1, nx, 1},
+                               {nz * nx, nx, nx * ny, nx},
+                               {ny * nx, nx * ny, p->N, nx * ny}};
+    int nb[3] = {0, 0, 0};
+    for (int a = 0; a < p->d.ndim; ++a)
+        HIPCHK(launch_energy_axis<R>(p->d.n[a], a == 0, F<R>(p, p->L.psiR), F<R>(p, p->L.psiI),
+                                     p->ws + p->L.tw[a], geo[a], p->d.nyquist == SPSTD_NYQ_ZERO,
+                                     part + a * kNormBlocks, kNormBlocks, &nb[a], p->st));
+    HIPCHK(launch_energy_pot<R>(F<R>(p, p->L.psiR), F<R>(p, p->L.psiI), F<R>(p, p->L.V), p->N,
+                                part + 3 * kNormBlocks, part + 4 * kNormBlocks, kNormBlocks, p->st));
+    std::vector<double> h((size_t)5 * kNormBlocks);
+    HIPCHK(hipMemcpyAsync(h.data(), part, h.size() * sizeof(double), hipMemcpyDeviceToHost, p->st));
+    HIPCHK(hipStreamSynchronize(p->st));
+    const double hb = p->d.hbar, ms = p->d.mass;
+    double kin = 0.0;
+    for (int a = 0; a < p->d.ndim; ++a) {
+        double s = 0.0;
+        for (int b = 0; b < nb[a]; ++b) s += h[(size_t)a * kNormBlocks + b];
+        const double L = (double)p->d.n[a] * p->d.dx[a];
+        const double k1 = 2.0 * kPi / L;
+        kin += hb * hb / (2.0 * ms) * k1 * k1 / (double)p->d.n[a] * s;
+    }
+    double pot = 0.0, nrm = 0.0;
+    for (int b = 0; b < kNormBlocks; ++b) {
+        pot += h[(size_t)3 * kNormBlocks + b];
+        nrm += h[(size_t)4 * kNormBlocks + b];
+    }
+    out[0] = kin * p->cellvol;
+    out[1] = pot * p->cellvol;
+    out[2] = nrm * p->cellvol;
+    return SPSTD_OK;
+}
+
 template <typename R>
 static spstd_status plan_init(Plan* p, const double* V, const double* psiR0, const double* psiI0) {
     spstd_status s;
@@ -588,6 +628,16 @@ spstd_status spstd_run(spstd_plan_t p, int64_t nsteps, double* probe_out, spstd_
         return SPSTD_ERR_NONFINITE;
     }
     return SPSTD_OK;
+}
+
+spstd_status spstd_energy(spstd_plan_t p, double* out) {
+    if (!p || !out) return SPSTD_ERR_ARG;
+    spstd_status s = (p->esz == 8) ? compute_energy<double>(p, out) : compute_energy<float>(p, out);
+    if (s == SPSTD_OK && !(std::isfinite(out[0]) && std::isfinite(out[1]) && std::isfinite(out[2]))) {
+        p->err = "state is not finite";
+        return SPSTD_ERR_NONFINITE;
+    }
+    return s;
 }
 
 spstd_status spstd_plan_info(spstd_plan_t p, spstd_stats* st) {

@@ -496,6 +496,93 @@ __global__ __launch_bounds__(256) void k_norm_partials(const R* __restrict__ a, 
     if (threadIdx.x == 0) partials[blockIdx.x] = red[0];
 }
 
+// ---------------------------------------------------------------------------
+// Energy diagnostics.  Along one axis the kinetic energy of psi = psi_R +
+// i psi_I is (hbar^2/2m*) (2 pi/L)^2 / n * sum over lines and bins of
+// ks^2 |FFT_axis(psi)(k)|^2 (Parseval with the symbol of Eq. 9-10): each line
+// of the field is one complex pencil (psi_R, psi_I), transformed forward
+// only.  Blocks walk the lines with a fixed stride and write one FP64
+// partial each, so the sum has a fixed order.
+// ---------------------------------------------------------------------------
+template <int THREADS>
+__device__ __forceinline__ void block_sum_store(double s, double* out) {
+    __shared__ double wsum[THREADS / 64 > 0 ? THREADS / 64 : 1];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+    if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int w = 0; w < (THREADS + 63) / 64; ++w) t += wsum[w];
+        *out = t;
+    }
+}
+
+template <typename R, int N, bool ROWS>
+__global__ __launch_bounds__((row_map<R, N, SPSTD_WPB>::THREADS)) void k_energy_axis(
+    const R* __restrict__ psiR, const R* __restrict__ psiI, const cpx<R>* __restrict__ tw,
+    EnergyGeom g, int nyq_zero, double* __restrict__ partials) {
+    using C = pencil_cfg<N>;
+    using M = row_map<R, N, SPSTD_WPB>;
+    using TU = tuning<R>;
+    __shared__ R lds[M::LDS_REALS];
+    int j, pin;
+    if constexpr (C::WAVE) {
+        const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+        // rows: lanes run along the line; columns: neighbouring lanes take
+        // neighbouring lines (neighbouring x)
+        const int pw = ROWS ? lane / C::T : lane % C::PPW;
+        j = ROWS ? lane % C::T : lane / C::PPW;
+        pin = wave * C::PPW + pw;
+    } else {
+        j = threadIdx.x;
+        pin = 0;
+    }
+    double acc = 0.0;
+    for (int64_t L0 = (int64_t)blockIdx.x * M::PPB; L0 < g.nlines; L0 += (int64_t)gridDim.x * M::PPB) {
+        const int64_t L = L0 + pin;
+        const bool valid = L < g.nlines;
+        const int64_t base = valid ? (L / g.n_lo) * g.stride_hi + (L % g.n_lo) : 0;
+        cpx<R> v[1][16];
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+            const int64_t q = base + (int64_t)(j + C::T * e) * g.stride;
+            v[0][e] = valid ? cpx<R>{psiR[q], psiI[q]} : cpx<R>{(R)0, (R)0};
+        }
+        fft_pencils<R, N, false, C::WAVE, M::SPLIT, TU::PRODUCTS, 1>(v, j, lds + pin * M::SL, M::SL, tw);
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+            const int kk = j + C::T * e;
+            const int ks = (kk <= N / 2) ? kk : kk - N;
+            double s = (double)ks * (double)ks;
+            if (nyq_zero && kk == N / 2) s = 0.0;
+            const double re = (double)v[0][e].x, im = (double)v[0][e].y;
+            acc += s * (re * re + im * im);
+        }
+    }
+    block_sum_store<M::THREADS>(acc, partials + blockIdx.x);
+}
+
+// Per-block FP64 partials of sum V (psiR^2 + psiI^2) and of sum psiR^2 + psiI^2.
+template <typename R>
+__global__ __launch_bounds__(256) void k_energy_pot(const R* __restrict__ a, const R* __restrict__ b,
+                                                    const R* __restrict__ V, int64_t n,
+                                                    double* __restrict__ pot, double* __restrict__ nrm) {
+    double sp = 0.0, sn = 0.0;
+    const int64_t per = (n + gridDim.x - 1) / gridDim.x;
+    const int64_t lo = (int64_t)blockIdx.x * per;
+    const int64_t hi = lo + per < n ? lo + per : n;
+    for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
+        const double x = (double)a[i], y = (double)b[i];
+        const double r2 = x * x + y * y;
+        sn += r2;
+        sp += (double)V[i] * r2;
+    }
+    block_sum_store<256>(sp, pot + blockIdx.x);
+    __syncthreads();
+    block_sum_store<256>(sn, nrm + blockIdx.x);
+}
+
 template <typename R>
 __global__ void k_axpby(int64_t n, R a, const R* __restrict__ x, R b, R* __restrict__ y) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
@@ -655,6 +742,41 @@ hipError_t launch_norm_partials(const R* psiR, const R* psiI, int64_t n, double*
     return hipGetLastError();
 }
 
+template <typename R, int N>
+static hipError_t energy_axis_n(const R* psiR, const R* psiI, const void* tw, const EnergyGeom& g,
+                                int rows, int nyq_zero, double* partials, int max_blocks, int* nblocks,
+                                hipStream_t st) {
+    using M = row_map<R, N, kWPB>;
+    int64_t b = (g.nlines + M::PPB - 1) / M::PPB;
+    if (b > max_blocks) b = max_blocks;
+    if (b < 1) b = 1;
+    *nblocks = (int)b;
+    if (rows)
+        hipLaunchKernelGGL((k_energy_axis<R, N, true>), dim3((unsigned)b), dim3(M::THREADS), 0, st, psiR,
+                           psiI, (const cpx<R>*)tw, g, nyq_zero, partials);
+    else if constexpr (pencil_cfg<N>::WAVE)
+        hipLaunchKernelGGL((k_energy_axis<R, N, false>), dim3((unsigned)b), dim3(M::THREADS), 0, st, psiR,
+                           psiI, (const cpx<R>*)tw, g, nyq_zero, partials);
+    else
+        return hipErrorInvalidValue;   // y/z lines are at most 1024 long
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_energy_axis(int64_t n, int rows, const R* psiR, const R* psiI, const void* tw,
+                              const EnergyGeom& g, int nyq_zero, double* partials, int max_blocks,
+                              int* nblocks, hipStream_t st) {
+    const int64_t nx = n;
+    SPSTD_ROW_CASES(energy_axis_n, psiR, psiI, tw, g, rows, nyq_zero, partials, max_blocks, nblocks, st)
+}
+
+template <typename R>
+hipError_t launch_energy_pot(const R* psiR, const R* psiI, const R* V, int64_t n, double* pot,
+                             double* nrm, int nblocks, hipStream_t st) {
+    hipLaunchKernelGGL((k_energy_pot<R>), dim3(nblocks), dim3(256), 0, st, psiR, psiI, V, n, pot, nrm);
+    return hipGetLastError();
+}
+
 static unsigned ew_blocks(int64_t n) {
     int64_t b = (n + 255) / 256;
     return (unsigned)(b < 4096 ? (b < 1 ? 1 : b) : 4096);
@@ -695,7 +817,12 @@ hipError_t launch_fill0(int64_t n, R* y, hipStream_t st) {
                                                 hipStream_t);                                   \
     template hipError_t launch_axpby<R>(int64_t, double, const R*, double, R*, hipStream_t);    \
     template hipError_t launch_xpay<R>(int64_t, const R*, double, const R*, R*, hipStream_t);   \
-    template hipError_t launch_fill0<R>(int64_t, R*, hipStream_t);
+    template hipError_t launch_fill0<R>(int64_t, R*, hipStream_t);                             \
+    template hipError_t launch_energy_axis<R>(int64_t, int, const R*, const R*, const void*,    \
+                                              const EnergyGeom&, int, double*, int, int*,       \
+                                              hipStream_t);                                     \
+    template hipError_t launch_energy_pot<R>(const R*, const R*, const R*, int64_t, double*,    \
+                                             double*, int, hipStream_t);
 
 SPSTD_INSTANTIATE(double)
 SPSTD_INSTANTIATE(float)

@@ -95,4 +95,27 @@ hipError_t launch_xpay(int64_t n, const R* x, double a, const R* y, R* z,
 template <typename R>
 hipError_t launch_fill0(int64_t n, R* y, hipStream_t st);
 
+// Lines of one axis for the energy sums: line L starts at
+// (L / n_lo) * stride_hi + (L % n_lo); element e lies e * stride further on.
+struct EnergyGeom {
+    int64_t nlines;
+    int64_t n_lo;
+    int64_t stride_hi;
+    int64_t stride;
+};
+
+// partials[b] (b < *nblocks <= max_blocks) = block sums of
+// ks^2 |FFT_axis(psiR + i psiI)(k)|^2 over the lines of the axis (ks the
+// signed bin index; the Nyquist bin counts 0 if nyq_zero).  rows: the lines
+// are contiguous (x axis).  Axis length n: 16..16384 for rows, 16..1024 else.
+template <typename R>
+hipError_t launch_energy_axis(int64_t n, int rows, const R* psiR, const R* psiI, const void* tw,
+                              const EnergyGeom& g, int nyq_zero, double* partials, int max_blocks,
+                              int* nblocks, hipStream_t st);
+
+// pot[b], nrm[b] (b < nblocks) = block sums of V |psi|^2 and |psi|^2.
+template <typename R>
+hipError_t launch_energy_pot(const R* psiR, const R* psiI, const R* V, int64_t n, double* pot,
+                             double* nrm, int nblocks, hipStream_t st);
+
 }  // namespace spstd

@@ -62,6 +62,7 @@ class Stats(ctypes.Structure):
 EXPORTS = ["spstd_xmax", "spstd_stable_dt", "spstd_workspace_size", "spstd_plan",
            "spstd_step", "spstd_run", "spstd_plan_info", "spstd_device_fields",
            "spstd_get_state", "spstd_set_state", "spstd_spectrum", "spstd_pass_times",
+           "spstd_energy",
            "spstd_destroy", "spstd_strerror", "spstd_last_error",
            "spstd_batch_workspace_size", "spstd_batch_create", "spstd_batch_load",
            "spstd_batch_step", "spstd_batch_read", "spstd_batch_release",
@@ -92,6 +93,7 @@ def lib():
         L.spstd_set_state.argtypes = [ctypes.c_void_p, pd, pd, c_i64]
         L.spstd_spectrum.argtypes = [pd, c_i64, c_int, c_d, c_d, c_int, pd, pd, P(c_int)]
         L.spstd_pass_times.argtypes = [ctypes.c_void_p, pi64, pd, pd]
+        L.spstd_energy.argtypes = [ctypes.c_void_p, pd]
         L.spstd_destroy.argtypes = [ctypes.c_void_p]
         vp = ctypes.c_void_p
         L.spstd_batch_workspace_size.argtypes = [P(BatchDesc), P(c_sz)]
@@ -247,6 +249,13 @@ class Plan:
         _check(lib().spstd_pass_times(self.h, n.ctypes.data_as(P(c_i64)), _dp(ms), _dp(by)),
                self.h)
         return {PASS_KINDS[i]: (int(n[i]), float(ms[i]), float(by[i])) for i in range(k)}
+
+    def energy(self):
+        """(kinetic, potential, norm) of the current state, each summed over
+        the grid times the cell volume; <H> = (kinetic + potential) / norm."""
+        out = np.zeros(3)
+        _check(lib().spstd_energy(self.h, _dp(out)), self.h)
+        return float(out[0]), float(out[1]), float(out[2])
 
     def info(self):
         st = Stats()

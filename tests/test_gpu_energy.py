@@ -1,0 +1,69 @@
+"""Energy diagnostics on the GPU (spstd_energy) versus the oracle's sums.
+
+The oracle forms <H> pieces from its own K operator; the engine forms the
+kinetic part by Parseval over forward transforms along each axis.  FP64
+bar: each piece within 1e-12 relative; FP32 within 2e-6 (the state is
+rounded to FP32 on the device, which alone moves the sums by ~1e-7).
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1805_03155_amd import spstd
+from paper_1805_03155_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def case(n, seed):
+    rng = np.random.default_rng(seed)
+    N = int(np.prod(n))
+    dx = tuple(0.2 + 0.1 * k for k in range(len(n)))
+    return W.Workload(f"e{seed}", tuple(n), dx, (0.0,) * len(n), 3.0 * rng.random(N),
+                      rng.standard_normal(N), rng.standard_normal(N),
+                      np.array([0], np.int64), 0, W.PAPER, hbar=0.8, mass=1.3)
+
+
+def plan(w, precision=spstd.FP64, nyquist=spstd.NYQ_FULL, steps=0, method=spstd.SYMPLECTIC):
+    return spstd.plan_from_workload(w, precision=precision, nyquist=nyquist,
+                                    nsteps_max=max(steps, 1), method=method)
+
+
+def check(got, want, tol):
+    for g, x in zip(got, want):
+        assert abs(g - x) <= tol * abs(x), (got, want)
+
+
+@pytest.mark.parametrize("n", [(16,), (256,), (8192,), (16384,), (64, 32), (16, 1024),
+                               (32, 16, 16), (16, 64, 128)])
+@pytest.mark.parametrize("nyq", [spstd.NYQ_FULL, spstd.NYQ_ZERO])
+def test_energy_of_a_random_state(n, nyq):
+    w = case(n, seed=len(n) * 1000 + n[0] + nyq)
+    want = oracle.energy(w.psiR, w.psiI, w.V, w.n, w.dx, w.hbar, w.mass, nyq)
+    check(plan(w, nyquist=nyq).energy(), want, 1e-12)
+    check(plan(w, spstd.FP32, nyquist=nyq).energy(), want, 2e-6)
+
+
+@pytest.mark.parametrize("n,steps", [((4096,), 300), ((16384,), 40), ((32, 16, 64), 30)])
+def test_energy_after_a_run_matches_the_oracle_on_the_state(n, steps):
+    w = case(n, seed=7)
+    p = plan(w, steps=steps)
+    p.run(steps)
+    r, i, _ = p.get_state()
+    check(p.energy(), oracle.energy(r, i, w.V, w.n, w.dx, w.hbar, w.mass), 1e-12)
+
+
+def test_energy_bounded_for_spstd_and_decays_for_rk4():
+    w = W.finite_well_1d(seed=0, steps=20000)
+    dt = oracle.stable_dt(*w.coeffs, w.V, w.n, w.dx)
+    for method in (spstd.SYMPLECTIC, spstd.RK4):
+        p = spstd.plan_from_workload(w, dt=dt, nsteps_max=w.steps, method=method)
+        E = [sum(p.energy()[:2])]
+        for _ in range(5):
+            p.step(4000)
+            E.append(sum(p.energy()[:2]))
+        dev = np.array(E) / E[0] - 1.0
+        if method == spstd.SYMPLECTIC:
+            assert np.abs(dev).max() < 1e-5
+        else:
+            assert np.all(np.diff(dev) < 0) and dev[-1] < -1e-3
