@@ -31,6 +31,9 @@ LAP_SPECTRAL = 0
 LAP_FD3 = 1
 METHOD_SYMPLECTIC = 0
 METHOD_RK4 = 1
+BC_PERIODIC = 0
+BC_DIRICHLET = 1
+BC_NEUMANN = 2
 
 
 def build(force: bool = True) -> str:
@@ -55,16 +58,19 @@ def lib():
         L.or_dft_naive.argtypes = [i64, pd, pd, pd, pd, i]
         L.or_fft.argtypes = [i64, pd, pd, i]
         L.or_fft.restype = i
+        pint = P(i)
         L.or_d2_axis.argtypes = [pi64, pd, i, i, pd, pd]
         L.or_d2_axis.restype = i
-        L.or_apply_K.argtypes = [pi64, pd, d, d, i, i, pd, pd, pd]
+        L.or_d2_axis_bc.argtypes = [pi64, pd, i, i, i, pd, pd]
+        L.or_d2_axis_bc.restype = i
+        L.or_apply_K.argtypes = [pi64, pd, d, d, i, i, pint, pd, pd, pd]
         L.or_apply_K.restype = i
         L.or_mode_matrix.argtypes = [i, pd, pd, d, pd]
         L.or_xmax.argtypes = [i, pd, pd]
         L.or_xmax.restype = d
         L.or_rho_bound.argtypes = [pi64, pd, d, d, pd]
         L.or_rho_bound.restype = d
-        L.or_run.argtypes = [pi64, pd, d, d, i, i, i, pd, pd, pd, i, pd, pd, d,
+        L.or_run.argtypes = [pi64, pd, d, d, i, i, pint, i, pd, pd, pd, i, pd, pd, d,
                              i64, i, pi64, pd, pd]
         L.or_run.restype = i
         L.or_num_threads.restype = i
@@ -115,34 +121,50 @@ def fft(x, sign=-1):
     return re + 1j * im
 
 
-def d2_axis(f, n, dx, axis, nyquist=NYQ_FULL):
-    """Spectral second derivative of a real field along one axis (Eq. 9-10).
+def _bc3(bc):
+    """Boundary code per axis (None: periodic everywhere)."""
+    if bc is None:
+        return None
+    b = np.zeros(3, dtype=np.int32)
+    b[: len(bc)] = bc
+    return b
+
+
+def _bcp(b):
+    return b.ctypes.data_as(ctypes.POINTER(ctypes.c_int)) if b is not None else None
+
+
+def d2_axis(f, n, dx, axis, nyquist=NYQ_FULL, bc=BC_PERIODIC):
+    """Spectral second derivative of a real field along one axis (Eq. 9-10;
+    Sec. 2.2 for the walled axes, BC_DIRICHLET / BC_NEUMANN, whose samples
+    sit at cell centres (j + 1/2) dx).
 
     ``f`` is a flat array in row-major [nz][ny][nx] order (x fastest)."""
     n3, d3 = _grid(n, dx)
     f = _f64(f).ravel()
     out = np.empty_like(f)
-    rc = lib().or_d2_axis(_ip(n3), _dp(d3), axis, nyquist, _dp(f), _dp(out))
+    rc = lib().or_d2_axis_bc(_ip(n3), _dp(d3), axis, bc, nyquist, _dp(f), _dp(out))
     if rc:
         raise ValueError("bad grid")
     return out
 
 
 def apply_K(f, V, n, dx, hbar=1.0, mass=1.0, nyquist=NYQ_FULL,
-            laplacian=LAP_SPECTRAL):
+            laplacian=LAP_SPECTRAL, bc=None):
     """K f = -(hbar/2m*) Laplacian f + (V/hbar) f   (Eq. 16)."""
     n3, d3 = _grid(n, dx)
     f = _f64(f).ravel()
     V = None if V is None else _f64(V).ravel()
     out = np.empty_like(f)
-    rc = lib().or_apply_K(_ip(n3), _dp(d3), hbar, mass, nyquist, laplacian,
+    b = _bc3(bc)
+    rc = lib().or_apply_K(_ip(n3), _dp(d3), hbar, mass, nyquist, laplacian, _bcp(b),
                           _dp(V), _dp(f), _dp(out))
     if rc:
         raise ValueError("bad grid")
     return out
 
 
-def energy(psiR, psiI, V, n, dx, hbar=1.0, mass=1.0, nyquist=NYQ_FULL):
+def energy(psiR, psiI, V, n, dx, hbar=1.0, mass=1.0, nyquist=NYQ_FULL, bc=None):
     """Energy diagnostics of psi = psiR + i psiI as plain sums over the grid
     (Sec. 2.2, Eq. 16, times hbar), each times the cell volume:
     kinetic = sum psi* (-(hbar^2/2m*) Laplacian) psi, potential =
@@ -151,8 +173,8 @@ def energy(psiR, psiI, V, n, dx, hbar=1.0, mass=1.0, nyquist=NYQ_FULL):
     _, d3 = _grid(n, dx)
     cell = float(np.prod(d3[: len(n)]))
     r, i = _f64(psiR).ravel(), _f64(psiI).ravel()
-    kr = apply_K(r, None, n, dx, hbar, mass, nyquist)
-    ki = apply_K(i, None, n, dx, hbar, mass, nyquist)
+    kr = apply_K(r, None, n, dx, hbar, mass, nyquist, bc=bc)
+    ki = apply_K(i, None, n, dx, hbar, mass, nyquist, bc=bc)
     kin = hbar * float(np.dot(r, kr) + np.dot(i, ki)) * cell
     rho = r * r + i * i
     pot = float(np.dot(_f64(V).ravel(), rho)) * cell
@@ -187,7 +209,7 @@ def stable_dt(c, d, V, n, dx, hbar=1.0, mass=1.0, fraction=0.5):
 
 def run(psiR, psiI, V, n, dx, c, d, dt, nsteps, probes=(), hbar=1.0, mass=1.0,
         nyquist=NYQ_FULL, laplacian=LAP_SPECTRAL, method=METHOD_SYMPLECTIC,
-        want_norm=False):
+        want_norm=False, bc=None):
     """Advance (psiR, psiI) by ``nsteps`` steps.
 
     Returns (psiR, psiI, probe_series[(nsteps+1), nprobes, 2], norm or None).
@@ -200,7 +222,8 @@ def run(psiR, psiI, V, n, dx, c, d, dt, nsteps, probes=(), hbar=1.0, mass=1.0,
     npr = len(pidx)
     series = np.zeros((nsteps + 1, npr, 2)) if npr else None
     norm = np.zeros(nsteps + 1) if want_norm else None
-    rc = lib().or_run(_ip(n3), _dp(d3), hbar, mass, nyquist, laplacian, method,
+    b = _bc3(bc)
+    rc = lib().or_run(_ip(n3), _dp(d3), hbar, mass, nyquist, laplacian, _bcp(b), method,
                       _dp(V), _dp(pr), _dp(pi_), len(c), _dp(c), _dp(d), float(dt),
                       int(nsteps), npr, _ip(pidx) if npr else None,
                       _dp(series), _dp(norm))

@@ -14,6 +14,9 @@
  *   or_fft            -- iterative radix-2 FFT, twiddles from cos/sin directly
  *   or_d2_axis        -- Sec. 2.1, Eq. (9)-(10): second derivative along one
  *                        axis by forward FT, wavenumber factor, inverse FT
+ *   or_d2_axis_bc     -- Sec. 2.2 (last paragraph): the same along an axis
+ *                        with Dirichlet or Neumann walls, by the sine or
+ *                        cosine basis of the walled axis (plain sums)
  *   or_apply_K        -- Eq. (16): K = -(hbar/2m*) Laplacian + V/hbar
  *   or_mode_matrix    -- Eq. (23): per-mode evolution matrix of one step
  *   or_xmax           -- Eq. (24)-(25): first x with |tr L^d| = 2
@@ -42,6 +45,9 @@
 #endif
 
 #define OR_PI 3.14159265358979323846264338327950288
+#define OR_BC_PERIODIC 0
+#define OR_BC_DIRICHLET 1
+#define OR_BC_NEUMANN 2
 
 /* ------------------------------------------------------------------ */
 /* Discrete Fourier transform by its definition:                       */
@@ -168,11 +174,67 @@ static int64_t pencil_base(const int64_t *n, int axis, int64_t p)
 }
 
 /* ------------------------------------------------------------------ */
-/* out = d^2 f / d(axis)^2 (spectral, Eq. 9-10).  n[3] = (nx, ny, nz); */
-/* L = n[axis] * dx.  Axes of length 1 give zero.                     */
+/* Walled axes (Sec. 2.2, last paragraph: sine transform for Dirichlet,  */
+/* cosine transform for Neumann walls).  Samples sit at cell centres     */
+/* x_j = (j + 1/2) Delta, j = 0..n-1, with walls at x = 0 and x = L =    */
+/* n Delta.  Basis vectors                                               */
+/*   Dirichlet: b_k(j) = sin(pi k (j + 1/2) / n),  k = 1..n              */
+/*   Neumann:   b_k(j) = cos(pi k (j + 1/2) / n),  k = 0..n-1            */
+/* are samples of the wall eigenfunctions, each an exact eigenvector of  */
+/* d^2/dx^2 with eigenvalue -(pi k / L)^2.  f is expanded by orthogonal  */
+/* projection, a_k = sum_j f_j b_k(j) / sum_j b_k(j)^2, and the          */
+/* expansion is differentiated term by term.  The Dirichlet k = n vector */
+/* alternates in sign (the Nyquist mode of the mirrored grid): under the */
+/* ZERO convention its eigenvalue is taken as 0, as for the periodic     */
+/* Nyquist bin.                                                          */
 /* ------------------------------------------------------------------ */
-int or_d2_axis(const int64_t *n, const double *dx, int axis, int nyq_zero,
-               const double *f, double *out)
+static int64_t wall_wavenumber_index(int bc, int64_t row)
+{
+    return bc == OR_BC_DIRICHLET ? row + 1 : row;
+}
+
+static double *wall_basis(int64_t n, int bc)
+{
+    double *B = (double *)malloc(sizeof(double) * (size_t)(n * n));
+    if (!B) return NULL;
+    for (int64_t r = 0; r < n; ++r) {
+        int64_t k = wall_wavenumber_index(bc, r);
+        for (int64_t j = 0; j < n; ++j) {
+            double arg = OR_PI * (double)k * ((double)j + 0.5) / (double)n;
+            B[r * n + j] = bc == OR_BC_DIRICHLET ? sin(arg) : cos(arg);
+        }
+    }
+    return B;
+}
+
+static void d2_pencil_wall(int64_t n, double L, int bc, int nyq_zero,
+                           const double *B, double *f, double *a)
+{
+    for (int64_t r = 0; r < n; ++r) {
+        double num = 0.0, den = 0.0;
+        for (int64_t j = 0; j < n; ++j) {
+            num += f[j] * B[r * n + j];
+            den += B[r * n + j] * B[r * n + j];
+        }
+        int64_t k = wall_wavenumber_index(bc, r);
+        double K = OR_PI * (double)k / L;
+        if (nyq_zero && bc == OR_BC_DIRICHLET && k == n) K = 0.0;
+        a[r] = -K * K * num / den;
+    }
+    for (int64_t j = 0; j < n; ++j) {
+        double s = 0.0;
+        for (int64_t r = 0; r < n; ++r) s += a[r] * B[r * n + j];
+        f[j] = s;
+    }
+}
+
+/* ------------------------------------------------------------------ */
+/* out = d^2 f / d(axis)^2 (spectral, Eq. 9-10).  n[3] = (nx, ny, nz); */
+/* L = n[axis] * dx.  Axes of length 1 give zero.  bc: boundary of the   */
+/* axis (OR_BC_PERIODIC, OR_BC_DIRICHLET, OR_BC_NEUMANN).                */
+/* ------------------------------------------------------------------ */
+int or_d2_axis_bc(const int64_t *n, const double *dx, int axis, int bc,
+                  int nyq_zero, const double *f, double *out)
 {
     int64_t len, stride, npen;
     axis_geometry(n, axis, &len, &stride, &npen);
@@ -180,8 +242,29 @@ int or_d2_axis(const int64_t *n, const double *dx, int axis, int nyq_zero,
         for (int64_t i = 0; i < n[0] * n[1] * n[2]; ++i) out[i] = 0.0;
         return 0;
     }
-    if (!is_pow2(len)) return -1;
     double L = (double)len * dx[axis];
+    if (bc != OR_BC_PERIODIC) {
+        if (bc != OR_BC_DIRICHLET && bc != OR_BC_NEUMANN) return -1;
+        double *B = wall_basis(len, bc);
+        if (!B) return -2;
+#pragma omp parallel
+        {
+            double *v = (double *)malloc(sizeof(double) * (size_t)len);
+            double *a = (double *)malloc(sizeof(double) * (size_t)len);
+#pragma omp for schedule(static)
+            for (int64_t p = 0; p < npen; ++p) {
+                int64_t b = pencil_base(n, axis, p);
+                for (int64_t j = 0; j < len; ++j) v[j] = f[b + j * stride];
+                d2_pencil_wall(len, L, bc, nyq_zero, B, v, a);
+                for (int64_t j = 0; j < len; ++j) out[b + j * stride] = v[j];
+            }
+            free(v);
+            free(a);
+        }
+        free(B);
+        return 0;
+    }
+    if (!is_pow2(len)) return -1;
 #pragma omp parallel
     {
         double *re = (double *)malloc(sizeof(double) * (size_t)len);
@@ -197,6 +280,12 @@ int or_d2_axis(const int64_t *n, const double *dx, int axis, int nyq_zero,
         free(im);
     }
     return 0;
+}
+
+int or_d2_axis(const int64_t *n, const double *dx, int axis, int nyq_zero,
+               const double *f, double *out)
+{
+    return or_d2_axis_bc(n, dx, axis, OR_BC_PERIODIC, nyq_zero, f, out);
 }
 
 /* Second-order central difference (f[i+1] - 2 f[i] + f[i-1]) / dx^2 with
@@ -228,16 +317,17 @@ static int fd3_axis(const int64_t *n, const double *dx, int axis,
 /* laplacian: 0 = spectral (Eq. 9-10), 1 = 3-point finite difference. */
 /* ------------------------------------------------------------------ */
 int or_apply_K(const int64_t *n, const double *dx, double hbar, double mass,
-               int nyq_zero, int laplacian, const double *V, const double *f,
-               double *out)
+               int nyq_zero, int laplacian, const int *bc, const double *V,
+               const double *f, double *out)
 {
     int64_t N = n[0] * n[1] * n[2];
     double *tmp = (double *)malloc(sizeof(double) * (size_t)N);
     if (!tmp) return -2;
     for (int64_t i = 0; i < N; ++i) out[i] = 0.0;
     for (int axis = 0; axis < 3; ++axis) {
-        int rc = laplacian ? fd3_axis(n, dx, axis, f, tmp)
-                           : or_d2_axis(n, dx, axis, nyq_zero, f, tmp);
+        int b = bc ? bc[axis] : OR_BC_PERIODIC;
+        int rc = laplacian ? (b == OR_BC_PERIODIC ? fd3_axis(n, dx, axis, f, tmp) : -1)
+                           : or_d2_axis_bc(n, dx, axis, b, nyq_zero, f, tmp);
         if (rc) { free(tmp); return rc; }
         for (int64_t i = 0; i < N; ++i) out[i] += tmp[i];
     }
@@ -338,7 +428,7 @@ static void record(int nprobes, const int64_t *pidx, const double *r,
 /* cell volume).  Either may be NULL.  psiR, psiI are advanced in place.*/
 /* ------------------------------------------------------------------ */
 int or_run(const int64_t *n, const double *dx, double hbar, double mass,
-           int nyq_zero, int laplacian, int method, const double *V,
+           int nyq_zero, int laplacian, const int *bc, int method, const double *V,
            double *psiR, double *psiI, int m, const double *c,
            const double *d, double dt, int64_t nsteps, int nprobes,
            const int64_t *probe_idx, double *probe_out, double *norm_out)
@@ -362,12 +452,12 @@ int or_run(const int64_t *n, const double *dx, double hbar, double mass,
         if (method == 0) {
             for (int l = 0; l < m && rc == 0; ++l) {
                 if (c[l] != 0.0) { /* A: psi_R <- psi_R + c_l dt K psi_I */
-                    rc = or_apply_K(n, dx, hbar, mass, nyq_zero, laplacian, V,
+                    rc = or_apply_K(n, dx, hbar, mass, nyq_zero, laplacian, bc, V,
                                     psiI, Kf);
                     for (int64_t q = 0; q < N; ++q) psiR[q] += c[l] * dt * Kf[q];
                 }
                 if (d[l] != 0.0 && rc == 0) { /* B: psi_I <- psi_I - d_l dt K psi_R */
-                    rc = or_apply_K(n, dx, hbar, mass, nyq_zero, laplacian, V,
+                    rc = or_apply_K(n, dx, hbar, mass, nyq_zero, laplacian, bc, V,
                                     psiR, Kf);
                     for (int64_t q = 0; q < N; ++q) psiI[q] -= d[l] * dt * Kf[q];
                 }
@@ -379,10 +469,10 @@ int or_run(const int64_t *n, const double *dx, double hbar, double mass,
                     yr[q] = psiR[q] + (s ? a_in[s] * dt * k[s - 1][0][q] : 0.0);
                     yi[q] = psiI[q] + (s ? a_in[s] * dt * k[s - 1][1][q] : 0.0);
                 }
-                rc = or_apply_K(n, dx, hbar, mass, nyq_zero, laplacian, V, yi,
+                rc = or_apply_K(n, dx, hbar, mass, nyq_zero, laplacian, bc, V, yi,
                                 k[s][0]);
                 if (rc == 0)
-                    rc = or_apply_K(n, dx, hbar, mass, nyq_zero, laplacian, V,
+                    rc = or_apply_K(n, dx, hbar, mass, nyq_zero, laplacian, bc, V,
                                     yr, k[s][1]);
                 for (int64_t q = 0; q < N; ++q) k[s][1][q] = -k[s][1][q];
             }

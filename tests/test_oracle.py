@@ -481,6 +481,114 @@ def test_table3_spstd_column_recomputed_at_quarter_bins():
     assert np.all(np.round(4 * ours) == np.round(4 * printed))
 
 
+# ------------------------------ walled axes (Sec. 2.2, last paragraph)
+@pytest.mark.parametrize("bc", [oracle.BC_DIRICHLET, oracle.BC_NEUMANN])
+@pytest.mark.parametrize("nz", [oracle.NYQ_FULL, oracle.NYQ_ZERO])
+def test_wall_modes_are_exact_eigenvectors(bc, nz):
+    # sin / cos (pi k x / L) sampled at the cell centres: d2 = -(pi k / L)^2 f;
+    # the alternating Dirichlet k = n mode follows the Nyquist convention
+    n, dx = 12, 0.3
+    L, x = n * dx, (np.arange(n) + 0.5) * dx
+    ks = range(1, n + 1) if bc == oracle.BC_DIRICHLET else range(0, n)
+    for k in ks:
+        f = (np.sin if bc == oracle.BC_DIRICHLET else np.cos)(np.pi * k * x / L)
+        lam = (np.pi * k / L) ** 2
+        if bc == oracle.BC_DIRICHLET and k == n and nz == oracle.NYQ_ZERO:
+            lam = 0.0
+        got = oracle.d2_axis(f, (n,), (dx,), 0, nyquist=nz, bc=bc)
+        # rounding scales with the largest eigenvalue, (pi/dx)^2
+        assert np.abs(got + lam * f).max() <= 1e-13 * (np.pi / dx) ** 2
+
+
+@pytest.mark.parametrize("bc", [oracle.BC_DIRICHLET, oracle.BC_NEUMANN])
+def test_wall_derivative_equals_the_mirrored_periodic_one(bc):
+    # an independent route: extend the axis by its mirror image (odd about
+    # the walls for Dirichlet, even for Neumann) to a periodic axis of twice
+    # the length and take the oracle's FFT-based derivative there
+    rng = np.random.default_rng(5)
+    n, (nx, ny), (dx, dy) = 16, (8, 16), (0.3, 0.2)
+    f = rng.standard_normal(nx * ny).reshape(ny, nx)
+    sign = -1.0 if bc == oracle.BC_DIRICHLET else 1.0
+    ext = np.concatenate([f, sign * f[::-1]], axis=0)          # y mirrored
+    want = oracle.d2_axis(ext.ravel(), (nx, 2 * ny), (dx, dy), 1).reshape(2 * ny, nx)[:ny]
+    got = oracle.d2_axis(f.ravel(), (nx, ny), (dx, dy), 1, bc=bc).reshape(ny, nx)
+    assert np.abs(got - want).max() <= 1e-13 * np.abs(want).max()
+    # the other axis keeps its own (periodic) derivative
+    px = oracle.d2_axis(f.ravel(), (nx, ny), (dx, dy), 0)
+    kx = oracle.apply_K(f.ravel(), None, (nx, ny), (dx, dy), bc=[oracle.BC_PERIODIC, bc])
+    assert np.abs(kx - (-0.5) * (px + got.ravel())).max() <= 1e-13 * np.abs(kx).max()
+
+
+def test_walled_well_levels_are_the_sine_ladder():
+    # V = 0 between Dirichlet walls: levels hbar theta(x_k)/dt with
+    # x_k = (hbar/2m*)(pi k/L)^2 dt, which tend to hbar^2 pi^2 k^2 / 2m* L^2
+    n, dx = 24, 0.25
+    L = n * dx
+    x = (np.arange(n) + 0.5) * dx
+    psi = np.exp(-((x - 0.37 * L) ** 2) / 0.5)
+    c, d = W.PAPER
+    dt = 0.05 * oracle.xmax(c, d) / oracle.rho_bound(None, (n,), (dx,))
+    _, _, ser, _ = oracle.run(psi, np.zeros(n), None, (n,), (dx,), c, d, dt, 40000, [n // 3],
+                              bc=[oracle.BC_DIRICHLET])
+    E, _ = spectrum.extract(ser, dt, 1.0, 4)
+    assert len(E) == 4
+    for k, e in enumerate(E, start=1):
+        want = modal.theta(c, d, 0.5 * (np.pi * k / L) ** 2 * dt) / dt
+        assert abs(e / want - 1.0) < 5e-5
+        assert abs(e / (0.5 * (np.pi * k / L) ** 2) - 1.0) < 1e-4
+
+
+def test_table2_by_running_the_dirichlet_well():
+    # Sec. 3.1 as run: 10 cells of 0.1 nm between Dirichlet walls, SI units,
+    # dt = (m*/4 hbar) dx^2, 1024 steps, a unit source two cells right of
+    # the centre (cell 6, x = 0.65 nm) and the probe on it; the extracted
+    # frequencies, read on the raw bin grid of a 1024-sample record, give
+    # the printed SPSTD column (omega_7 at 98.52 bins is printed as 98)
+    t, si = GOLD["table2_1d_well"], GOLD["si_constants"]
+    hb, me = si["hbar"], si["m_e"]
+    n = int(round(t["L_m"] / t["dx_m"]))
+    dt = t["dt_factor"] * me / hb * t["dx_m"] ** 2
+    c = GOLD["coefficients"]["c"]
+    d = list(reversed(c))
+    psi = np.zeros(n)
+    psi[6] = 1.0
+    _, _, ser, _ = oracle.run(psi, np.zeros(n), None, (n,), (t["dx_m"],), c, d, dt, t["nmax"],
+                              [6], hbar=hb, mass=me, bc=[oracle.BC_DIRICHLET])
+    dw = 2 * np.pi / (t["nmax"] * dt)
+    got = spectrum.extract(ser, dt, 1.0, 8)[0] / dw
+    printed = np.array(t["spstd"]) * 1e15 / dw
+    assert len(got) == 8
+    assert (np.round(got) == np.round(printed)).sum() >= 7
+    assert np.all(np.abs(np.round(got) - np.round(printed)) <= 1)
+
+
+def test_table3_by_running_the_dirichlet_box():
+    # Sec. 3.2 as run: 10 x 10 cells of 0.1 nm inside Dirichlet walls, dt =
+    # (m*/8 hbar) dx^2, 2048 steps, a unit source at cell (6, 6) (every mode
+    # of the table has weight there) with the probe on it; each printed mode
+    # is matched to the nearest extracted level, read at quarter bins
+    t, si = GOLD["table3_2d_well"], GOLD["si_constants"]
+    hb, me = si["hbar"], si["m_e"]
+    n = int(round(t["L_m"] / t["dx_m"]))
+    dt = t["dt_factor"] * me / hb * t["dx_m"] ** 2
+    c = GOLD["coefficients"]["c"]
+    d = list(reversed(c))
+    psi = np.zeros(n * n)
+    src = 6 * n + 6
+    psi[src] = 1.0
+    _, _, ser, _ = oracle.run(psi, np.zeros(n * n), None, (n, n), (t["dx_m"],) * 2, c, d, dt,
+                              t["nmax"], [src], hbar=hb, mass=me,
+                              bc=[oracle.BC_DIRICHLET, oracle.BC_DIRICHLET])
+    dw = 2 * np.pi / (t["nmax"] * dt)
+    E = spectrum.extract(ser, dt, 1.0, 40)[0] / dw
+    for (a, b), printed in zip(t["modes"], np.array(t["spstd"]) * 1e15 / dw):
+        closed = t["nmax"] * modal.theta(
+            c, d, hb / (2 * me) * (np.pi / t["L_m"]) ** 2 * (a * a + b * b) * dt) / (2 * np.pi)
+        got = E[np.argmin(np.abs(E - closed))]
+        assert abs(got - closed) < 0.02
+        assert np.round(4 * got) == np.round(4 * printed)
+
+
 def test_table4_analytical_column_is_half_integer_ladder():
     a = np.array(GOLD["table4_3d_oscillator"]["analytical"])
     q = np.array(GOLD["table4_3d_oscillator"]["quanta"])
