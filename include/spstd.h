@@ -46,6 +46,7 @@ typedef enum spstd_status {
 enum { SPSTD_FP64 = 0, SPSTD_FP32 = 1 };            /* storage and arithmetic of fields */
 enum { SPSTD_NYQ_FULL = 0, SPSTD_NYQ_ZERO = 1 };    /* Nyquist bin convention, see below */
 enum { SPSTD_SYMPLECTIC = 0, SPSTD_RK4 = 1 };        /* time integrator */
+enum { SPSTD_BC_PERIODIC = 0, SPSTD_BC_DIRICHLET = 1, SPSTD_BC_NEUMANN = 2 };  /* per axis */
 
 #define SPSTD_ALLOW_UNSTABLE 0x1u                    /* flags: accept dt beyond the edge */
 #define SPSTD_EAGER 0x2u                             /* flags: launch kernels one by one
@@ -61,8 +62,8 @@ enum { SPSTD_SYMPLECTIC = 0, SPSTD_RK4 = 1 };        /* time integrator */
  * Problem descriptor (caller-owned; copied by spstd_plan).
  *   ndim         1, 2 or 3.
  *   n[3]         points per axis (unused axes must be 1).  Powers of two;
- *                x: 16..16384; y, z: 16..1024.  Periodic boundaries (Sec. 2.2,
- *                last paragraph: periodic conditions use the DFT).
+ *                periodic x: 16..16384, y, z: 16..1024; walled (see bc)
+ *                x: 16..8192, y, z: 16..512.
  *   dx[3]        grid spacing per axis (> 0), so L_d = n_d * dx_d.
  *   hbar, mass   hbar and m* (> 0); the configs use 1 and 1.
  *   precision    SPSTD_FP64 or SPSTD_FP32 (fields, potential and transforms
@@ -84,9 +85,15 @@ enum { SPSTD_SYMPLECTIC = 0, SPSTD_RK4 = 1 };        /* time integrator */
  *                derivatives, real part kept after each inverse transform).
  *   nprobes      0..64 probe points; probe_idx (host) their linear indices.
  *   flags        SPSTD_ALLOW_UNSTABLE, SPSTD_EAGER, SPSTD_TIMING, SPSTD_NO_RESIDENT
- *                (OR-ed), or 0.  1D symplectic plans with n <= 4096 and at most
- *                8 probes (and no SPSTD_TIMING) run each spstd_step call as one
- *                launch of a kernel that keeps the grid in registers.
+ *                (OR-ed), or 0.  Periodic 1D symplectic plans with at most 8
+ *                probes (and no SPSTD_TIMING) run each spstd_step call as one
+ *                launch of a kernel that keeps the grid on chip.
+ *   bc[3]        boundary per axis (Sec. 2.2, last paragraph):
+ *                SPSTD_BC_PERIODIC (DFT; sample j at j * dx), or walls at
+ *                x = 0 and x = L_d with samples at cell centres (j + 1/2) dx:
+ *                SPSTD_BC_DIRICHLET (psi = 0 at the walls, sine transform),
+ *                SPSTD_BC_NEUMANN (zero normal derivative, cosine transform).
+ *                A zero-initialised descriptor is periodic everywhere.
  */
 typedef struct spstd_desc {
     int ndim;
@@ -103,6 +110,7 @@ typedef struct spstd_desc {
     int nprobes;
     const int64_t *probe_idx;
     uint32_t flags;
+    int bc[3];
 } spstd_desc;
 
 typedef struct spstd_plan_s *spstd_plan_t;

@@ -193,8 +193,17 @@ static int64_t wall_wavenumber_index(int bc, int64_t row)
     return bc == OR_BC_DIRICHLET ? row + 1 : row;
 }
 
+/* The basis of the last (n, bc) asked for is kept: a run applies the same
+ * axis operator at every substep. */
+static double *g_basis = NULL;
+static int64_t g_basis_n = 0;
+static int g_basis_bc = -1;
+
 static double *wall_basis(int64_t n, int bc)
 {
+    if (g_basis && g_basis_n == n && g_basis_bc == bc) return g_basis;
+    free(g_basis);
+    g_basis = NULL;
     double *B = (double *)malloc(sizeof(double) * (size_t)(n * n));
     if (!B) return NULL;
     for (int64_t r = 0; r < n; ++r) {
@@ -204,6 +213,9 @@ static double *wall_basis(int64_t n, int bc)
             B[r * n + j] = bc == OR_BC_DIRICHLET ? sin(arg) : cos(arg);
         }
     }
+    g_basis = B;
+    g_basis_n = n;
+    g_basis_bc = bc;
     return B;
 }
 
@@ -221,11 +233,9 @@ static void d2_pencil_wall(int64_t n, double L, int bc, int nyq_zero,
         if (nyq_zero && bc == OR_BC_DIRICHLET && k == n) K = 0.0;
         a[r] = -K * K * num / den;
     }
-    for (int64_t j = 0; j < n; ++j) {
-        double s = 0.0;
-        for (int64_t r = 0; r < n; ++r) s += a[r] * B[r * n + j];
-        f[j] = s;
-    }
+    for (int64_t j = 0; j < n; ++j) f[j] = 0.0;
+    for (int64_t r = 0; r < n; ++r)
+        for (int64_t j = 0; j < n; ++j) f[j] += a[r] * B[r * n + j];
 }
 
 /* ------------------------------------------------------------------ */
@@ -261,7 +271,6 @@ int or_d2_axis_bc(const int64_t *n, const double *dx, int axis, int bc,
             free(v);
             free(a);
         }
-        free(B);
         return 0;
     }
     if (!is_pow2(len)) return -1;

@@ -95,9 +95,18 @@ static spstd_status validate(const spstd_desc* d, std::string* why) {
     if (!d) { *why = "null descriptor"; return SPSTD_ERR_ARG; }
     if (d->ndim < 1 || d->ndim > 3) { *why = "ndim must be 1, 2 or 3"; return SPSTD_ERR_ARG; }
     for (int a = 0; a < 3; ++a) {
+        if (d->bc[a] != SPSTD_BC_PERIODIC && d->bc[a] != SPSTD_BC_DIRICHLET && d->bc[a] != SPSTD_BC_NEUMANN) {
+            *why = "bad boundary code"; return SPSTD_ERR_ARG;
+        }
         if (a < d->ndim) {
-            bool ok = (a == 0) ? row_len_ok(d->n[a]) : axis_len_ok(d->n[a]);
-            if (!ok) { *why = "axis length must be a power of two (x: 16..16384, y/z: 16..1024)"; return SPSTD_ERR_ARG; }
+            const bool wall = d->bc[a] != SPSTD_BC_PERIODIC;
+            const int64_t nt = wall ? 2 * d->n[a] : d->n[a];
+            bool ok = (a == 0) ? row_len_ok(nt) : axis_len_ok(nt);
+            if (wall && d->n[a] < 16) ok = false;
+            if (!ok) {
+                *why = "axis length must be a power of two (x: 16..16384, y/z: 16..1024; walled: half that)";
+                return SPSTD_ERR_ARG;
+            }
             if (!(d->dx[a] > 0.0) || !std::isfinite(d->dx[a])) { *why = "dx must be positive"; return SPSTD_ERR_ARG; }
         } else if (d->n[a] != 1) {
             *why = "unused axes must have length 1";
@@ -153,7 +162,7 @@ static Layout layout_of(const spstd_desc* d, int64_t nsteps_max) {
     }
     for (int a = 0; a < 3; ++a) {
         L.tw[a] = off;
-        if (a < d->ndim) off += align256((size_t)d->n[a] * 2 * esz);
+        if (a < d->ndim) off += align256((size_t)transform_len(*d, a) * 2 * esz);
     }
     L.pidx = off; off += align256(sizeof(int64_t) * (size_t)(d->nprobes > 0 ? d->nprobes : 1));
     L.probes = off;
@@ -199,6 +208,20 @@ static spstd_status upload(Plan* p, size_t off, const double* src) {
     return SPSTD_OK;
 }
 
+static_assert(WALL_NONE == SPSTD_BC_PERIODIC && WALL_DIRICHLET == SPSTD_BC_DIRICHLET &&
+                  WALL_NEUMANN == SPSTD_BC_NEUMANN,
+              "kernel wall codes follow the ABI's boundary codes");
+
+static bool walled(const Plan* p, int a) { return p->d.bc[a] != SPSTD_BC_PERIODIC; }
+
+// Lines of axis a of the plan's grid, for the line-generic kernels.
+static EnergyGeom lines_of(const Plan* p, int a) {
+    const int64_t nx = p->d.n[0], ny = p->d.n[1], nz = p->d.n[2];
+    if (a == 0) return EnergyGeom{ny * nz, 1, nx, 1};
+    if (a == 1) return EnergyGeom{nz * nx, nx, nx * ny, nx};
+    return EnergyGeom{ny * nx, nx * ny, p->N, nx * ny};
+}
+
 // dst += T_{y,z} src for every axis beyond x, with the scale columns of the
 // A (ab = 0) or B (ab = 1) substep
 template <typename R>
@@ -206,11 +229,27 @@ static hipError_t yz_passes(Plan* p, const R* src, R* dst, const ScaleRef& sc, i
     for (int a = 1; a < p->d.ndim; ++a) {
         PassTimer tm(p, a == 1 ? SPSTD_PASS_Y : SPSTD_PASS_Z);
         const int col = (ab ? SC_KXB : SC_KXA) + a;
-        hipError_t e = launch_axis_acc<R>(p->d.n[a], src, dst, p->ws + p->L.tw[a], axis_geom_of(p->d, a, 1),
-                                          sc, col, p->d.nyquist, p->st);
+        hipError_t e = walled(p, a)
+            ? launch_wall_acc<R>(p->d.n[a], 0, p->d.bc[a], src, dst, nullptr, p->ws + p->L.tw[a],
+                                 lines_of(p, a), p->N, sc, col, -1, p->d.nyquist, p->st)
+            : launch_axis_acc<R>(p->d.n[a], src, dst, p->ws + p->L.tw[a], axis_geom_of(p->d, a, 1),
+                                 sc, col, p->d.nyquist, p->st);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
+}
+
+// dst += T_x src + (V/hbar) src with the scale columns (kcol, pcol): one x
+// half-stage.
+template <typename R>
+static hipError_t x_half(Plan* p, const R* src, R* dst, const ScaleRef& sc, int kcol, int pcol) {
+    const R* V = F<R>(p, p->L.V);
+    const void* twx = p->ws + p->L.tw[0];
+    if (walled(p, 0))
+        return launch_wall_acc<R>(p->d.n[0], 1, p->d.bc[0], src, dst, V, twx, lines_of(p, 0), p->N, sc, kcol,
+                                  pcol, p->d.nyquist, p->st);
+    const RowGeom rg{p->N / p->d.n[0], p->N / p->d.n[0]};
+    return launch_x_acc<R>(p->d.n[0], src, dst, V, twx, rg, sc, kcol, pcol, p->d.nyquist, p->st);
 }
 
 template <typename R>
@@ -227,14 +266,18 @@ static hipError_t enqueue_symplectic_step(Plan* p) {
         const ScaleRef sc{p->ws + p->L.scales, p->d.m + 1, l};
         if (a) e = yz_passes<R>(p, pi, pr, sc, 0);
         if (e != hipSuccess) break;
-        if (a || b) {
-            PassTimer tm(p, (a && b) ? SPSTD_PASS_XAB : SPSTD_PASS_X);
-            if (a && b)
-                e = launch_x_ab<R>(nx, pr, pi, V, twx, rg, sc, p->d.nyquist, p->st);
-            else if (a)
-                e = launch_x_acc<R>(nx, pi, pr, V, twx, rg, sc, SC_KXA, SC_PA, p->d.nyquist, p->st);
-            else
-                e = launch_x_acc<R>(nx, pr, pi, V, twx, rg, sc, SC_KXB, SC_PB, p->d.nyquist, p->st);
+        if (a && b && !walled(p, 0)) {
+            PassTimer tm(p, SPSTD_PASS_XAB);
+            e = launch_x_ab<R>(nx, pr, pi, V, twx, rg, sc, p->d.nyquist, p->st);
+        } else {
+            if (a) {
+                PassTimer tm(p, SPSTD_PASS_X);
+                e = x_half<R>(p, pi, pr, sc, SC_KXA, SC_PA);
+            }
+            if (b && e == hipSuccess) {
+                PassTimer tm(p, SPSTD_PASS_X);
+                e = x_half<R>(p, pr, pi, sc, SC_KXB, SC_PB);
+            }
         }
         if (e != hipSuccess) break;
         if (b) e = yz_passes<R>(p, pr, pi, sc, 1);
@@ -246,15 +289,12 @@ static hipError_t enqueue_symplectic_step(Plan* p) {
 // the scale table holds coefficient +1 in its A columns and -1 in its B columns
 template <typename R>
 static hipError_t apply_K(Plan* p, const R* src, R* kout, double coef) {
-    const R* V = F<R>(p, p->L.V);
     const ScaleRef sc{p->ws + p->L.scales, p->d.m + 1, p->d.m};
     const int ab = coef > 0.0 ? 0 : 1;
     hipError_t e = launch_fill0<R>(p->N, kout, p->st);
     if (e == hipSuccess) e = yz_passes<R>(p, src, kout, sc, ab);
     PassTimer tm(p, SPSTD_PASS_X);
-    if (e == hipSuccess)
-        e = launch_x_acc<R>(p->d.n[0], src, kout, V, p->ws + p->L.tw[0], RowGeom{p->N / p->d.n[0], p->N / p->d.n[0]},
-                            sc, ab ? SC_KXB : SC_KXA, ab ? SC_PB : SC_PA, p->d.nyquist, p->st);
+    if (e == hipSuccess) e = x_half<R>(p, src, kout, sc, ab ? SC_KXB : SC_KXA, ab ? SC_PB : SC_PA);
     return e;
 }
 
@@ -293,7 +333,7 @@ static hipError_t enqueue_rk4_step(Plan* p) {
 
 static bool uses_resident(const Plan* p) {
     const spstd_desc& d = p->d;
-    return d.ndim == 1 && d.method == SPSTD_SYMPLECTIC && resident_len_ok(d.n[0]) &&
+    return d.ndim == 1 && d.bc[0] == SPSTD_BC_PERIODIC && d.method == SPSTD_SYMPLECTIC && resident_len_ok(d.n[0]) &&
            d.nprobes <= kResMaxProbes && d.m <= SPSTD_MAX_STAGES &&
            !(d.flags & (SPSTD_NO_RESIDENT | SPSTD_TIMING));
 }
@@ -404,14 +444,10 @@ static spstd_status compute_norm(Plan* p, double* out) {
 template <typename R>
 static spstd_status compute_energy(Plan* p, double* out) {
     double* part = reinterpret_cast<double*>(p->ws + p->L.partials) + kNormBlocks;
-    const int64_t nx = p->d.n[0], ny = p->d.ndim > 1 ? p->d.n[1] : 1, nz = p->d.ndim > 2 ? p->d.n[2] : 1;
-    const EnergyGeom geo[3] = {{ny * nz, 1, nx, 1},
-                               {nz * nx, nx, nx * ny, nx},
-                               {ny * nx, nx * ny, p->N, nx * ny}};
     int nb[3] = {0, 0, 0};
     for (int a = 0; a < p->d.ndim; ++a)
-        HIPCHK(launch_energy_axis<R>(p->d.n[a], a == 0, F<R>(p, p->L.psiR), F<R>(p, p->L.psiI),
-                                     p->ws + p->L.tw[a], geo[a], p->d.nyquist == SPSTD_NYQ_ZERO,
+        HIPCHK(launch_energy_axis<R>(p->d.n[a], a == 0, p->d.bc[a], F<R>(p, p->L.psiR), F<R>(p, p->L.psiI),
+                                     p->ws + p->L.tw[a], lines_of(p, a), p->d.nyquist == SPSTD_NYQ_ZERO,
                                      part + a * kNormBlocks, kNormBlocks, &nb[a], p->st));
     HIPCHK(launch_energy_pot<R>(F<R>(p, p->L.psiR), F<R>(p, p->L.psiI), F<R>(p, p->L.V), p->N,
                                 part + 3 * kNormBlocks, part + 4 * kNormBlocks, kNormBlocks, p->st));
@@ -423,9 +459,11 @@ static spstd_status compute_energy(Plan* p, double* out) {
     for (int a = 0; a < p->d.ndim; ++a) {
         double s = 0.0;
         for (int b = 0; b < nb[a]; ++b) s += h[(size_t)a * kNormBlocks + b];
-        const double L = (double)p->d.n[a] * p->d.dx[a];
-        const double k1 = 2.0 * kPi / L;
-        kin += hb * hb / (2.0 * ms) * k1 * k1 / (double)p->d.n[a] * s;
+        // a walled line enters as its mirrored extension, which counts each
+        // sample twice
+        const double nt = (double)transform_len(p->d, a);
+        const double k1 = 2.0 * kPi / (nt * p->d.dx[a]);
+        kin += hb * hb / (2.0 * ms) * k1 * k1 / nt * s * (walled(p, a) ? 0.5 : 1.0);
     }
     double pot = 0.0, nrm = 0.0;
     for (int b = 0; b < kNormBlocks; ++b) {
@@ -445,7 +483,7 @@ static spstd_status plan_init(Plan* p, const double* V, const double* psiR0, con
     if ((s = upload<R>(p, p->L.psiI, psiI0)) != SPSTD_OK) return s;
     if ((s = upload<R>(p, p->L.V, V)) != SPSTD_OK) return s;
     for (int a = 0; a < p->d.ndim; ++a) {
-        std::vector<double> t = twiddles(p->d.n[a]);
+        std::vector<double> t = twiddles(transform_len(p->d, a));
         if (sizeof(R) == 8) {
             HIPCHK(hipMemcpyAsync(p->ws + p->L.tw[a], t.data(), t.size() * 8, hipMemcpyHostToDevice, p->st));
             HIPCHK(hipStreamSynchronize(p->st));

@@ -91,12 +91,20 @@ static inline std::vector<double> twiddles(int64_t n) {
     return t;
 }
 
-// kinetic scale of axis a for substep coefficient coef: coef (hbar/2m) (2 pi/L)^2 / n
+// Transform length of axis a: n, or 2n for a walled axis (its samples and
+// their mirror image form one period of length 2L).
+static inline int64_t transform_len(const spstd_desc& d, int a) {
+    return d.bc[a] == SPSTD_BC_PERIODIC ? d.n[a] : 2 * d.n[a];
+}
+
+// kinetic scale of axis a for substep coefficient coef:
+// coef (hbar/2m) (2 pi/P)^2 / nt with nt the transform length and P = nt dx
+// its period (the bare pass multiplies bin kk by kk^2).
 static inline double kin_scale(const spstd_desc& d, int a, double coef) {
     if (a >= d.ndim) return 0.0;
-    const double L = (double)d.n[a] * d.dx[a];
-    const double k1 = 2.0 * kPi / L;
-    return coef * d.hbar / (2.0 * d.mass) * k1 * k1 / (double)d.n[a];
+    const double nt = (double)transform_len(d, a);
+    const double k1 = 2.0 * kPi / (nt * d.dx[a]);
+    return coef * d.hbar / (2.0 * d.mass) * k1 * k1 / nt;
 }
 
 // One row of the scale table for substep coefficients a (A) and b (B).

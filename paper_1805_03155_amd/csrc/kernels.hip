@@ -24,7 +24,13 @@ bool row_len_ok(int64_t n) { return n >= 16 && n <= 16384 && (n & (n - 1)) == 0;
 
 // Build-time tuning switches (defaults are the measured choices):
 //   TW_PRODUCTS_*  twiddles of a pass from two table reads and products
-//   SPLIT_*        real-then-imaginary LDS exchange (half the LDS per wave)
+//   SPLIT_*        real-then-imaginary LDS exchange (half the LDS per wave);
+//                  SPLIT_XAB_F32 for the fused FP32 x pass, which is faster
+//                  with the joint exchange while the other FP32 passes gain
+//                  occupancy from the split one
+//   YZ_PPL_F64, YZ_MIN_WAVES, YZ_NT  y/z pass variants measured slower
+//                  (two pencils per FP64 lane group, a forced 4 waves per
+//                  SIMD, non-temporal loads and stores)
 //   X_RELOAD       x passes re-read their inputs in the epilogue instead of
 //                  keeping them in registers through the transforms
 //   MIN_WAVES      minimum waves per SIMD requested for the pass kernels
@@ -47,7 +53,10 @@ bool row_len_ok(int64_t n) { return n >= 16 && n <= 16384 && (n & (n - 1)) == 0;
 #define SPSTD_SPLIT_F64 1
 #endif
 #ifndef SPSTD_SPLIT_F32
-#define SPSTD_SPLIT_F32 0
+#define SPSTD_SPLIT_F32 1
+#endif
+#ifndef SPSTD_SPLIT_XAB_F32
+#define SPSTD_SPLIT_XAB_F32 0
 #endif
 #ifndef SPSTD_X_RELOAD
 #define SPSTD_X_RELOAD 0
@@ -57,6 +66,15 @@ bool row_len_ok(int64_t n) { return n >= 16 && n <= 16384 && (n & (n - 1)) == 0;
 #endif
 #ifndef SPSTD_YZ_PPL_F32
 #define SPSTD_YZ_PPL_F32 2
+#endif
+#ifndef SPSTD_YZ_PPL_F64
+#define SPSTD_YZ_PPL_F64 1
+#endif
+#ifndef SPSTD_YZ_MIN_WAVES
+#define SPSTD_YZ_MIN_WAVES 0
+#endif
+#ifndef SPSTD_YZ_NT
+#define SPSTD_YZ_NT 0
 #endif
 #ifndef SPSTD_WPB
 #define SPSTD_WPB 4
@@ -76,6 +94,11 @@ bool row_len_ok(int64_t n) { return n >= 16 && n <= 16384 && (n & (n - 1)) == 0;
 #else
 #define SPSTD_WAVES_ATTR
 #endif
+#if SPSTD_YZ_MIN_WAVES > 0
+#define SPSTD_YZ_WAVES_ATTR __attribute__((amdgpu_waves_per_eu(SPSTD_YZ_MIN_WAVES)))
+#else
+#define SPSTD_YZ_WAVES_ATTR SPSTD_WAVES_ATTR
+#endif
 
 template <typename R>
 struct tuning;
@@ -83,12 +106,14 @@ template <>
 struct tuning<double> {
     static constexpr bool PRODUCTS = SPSTD_TW_PRODUCTS_F64;
     static constexpr bool SPLIT = SPSTD_SPLIT_F64;
-    static constexpr int YZ_PPL = 1;
+    static constexpr bool SPLIT_XAB = SPSTD_SPLIT_F64;
+    static constexpr int YZ_PPL = SPSTD_YZ_PPL_F64;
 };
 template <>
 struct tuning<float> {
     static constexpr bool PRODUCTS = SPSTD_TW_PRODUCTS_F32;
     static constexpr bool SPLIT = SPSTD_SPLIT_F32;
+    static constexpr bool SPLIT_XAB = SPSTD_SPLIT_XAB_F32;
     static constexpr int YZ_PPL = SPSTD_YZ_PPL_F32;
 };
 
@@ -151,8 +176,19 @@ struct vec_of<double, 2> { using type = double4; };
 template <>
 struct vec_of<float, 2> { using type = float4; };
 
+// Streaming variant: the passes touch each element once, so the loads and
+// stores may bypass cache retention (SPSTD_YZ_NT).
+template <typename R, int P>
+using ext_vec = R __attribute__((ext_vector_type(2 * P)));
+
 template <typename R, int P>
 __device__ __forceinline__ void load_group(const R* src, cpx<R> (&v)[P][16], int e) {
+    if constexpr (SPSTD_YZ_NT) {
+        const ext_vec<R, P> a = __builtin_nontemporal_load(reinterpret_cast<const ext_vec<R, P>*>(src));
+#pragma unroll
+        for (int q = 0; q < P; ++q) v[q][e] = cpx<R>{a[2 * q], a[2 * q + 1]};
+        return;
+    }
     using V = typename vec_of<R, P>::type;
     const V a = *reinterpret_cast<const V*>(src);
     if constexpr (P == 1) {
@@ -165,6 +201,17 @@ __device__ __forceinline__ void load_group(const R* src, cpx<R> (&v)[P][16], int
 
 template <typename R, int P>
 __device__ __forceinline__ void add_group(R* dst, const cpx<R> (&v)[P][16], int e) {
+    if constexpr (SPSTD_YZ_NT) {
+        ext_vec<R, P>* q = reinterpret_cast<ext_vec<R, P>*>(dst);
+        ext_vec<R, P> a = __builtin_nontemporal_load(q);
+#pragma unroll
+        for (int k = 0; k < P; ++k) {
+            a[2 * k] += v[k][e].x;
+            a[2 * k + 1] += v[k][e].y;
+        }
+        __builtin_nontemporal_store(a, q);
+        return;
+    }
     using V = typename vec_of<R, P>::type;
     V* q = reinterpret_cast<V*>(dst);
     V a = *q;
@@ -184,7 +231,7 @@ __device__ __forceinline__ void add_group(R* dst, const cpx<R> (&v)[P][16], int 
 // neighbouring columns), position j = l / PPW.
 // ---------------------------------------------------------------------------
 template <typename R, int N, int WPB, int P>
-__global__ __launch_bounds__(64 * WPB) SPSTD_WAVES_ATTR void k_axis_acc(
+__global__ __launch_bounds__(64 * WPB) SPSTD_YZ_WAVES_ATTR void k_axis_acc(
     const R* __restrict__ src, R* __restrict__ dst, const cpx<R>* __restrict__ tw, AxisGeom g,
     ScaleRef sc, int col, int nyq_zero) {
     using C = pencil_cfg<N>;
@@ -253,14 +300,14 @@ __global__ __launch_bounds__(64 * WPB) SPSTD_WAVES_ATTR void k_axis_acc(
 // (neighbouring lanes read neighbouring x), or one pencil per block for
 // N > 1024.
 // ---------------------------------------------------------------------------
-template <typename R, int N, int WPB>
+template <typename R, int N, int WPB, bool SPLIT_PREF = tuning<R>::SPLIT>
 struct row_map {
     using C = pencil_cfg<N>;
     static constexpr int PPB = C::WAVE ? WPB * C::PPW : 1;   // pencils per block
     static constexpr int THREADS = C::WAVE ? 64 * WPB : C::T;
     static constexpr int LS = lds_size<N>::value;
     // large pencils always exchange re and im in turn to stay within LDS
-    static constexpr bool SPLIT = C::WAVE ? tuning<R>::SPLIT : true;
+    static constexpr bool SPLIT = C::WAVE ? SPLIT_PREF : true;
     static constexpr int SL = (SPLIT ? 1 : 2) * LS;
     // a 16-point pencil is one radix-16 pass in registers: no LDS at all
     static constexpr int LDS_REALS = N == 16 ? 1 : PPB * SL;
@@ -368,7 +415,7 @@ __global__ __launch_bounds__((row_map<R, N, WPB>::THREADS)) SPSTD_WAVES_ATTR voi
     R* __restrict__ psiR, R* __restrict__ psiI, const R* __restrict__ V,
     const cpx<R>* __restrict__ tw, RowGeom rg, ScaleRef sc, int nyq_zero) {
     using C = pencil_cfg<N>;
-    using M = row_map<R, N, WPB>;
+    using M = row_map<R, N, WPB, tuning<R>::SPLIT_XAB>;
     using TU = tuning<R>;
     __shared__ R lds[M::LDS_REALS];
     const row_lane<R, N, WPB> L = row_coords<R, N, WPB>();
@@ -518,10 +565,22 @@ __device__ __forceinline__ void block_sum_store(double s, double* out) {
     }
 }
 
-template <typename R, int N, bool ROWS>
+// Transform position i = j + T e of an N-point pencil read from memory.  A
+// periodic line maps i to itself.  A walled line holds n = N/2 cell-centred
+// samples; the transform sees it extended by its mirror image about the wall
+// at x = L (position N - 1 - i for i >= n), times msign (-1 for Dirichlet,
+// odd about the walls; +1 for Neumann, even).  The extended line has period
+// 2L, so the pencil transform of length 2n diagonalises the walled operator.
+template <int N, bool WALL>
+__device__ __forceinline__ int line_pos(int j, int e) {
+    constexpr int T = N / 16;
+    return (WALL && e >= 8) ? N - 1 - (j + T * e) : j + T * e;
+}
+
+template <typename R, int N, bool ROWS, bool WALL>
 __global__ __launch_bounds__((row_map<R, N, SPSTD_WPB>::THREADS)) void k_energy_axis(
     const R* __restrict__ psiR, const R* __restrict__ psiI, const cpx<R>* __restrict__ tw,
-    EnergyGeom g, int nyq_zero, double* __restrict__ partials) {
+    EnergyGeom g, int nyq_zero, R msign, double* __restrict__ partials) {
     using C = pencil_cfg<N>;
     using M = row_map<R, N, SPSTD_WPB>;
     using TU = tuning<R>;
@@ -546,8 +605,9 @@ __global__ __launch_bounds__((row_map<R, N, SPSTD_WPB>::THREADS)) void k_energy_
         cpx<R> v[1][16];
 #pragma unroll
         for (int e = 0; e < 16; ++e) {
-            const int64_t q = base + (int64_t)(j + C::T * e) * g.stride;
-            v[0][e] = valid ? cpx<R>{psiR[q], psiI[q]} : cpx<R>{(R)0, (R)0};
+            const int64_t q = base + (int64_t)line_pos<N, WALL>(j, e) * g.stride;
+            const R sg = (WALL && e >= 8) ? msign : (R)1;
+            v[0][e] = valid ? cpx<R>{sg * psiR[q], sg * psiI[q]} : cpx<R>{(R)0, (R)0};
         }
         fft_pencils<R, N, false, C::WAVE, M::SPLIT, TU::PRODUCTS, 1>(v, j, lds + pin * M::SL, M::SL, tw);
 #pragma unroll
@@ -561,6 +621,73 @@ __global__ __launch_bounds__((row_map<R, N, SPSTD_WPB>::THREADS)) void k_energy_
         }
     }
     block_sum_store<M::THREADS>(acc, partials + blockIdx.x);
+}
+
+// ---------------------------------------------------------------------------
+// Pass along a walled axis (Sec. 2.2, last paragraph: sine transform between
+// Dirichlet walls, cosine transform between Neumann walls), any axis:
+//   dst += k * T_axis src  (+ p * V * src when pcol >= 0)
+// on the cell-centred samples of the axis, with T_axis applied as the
+// periodic operator of the mirrored line (line_pos): an N = 2n point
+// transform whose bins are the wall modes.  Two neighbouring lines (rows, or
+// x columns) form one complex pencil; only the n stored samples are updated.
+// ROWS: the lines are contiguous (x axis), lanes run along them; otherwise
+// neighbouring lanes take neighbouring lines.  Instance of a line: its first
+// sample / npts (stacked instances of a batch).
+// ---------------------------------------------------------------------------
+template <typename R, int N, bool ROWS>
+__global__ __launch_bounds__((row_map<R, N, SPSTD_WPB>::THREADS)) void k_wall_acc(
+    const R* __restrict__ src, R* __restrict__ dst, const R* __restrict__ V,
+    const cpx<R>* __restrict__ tw, EnergyGeom g, int64_t npts, ScaleRef sc, int kcol, int pcol,
+    int nyq_zero, R msign) {
+    using C = pencil_cfg<N>;
+    using M = row_map<R, N, SPSTD_WPB>;
+    using TU = tuning<R>;
+    __shared__ R lds[M::LDS_REALS];
+    int j, pin;
+    if constexpr (C::WAVE) {
+        const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+        const int pw = ROWS ? lane / C::T : lane % C::PPW;
+        j = ROWS ? lane % C::T : lane / C::PPW;
+        pin = wave * C::PPW + pw;
+    } else {
+        j = threadIdx.x;
+        pin = 0;
+    }
+    const int64_t q = (int64_t)blockIdx.x * M::PPB + pin;     // pencil: lines 2q, 2q + 1
+    const bool ok0 = 2 * q < g.nlines, ok1 = 2 * q + 1 < g.nlines;
+    const int64_t L0 = ok0 ? 2 * q : 0, L1 = ok1 ? 2 * q + 1 : L0;
+    const int64_t b0 = (L0 / g.n_lo) * g.stride_hi + (L0 % g.n_lo);
+    const int64_t b1 = (L1 / g.n_lo) * g.stride_hi + (L1 % g.n_lo);
+    const int64_t i0 = b0 / npts, i1 = b1 / npts;
+    const R k0 = scale_of<R>(sc, i0, kcol), k1 = scale_of<R>(sc, i1, kcol);
+    const R p0 = pcol >= 0 ? scale_of<R>(sc, i0, pcol) : (R)0;
+    const R p1 = pcol >= 0 ? scale_of<R>(sc, i1, pcol) : (R)0;
+    cpx<R> v[1][16];
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+        const int64_t m = (int64_t)line_pos<N, true>(j, e) * g.stride;
+        const R sg = e >= 8 ? msign : (R)1;
+        v[0][e] = cpx<R>{ok0 ? sg * src[b0 + m] : (R)0, ok1 ? sg * src[b1 + m] : (R)0};
+    }
+    R* l0 = lds + pin * M::SL;
+    fft_pencils<R, N, false, C::WAVE, M::SPLIT, TU::PRODUCTS, 1>(v, j, l0, M::SL, tw);
+    apply_k2<R, N>(v[0], j, nyq_zero);
+    fft_pencils<R, N, true, C::WAVE, M::SPLIT, TU::PRODUCTS, 1>(v, j, l0, M::SL, tw);
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        const int64_t m = (int64_t)(j + C::T * e) * g.stride;
+        if (ok0) {
+            R t = dst[b0 + m] + k0 * v[0][e].x;
+            if (pcol >= 0) t += p0 * V[b0 + m] * src[b0 + m];
+            dst[b0 + m] = t;
+        }
+        if (ok1) {
+            R t = dst[b1 + m] + k1 * v[0][e].y;
+            if (pcol >= 0) t += p1 * V[b1 + m] * src[b1 + m];
+            dst[b1 + m] = t;
+        }
+    }
 }
 
 // Per-block FP64 partials of sum V (psiR^2 + psiI^2) and of sum psiR^2 + psiI^2.
@@ -744,30 +871,77 @@ hipError_t launch_norm_partials(const R* psiR, const R* psiI, int64_t n, double*
 
 template <typename R, int N>
 static hipError_t energy_axis_n(const R* psiR, const R* psiI, const void* tw, const EnergyGeom& g,
-                                int rows, int nyq_zero, double* partials, int max_blocks, int* nblocks,
-                                hipStream_t st) {
+                                int rows, int wall, int nyq_zero, double* partials, int max_blocks,
+                                int* nblocks, hipStream_t st) {
     using M = row_map<R, N, kWPB>;
     int64_t b = (g.nlines + M::PPB - 1) / M::PPB;
     if (b > max_blocks) b = max_blocks;
     if (b < 1) b = 1;
     *nblocks = (int)b;
-    if (rows)
-        hipLaunchKernelGGL((k_energy_axis<R, N, true>), dim3((unsigned)b), dim3(M::THREADS), 0, st, psiR,
-                           psiI, (const cpx<R>*)tw, g, nyq_zero, partials);
-    else if constexpr (pencil_cfg<N>::WAVE)
-        hipLaunchKernelGGL((k_energy_axis<R, N, false>), dim3((unsigned)b), dim3(M::THREADS), 0, st, psiR,
-                           psiI, (const cpx<R>*)tw, g, nyq_zero, partials);
-    else
+    const R ms = wall == WALL_NEUMANN ? (R)1 : (R)-1;
+    const cpx<R>* t = (const cpx<R>*)tw;
+#define SPSTD_ENERGY_LAUNCH(ROWS_, WALL_)                                                              \
+    hipLaunchKernelGGL((k_energy_axis<R, N, ROWS_, WALL_>), dim3((unsigned)b), dim3(M::THREADS), 0, st, \
+                       psiR, psiI, t, g, nyq_zero, ms, partials)
+    if (rows) {
+        if (wall) SPSTD_ENERGY_LAUNCH(true, true);
+        else SPSTD_ENERGY_LAUNCH(true, false);
+    } else if constexpr (pencil_cfg<N>::WAVE) {
+        if (wall) SPSTD_ENERGY_LAUNCH(false, true);
+        else SPSTD_ENERGY_LAUNCH(false, false);
+    } else {
         return hipErrorInvalidValue;   // y/z lines are at most 1024 long
+    }
+#undef SPSTD_ENERGY_LAUNCH
     return hipGetLastError();
 }
 
 template <typename R>
-hipError_t launch_energy_axis(int64_t n, int rows, const R* psiR, const R* psiI, const void* tw,
-                              const EnergyGeom& g, int nyq_zero, double* partials, int max_blocks,
-                              int* nblocks, hipStream_t st) {
-    const int64_t nx = n;
-    SPSTD_ROW_CASES(energy_axis_n, psiR, psiI, tw, g, rows, nyq_zero, partials, max_blocks, nblocks, st)
+hipError_t launch_energy_axis(int64_t n, int rows, int wall, const R* psiR, const R* psiI,
+                              const void* tw, const EnergyGeom& g, int nyq_zero, double* partials,
+                              int max_blocks, int* nblocks, hipStream_t st) {
+    const int64_t nx = wall ? 2 * n : n;
+    SPSTD_ROW_CASES(energy_axis_n, psiR, psiI, tw, g, rows, wall, nyq_zero, partials, max_blocks, nblocks, st)
+}
+
+template <typename R, int N>
+static hipError_t wall_acc_n(const R* src, R* dst, const R* V, const void* tw, const EnergyGeom& g,
+                             int64_t npts, const ScaleRef& sc, int kcol, int pcol, int rows, int wall,
+                             int nyq_zero, hipStream_t st) {
+    using M = row_map<R, N, kWPB>;
+    const int64_t npen = (g.nlines + 1) / 2;
+    const int64_t b = (npen + M::PPB - 1) / M::PPB;
+    const R ms = wall == WALL_NEUMANN ? (R)1 : (R)-1;
+    if (rows)
+        hipLaunchKernelGGL((k_wall_acc<R, N, true>), dim3((unsigned)b), dim3(M::THREADS), 0, st, src, dst, V,
+                           (const cpx<R>*)tw, g, npts, sc, kcol, pcol, nyq_zero, ms);
+    else if constexpr (pencil_cfg<N>::WAVE)
+        hipLaunchKernelGGL((k_wall_acc<R, N, false>), dim3((unsigned)b), dim3(M::THREADS), 0, st, src, dst, V,
+                           (const cpx<R>*)tw, g, npts, sc, kcol, pcol, nyq_zero, ms);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_wall_acc(int64_t n, int rows, int wall, const R* src, R* dst, const R* V,
+                           const void* tw, const EnergyGeom& g, int64_t npts, const ScaleRef& sc,
+                           int kcol, int pcol, int nyq_zero, hipStream_t st) {
+    if (wall != WALL_DIRICHLET && wall != WALL_NEUMANN) return hipErrorInvalidValue;
+    const int64_t nx = 2 * n;
+    switch (nx) {
+        case 32: return wall_acc_n<R, 32>(src, dst, V, tw, g, npts, sc, kcol, pcol, rows, wall, nyq_zero, st);
+        case 64: return wall_acc_n<R, 64>(src, dst, V, tw, g, npts, sc, kcol, pcol, rows, wall, nyq_zero, st);
+        case 128: return wall_acc_n<R, 128>(src, dst, V, tw, g, npts, sc, kcol, pcol, rows, wall, nyq_zero, st);
+        case 256: return wall_acc_n<R, 256>(src, dst, V, tw, g, npts, sc, kcol, pcol, rows, wall, nyq_zero, st);
+        case 512: return wall_acc_n<R, 512>(src, dst, V, tw, g, npts, sc, kcol, pcol, rows, wall, nyq_zero, st);
+        case 1024: return wall_acc_n<R, 1024>(src, dst, V, tw, g, npts, sc, kcol, pcol, rows, wall, nyq_zero, st);
+        case 2048: return wall_acc_n<R, 2048>(src, dst, V, tw, g, npts, sc, kcol, pcol, rows, wall, nyq_zero, st);
+        case 4096: return wall_acc_n<R, 4096>(src, dst, V, tw, g, npts, sc, kcol, pcol, rows, wall, nyq_zero, st);
+        case 8192: return wall_acc_n<R, 8192>(src, dst, V, tw, g, npts, sc, kcol, pcol, rows, wall, nyq_zero, st);
+        case 16384: return wall_acc_n<R, 16384>(src, dst, V, tw, g, npts, sc, kcol, pcol, rows, wall, nyq_zero, st);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 template <typename R>
@@ -818,9 +992,12 @@ hipError_t launch_fill0(int64_t n, R* y, hipStream_t st) {
     template hipError_t launch_axpby<R>(int64_t, double, const R*, double, R*, hipStream_t);    \
     template hipError_t launch_xpay<R>(int64_t, const R*, double, const R*, R*, hipStream_t);   \
     template hipError_t launch_fill0<R>(int64_t, R*, hipStream_t);                             \
-    template hipError_t launch_energy_axis<R>(int64_t, int, const R*, const R*, const void*,    \
+    template hipError_t launch_energy_axis<R>(int64_t, int, int, const R*, const R*, const void*, \
                                               const EnergyGeom&, int, double*, int, int*,       \
                                               hipStream_t);                                     \
+    template hipError_t launch_wall_acc<R>(int64_t, int, int, const R*, R*, const R*, const void*, \
+                                           const EnergyGeom&, int64_t, const ScaleRef&, int, int, \
+                                           int, hipStream_t);                                   \
     template hipError_t launch_energy_pot<R>(const R*, const R*, const R*, int64_t, double*,    \
                                              double*, int, hipStream_t);
 

@@ -95,6 +95,9 @@ hipError_t launch_xpay(int64_t n, const R* x, double a, const R* y, R* z,
 template <typename R>
 hipError_t launch_fill0(int64_t n, R* y, hipStream_t st);
 
+// Boundary of a line (the same values as the C ABI's SPSTD_BC_*).
+enum { WALL_NONE = 0, WALL_DIRICHLET = 1, WALL_NEUMANN = 2 };
+
 // Lines of one axis for the energy sums: line L starts at
 // (L / n_lo) * stride_hi + (L % n_lo); element e lies e * stride further on.
 struct EnergyGeom {
@@ -107,11 +110,25 @@ struct EnergyGeom {
 // partials[b] (b < *nblocks <= max_blocks) = block sums of
 // ks^2 |FFT_axis(psiR + i psiI)(k)|^2 over the lines of the axis (ks the
 // signed bin index; the Nyquist bin counts 0 if nyq_zero).  rows: the lines
-// are contiguous (x axis).  Axis length n: 16..16384 for rows, 16..1024 else.
+// are contiguous (x axis).  wall (WALL_*): a walled line of n samples is
+// transformed as its mirrored extension of 2n points (tw then holds 2n
+// twiddles), which counts every sample twice.  Transform length: 16..16384
+// for rows, 16..1024 else.
 template <typename R>
-hipError_t launch_energy_axis(int64_t n, int rows, const R* psiR, const R* psiI, const void* tw,
-                              const EnergyGeom& g, int nyq_zero, double* partials, int max_blocks,
-                              int* nblocks, hipStream_t st);
+hipError_t launch_energy_axis(int64_t n, int rows, int wall, const R* psiR, const R* psiI,
+                              const void* tw, const EnergyGeom& g, int nyq_zero, double* partials,
+                              int max_blocks, int* nblocks, hipStream_t st);
+
+// Pass along a walled axis (wall = WALL_DIRICHLET or WALL_NEUMANN)
+// of n samples: dst += k * T src (+ p * V * src if pcol >= 0), with (k, p)
+// from columns (kcol, pcol) of each line's instance (first sample / npts).
+// T is the periodic operator of the mirrored line of 2n points (tw: 2n
+// twiddles).  Lines come in pairs (2q, 2q + 1) sharing a complex pencil, so
+// for columns n_lo must be even.  2n: 32..16384 for rows, 32..1024 else.
+template <typename R>
+hipError_t launch_wall_acc(int64_t n, int rows, int wall, const R* src, R* dst, const R* V,
+                           const void* tw, const EnergyGeom& g, int64_t npts, const ScaleRef& sc,
+                           int kcol, int pcol, int nyq_zero, hipStream_t st);
 
 // pot[b], nrm[b] (b < nblocks) = block sums of V |psi|^2 and |psi|^2.
 template <typename R>

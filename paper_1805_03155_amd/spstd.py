@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(_HERE, "libspstd.so")
 FP64, FP32 = 0, 1
 NYQ_FULL, NYQ_ZERO = 0, 1
 SYMPLECTIC, RK4 = 0, 1
+BC_PERIODIC, BC_DIRICHLET, BC_NEUMANN = 0, 1, 2
 ALLOW_UNSTABLE = 0x1
 EAGER = 0x2          # no step-chunk graphs
 TIMING = 0x4         # pass kernels bracketed by HIP events (pass_times)
@@ -45,7 +46,7 @@ class Desc(ctypes.Structure):
                 ("mass", c_d), ("precision", c_int), ("method", c_int), ("m", c_int),
                 ("c", P(c_d)), ("d", P(c_d)), ("dt", c_d), ("cfl_fraction", c_d),
                 ("nyquist", c_int), ("nprobes", c_int), ("probe_idx", P(c_i64)),
-                ("flags", c_u32)]
+                ("flags", c_u32), ("bc", c_int * 3)]
 
 
 class BatchDesc(ctypes.Structure):
@@ -136,8 +137,10 @@ def _f64(a):
 
 
 def make_desc(n, dx, c=None, d=None, dt=0.0, cfl_fraction=0.5, hbar=1.0, mass=1.0,
-              precision=FP64, method=SYMPLECTIC, nyquist=NYQ_FULL, probes=(), flags=0):
-    """Build a descriptor; the returned object keeps its arrays alive."""
+              precision=FP64, method=SYMPLECTIC, nyquist=NYQ_FULL, probes=(), flags=0, bc=None):
+    """Build a descriptor; the returned object keeps its arrays alive.
+    bc: boundary per axis (BC_PERIODIC, BC_DIRICHLET, BC_NEUMANN), default
+    periodic."""
     desc = Desc()
     desc.ndim = len(n)
     for a in range(3):
@@ -159,6 +162,8 @@ def make_desc(n, dx, c=None, d=None, dt=0.0, cfl_fraction=0.5, hbar=1.0, mass=1.
     desc.nprobes = len(pidx)
     desc.probe_idx = pidx.ctypes.data_as(P(c_i64)) if len(pidx) else None
     desc.flags = flags
+    for a in range(3):
+        desc.bc[a] = int(bc[a]) if bc is not None and a < len(bc) else BC_PERIODIC
     desc._keep = keep
     return desc
 
@@ -299,7 +304,7 @@ def plan_from_workload(w, precision=FP64, method=SYMPLECTIC, dt=0.0, nsteps_max=
     c, d = coeffs if coeffs is not None else w.coeffs
     desc = make_desc(w.n, w.dx, c, d, dt=dt, cfl_fraction=w.cfl_fraction, hbar=w.hbar,
                      mass=w.mass, precision=precision, method=method, nyquist=nyquist,
-                     probes=w.probes, flags=flags)
+                     probes=w.probes, flags=flags, bc=w.bc)
     return Plan(desc, w.V, w.psiR, w.psiI,
                 nsteps_max=w.steps if nsteps_max is None else nsteps_max,
                 device=device, stream=stream)

@@ -60,6 +60,7 @@ class Workload:
     mass: float = 1.0
     cfl_fraction: float = 0.5
     meta: dict = field(default_factory=dict)
+    bc: tuple = None    # boundary per axis (0 periodic, 1 Dirichlet, 2 Neumann); None: periodic
 
     @property
     def npoints(self) -> int:
@@ -123,6 +124,42 @@ def harmonic_3d(seed=0, n=64, half_box=8.0, omega=1.0, steps=10000,
                     np.array(probes, np.int64), steps, coeffs,
                     meta=dict(seed=seed, omega=omega, center=(cx, cy, cz),
                               V1=0.5 * omega ** 2 * x ** 2))
+
+
+def cell_centres(n, L):
+    """Sample points (j + 1/2) L / n of an axis between walls at 0 and L."""
+    return (np.arange(n) + 0.5) * (L / n)
+
+
+def walled_box(seed=0, n=(64, 32), L=(8.0, 6.0), bc=(1, 1), V0=0.0, steps=2000,
+               coeffs=PAPER, nprobes=2):
+    """A box with walls (Dirichlet 1 / Neumann 2 / periodic 0 per axis) on
+    cell-centred samples: V = V0 * (seeded smooth bump), psi_R = a seeded
+    Gaussian away from the centre, psi_I = 0, probes at seeded points within
+    half a unit of the Gaussian's centre (where the state has weight)."""
+    rng = np.random.default_rng(seed)
+    dim = len(n)
+    axes = [cell_centres(m, l) for m, l in zip(n, L)]
+    grids = np.meshgrid(*reversed(axes), indexing="ij")[::-1]      # x first
+    ctr = [l * rng.uniform(0.3, 0.45) for l in L]
+    r2 = sum((g - c) ** 2 for g, c in zip(grids, ctr))
+    bump = np.exp(-sum((g - 0.6 * l) ** 2 for g, l in zip(grids, L)) / 2.0)
+    V = (V0 * bump).ravel()
+    psiR = np.exp(-r2 / 1.0).ravel()
+    npts = int(np.prod(n))
+    dx = tuple(l / m for m, l in zip(n, L))
+    probes = []
+    for _ in range(nprobes):
+        idx = [min(m - 1, max(0, int((c + rng.uniform(-0.5, 0.5)) / h)))
+               for c, m, h in zip(ctr, n, dx)]
+        lin = 0
+        for k in reversed(range(dim)):
+            lin = lin * n[k] + idx[k]
+        probes.append(lin)
+    probes = np.array(probes, np.int64)
+    return Workload(f"walled_{'x'.join(map(str, n))}", tuple(n), dx, (0.0,) * dim, V, psiR,
+                    np.zeros(npts), probes, steps, coeffs, bc=tuple(bc),
+                    meta=dict(seed=seed, L=L))
 
 
 def harmonic_1d_potential(n, half_box, omega=1.0):

@@ -61,9 +61,14 @@ def test_workspace_size_grows_with_probe_capacity_and_precision():
 
 @pytest.mark.parametrize("bad", [dict(n=(24,), dx=(0.1,)), dict(n=(16, 2048), dx=(0.1, 0.1)),
                                  dict(n=(32,), dx=(-1.0,)), dict(n=(8,), dx=(0.1,)),
-                                 dict(n=(32,), dx=(0.1,), probes=(40,))])
+                                 dict(n=(32,), dx=(0.1,), probes=(40,)),
+                                 # walled axes transform twice their length
+                                 dict(n=(16384,), dx=(0.1,), bc=(1,)),
+                                 dict(n=(16, 1024), dx=(0.1, 0.1), bc=(0, 2)),
+                                 dict(n=(32,), dx=(0.1,), bc=(3,))])
 def test_bad_descriptors_rejected(bad):
-    desc = spstd.make_desc(bad["n"], bad["dx"], *W.PAPER, probes=bad.get("probes", ()))
+    desc = spstd.make_desc(bad["n"], bad["dx"], *W.PAPER, probes=bad.get("probes", ()),
+                           bc=bad.get("bc"))
     with pytest.raises(spstd.SpstdError) as ei:
         spstd.workspace_size(desc, 10)
     assert ei.value.code == 1
