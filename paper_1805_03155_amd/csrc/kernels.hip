@@ -33,7 +33,9 @@ bool row_len_ok(int64_t n) { return n >= 16 && n <= 16384 && (n & (n - 1)) == 0;
 //                  SIMD, non-temporal loads and stores)
 //   X_RELOAD       x passes re-read their inputs in the epilogue instead of
 //                  keeping them in registers through the transforms
-//   MIN_WAVES      minimum waves per SIMD requested for the pass kernels
+//   MIN_WAVES      minimum waves per SIMD requested for the pass kernels (2
+//                  keeps the FP64 x passes of 512..2048-point rows out of
+//                  accumulation registers, at one wave per SIMD otherwise)
 //   YZ_PPL_F32     complex pencils per lane group in FP32 y/z passes
 //   EPI_CHUNK      epilogue elements scheduled together (caps the loads in
 //                  flight, and with them the registers)
@@ -62,7 +64,7 @@ bool row_len_ok(int64_t n) { return n >= 16 && n <= 16384 && (n & (n - 1)) == 0;
 #define SPSTD_X_RELOAD 0
 #endif
 #ifndef SPSTD_MIN_WAVES
-#define SPSTD_MIN_WAVES 0
+#define SPSTD_MIN_WAVES 2
 #endif
 #ifndef SPSTD_YZ_PPL_F32
 #define SPSTD_YZ_PPL_F32 2

@@ -223,12 +223,15 @@ class Plan:
                                   ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h))
         _check(rc)
         self.h = h
+        self._destroy = lib().spstd_destroy
         self.nprobes = desc.nprobes
 
     def __del__(self):
-        h = getattr(self, "h", None)
-        if h is not None and h.value:
-            lib().spstd_destroy(h)
+        # the destroy function is bound at creation: module globals may be
+        # gone when the interpreter shuts down
+        h, fn = getattr(self, "h", None), getattr(self, "_destroy", None)
+        if h is not None and h.value and fn is not None:
+            fn(h)
             self.h = None
 
     def step(self, nsteps):
@@ -356,11 +359,12 @@ class Batch:
                                           ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h))
         _check(rc)
         self.h = h
+        self._destroy = lib().spstd_batch_destroy
 
     def __del__(self):
-        h = getattr(self, "h", None)
-        if h is not None and h.value:
-            lib().spstd_batch_destroy(h)
+        h, fn = getattr(self, "h", None), getattr(self, "_destroy", None)
+        if h is not None and h.value and fn is not None:
+            fn(h)
             self.h = None
 
     def load(self, slot, dx, V, psiR, psiI=None, probes=(), dt=0.0, cfl_fraction=0.5,

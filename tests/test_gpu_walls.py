@@ -75,8 +75,9 @@ def test_walled_energy_matches_the_oracle(bc):
 
 
 def test_infinite_well_levels_are_the_sine_ladder():
-    n, L = 128, 10.0
-    w = W.walled_box(seed=4, n=(n,), L=(L,), bc=(D,), V0=0.0, steps=20000)
+    # a record of T = 140 resolves levels (pi k / L)^2 / 2 spaced 0.9 apart
+    n, L = 32, 4.0
+    w = W.walled_box(seed=4, n=(n,), L=(L,), bc=(D,), V0=0.0, steps=40000)
     w.probes = np.array([n // 3], np.int64)
     dt = 0.5 * oracle.stable_dt(*w.coeffs, w.V, w.n, w.dx)
     p = spstd.plan_from_workload(w, dt=dt, nsteps_max=w.steps)
@@ -86,4 +87,4 @@ def test_infinite_well_levels_are_the_sine_ladder():
     assert len(E) == 4
     for k, e in enumerate(E, start=1):
         want = modal.theta(c, d, 0.5 * (np.pi * k / L) ** 2 * dt) / dt
-        assert abs(e / want - 1.0) < 2e-5
+        assert abs(e / want - 1.0) < 5e-5
