@@ -47,6 +47,7 @@ enum { SPSTD_FP64 = 0, SPSTD_FP32 = 1 };            /* storage and arithmetic of
 enum { SPSTD_NYQ_FULL = 0, SPSTD_NYQ_ZERO = 1 };    /* Nyquist bin convention, see below */
 enum { SPSTD_SYMPLECTIC = 0, SPSTD_RK4 = 1 };        /* time integrator */
 enum { SPSTD_BC_PERIODIC = 0, SPSTD_BC_DIRICHLET = 1, SPSTD_BC_NEUMANN = 2 };  /* per axis */
+enum { SPSTD_LAP_SPECTRAL = 0, SPSTD_LAP_FD3 = 1 };  /* spatial second derivative */
 
 #define SPSTD_ALLOW_UNSTABLE 0x1u                    /* flags: accept dt beyond the edge */
 #define SPSTD_EAGER 0x2u                             /* flags: launch kernels one by one
@@ -94,6 +95,14 @@ enum { SPSTD_BC_PERIODIC = 0, SPSTD_BC_DIRICHLET = 1, SPSTD_BC_NEUMANN = 2 };  /
  *                SPSTD_BC_DIRICHLET (psi = 0 at the walls, sine transform),
  *                SPSTD_BC_NEUMANN (zero normal derivative, cosine transform).
  *                A zero-initialised descriptor is periodic everywhere.
+ *   laplacian    SPSTD_LAP_SPECTRAL (Eq. 9-10, the method) or SPSTD_LAP_FD3:
+ *                the second-order central difference (f[j+1] - 2 f[j] +
+ *                f[j-1]) / dx^2 per axis with periodic wrap, the FDTD
+ *                comparison of Table 1 and Tables 2-3 (periodic axes only;
+ *                rho then uses the difference operator's bound 4/dx^2 per
+ *                axis in place of (pi/dx)^2; no spstd_energy).  With m = 1,
+ *                c = d = (1) the spectral setting is the PSTD comparison
+ *                (Eq. 11-12).
  */
 typedef struct spstd_desc {
     int ndim;
@@ -111,6 +120,7 @@ typedef struct spstd_desc {
     const int64_t *probe_idx;
     uint32_t flags;
     int bc[3];
+    int laplacian;
 } spstd_desc;
 
 typedef struct spstd_plan_s *spstd_plan_t;

@@ -125,6 +125,10 @@ static spstd_status validate(const spstd_desc* d, std::string* why) {
             if (!std::isfinite(d->c[l]) || !std::isfinite(d->d[l])) { *why = "non-finite coefficient"; return SPSTD_ERR_ARG; }
     }
     if (d->nyquist != SPSTD_NYQ_FULL && d->nyquist != SPSTD_NYQ_ZERO) { *why = "bad nyquist"; return SPSTD_ERR_ARG; }
+    if (d->laplacian != SPSTD_LAP_SPECTRAL && d->laplacian != SPSTD_LAP_FD3) { *why = "bad laplacian"; return SPSTD_ERR_ARG; }
+    if (d->laplacian == SPSTD_LAP_FD3)
+        for (int a = 0; a < 3; ++a)
+            if (d->bc[a] != SPSTD_BC_PERIODIC) { *why = "the difference operator is periodic only"; return SPSTD_ERR_ARG; }
     if (!(d->dt >= 0.0) || !std::isfinite(d->dt)) { *why = "dt must be >= 0"; return SPSTD_ERR_ARG; }
     if (d->dt == 0.0 && !(d->cfl_fraction > 0.0 && std::isfinite(d->cfl_fraction))) {
         *why = "cfl_fraction must be positive when dt is 0"; return SPSTD_ERR_ARG;
@@ -139,7 +143,7 @@ static spstd_status validate(const spstd_desc* d, std::string* why) {
 }
 
 static double rho_of(const spstd_desc* d, const double* V, int64_t N) {
-    return rho_bound_of(d->ndim, d->dx, d->hbar, d->mass, V, N);
+    return rho_bound_of(d->ndim, d->dx, d->hbar, d->mass, V, N, d->laplacian == SPSTD_LAP_FD3);
 }
 
 static spstd_status edge_of(const spstd_desc* d, double* x) {
@@ -239,6 +243,15 @@ static hipError_t yz_passes(Plan* p, const R* src, R* dst, const ScaleRef& sc, i
     return hipSuccess;
 }
 
+// dst += (three-point T) src + (V/hbar) src over all axes at once, with the
+// kinetic columns of the A (ab = 0) or B (ab = 1) substep.
+template <typename R>
+static hipError_t fd_half(Plan* p, const R* src, R* dst, const ScaleRef& sc, int ab) {
+    PassTimer tm(p, SPSTD_PASS_X);
+    return launch_fd_acc<R>(src, dst, F<R>(p, p->L.V), p->d.n, sc, ab ? SC_KXB : SC_KXA, ab ? SC_PB : SC_PA,
+                            p->st);
+}
+
 // dst += T_x src + (V/hbar) src with the scale columns (kcol, pcol): one x
 // half-stage.
 template <typename R>
@@ -264,6 +277,11 @@ static hipError_t enqueue_symplectic_step(Plan* p) {
     for (int l = 0; l < p->d.m && e == hipSuccess; ++l) {
         const bool a = p->c[l] != 0.0, b = p->dd[l] != 0.0;
         const ScaleRef sc{p->ws + p->L.scales, p->d.m + 1, l};
+        if (p->d.laplacian == SPSTD_LAP_FD3) {
+            if (a) e = fd_half<R>(p, pi, pr, sc, 0);
+            if (b && e == hipSuccess) e = fd_half<R>(p, pr, pi, sc, 1);
+            continue;
+        }
         if (a) e = yz_passes<R>(p, pi, pr, sc, 0);
         if (e != hipSuccess) break;
         if (a && b && !walled(p, 0)) {
@@ -292,6 +310,7 @@ static hipError_t apply_K(Plan* p, const R* src, R* kout, double coef) {
     const ScaleRef sc{p->ws + p->L.scales, p->d.m + 1, p->d.m};
     const int ab = coef > 0.0 ? 0 : 1;
     hipError_t e = launch_fill0<R>(p->N, kout, p->st);
+    if (p->d.laplacian == SPSTD_LAP_FD3) return e == hipSuccess ? fd_half<R>(p, src, kout, sc, ab) : e;
     if (e == hipSuccess) e = yz_passes<R>(p, src, kout, sc, ab);
     PassTimer tm(p, SPSTD_PASS_X);
     if (e == hipSuccess) e = x_half<R>(p, src, kout, sc, ab ? SC_KXB : SC_KXA, ab ? SC_PB : SC_PA);
@@ -333,7 +352,8 @@ static hipError_t enqueue_rk4_step(Plan* p) {
 
 static bool uses_resident(const Plan* p) {
     const spstd_desc& d = p->d;
-    return d.ndim == 1 && d.bc[0] == SPSTD_BC_PERIODIC && d.method == SPSTD_SYMPLECTIC && resident_len_ok(d.n[0]) &&
+    return d.ndim == 1 && d.bc[0] == SPSTD_BC_PERIODIC && d.laplacian == SPSTD_LAP_SPECTRAL &&
+           d.method == SPSTD_SYMPLECTIC && resident_len_ok(d.n[0]) &&
            d.nprobes <= kResMaxProbes && d.m <= SPSTD_MAX_STAGES &&
            !(d.flags & (SPSTD_NO_RESIDENT | SPSTD_TIMING));
 }
@@ -670,6 +690,10 @@ spstd_status spstd_run(spstd_plan_t p, int64_t nsteps, double* probe_out, spstd_
 
 spstd_status spstd_energy(spstd_plan_t p, double* out) {
     if (!p || !out) return SPSTD_ERR_ARG;
+    if (p->d.laplacian != SPSTD_LAP_SPECTRAL) {
+        p->err = "energy diagnostics use the spectral second derivative";
+        return SPSTD_ERR_ARG;
+    }
     spstd_status s = (p->esz == 8) ? compute_energy<double>(p, out) : compute_energy<float>(p, out);
     if (s == SPSTD_OK && !(std::isfinite(out[0]) && std::isfinite(out[1]) && std::isfinite(out[2]))) {
         p->err = "state is not finite";

@@ -107,15 +107,21 @@ static inline double kin_scale(const spstd_desc& d, int a, double coef) {
     return coef * d.hbar / (2.0 * d.mass) * k1 * k1 / nt;
 }
 
+// Kinetic scale of axis a under the three-point difference: the stencil
+// kernel adds k (2 f[j] - f[j+1] - f[j-1]) with k = coef (hbar/2m*) / dx^2.
+static inline double kin_scale_fd(const spstd_desc& d, int a, double coef) {
+    if (a >= d.ndim) return 0.0;
+    return coef * d.hbar / (2.0 * d.mass) / (d.dx[a] * d.dx[a]);
+}
+
 // One row of the scale table for substep coefficients a (A) and b (B).
 static inline void scale_row(const spstd_desc& d, double a, double b, double* row) {
-    row[SC_KXA] = kin_scale(d, 0, a);
-    row[SC_KYA] = kin_scale(d, 1, a);
-    row[SC_KZA] = kin_scale(d, 2, a);
+    const bool fd = d.laplacian == SPSTD_LAP_FD3;
+    for (int ax = 0; ax < 3; ++ax) {
+        row[SC_KXA + ax] = fd ? kin_scale_fd(d, ax, a) : kin_scale(d, ax, a);
+        row[SC_KXB + ax] = fd ? kin_scale_fd(d, ax, b) : kin_scale(d, ax, b);
+    }
     row[SC_PA] = a / d.hbar;
-    row[SC_KXB] = kin_scale(d, 0, b);
-    row[SC_KYB] = kin_scale(d, 1, b);
-    row[SC_KZB] = kin_scale(d, 2, b);
     row[SC_PB] = b / d.hbar;
 }
 
@@ -143,9 +149,10 @@ static inline AxisGeom axis_geom_of_n(int ndim, const int64_t* n, int a, int64_t
 // Spectral-radius bound of K on a grid with potential V (Eq. 24-30 with V):
 // (hbar/2m*) sum_d (pi/dx_d)^2 + max|V|/hbar over the grid's axes.
 static inline double rho_bound_of(int ndim, const double* dx, double hbar, double mass, const double* V,
-                                  int64_t N) {
+                                  int64_t N, bool fd3 = false) {
+    // the three-point difference's symbol 4 sin^2(k dx/2)/dx^2 peaks at 4/dx^2
     double r = 0.0;
-    for (int a = 0; a < ndim; ++a) r += (kPi / dx[a]) * (kPi / dx[a]);
+    for (int a = 0; a < ndim; ++a) r += fd3 ? 4.0 / (dx[a] * dx[a]) : (kPi / dx[a]) * (kPi / dx[a]);
     r *= hbar / (2.0 * mass);
     double vm = 0.0;
     for (int64_t i = 0; i < N; ++i) vm = std::fmax(vm, std::fabs(V[i]));

@@ -692,6 +692,34 @@ __global__ __launch_bounds__((row_map<R, N, SPSTD_WPB>::THREADS)) void k_wall_ac
     }
 }
 
+// ---------------------------------------------------------------------------
+// Finite-difference comparison (the FDTD column of Tables 1-3): one substep
+// over all axes at once,
+//   dst += sum_d k_d (2 f[j] - f[j + e_d] - f[j - e_d]) + p V f,
+// periodic wrap, k_d = coef (hbar/2m*) / dx_d^2 from column kcol0 + d.
+// ---------------------------------------------------------------------------
+template <typename R>
+__global__ __launch_bounds__(256) void k_fd_acc(const R* __restrict__ src, R* __restrict__ dst,
+                                                const R* __restrict__ V, int64_t nx, int64_t ny,
+                                                int64_t nz, ScaleRef sc, int kcol0, int pcol) {
+    const R kx = scale_of<R>(sc, 0, kcol0), ky = scale_of<R>(sc, 0, kcol0 + 1);
+    const R kz = scale_of<R>(sc, 0, kcol0 + 2), pv = scale_of<R>(sc, 0, pcol);
+    const int64_t plane = nx * ny, N = plane * nz;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t x = i % nx, y = (i / nx) % ny, z = i / plane;
+        const R f = src[i];
+        const R two = f + f;
+        R acc = kx * (two - src[x ? i - 1 : i + nx - 1] - src[x + 1 < nx ? i + 1 : i - (nx - 1)]);
+        if (ny > 1)
+            acc += ky * (two - src[y ? i - nx : i + (ny - 1) * nx] - src[y + 1 < ny ? i + nx : i - (ny - 1) * nx]);
+        if (nz > 1)
+            acc += kz * (two - src[z ? i - plane : i + (nz - 1) * plane] -
+                         src[z + 1 < nz ? i + plane : i - (nz - 1) * plane]);
+        dst[i] = dst[i] + acc + pv * V[i] * f;
+    }
+}
+
 // Per-block FP64 partials of sum V (psiR^2 + psiI^2) and of sum psiR^2 + psiI^2.
 template <typename R>
 __global__ __launch_bounds__(256) void k_energy_pot(const R* __restrict__ a, const R* __restrict__ b,
@@ -959,6 +987,14 @@ static unsigned ew_blocks(int64_t n) {
 }
 
 template <typename R>
+hipError_t launch_fd_acc(const R* src, R* dst, const R* V, const int64_t* n, const ScaleRef& sc, int kcol0,
+                         int pcol, hipStream_t st) {
+    hipLaunchKernelGGL((k_fd_acc<R>), dim3(ew_blocks(n[0] * n[1] * n[2])), dim3(256), 0, st, src, dst, V, n[0],
+                       n[1], n[2], sc, kcol0, pcol);
+    return hipGetLastError();
+}
+
+template <typename R>
 hipError_t launch_axpby(int64_t n, double a, const R* x, double b, R* y, hipStream_t st) {
     hipLaunchKernelGGL((k_axpby<R>), dim3(ew_blocks(n)), dim3(256), 0, st, n, (R)a, x, (R)b, y);
     return hipGetLastError();
@@ -994,6 +1030,8 @@ hipError_t launch_fill0(int64_t n, R* y, hipStream_t st) {
     template hipError_t launch_axpby<R>(int64_t, double, const R*, double, R*, hipStream_t);    \
     template hipError_t launch_xpay<R>(int64_t, const R*, double, const R*, R*, hipStream_t);   \
     template hipError_t launch_fill0<R>(int64_t, R*, hipStream_t);                             \
+    template hipError_t launch_fd_acc<R>(const R*, R*, const R*, const int64_t*, const ScaleRef&, \
+                                         int, int, hipStream_t);                                \
     template hipError_t launch_energy_axis<R>(int64_t, int, int, const R*, const R*, const void*, \
                                               const EnergyGeom&, int, double*, int, int*,       \
                                               hipStream_t);                                     \

@@ -95,6 +95,13 @@ hipError_t launch_xpay(int64_t n, const R* x, double a, const R* y, R* z,
 template <typename R>
 hipError_t launch_fill0(int64_t n, R* y, hipStream_t st);
 
+// Three-point difference substep over all axes of one grid n[3]:
+// dst += sum_d k_d (2 f - f[+e_d] - f[-e_d]) + p V f, periodic wrap, with
+// k_d from scale columns kcol0 + d and p from pcol (instance 0).
+template <typename R>
+hipError_t launch_fd_acc(const R* src, R* dst, const R* V, const int64_t* n, const ScaleRef& sc, int kcol0,
+                         int pcol, hipStream_t st);
+
 // Boundary of a line (the same values as the C ABI's SPSTD_BC_*).
 enum { WALL_NONE = 0, WALL_DIRICHLET = 1, WALL_NEUMANN = 2 };
 

@@ -18,6 +18,7 @@ FP64, FP32 = 0, 1
 NYQ_FULL, NYQ_ZERO = 0, 1
 SYMPLECTIC, RK4 = 0, 1
 BC_PERIODIC, BC_DIRICHLET, BC_NEUMANN = 0, 1, 2
+LAP_SPECTRAL, LAP_FD3 = 0, 1
 ALLOW_UNSTABLE = 0x1
 EAGER = 0x2          # no step-chunk graphs
 TIMING = 0x4         # pass kernels bracketed by HIP events (pass_times)
@@ -46,7 +47,7 @@ class Desc(ctypes.Structure):
                 ("mass", c_d), ("precision", c_int), ("method", c_int), ("m", c_int),
                 ("c", P(c_d)), ("d", P(c_d)), ("dt", c_d), ("cfl_fraction", c_d),
                 ("nyquist", c_int), ("nprobes", c_int), ("probe_idx", P(c_i64)),
-                ("flags", c_u32), ("bc", c_int * 3)]
+                ("flags", c_u32), ("bc", c_int * 3), ("laplacian", c_int)]
 
 
 class BatchDesc(ctypes.Structure):
@@ -137,7 +138,8 @@ def _f64(a):
 
 
 def make_desc(n, dx, c=None, d=None, dt=0.0, cfl_fraction=0.5, hbar=1.0, mass=1.0,
-              precision=FP64, method=SYMPLECTIC, nyquist=NYQ_FULL, probes=(), flags=0, bc=None):
+              precision=FP64, method=SYMPLECTIC, nyquist=NYQ_FULL, probes=(), flags=0, bc=None,
+              laplacian=LAP_SPECTRAL):
     """Build a descriptor; the returned object keeps its arrays alive.
     bc: boundary per axis (BC_PERIODIC, BC_DIRICHLET, BC_NEUMANN), default
     periodic."""
@@ -164,6 +166,7 @@ def make_desc(n, dx, c=None, d=None, dt=0.0, cfl_fraction=0.5, hbar=1.0, mass=1.
     desc.flags = flags
     for a in range(3):
         desc.bc[a] = int(bc[a]) if bc is not None and a < len(bc) else BC_PERIODIC
+    desc.laplacian = laplacian
     desc._keep = keep
     return desc
 
@@ -302,12 +305,13 @@ class Plan:
 
 
 def plan_from_workload(w, precision=FP64, method=SYMPLECTIC, dt=0.0, nsteps_max=None,
-                       nyquist=NYQ_FULL, flags=0, coeffs=None, device="cuda", stream=None):
+                       nyquist=NYQ_FULL, flags=0, coeffs=None, device="cuda", stream=None,
+                       laplacian=LAP_SPECTRAL):
     """Plan for a workloads.Workload (same arrays the oracle is given)."""
     c, d = coeffs if coeffs is not None else w.coeffs
     desc = make_desc(w.n, w.dx, c, d, dt=dt, cfl_fraction=w.cfl_fraction, hbar=w.hbar,
                      mass=w.mass, precision=precision, method=method, nyquist=nyquist,
-                     probes=w.probes, flags=flags, bc=w.bc)
+                     probes=w.probes, flags=flags, bc=w.bc, laplacian=laplacian)
     return Plan(desc, w.V, w.psiR, w.psiI,
                 nsteps_max=w.steps if nsteps_max is None else nsteps_max,
                 device=device, stream=stream)

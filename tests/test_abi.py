@@ -49,6 +49,18 @@ def test_stable_dt_matches_oracle():
             oracle.stable_dt(*w.coeffs, w.V, w.n, w.dx), rel=1e-13)
 
 
+def test_stable_dt_of_the_difference_operator():
+    # rho of the three-point operator: (hbar/2m*) sum 4/dx^2 + max|V|/hbar
+    n, dx = (64, 32), (0.25, 0.4)
+    V = np.linspace(0.0, 3.0, 64 * 32)
+    desc = spstd.make_desc(n, dx, *W.PAPER, laplacian=spstd.LAP_FD3)
+    rho = 0.5 * (4 / 0.25 ** 2 + 4 / 0.4 ** 2) + 3.0
+    assert abs(spstd.stable_dt(desc, V) / (0.5 * oracle.xmax(*W.PAPER) / rho) - 1) < 1e-13
+    bad = spstd.make_desc(n, dx, *W.PAPER, laplacian=spstd.LAP_FD3, bc=(1, 0))
+    with pytest.raises(spstd.SpstdError):
+        spstd.workspace_size(bad, 10)
+
+
 def test_workspace_size_grows_with_probe_capacity_and_precision():
     w = W.harmonic_3d(n=32, half_box=8.0)
     d64 = spstd.make_desc(w.n, w.dx, *w.coeffs, probes=w.probes)
