@@ -13,7 +13,7 @@ import pytest
 from scipy.optimize import brentq
 
 import oracle
-from oracle import modal, spectrum
+from oracle import eigenstate, modal, spectrum
 from paper_1805_03155_amd import workloads as W
 
 GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden",
@@ -446,6 +446,29 @@ def test_energy_bounded_for_spstd_and_decays_for_rk4():
             assert np.abs(dev).max() < 1e-5
         else:
             assert np.all(np.diff(dev) < 0) and dev[-1] < -1e-3
+
+
+# ------------------------------- eigenstate reconstruction (Figs. 1, 2, 4)
+def test_reconstructed_eigenstates_are_the_dense_eigenvectors():
+    # start from 0.8 phi_1 + 0.6 phi_3 (eigenvectors of the dense K, built
+    # from its definition); the windowed sum at E_j = hbar theta(lambda_j dt)/dt
+    # returns phi_j with weight a_j sum(w), the other mode suppressed by the
+    # window (levels 19 bins apart over the record)
+    w = W.finite_well_1d(seed=0)
+    n, dx = w.n[0], w.dx[0]
+    lam, phi = np.linalg.eigh(modal.hamiltonian_1d(w.V, dx))
+    c, d = w.coeffs
+    dt = oracle.stable_dt(c, d, w.V, w.n, w.dx)
+    E = [modal.theta(c, d, lam[j] * dt) / dt for j in (1, 3)]
+    M = 12000
+    acc, _ = eigenstate.reconstruct(0.8 * phi[:, 1] + 0.6 * phi[:, 3], np.zeros(n), w.V, w.n, w.dx,
+                                    c, d, dt, E, M)
+    wsum = spectrum.window(M).sum()
+    for a, j, amp, other in ((acc[0], 1, 0.8, 3), (acc[1], 3, 0.6, 1)):
+        along = abs(np.vdot(phi[:, j], a))
+        assert 1.0 - along / np.linalg.norm(a) < 1e-9
+        assert abs(along / (amp * wsum) - 1.0) < 1e-4
+        assert abs(np.vdot(phi[:, other], a)) / np.linalg.norm(a) < 5e-5
 
 
 # ------------------------------------- T10: the paper's printed tables
