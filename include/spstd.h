@@ -58,6 +58,7 @@ enum { SPSTD_LAP_SPECTRAL = 0, SPSTD_LAP_FD3 = 1 };  /* spatial second derivativ
                                                         even where the resident kernel applies */
 #define SPSTD_MAX_STAGES 16
 #define SPSTD_MAX_PROBES 64
+#define SPSTD_MAX_EIG 8
 
 /*
  * Problem descriptor (caller-owned; copied by spstd_plan).
@@ -103,6 +104,8 @@ enum { SPSTD_LAP_SPECTRAL = 0, SPSTD_LAP_FD3 = 1 };  /* spatial second derivativ
  *                axis in place of (pi/dx)^2; no spstd_energy).  With m = 1,
  *                c = d = (1) the spectral setting is the PSTD comparison
  *                (Eq. 11-12).
+ *   neig         0..8: eigenstate accumulators reserved in the workspace
+ *                (spstd_eig_begin); each costs 16 bytes per grid point.
  */
 typedef struct spstd_desc {
     int ndim;
@@ -121,6 +124,7 @@ typedef struct spstd_desc {
     uint32_t flags;
     int bc[3];
     int laplacian;
+    int neig;
 } spstd_desc;
 
 typedef struct spstd_plan_s *spstd_plan_t;
@@ -206,6 +210,29 @@ spstd_status spstd_run(spstd_plan_t plan, int64_t nsteps, double *probe_out,
  * pointers), SPSTD_ERR_NONFINITE (state not finite), SPSTD_ERR_DEVICE.
  */
 spstd_status spstd_energy(spstd_plan_t plan, double *out);
+
+/*
+ * Eigenstate reconstruction (Sec. 3.1-3.2, Figs. 1, 2 and 4: eigenstates at
+ * chosen eigenfrequencies from the same time-domain run).  After this call
+ * each of the next nsteps steps adds its resulting state, weighted, into
+ * one accumulator per energy:
+ *   phi_k(r) = sum_{m=0}^{nsteps-1} w_m psi(r, t_m) exp(+i E_k m dt / hbar)
+ * with psi(r, t_m) the state after m + 1 steps counted from this call and
+ * w_m the symmetric 4-term Blackman-Harris window of length nsteps (the
+ * spectrum's window).  E: host array of nE energies (nE <= the plan's
+ * neig), e.g. levels returned by spstd_spectrum.  Steps beyond nsteps add
+ * nothing.  Accumulators are FP64 in every precision.  Resets earlier
+ * accumulations.  Errors: SPSTD_ERR_ARG (neig == 0, nE outside 1..neig,
+ * nsteps < 2, non-finite E), SPSTD_ERR_DEVICE.
+ */
+spstd_status spstd_eig_begin(spstd_plan_t plan, const double *E, int nE, int64_t nsteps);
+
+/*
+ * Copy accumulator k (0 <= k < nE of the last spstd_eig_begin) to host
+ * arrays re and im of the grid's size (row-major, x fastest).  Synchronises
+ * the plan's stream.  Errors: SPSTD_ERR_ARG, SPSTD_ERR_DEVICE.
+ */
+spstd_status spstd_eig_read(spstd_plan_t plan, int k, double *re, double *im);
 
 /* Statistics without running (steps_done, dt, x_max, rho, norm0). */
 spstd_status spstd_plan_info(spstd_plan_t plan, spstd_stats *stats_out);

@@ -24,7 +24,7 @@ static const double kRK4Edge = 2.8284271247461900976;
 // plan
 // ---------------------------------------------------------------------------
 struct Layout {
-    size_t psiR, psiI, V, rk[6], tw[3], pidx, probes, counter, partials, rinst, scales, total;
+    size_t psiR, psiI, V, rk[6], tw[3], pidx, probes, counter, partials, rinst, scales, eig, ecount, total;
 };
 
 static const int kNormBlocks = 256;
@@ -43,6 +43,8 @@ struct Plan {
     int64_t twlen[3];
     hipGraphExec_t graph;
     bool graph_ready;
+    bool eig_on = false;
+    EigParams eig{};
     std::string err;
     // SPSTD_TIMING: event pairs around pass launches and their kinds
     std::vector<hipEvent_t> ev_pool;
@@ -126,6 +128,7 @@ static spstd_status validate(const spstd_desc* d, std::string* why) {
     }
     if (d->nyquist != SPSTD_NYQ_FULL && d->nyquist != SPSTD_NYQ_ZERO) { *why = "bad nyquist"; return SPSTD_ERR_ARG; }
     if (d->laplacian != SPSTD_LAP_SPECTRAL && d->laplacian != SPSTD_LAP_FD3) { *why = "bad laplacian"; return SPSTD_ERR_ARG; }
+    if (d->neig < 0 || d->neig > SPSTD_MAX_EIG) { *why = "neig must be 0..8"; return SPSTD_ERR_ARG; }
     if (d->laplacian == SPSTD_LAP_FD3)
         for (int a = 0; a < 3; ++a)
             if (d->bc[a] != SPSTD_BC_PERIODIC) { *why = "the difference operator is periodic only"; return SPSTD_ERR_ARG; }
@@ -177,6 +180,9 @@ static Layout layout_of(const spstd_desc* d, int64_t nsteps_max) {
     L.rinst = off; off += align256(sizeof(ResidentInst<double>));
     // per-stage pass scales, then one row for the RK4 operator applications
     L.scales = off; off += align256((size_t)(d->m + 1) * SC_COLS * esz);
+    // eigenstate accumulators: neig complex FP64 fields, then their step count
+    L.eig = off; off += align256((size_t)d->neig * 2 * (size_t)N * sizeof(double));
+    L.ecount = off; off += 256;
     L.total = off;
     return L;
 }
@@ -352,7 +358,7 @@ static hipError_t enqueue_rk4_step(Plan* p) {
 
 static bool uses_resident(const Plan* p) {
     const spstd_desc& d = p->d;
-    return d.ndim == 1 && d.bc[0] == SPSTD_BC_PERIODIC && d.laplacian == SPSTD_LAP_SPECTRAL &&
+    return d.ndim == 1 && d.bc[0] == SPSTD_BC_PERIODIC && d.laplacian == SPSTD_LAP_SPECTRAL && d.neig == 0 &&
            d.method == SPSTD_SYMPLECTIC && resident_len_ok(d.n[0]) &&
            d.nprobes <= kResMaxProbes && d.m <= SPSTD_MAX_STAGES &&
            !(d.flags & (SPSTD_NO_RESIDENT | SPSTD_TIMING));
@@ -396,6 +402,10 @@ static hipError_t enqueue_steps_eager(Plan* p, int64_t n) {
                                 reinterpret_cast<double*>(p->ws + p->L.probes),
                                 reinterpret_cast<int64_t*>(p->ws + p->L.counter), p->nsteps_max + 1,
                                 p->st);
+        if (e == hipSuccess && p->eig_on) {
+            e = launch_eig_acc<R>(F<R>(p, p->L.psiR), F<R>(p, p->L.psiI), p->N, p->eig, p->st);
+            if (e == hipSuccess) e = launch_count_tick(reinterpret_cast<int64_t*>(p->ws + p->L.ecount), p->st);
+        }
     }
     return e;
 }
@@ -684,6 +694,43 @@ spstd_status spstd_run(spstd_plan_t p, int64_t nsteps, double* probe_out, spstd_
     if (!std::isfinite(p->norm)) {
         p->err = "state is not finite";
         return SPSTD_ERR_NONFINITE;
+    }
+    return SPSTD_OK;
+}
+
+spstd_status spstd_eig_begin(spstd_plan_t p, const double* E, int nE, int64_t nsteps) {
+    if (!p || !E || p->d.neig == 0 || nE < 1 || nE > p->d.neig || nsteps < 2) return SPSTD_ERR_ARG;
+    for (int k = 0; k < nE; ++k)
+        if (!std::isfinite(E[k])) return SPSTD_ERR_ARG;
+    EigParams ep{};
+    for (int k = 0; k < nE; ++k) ep.E[k] = E[k];
+    ep.nE = nE;
+    ep.M = nsteps;
+    ep.dt_over_hbar = p->dt / p->d.hbar;
+    ep.acc = reinterpret_cast<double*>(p->ws + p->L.eig);
+    ep.count = reinterpret_cast<const int64_t*>(p->ws + p->L.ecount);
+    HIPCHK(launch_fill0<double>((int64_t)nE * 2 * p->N, ep.acc, p->st));
+    HIPCHK(launch_fill0<int64_t>(1, reinterpret_cast<int64_t*>(p->ws + p->L.ecount), p->st));
+    // the step graph holds the accumulation's arguments: capture it again
+    if (p->graph_ready) {
+        HIPCHK(hipStreamSynchronize(p->st));
+        (void)hipGraphExecDestroy(p->graph);
+        p->graph_ready = false;
+    }
+    p->eig = ep;
+    p->eig_on = true;
+    return SPSTD_OK;
+}
+
+spstd_status spstd_eig_read(spstd_plan_t p, int k, double* re, double* im) {
+    if (!p || !re || !im || !p->eig_on || k < 0 || k >= p->eig.nE) return SPSTD_ERR_ARG;
+    std::vector<double> tmp((size_t)2 * p->N);
+    HIPCHK(hipMemcpyAsync(tmp.data(), p->eig.acc + (size_t)2 * k * p->N, tmp.size() * sizeof(double),
+                          hipMemcpyDeviceToHost, p->st));
+    HIPCHK(hipStreamSynchronize(p->st));
+    for (int64_t i = 0; i < p->N; ++i) {
+        re[i] = tmp[2 * i];
+        im[i] = tmp[2 * i + 1];
     }
     return SPSTD_OK;
 }

@@ -720,6 +720,42 @@ __global__ __launch_bounds__(256) void k_fd_acc(const R* __restrict__ src, R* __
     }
 }
 
+// ---------------------------------------------------------------------------
+// Eigenstate accumulation: one windowed Fourier term per step and energy.
+// The window weight and the phase factors depend only on the step; the
+// block's first threads form them once in FP64 and share them.
+// ---------------------------------------------------------------------------
+template <typename R>
+__global__ __launch_bounds__(256) void k_eig_acc(const R* __restrict__ psiR, const R* __restrict__ psiI,
+                                                 int64_t npts, EigParams ep) {
+    __shared__ double cs[8][2];
+    const int64_t m = *ep.count;
+    if (m >= ep.M) return;
+    if ((int)threadIdx.x < ep.nE) {
+        const double t = 2.0 * 3.14159265358979323846 * (double)m / (double)(ep.M - 1);
+        const double w = 0.35875 - 0.48829 * cos(t) + 0.14128 * cos(2.0 * t) - 0.01168 * cos(3.0 * t);
+        const double ph = ep.E[threadIdx.x] * (double)m * ep.dt_over_hbar;
+        cs[threadIdx.x][0] = w * cos(ph);
+        cs[threadIdx.x][1] = w * sin(ph);
+    }
+    __syncthreads();
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < npts;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const double a = (double)psiR[i], b = (double)psiI[i];
+        for (int k = 0; k < ep.nE; ++k) {
+            double2* q = reinterpret_cast<double2*>(ep.acc + 2 * ((int64_t)k * npts + i));
+            double2 v = *q;
+            v.x += cs[k][0] * a - cs[k][1] * b;
+            v.y += cs[k][1] * a + cs[k][0] * b;
+            *q = v;
+        }
+    }
+}
+
+__global__ void k_count_tick(int64_t* count) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *count = *count + 1;
+}
+
 // Per-block FP64 partials of sum V (psiR^2 + psiI^2) and of sum psiR^2 + psiI^2.
 template <typename R>
 __global__ __launch_bounds__(256) void k_energy_pot(const R* __restrict__ a, const R* __restrict__ b,
@@ -995,6 +1031,17 @@ hipError_t launch_fd_acc(const R* src, R* dst, const R* V, const int64_t* n, con
 }
 
 template <typename R>
+hipError_t launch_eig_acc(const R* psiR, const R* psiI, int64_t npts, const EigParams& ep, hipStream_t st) {
+    hipLaunchKernelGGL((k_eig_acc<R>), dim3(ew_blocks(npts)), dim3(256), 0, st, psiR, psiI, npts, ep);
+    return hipGetLastError();
+}
+
+hipError_t launch_count_tick(int64_t* count, hipStream_t st) {
+    hipLaunchKernelGGL(k_count_tick, dim3(1), dim3(64), 0, st, count);
+    return hipGetLastError();
+}
+
+template <typename R>
 hipError_t launch_axpby(int64_t n, double a, const R* x, double b, R* y, hipStream_t st) {
     hipLaunchKernelGGL((k_axpby<R>), dim3(ew_blocks(n)), dim3(256), 0, st, n, (R)a, x, (R)b, y);
     return hipGetLastError();
@@ -1030,6 +1077,7 @@ hipError_t launch_fill0(int64_t n, R* y, hipStream_t st) {
     template hipError_t launch_axpby<R>(int64_t, double, const R*, double, R*, hipStream_t);    \
     template hipError_t launch_xpay<R>(int64_t, const R*, double, const R*, R*, hipStream_t);   \
     template hipError_t launch_fill0<R>(int64_t, R*, hipStream_t);                             \
+    template hipError_t launch_eig_acc<R>(const R*, const R*, int64_t, const EigParams&, hipStream_t); \
     template hipError_t launch_fd_acc<R>(const R*, R*, const R*, const int64_t*, const ScaleRef&, \
                                          int, int, hipStream_t);                                \
     template hipError_t launch_energy_axis<R>(int64_t, int, int, const R*, const R*, const void*, \
@@ -1043,5 +1091,6 @@ hipError_t launch_fill0(int64_t n, R* y, hipStream_t st) {
 
 SPSTD_INSTANTIATE(double)
 SPSTD_INSTANTIATE(float)
+template hipError_t launch_fill0<int64_t>(int64_t, int64_t*, hipStream_t);
 
 }  // namespace spstd

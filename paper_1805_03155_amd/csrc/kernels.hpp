@@ -95,6 +95,23 @@ hipError_t launch_xpay(int64_t n, const R* x, double a, const R* y, R* z,
 template <typename R>
 hipError_t launch_fill0(int64_t n, R* y, hipStream_t st);
 
+// Windowed Fourier accumulation of the state (eigenstate reconstruction):
+// with m = *count, if m < M: acc_k[i] += w_m exp(+i E_k m dt/hbar) psi[i]
+// for k < nE, w_m the symmetric 4-term Blackman-Harris window of length M;
+// acc_k is [npts] complex FP64 (re, im interleaved) at acc + 2 k npts.
+struct EigParams {
+    double E[8];
+    int nE;
+    int64_t M;
+    double dt_over_hbar;
+    double* acc;
+    const int64_t* count;
+};
+template <typename R>
+hipError_t launch_eig_acc(const R* psiR, const R* psiI, int64_t npts, const EigParams& ep, hipStream_t st);
+// (*count)++ (one thread; after the accumulation of a step)
+hipError_t launch_count_tick(int64_t* count, hipStream_t st);
+
 // Three-point difference substep over all axes of one grid n[3]:
 // dst += sum_d k_d (2 f - f[+e_d] - f[-e_d]) + p V f, periodic wrap, with
 // k_d from scale columns kcol0 + d and p from pcol (instance 0).

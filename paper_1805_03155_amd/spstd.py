@@ -47,7 +47,7 @@ class Desc(ctypes.Structure):
                 ("mass", c_d), ("precision", c_int), ("method", c_int), ("m", c_int),
                 ("c", P(c_d)), ("d", P(c_d)), ("dt", c_d), ("cfl_fraction", c_d),
                 ("nyquist", c_int), ("nprobes", c_int), ("probe_idx", P(c_i64)),
-                ("flags", c_u32), ("bc", c_int * 3), ("laplacian", c_int)]
+                ("flags", c_u32), ("bc", c_int * 3), ("laplacian", c_int), ("neig", c_int)]
 
 
 class BatchDesc(ctypes.Structure):
@@ -64,7 +64,7 @@ class Stats(ctypes.Structure):
 EXPORTS = ["spstd_xmax", "spstd_stable_dt", "spstd_workspace_size", "spstd_plan",
            "spstd_step", "spstd_run", "spstd_plan_info", "spstd_device_fields",
            "spstd_get_state", "spstd_set_state", "spstd_spectrum", "spstd_pass_times",
-           "spstd_energy",
+           "spstd_energy", "spstd_eig_begin", "spstd_eig_read",
            "spstd_destroy", "spstd_strerror", "spstd_last_error",
            "spstd_batch_workspace_size", "spstd_batch_create", "spstd_batch_load",
            "spstd_batch_step", "spstd_batch_read", "spstd_batch_release",
@@ -96,6 +96,8 @@ def lib():
         L.spstd_spectrum.argtypes = [pd, c_i64, c_int, c_d, c_d, c_int, pd, pd, P(c_int)]
         L.spstd_pass_times.argtypes = [ctypes.c_void_p, pi64, pd, pd]
         L.spstd_energy.argtypes = [ctypes.c_void_p, pd]
+        L.spstd_eig_begin.argtypes = [ctypes.c_void_p, pd, c_int, c_i64]
+        L.spstd_eig_read.argtypes = [ctypes.c_void_p, c_int, pd, pd]
         L.spstd_destroy.argtypes = [ctypes.c_void_p]
         vp = ctypes.c_void_p
         L.spstd_batch_workspace_size.argtypes = [P(BatchDesc), P(c_sz)]
@@ -139,7 +141,7 @@ def _f64(a):
 
 def make_desc(n, dx, c=None, d=None, dt=0.0, cfl_fraction=0.5, hbar=1.0, mass=1.0,
               precision=FP64, method=SYMPLECTIC, nyquist=NYQ_FULL, probes=(), flags=0, bc=None,
-              laplacian=LAP_SPECTRAL):
+              laplacian=LAP_SPECTRAL, neig=0):
     """Build a descriptor; the returned object keeps its arrays alive.
     bc: boundary per axis (BC_PERIODIC, BC_DIRICHLET, BC_NEUMANN), default
     periodic."""
@@ -167,6 +169,7 @@ def make_desc(n, dx, c=None, d=None, dt=0.0, cfl_fraction=0.5, hbar=1.0, mass=1.
     for a in range(3):
         desc.bc[a] = int(bc[a]) if bc is not None and a < len(bc) else BC_PERIODIC
     desc.laplacian = laplacian
+    desc.neig = int(neig)
     desc._keep = keep
     return desc
 
@@ -268,6 +271,20 @@ class Plan:
         _check(lib().spstd_energy(self.h, _dp(out)), self.h)
         return float(out[0]), float(out[1]), float(out[2])
 
+    def eig_begin(self, energies, nsteps):
+        """Accumulate the windowed Fourier sums of the next nsteps states at
+        the given energies (plan made with neig >= len(energies))."""
+        E = _f64(np.atleast_1d(energies))
+        self._neig = len(E)
+        _check(lib().spstd_eig_begin(self.h, _dp(E), len(E), int(nsteps)), self.h)
+
+    def eig_read(self, k):
+        """Accumulator k as a complex array of the grid's size."""
+        re = np.zeros(self.npoints)
+        im = np.zeros(self.npoints)
+        _check(lib().spstd_eig_read(self.h, int(k), _dp(re), _dp(im)), self.h)
+        return re + 1j * im
+
     def info(self):
         st = Stats()
         _check(lib().spstd_plan_info(self.h, ctypes.byref(st)), self.h)
@@ -306,12 +323,12 @@ class Plan:
 
 def plan_from_workload(w, precision=FP64, method=SYMPLECTIC, dt=0.0, nsteps_max=None,
                        nyquist=NYQ_FULL, flags=0, coeffs=None, device="cuda", stream=None,
-                       laplacian=LAP_SPECTRAL):
+                       laplacian=LAP_SPECTRAL, neig=0):
     """Plan for a workloads.Workload (same arrays the oracle is given)."""
     c, d = coeffs if coeffs is not None else w.coeffs
     desc = make_desc(w.n, w.dx, c, d, dt=dt, cfl_fraction=w.cfl_fraction, hbar=w.hbar,
                      mass=w.mass, precision=precision, method=method, nyquist=nyquist,
-                     probes=w.probes, flags=flags, bc=w.bc, laplacian=laplacian)
+                     probes=w.probes, flags=flags, bc=w.bc, laplacian=laplacian, neig=neig)
     return Plan(desc, w.V, w.psiR, w.psiI,
                 nsteps_max=w.steps if nsteps_max is None else nsteps_max,
                 device=device, stream=stream)
