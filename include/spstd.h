@@ -56,6 +56,8 @@ enum { SPSTD_LAP_SPECTRAL = 0, SPSTD_LAP_FD3 = 1 };  /* spatial second derivativ
                                                         bracketed by HIP events (spstd_pass_times) */
 #define SPSTD_NO_RESIDENT 0x8u                       /* flags: 1D plans use the pass kernels
                                                         even where the resident kernel applies */
+#define SPSTD_AUTOTUNE 0x10u                         /* batch flags: time the candidate schedules
+                                                        at creation and keep the faster */
 #define SPSTD_MAX_STAGES 16
 #define SPSTD_MAX_PROBES 64
 #define SPSTD_MAX_EIG 8
@@ -313,7 +315,14 @@ typedef struct spstd_batch_s *spstd_batch_t;
  *   capacity      number of slots (>= 1).
  *   nprobes       probe points per slot, 0..8.
  *   nsteps_max    probe samples kept per slot after sample 0.
- *   flags         SPSTD_ALLOW_UNSTABLE, SPSTD_NO_RESIDENT.
+ *   flags         SPSTD_ALLOW_UNSTABLE, SPSTD_NO_RESIDENT, SPSTD_AUTOTUNE.
+ *                 A 1D batch of up to 16384 points has two schedules: the
+ *                 resident kernel (whole step chunks in one launch) or the
+ *                 pass kernels replayed as step graphs.  SPSTD_AUTOTUNE runs
+ *                 both for a few steps on the empty batch at creation (every
+ *                 slot stepping a zero state at a nominal dt), keeps the
+ *                 faster, and remembers the choice for this (shape,
+ *                 precision, capacity) for the rest of the process.
  */
 typedef struct spstd_batch_desc {
     int ndim;
@@ -371,6 +380,12 @@ spstd_status spstd_batch_read(spstd_batch_t batch, int slot, double *probes_out,
 
 /* Free a slot (its fields and scales are cleared).  Synchronises. */
 spstd_status spstd_batch_release(spstd_batch_t batch, int slot);
+
+/* The schedule in use: *resident = 1 for the resident 1D kernel, 0 for the
+ * pass kernels; *tuned_us = the measured microseconds per step of each
+ * schedule at creation ([resident, passes]; 0 where not measured; may be
+ * NULL). */
+spstd_status spstd_batch_schedule(spstd_batch_t batch, int *resident, double *tuned_us);
 
 /* Slot state: active flag, steps since its load, time step. */
 spstd_status spstd_batch_slot_info(spstd_batch_t batch, int slot, int *active, int64_t *steps_done,

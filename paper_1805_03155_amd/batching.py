@@ -32,7 +32,7 @@ def run_instances(instances, steps, precision=spstd.FP32, coeffs=None, nprobes=1
     for shape, idx in groups.items():
         st = torch.cuda.Stream(device=device)
         b = spstd.Batch(shape, coeffs, capacity=len(idx), nprobes=nprobes, nsteps_max=steps,
-                        precision=precision, device=device, stream=st)
+                        precision=precision, device=device, stream=st, flags=spstd.AUTOTUNE)
         for s, i in enumerate(idx):
             w = instances[i]
             dts[i] = b.load(s, w.dx, w.V, w.psiR, w.psiI, w.probes[:nprobes],
@@ -53,5 +53,6 @@ def run_instances(instances, steps, precision=spstd.FP32, coeffs=None, nprobes=1
     su = sum(np.prod(w.n) for w in instances) * steps * subs / 2.0
     stats = {"elapsed_s": el, "stage_updates": su, "stage_updates_per_s": su / el,
              "groups": {str(k): len(v[2]) for k, v in batches.items()},
+             "schedules": {str(k): v[0].schedule()[0] for k, v in batches.items()},
              "points": int(sum(np.prod(w.n) for w in instances))}
     return results, stats

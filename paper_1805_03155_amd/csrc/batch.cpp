@@ -10,8 +10,11 @@
 
 #include <cmath>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <new>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "../../include/spstd.h"
@@ -74,6 +77,7 @@ struct Batch {
     int nres = 0;               // active slots in the resident table
     hipGraphExec_t graph;
     bool graph_ready = false;
+    double tuned_us[2] = {0.0, 0.0};   // [resident, passes] per step at creation
     std::string err;
 };
 
@@ -239,6 +243,106 @@ static spstd_status batch_step_t(Batch* b, int64_t n) {
     return SPSTD_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Schedule autotuner for 1D batches: resident kernel against pass-kernel
+// graphs, timed on the empty batch (every slot stepping a zero state with the
+// scales of a nominal instance) and remembered per (n, precision, capacity).
+// ---------------------------------------------------------------------------
+static std::mutex g_tune_mu;
+static std::map<std::tuple<int64_t, size_t, int>, std::pair<bool, std::pair<double, double>>> g_tune;
+
+template <typename R>
+static spstd_status time_steps(Batch* b, int64_t warm, int64_t n, double* us) {
+    spstd_status s = batch_step_t<R>(b, warm);
+    if (s != SPSTD_OK) return s;
+    hipEvent_t e0, e1;
+    BCHK(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return SPSTD_ERR_DEVICE;
+    }
+    hipError_t e = hipEventRecord(e0, b->st);
+    if (e == hipSuccess) s = batch_step_t<R>(b, n);
+    if (e == hipSuccess && s == SPSTD_OK) e = hipEventRecord(e1, b->st);
+    if (e == hipSuccess && s == SPSTD_OK) e = hipEventSynchronize(e1);
+    float ms = 0.0f;
+    if (e == hipSuccess && s == SPSTD_OK) e = hipEventElapsedTime(&ms, e0, e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (e != hipSuccess) {
+        b->err = hipGetErrorString(e);
+        return SPSTD_ERR_DEVICE;
+    }
+    *us = s == SPSTD_OK ? 1e3 * ms / (double)n : 0.0;
+    return s;
+}
+
+template <typename R>
+static spstd_status batch_autotune(Batch* b) {
+    const auto key = std::make_tuple(b->d.n[0], b->esz, b->d.capacity);
+    {
+        std::lock_guard<std::mutex> g(g_tune_mu);
+        auto it = g_tune.find(key);
+        if (it != g_tune.end()) {
+            b->resident = it->second.first;
+            b->tuned_us[0] = it->second.second.first;
+            b->tuned_us[1] = it->second.second.second;
+            return SPSTD_OK;
+        }
+    }
+    // nominal instance: dx = hbar = m* = 1, V = 0, dt = 0.5 x_max / rho
+    spstd_desc one{};
+    one.ndim = 1;
+    one.n[0] = b->d.n[0];
+    one.n[1] = one.n[2] = 1;
+    one.dx[0] = one.dx[1] = one.dx[2] = 1.0;
+    one.hbar = one.mass = 1.0;
+    const double dt = 0.5 * b->xmax / (0.5 * kPi * kPi);
+    std::vector<double> rows((size_t)b->d.m * SC_COLS);
+    for (int l = 0; l < b->d.m; ++l) scale_row(one, b->c[l] * dt, -b->dd[l] * dt, &rows[(size_t)l * SC_COLS]);
+    std::vector<R> rr(rows.size() * (size_t)b->d.capacity);
+    for (int i = 0; i < b->d.capacity; ++i)
+        for (size_t k = 0; k < rows.size(); ++k) rr[(size_t)i * rows.size() + k] = (R)rows[k];
+    std::vector<int> act(b->d.capacity, 1);
+    BCHK(hipMemcpyAsync(b->ws + b->L.scales, rr.data(), rr.size() * sizeof(R), hipMemcpyHostToDevice, b->st));
+    BCHK(hipMemcpyAsync(b->ws + b->L.active, act.data(), act.size() * sizeof(int), hipMemcpyHostToDevice, b->st));
+    BCHK(hipStreamSynchronize(b->st));
+    for (Slot& sl : b->slots) {
+        sl.active = true;
+        sl.dt = dt;
+        sl.hbar = sl.mass = 1.0;
+        for (int a = 0; a < 3; ++a) sl.dx[a] = 1.0;
+        for (int q = 0; q < b->d.nprobes; ++q) sl.probe_idx[q] = 0;
+    }
+    const int64_t trial = 2 * kBatchGraphChunk;
+    double us[2] = {0.0, 0.0};
+    b->resident = true;
+    b->rtab_dirty = true;
+    spstd_status s = time_steps<R>(b, kBatchGraphChunk, trial, &us[0]);
+    if (s == SPSTD_OK) {
+        b->resident = false;
+        s = time_steps<R>(b, kBatchGraphChunk, trial, &us[1]);
+    }
+    // back to an empty batch: zero scales, counters and active flags (the
+    // fields stayed zero: a zero state steps to zero)
+    std::vector<R> zr(rr.size(), (R)0);
+    std::vector<int> za(b->d.capacity, 0);
+    std::vector<int64_t> zc(b->d.capacity, 0);
+    BCHK(hipMemcpyAsync(b->ws + b->L.scales, zr.data(), zr.size() * sizeof(R), hipMemcpyHostToDevice, b->st));
+    BCHK(hipMemcpyAsync(b->ws + b->L.active, za.data(), za.size() * sizeof(int), hipMemcpyHostToDevice, b->st));
+    BCHK(hipMemcpyAsync(b->ws + b->L.counter, zc.data(), zc.size() * sizeof(int64_t), hipMemcpyHostToDevice, b->st));
+    BCHK(hipStreamSynchronize(b->st));
+    for (Slot& sl : b->slots) sl = Slot{};
+    b->rtab_dirty = true;
+    if (s != SPSTD_OK) return s;
+    b->resident = us[0] <= us[1];
+    b->tuned_us[0] = us[0];
+    b->tuned_us[1] = us[1];
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    g_tune[key] = std::make_pair(b->resident, std::make_pair(us[0], us[1]));
+    return SPSTD_OK;
+}
+
 template <typename R>
 static spstd_status batch_upload_slot(Batch* b, int slot, const double* V, const double* pr, const double* pi,
                                       const double* row_tab) {
@@ -340,7 +444,25 @@ spstd_status spstd_batch_create(const spstd_batch_desc* d, void* d_workspace, si
         delete b;
         return SPSTD_ERR_DEVICE;
     }
+    if (b->resident && (d->flags & SPSTD_AUTOTUNE)) {
+        s = (b->esz == 8) ? batch_autotune<double>(b) : batch_autotune<float>(b);
+        if (s != SPSTD_OK) {
+            if (b->graph_ready) (void)hipGraphExecDestroy(b->graph);
+            delete b;
+            return s;
+        }
+    }
     *out = b;
+    return SPSTD_OK;
+}
+
+spstd_status spstd_batch_schedule(spstd_batch_t b, int* resident, double* tuned_us) {
+    if (!b || !resident) return SPSTD_ERR_ARG;
+    *resident = b->resident ? 1 : 0;
+    if (tuned_us) {
+        tuned_us[0] = b->tuned_us[0];
+        tuned_us[1] = b->tuned_us[1];
+    }
     return SPSTD_OK;
 }
 

@@ -126,7 +126,7 @@ class Server:
         stream = self.torch.cuda.Stream(device=self.device)
         b = spstd.Batch(n, self.coeffs, capacity=int(cap), nprobes=self.nprobes,
                         nsteps_max=self.max_steps, precision=prec, device=self.device,
-                        stream=stream)
+                        stream=stream, flags=spstd.AUTOTUNE)
         nbytes = b.ws.numel()
         c = _Class(key, b, stream, nbytes)
         self.classes[key] = c

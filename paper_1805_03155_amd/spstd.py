@@ -23,6 +23,7 @@ ALLOW_UNSTABLE = 0x1
 EAGER = 0x2          # no step-chunk graphs
 TIMING = 0x4         # pass kernels bracketed by HIP events (pass_times)
 NO_RESIDENT = 0x8    # 1D plans use the pass kernels, not the resident kernel
+AUTOTUNE = 0x10      # batches: time both 1D schedules at creation, keep the faster
 PASS_KINDS = ("y", "z", "xab", "x")
 MAX_PROBES = 64
 
@@ -68,7 +69,8 @@ EXPORTS = ["spstd_xmax", "spstd_stable_dt", "spstd_workspace_size", "spstd_plan"
            "spstd_destroy", "spstd_strerror", "spstd_last_error",
            "spstd_batch_workspace_size", "spstd_batch_create", "spstd_batch_load",
            "spstd_batch_step", "spstd_batch_read", "spstd_batch_release",
-           "spstd_batch_slot_info", "spstd_batch_destroy", "spstd_batch_last_error"]
+           "spstd_batch_slot_info", "spstd_batch_destroy", "spstd_batch_last_error",
+           "spstd_batch_schedule"]
 
 _lib = None
 
@@ -107,6 +109,7 @@ def lib():
         L.spstd_batch_read.argtypes = [vp, c_int, pd, pd, pd, pi64]
         L.spstd_batch_release.argtypes = [vp, c_int]
         L.spstd_batch_slot_info.argtypes = [vp, c_int, P(c_int), pi64, pd]
+        L.spstd_batch_schedule.argtypes = [vp, P(c_int), pd]
         L.spstd_batch_destroy.argtypes = [vp]
         L.spstd_batch_last_error.argtypes = [vp]
         L.spstd_batch_last_error.restype = ctypes.c_char_p
@@ -407,6 +410,14 @@ class Batch:
 
     def step(self, nsteps):
         _check(lib().spstd_batch_step(self.h, int(nsteps)), batch=self.h)
+
+    def schedule(self):
+        """("resident" or "passes", measured us/step [resident, passes] at
+        creation, zeros where not tuned)."""
+        r = c_int()
+        us = np.zeros(2)
+        _check(lib().spstd_batch_schedule(self.h, ctypes.byref(r), _dp(us)))
+        return ("resident" if r.value else "passes"), (float(us[0]), float(us[1]))
 
     def slot_info(self, slot):
         a, s, dt = c_int(), c_i64(), c_d()

@@ -114,3 +114,32 @@ def test_batch_release_and_reload_slot():
     assert ei.value.code == 6
     with pytest.raises(spstd.SpstdError):
         b.load(1, w0.dx, w0.V, w0.psiR, w0.psiI, w0.probes)   # slot busy
+
+
+@pytest.mark.parametrize("n,prec", [(512, spstd.FP64), (8192, spstd.FP64), (2048, spstd.FP32)])
+def test_autotuned_batch_starts_empty_and_matches_alone(n, prec):
+    steps = 40
+    b = spstd.Batch((n,), W.PAPER, capacity=3, nprobes=2, nsteps_max=steps, precision=prec,
+                    flags=spstd.AUTOTUNE)
+    sched, us = b.schedule()
+    assert us[0] > 0 and us[1] > 0
+    assert sched == ("resident" if us[0] <= us[1] else "passes")
+    # the same key again: the remembered choice, no new timing
+    b2 = spstd.Batch((n,), W.PAPER, capacity=3, nprobes=2, nsteps_max=steps, precision=prec,
+                     flags=spstd.AUTOTUNE)
+    assert b2.schedule() == (sched, us)
+    for s in range(3):
+        assert b.slot_info(s)[0] is False
+    ws = {s: inst((n,), seed=300 + s, nprobes=2) for s in (0, 2)}
+    dts = {}
+    for s, w in ws.items():
+        dts[s] = 0.9 * oracle.stable_dt(*w.coeffs, w.V, w.n, w.dx)
+        b.load(s, w.dx, w.V, w.psiR, w.psiI, w.probes, dt=dts[s])
+    b.step(steps)
+    tol = 1e-13 if prec == spstd.FP64 else 2e-5
+    for s, w in ws.items():
+        ser, r, i, k = b.read(s)
+        assert k == steps
+        ra, ia, sa = alone(w, dts[s], steps, prec)
+        assert rel(np.concatenate([r, i]), np.concatenate([ra, ia])) < tol
+        assert rel(ser, sa) < tol
