@@ -160,6 +160,23 @@ def serving_leg(count, rate, steps, seed=0, budget_gb=64):
     return out
 
 
+def serving_sweep(count, rates, steps, budgets_gb=(64,), small_budget_gb=2, small_rate=30.0):
+    """The serving workload at several offered rates (same seeded request
+    mix at each rate), plus one run whose HBM budget forces queueing."""
+    out = []
+    for rate in rates:
+        log(f"serving sweep: {count} requests at {rate}/s")
+        r = serving_leg(count, rate, steps, budget_gb=budgets_gb[0])
+        r["offered_per_s"] = rate
+        out.append(r)
+        log(f"  p50 {r['p50_s']:.2f} s, p99 {r['p99_s']:.2f} s, {r['completed_per_s']:.2f} done/s")
+    log(f"serving sweep: {count} requests at {small_rate}/s under a {small_budget_gb} GB budget")
+    r = serving_leg(count, small_rate, steps, budget_gb=small_budget_gb)
+    r["offered_per_s"] = small_rate
+    out.append(r)
+    return out
+
+
 def pmc_sample(w, steps):
     """Short run for hardware-counter passes: a plain device copy of a known
     size (the calibration of FETCH_SIZE / WRITE_SIZE), then a few eager
@@ -259,6 +276,8 @@ def main():
     ap.add_argument("--study", choices=["precision", "rk4"],
                     help="long-run accuracy study instead of the timing line")
     ap.add_argument("--study-steps", type=int, default=100000)
+    ap.add_argument("--serve-sweep", action="store_true",
+                    help="serving at offered rates 10..1000/s instead of the timing line")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: this engine has no multi-GPU path "
@@ -276,6 +295,10 @@ def main():
         return
     if args.study:
         print(json.dumps(precision_study(w, args.study, args.study_steps)), flush=True)
+        return
+    if args.serve_sweep:
+        sweep = serving_sweep(args.serve_requests, (10.0, 30.0, 100.0, 300.0, 1000.0), (2000, 20000))
+        print(json.dumps({"serving_sweep": sweep}), flush=True)
         return
     res = {}
     for prec in ("fp64", "fp32"):
