@@ -304,6 +304,9 @@ static spstd_status batch_autotune(Batch* b) {
     for (int i = 0; i < b->d.capacity; ++i)
         for (size_t k = 0; k < rows.size(); ++k) rr[(size_t)i * rows.size() + k] = (R)rows[k];
     std::vector<int> act(b->d.capacity, 1);
+    // every slot samples point 0 during the trial
+    std::vector<int64_t> pz((size_t)b->d.capacity * (b->d.nprobes > 0 ? b->d.nprobes : 1), 0);
+    BCHK(hipMemcpyAsync(b->ws + b->L.pidx, pz.data(), pz.size() * sizeof(int64_t), hipMemcpyHostToDevice, b->st));
     BCHK(hipMemcpyAsync(b->ws + b->L.scales, rr.data(), rr.size() * sizeof(R), hipMemcpyHostToDevice, b->st));
     BCHK(hipMemcpyAsync(b->ws + b->L.active, act.data(), act.size() * sizeof(int), hipMemcpyHostToDevice, b->st));
     BCHK(hipStreamSynchronize(b->st));
@@ -423,6 +426,11 @@ spstd_status spstd_batch_create(const spstd_batch_desc* d, void* d_workspace, si
     }
     std::vector<int> act(d->capacity, 0);
     std::vector<int64_t> cnt(d->capacity, 0);
+    // probe indices start at point 0 (in range) for every slot: the probe
+    // kernel reads the indices of every slot it marks as sampled
+    std::vector<int64_t> pz((size_t)d->capacity * (d->nprobes > 0 ? d->nprobes : 1), 0);
+    if (e == hipSuccess) e = hipMemcpyAsync(b->ws + L.pidx, pz.data(), pz.size() * sizeof(int64_t),
+                                            hipMemcpyHostToDevice, b->st);
     if (e == hipSuccess) e = hipMemcpyAsync(b->ws + L.active, act.data(), act.size() * sizeof(int),
                                             hipMemcpyHostToDevice, b->st);
     if (e == hipSuccess) e = hipMemcpyAsync(b->ws + L.counter, cnt.data(), cnt.size() * sizeof(int64_t),
