@@ -275,10 +275,11 @@ spstd_status spstd_spectrum(const double *series, int64_t nsamples, int nprobes,
  * Kinds of pass kernels, for spstd_pass_times.  Y and Z: one directional
  * second-derivative pass along y or z added into a field; XAB: the fused A
  * and B halves along x of one stage (Eq. 18 and its psi_I mirror); X: one
- * half-stage along x.
+ * half-stage along x; YBA: the y pass of the B half of a stage fused with
+ * the y pass of the A half of the next stage (one sweep of the y pencils).
  */
 enum { SPSTD_PASS_Y = 0, SPSTD_PASS_Z = 1, SPSTD_PASS_XAB = 2, SPSTD_PASS_X = 3,
-       SPSTD_NPASS_KINDS = 4 };
+       SPSTD_PASS_YBA = 4, SPSTD_NPASS_KINDS = 5 };
 
 /*
  * Per-kind kernel timing of a plan made with SPSTD_TIMING: synchronises the

@@ -114,15 +114,9 @@ static spstd_status validate_batch(const spstd_batch_desc* d) {
 }
 
 template <typename R>
-static hipError_t batch_yz(Batch* b, const R* src, R* dst, const ScaleRef& sc, int ab) {
-    for (int a = 1; a < b->d.ndim; ++a) {
-        const int col = (ab ? SC_KXB : SC_KXA) + a;
-        hipError_t e = launch_axis_acc<R>(b->d.n[a], src, dst, b->ws + b->L.tw[a],
-                                          axis_geom_of_n(b->d.ndim, b->d.n, a, b->d.capacity), sc, col,
-                                          b->d.nyquist, b->st);
-        if (e != hipSuccess) return e;
-    }
-    return hipSuccess;
+static hipError_t batch_axis(Batch* b, int a, const R* src, R* dst, const ScaleRef& sc, int col) {
+    return launch_axis_acc<R>(b->d.n[a], src, dst, b->ws + b->L.tw[a],
+                              axis_geom_of_n(b->d.ndim, b->d.n, a, b->d.capacity), sc, col, b->d.nyquist, b->st);
 }
 
 template <typename R>
@@ -135,16 +129,41 @@ static hipError_t batch_step_once(Batch* b) {
     const int64_t nx = b->d.n[0];
     const void* twx = b->ws + b->L.tw[0];
     hipError_t e = hipSuccess;
+    // A half y, z, x; B half x, z, y: the B half's y pass and the next A
+    // half's y pass are one sweep (as in the single-plan engine)
+    int owed = -1;
     for (int l = 0; l < b->d.m && e == hipSuccess; ++l) {
         const bool a = b->c[l] != 0.0, bb = b->dd[l] != 0.0;
         const ScaleRef sc{b->ws + b->L.scales, b->d.m, l};
-        if (a) e = batch_yz<R>(b, pi, pr, sc, 0);
+        if (b->d.ndim >= 2) {
+            if (a && owed >= 0) {
+                const ScaleRef so{b->ws + b->L.scales, b->d.m, owed};
+                e = launch_axis_ba<R>(b->d.n[1], pr, pi, b->ws + b->L.tw[1],
+                                      axis_geom_of_n(b->d.ndim, b->d.n, 1, b->d.capacity), so, sc, SC_KYB, SC_KYA,
+                                      b->d.nyquist, b->st);
+            } else {
+                if (owed >= 0) {
+                    const ScaleRef so{b->ws + b->L.scales, b->d.m, owed};
+                    e = batch_axis<R>(b, 1, pr, pi, so, SC_KYB);
+                }
+                if (a && e == hipSuccess) e = batch_axis<R>(b, 1, pi, pr, sc, SC_KYA);
+            }
+            owed = -1;
+            if (a && e == hipSuccess && b->d.ndim == 3) e = batch_axis<R>(b, 2, pi, pr, sc, SC_KZA);
+        }
         if (e != hipSuccess) break;
         if (a && bb) e = launch_x_ab<R>(nx, pr, pi, V, twx, rg, sc, b->d.nyquist, b->st);
         else if (a) e = launch_x_acc<R>(nx, pi, pr, V, twx, rg, sc, SC_KXA, SC_PA, b->d.nyquist, b->st);
         else if (bb) e = launch_x_acc<R>(nx, pr, pi, V, twx, rg, sc, SC_KXB, SC_PB, b->d.nyquist, b->st);
         if (e != hipSuccess) break;
-        if (bb) e = batch_yz<R>(b, pr, pi, sc, 1);
+        if (bb && b->d.ndim >= 2) {
+            if (b->d.ndim == 3) e = batch_axis<R>(b, 2, pr, pi, sc, SC_KZB);
+            owed = l;
+        }
+    }
+    if (e == hipSuccess && owed >= 0) {
+        const ScaleRef so{b->ws + b->L.scales, b->d.m, owed};
+        e = batch_axis<R>(b, 1, pr, pi, so, SC_KYB);
     }
     if (e == hipSuccess && b->d.nprobes > 0)
         e = launch_probe_batch<R>(pr, pi, b->npts, reinterpret_cast<const int64_t*>(b->ws + b->L.pidx),

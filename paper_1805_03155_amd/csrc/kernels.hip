@@ -298,6 +298,104 @@ __global__ __launch_bounds__(64 * WPB) SPSTD_YZ_WAVES_ATTR void k_axis_acc(
 }
 
 // ---------------------------------------------------------------------------
+// y pass at a stage boundary: the B half of stage l and the A half of stage
+// l + 1 along the same pencils in one sweep,
+//   psi_I += sB T_y psi_R,  then  psi_R += sA T_y psi_I(new).
+// With the B half ordered x, z, y and the A half y, z, x, the y pencil of
+// psi_I holds its x and z contributions of stage l when its y contribution
+// is added, so the pencil is complete in registers when the A half of stage
+// l + 1 transforms it.  Reads psi_R, psi_I; writes both (32 B per point in
+// FP64 against 48 B for the two passes it replaces).
+// ---------------------------------------------------------------------------
+template <typename R, int N, int WPB, int P>
+__global__ __launch_bounds__(64 * WPB) SPSTD_YZ_WAVES_ATTR void k_axis_ba(
+    R* __restrict__ psiR, R* __restrict__ psiI, const cpx<R>* __restrict__ tw, AxisGeom g,
+    ScaleRef scB, ScaleRef scA, int colB, int colA, int nyq_zero) {
+    using C = pencil_cfg<N>;
+    using TU = tuning<R>;
+    using V = typename vec_of<R, P>::type;
+    static_assert(C::WAVE, "y/z pencils must fit in one wavefront");
+    constexpr int LS = lds_size<N>::value;
+    constexpr int SL = (TU::SPLIT ? 1 : 2) * LS;
+    __shared__ R lds[N == 16 ? 1 : WPB * C::PPW * P * SL];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int p = lane % C::PPW, j = lane / C::PPW;
+    const int64_t groups_x = g.half_x / P;
+    const int64_t ngroups = groups_x * g.n_outer;
+    constexpr int GPB = WPB * C::PPW;
+    int64_t group;
+    if (SPSTD_YZ_ORDER == 1 && groups_x % GPB == 0) {
+        const int64_t b = blockIdx.x;
+        group = ((b % g.n_outer) * (groups_x / GPB) + b / g.n_outer) * GPB + wave * C::PPW + p;
+    } else {
+        group = ((int64_t)blockIdx.x * WPB + wave) * C::PPW + p;
+    }
+    const bool valid = group < ngroups;
+    const int64_t gx = valid ? group % groups_x : 0, outer = valid ? group / groups_x : 0;
+    const int64_t inst = outer / g.n_in;
+    const int64_t base = inst * g.stride_hi + (outer - inst * g.n_in) * g.stride_lo + 2 * P * gx;
+    const R sB = scale_of<R>(scB, inst, colB), sA = scale_of<R>(scA, inst, colA);
+    if (__all(!valid || (sB == (R)0 && sA == (R)0))) return;
+
+    cpx<R> v[P][16], f[P][16];
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+        if (valid) {
+            load_group<R, P>(psiR + base + (int64_t)(j + C::T * e) * g.stride, v, e);
+        } else {
+#pragma unroll
+            for (int q = 0; q < P; ++q) v[q][e] = cpx<R>{(R)0, (R)0};
+        }
+#pragma unroll
+        for (int q = 0; q < P; ++q) f[q][e] = v[q][e];
+    }
+    R* l0 = lds + (wave * C::PPW + p) * P * SL;
+    // B half of stage l: psi_I += sB T psi_R
+    fft_pencils<R, N, false, true, TU::SPLIT, TU::PRODUCTS, P>(v, j, l0, SL, tw);
+#pragma unroll
+    for (int q = 0; q < P; ++q) apply_k2<R, N>(v[q], j, nyq_zero);
+    fft_pencils<R, N, true, true, TU::SPLIT, TU::PRODUCTS, P>(v, j, l0, SL, tw);
+    epi_begin();
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+        V a{};
+        V* q = reinterpret_cast<V*>(psiI + base + (int64_t)(j + C::T * e) * g.stride);
+        if (valid) a = *q;
+        if constexpr (P == 1) {
+            a.x += sB * v[0][e].x; a.y += sB * v[0][e].y;
+            v[0][e] = cpx<R>{a.x, a.y};
+        } else {
+            a.x += sB * v[0][e].x; a.y += sB * v[0][e].y;
+            a.z += sB * v[1][e].x; a.w += sB * v[1][e].y;
+            v[0][e] = cpx<R>{a.x, a.y};
+            v[1][e] = cpx<R>{a.z, a.w};
+        }
+        if (valid) *q = a;
+        epi_fence(e);
+    }
+    // A half of stage l + 1: psi_R += sA T psi_I(new)
+    fft_pencils<R, N, false, true, TU::SPLIT, TU::PRODUCTS, P>(v, j, l0, SL, tw);
+#pragma unroll
+    for (int q = 0; q < P; ++q) apply_k2<R, N>(v[q], j, nyq_zero);
+    fft_pencils<R, N, true, true, TU::SPLIT, TU::PRODUCTS, P>(v, j, l0, SL, tw);
+    epi_begin();
+    if (valid) {
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+            V a;
+            if constexpr (P == 1) {
+                a.x = f[0][e].x + sA * v[0][e].x; a.y = f[0][e].y + sA * v[0][e].y;
+            } else {
+                a.x = f[0][e].x + sA * v[0][e].x; a.y = f[0][e].y + sA * v[0][e].y;
+                a.z = f[1][e].x + sA * v[1][e].x; a.w = f[1][e].y + sA * v[1][e].y;
+            }
+            *reinterpret_cast<V*>(psiR + base + (int64_t)(j + C::T * e) * g.stride) = a;
+            epi_fence(e);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // x pass helpers: lane l -> position j = l % T, pencil-in-wave p = l / T
 // (neighbouring lanes read neighbouring x), or one pencil per block for
 // N > 1024.
@@ -816,6 +914,35 @@ static hipError_t axis_acc_n(const R* src, R* dst, const void* tw, const AxisGeo
     return hipGetLastError();
 }
 
+template <typename R, int N>
+static hipError_t axis_ba_n(R* psiR, R* psiI, const void* tw, const AxisGeom& g, const ScaleRef& scB,
+                            const ScaleRef& scA, int colB, int colA, int nyq_zero, hipStream_t st) {
+    using C = pencil_cfg<N>;
+    constexpr int P = tuning<R>::YZ_PPL;
+    if (g.half_x % P) return hipErrorInvalidValue;
+    const int64_t ngroups = g.half_x / P * g.n_outer;
+    const int64_t waves = (ngroups + C::PPW - 1) / C::PPW;
+    const int64_t blocks = (waves + kWPB - 1) / kWPB;
+    hipLaunchKernelGGL((k_axis_ba<R, N, kWPB, P>), dim3((unsigned)blocks), dim3(64 * kWPB), 0, st, psiR, psiI,
+                       (const cpx<R>*)tw, g, scB, scA, colB, colA, nyq_zero);
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_axis_ba(int64_t n, R* psiR, R* psiI, const void* tw, const AxisGeom& g, const ScaleRef& scB,
+                          const ScaleRef& scA, int colB, int colA, int nyq_zero, hipStream_t st) {
+    switch (n) {
+        case 16: return axis_ba_n<R, 16>(psiR, psiI, tw, g, scB, scA, colB, colA, nyq_zero, st);
+        case 32: return axis_ba_n<R, 32>(psiR, psiI, tw, g, scB, scA, colB, colA, nyq_zero, st);
+        case 64: return axis_ba_n<R, 64>(psiR, psiI, tw, g, scB, scA, colB, colA, nyq_zero, st);
+        case 128: return axis_ba_n<R, 128>(psiR, psiI, tw, g, scB, scA, colB, colA, nyq_zero, st);
+        case 256: return axis_ba_n<R, 256>(psiR, psiI, tw, g, scB, scA, colB, colA, nyq_zero, st);
+        case 512: return axis_ba_n<R, 512>(psiR, psiI, tw, g, scB, scA, colB, colA, nyq_zero, st);
+        case 1024: return axis_ba_n<R, 1024>(psiR, psiI, tw, g, scB, scA, colB, colA, nyq_zero, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
 template <typename R>
 hipError_t launch_axis_acc(int64_t n, const R* src, R* dst, const void* tw, const AxisGeom& g,
                            const ScaleRef& sc, int col, int nyq_zero, hipStream_t st) {
@@ -1062,6 +1189,9 @@ hipError_t launch_fill0(int64_t n, R* y, hipStream_t st) {
 #define SPSTD_INSTANTIATE(R)                                                                    \
     template hipError_t launch_axis_acc<R>(int64_t, const R*, R*, const void*, const AxisGeom&, \
                                            const ScaleRef&, int, int, hipStream_t);             \
+    template hipError_t launch_axis_ba<R>(int64_t, R*, R*, const void*, const AxisGeom&,        \
+                                          const ScaleRef&, const ScaleRef&, int, int, int,      \
+                                          hipStream_t);                                         \
     template hipError_t launch_x_acc<R>(int64_t, const R*, R*, const R*, const void*,           \
                                         const RowGeom&, const ScaleRef&, int, int, int,         \
                                         hipStream_t);                                           \

@@ -50,6 +50,13 @@ hipError_t launch_axis_acc(int64_t n, const R* src, R* dst, const void* tw,
                            const AxisGeom& g, const ScaleRef& sc, int col, int nyq_zero,
                            hipStream_t st);
 
+// One sweep of y (or z) pencils at a stage boundary:
+//   psiI += sB T psiR  (column colB of stage scB.l), then
+//   psiR += sA T psiI  (column colA of stage scA.l), T the bare axis operator.
+template <typename R>
+hipError_t launch_axis_ba(int64_t n, R* psiR, R* psiI, const void* tw, const AxisGeom& g, const ScaleRef& scB,
+                          const ScaleRef& scA, int colB, int colA, int nyq_zero, hipStream_t st);
+
 // dst += k * IFFT_x(ks^2 FFT_x(src)) + p * V * src with (k, p) of columns
 // (kcol, pcol): one half-stage along x.
 template <typename R>

@@ -24,7 +24,7 @@ EAGER = 0x2          # no step-chunk graphs
 TIMING = 0x4         # pass kernels bracketed by HIP events (pass_times)
 NO_RESIDENT = 0x8    # 1D plans use the pass kernels, not the resident kernel
 AUTOTUNE = 0x10      # batches: time both 1D schedules at creation, keep the faster
-PASS_KINDS = ("y", "z", "xab", "x")
+PASS_KINDS = ("y", "z", "xab", "x", "yba")
 MAX_PROBES = 64
 
 STATUS = {0: "SPSTD_OK", 1: "SPSTD_ERR_ARG", 2: "SPSTD_ERR_UNSTABLE",
