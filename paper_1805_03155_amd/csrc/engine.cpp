@@ -28,6 +28,11 @@ struct Layout {
 };
 
 static const int kNormBlocks = 256;
+
+// Axis whose passes are fused at stage boundaries in 3D grids (1: y, 2: z).
+#ifndef SPSTD_FUSE_AXIS
+#define SPSTD_FUSE_AXIS 1
+#endif
 static const int kGraphChunk = 16;
 
 struct Plan {
@@ -285,15 +290,17 @@ static hipError_t enqueue_symplectic_step(Plan* p) {
     const int64_t nx = p->d.n[0];
     const void* twx = p->ws + p->L.tw[0];
     hipError_t e = hipSuccess;
-    // The B half runs x, z, y and the A half y, z, x, so the y pass owed by
-    // the B half of one stage and the y pass of the next A half are one
-    // sweep of the y pencils (launch_axis_ba).  Steps end with the owed pass
+    // The B half ends with the pass along axis fa (y, or z with
+    // SPSTD_FUSE_AXIS=2) and the A half starts with it, so the pass owed by
+    // the B half of one stage and the first pass of the next A half are one
+    // sweep of those pencils (launch_axis_ba).  Steps end with the owed pass
     // on its own: the probes sample the completed step.
-    const bool fuse_y = p->d.ndim >= 2 && !walled(p, 1);
-    int owed = -1;   // stage whose B half still owes its y pass
-    auto owed_y = [&](int stage) -> hipError_t {
+    const int fa = p->d.ndim == 3 ? SPSTD_FUSE_AXIS : 1, oa = 3 - fa;
+    const bool fuse = p->d.ndim >= 2 && !walled(p, fa);
+    int owed = -1;   // stage whose B half still owes its pass along fa
+    auto owed_pass = [&](int stage) -> hipError_t {
         const ScaleRef so{p->ws + p->L.scales, p->d.m + 1, stage};
-        return axis_pass<R>(p, 1, pr, pi, so, SC_KYB);
+        return axis_pass<R>(p, fa, pr, pi, so, SC_KXB + fa);
     };
     for (int l = 0; l < p->d.m && e == hipSuccess; ++l) {
         const bool a = p->c[l] != 0.0, b = p->dd[l] != 0.0;
@@ -307,14 +314,14 @@ static hipError_t enqueue_symplectic_step(Plan* p) {
             const ScaleRef so{p->ws + p->L.scales, p->d.m + 1, owed};
             {
                 PassTimer tm(p, SPSTD_PASS_YBA);
-                e = launch_axis_ba<R>(p->d.n[1], pr, pi, p->ws + p->L.tw[1], axis_geom_of(p->d, 1, 1), so, sc,
-                                      SC_KYB, SC_KYA, p->d.nyquist, p->st);
+                e = launch_axis_ba<R>(p->d.n[fa], pr, pi, p->ws + p->L.tw[fa], axis_geom_of(p->d, fa, 1), so, sc,
+                                      SC_KXB + fa, SC_KXA + fa, p->d.nyquist, p->st);
             }
             owed = -1;
-            if (e == hipSuccess && p->d.ndim == 3) e = axis_pass<R>(p, 2, pi, pr, sc, SC_KZA);
+            if (e == hipSuccess && p->d.ndim == 3) e = axis_pass<R>(p, oa, pi, pr, sc, SC_KXA + oa);
         } else {
             if (owed >= 0) {
-                e = owed_y(owed);
+                e = owed_pass(owed);
                 owed = -1;
             }
             if (a && e == hipSuccess) e = yz_passes<R>(p, pi, pr, sc, 0);
@@ -335,15 +342,15 @@ static hipError_t enqueue_symplectic_step(Plan* p) {
         }
         if (e != hipSuccess) break;
         if (b) {
-            if (fuse_y) {
-                if (p->d.ndim == 3) e = axis_pass<R>(p, 2, pr, pi, sc, SC_KZB);
+            if (fuse) {
+                if (p->d.ndim == 3) e = axis_pass<R>(p, oa, pr, pi, sc, SC_KXB + oa);
                 owed = l;
             } else {
                 e = yz_passes<R>(p, pr, pi, sc, 1);
             }
         }
     }
-    if (e == hipSuccess && owed >= 0) e = owed_y(owed);
+    if (e == hipSuccess && owed >= 0) e = owed_pass(owed);
     return e;
 }
 
