@@ -28,6 +28,9 @@ bool row_len_ok(int64_t n) { return n >= 16 && n <= 16384 && (n & (n - 1)) == 0;
 //                  SPLIT_XAB_F32 for the fused FP32 x pass, which is faster
 //                  with the joint exchange while the other FP32 passes gain
 //                  occupancy from the split one
+//   BA_RELOAD_*    the stage-boundary y sweep re-reads psi_R for its second
+//                  epilogue instead of keeping it in registers (measured
+//                  slower: 106 -> 121 us FP64, 65 -> 68 us FP32 at 256^3)
 //   YZ_PPL_F64, YZ_MIN_WAVES, YZ_NT  y/z pass variants measured slower
 //                  (two pencils per FP64 lane group, a forced 4 waves per
 //                  SIMD, non-temporal loads and stores)
@@ -78,6 +81,12 @@ bool row_len_ok(int64_t n) { return n >= 16 && n <= 16384 && (n & (n - 1)) == 0;
 #ifndef SPSTD_YZ_NT
 #define SPSTD_YZ_NT 0
 #endif
+#ifndef SPSTD_BA_RELOAD_F64
+#define SPSTD_BA_RELOAD_F64 0
+#endif
+#ifndef SPSTD_BA_RELOAD_F32
+#define SPSTD_BA_RELOAD_F32 0
+#endif
 #ifndef SPSTD_WPB
 #define SPSTD_WPB 4
 #endif
@@ -110,6 +119,7 @@ struct tuning<double> {
     static constexpr bool SPLIT = SPSTD_SPLIT_F64;
     static constexpr bool SPLIT_XAB = SPSTD_SPLIT_F64;
     static constexpr int YZ_PPL = SPSTD_YZ_PPL_F64;
+    static constexpr bool BA_RELOAD = SPSTD_BA_RELOAD_F64;
 };
 template <>
 struct tuning<float> {
@@ -117,6 +127,7 @@ struct tuning<float> {
     static constexpr bool SPLIT = SPSTD_SPLIT_F32;
     static constexpr bool SPLIT_XAB = SPSTD_SPLIT_XAB_F32;
     static constexpr int YZ_PPL = SPSTD_YZ_PPL_F32;
+    static constexpr bool BA_RELOAD = SPSTD_BA_RELOAD_F32;
 };
 
 // Compiler-only memory barrier: values loaded before it are not reused
@@ -337,7 +348,8 @@ __global__ __launch_bounds__(64 * WPB) SPSTD_YZ_WAVES_ATTR void k_axis_ba(
     const R sB = scale_of<R>(scB, inst, colB), sA = scale_of<R>(scA, inst, colA);
     if (__all(!valid || (sB == (R)0 && sA == (R)0))) return;
 
-    cpx<R> v[P][16], f[P][16];
+    constexpr bool RL = TU::BA_RELOAD;
+    cpx<R> v[P][16], f[P][RL ? 1 : 16];
 #pragma unroll
     for (int e = 0; e < 16; ++e) {
         if (valid) {
@@ -346,9 +358,12 @@ __global__ __launch_bounds__(64 * WPB) SPSTD_YZ_WAVES_ATTR void k_axis_ba(
 #pragma unroll
             for (int q = 0; q < P; ++q) v[q][e] = cpx<R>{(R)0, (R)0};
         }
+        if constexpr (!RL) {
 #pragma unroll
-        for (int q = 0; q < P; ++q) f[q][e] = v[q][e];
+            for (int q = 0; q < P; ++q) f[q][e] = v[q][e];
+        }
     }
+    if constexpr (RL) reload_fence();
     R* l0 = lds + (wave * C::PPW + p) * P * SL;
     // B half of stage l: psi_I += sB T psi_R
     fft_pencils<R, N, false, true, TU::SPLIT, TU::PRODUCTS, P>(v, j, l0, SL, tw);
@@ -382,14 +397,23 @@ __global__ __launch_bounds__(64 * WPB) SPSTD_YZ_WAVES_ATTR void k_axis_ba(
     if (valid) {
 #pragma unroll
         for (int e = 0; e < 16; ++e) {
+            V* q = reinterpret_cast<V*>(psiR + base + (int64_t)(j + C::T * e) * g.stride);
             V a;
-            if constexpr (P == 1) {
+            if constexpr (RL) {
+                a = *q;   // psi_R as loaded at the start (unchanged in memory)
+                if constexpr (P == 1) {
+                    a.x += sA * v[0][e].x; a.y += sA * v[0][e].y;
+                } else {
+                    a.x += sA * v[0][e].x; a.y += sA * v[0][e].y;
+                    a.z += sA * v[1][e].x; a.w += sA * v[1][e].y;
+                }
+            } else if constexpr (P == 1) {
                 a.x = f[0][e].x + sA * v[0][e].x; a.y = f[0][e].y + sA * v[0][e].y;
             } else {
                 a.x = f[0][e].x + sA * v[0][e].x; a.y = f[0][e].y + sA * v[0][e].y;
                 a.z = f[1][e].x + sA * v[1][e].x; a.w = f[1][e].y + sA * v[1][e].y;
             }
-            *reinterpret_cast<V*>(psiR + base + (int64_t)(j + C::T * e) * g.stride) = a;
+            *q = a;
             epi_fence(e);
         }
     }
