@@ -87,6 +87,12 @@ bool row_len_ok(int64_t n) { return n >= 16 && n <= 16384 && (n & (n - 1)) == 0;
 #ifndef SPSTD_BA_RELOAD_F32
 #define SPSTD_BA_RELOAD_F32 0
 #endif
+#ifndef SPSTD_V_NT_F64
+#define SPSTD_V_NT_F64 1
+#endif
+#ifndef SPSTD_V_NT_F32
+#define SPSTD_V_NT_F32 0
+#endif
 #ifndef SPSTD_WPB
 #define SPSTD_WPB 4
 #endif
@@ -120,6 +126,7 @@ struct tuning<double> {
     static constexpr bool SPLIT_XAB = SPSTD_SPLIT_F64;
     static constexpr int YZ_PPL = SPSTD_YZ_PPL_F64;
     static constexpr bool BA_RELOAD = SPSTD_BA_RELOAD_F64;
+    static constexpr bool V_NT = SPSTD_V_NT_F64;
 };
 template <>
 struct tuning<float> {
@@ -128,7 +135,19 @@ struct tuning<float> {
     static constexpr bool SPLIT_XAB = SPSTD_SPLIT_XAB_F32;
     static constexpr int YZ_PPL = SPSTD_YZ_PPL_F32;
     static constexpr bool BA_RELOAD = SPSTD_BA_RELOAD_F32;
+    static constexpr bool V_NT = SPSTD_V_NT_F32;
 };
+
+// The potential is read once per x pass.  In FP64 the three fields of a
+// 256^3 grid (403 MB) exceed the 256 MB last-level cache, and reading V
+// without keeping it there leaves the cache to psi_R and psi_I, which the
+// next pass reads (the z pass after the fused x pass: 86 -> 71 us); in FP32
+// the fields fit and V is better cached (non-temporal V: x pass 63 -> 80 us).
+template <typename R>
+__device__ __forceinline__ R load_v(const R* p) {
+    if constexpr (tuning<R>::V_NT) return __builtin_nontemporal_load(p);
+    else return *p;
+}
 
 // Compiler-only memory barrier: values loaded before it are not reused
 // after it (the epilogues re-read their inputs rather than keep them live
@@ -528,8 +547,8 @@ __global__ __launch_bounds__((row_map<R, N, WPB>::THREADS)) SPSTD_WAVES_ATTR voi
 #else
         const R a = f0[e], c = f1[e];
 #endif
-        if (v0) db[i0] = db[i0] + k0 * v[0][e].x + p0 * Vb[i0] * a;
-        if (v1) db[i1] = db[i1] + k1 * v[0][e].y + p1 * Vb[i1] * c;
+        if (v0) db[i0] = db[i0] + k0 * v[0][e].x + p0 * load_v(Vb + i0) * a;
+        if (v1) db[i1] = db[i1] + k1 * v[0][e].y + p1 * load_v(Vb + i1) * c;
         epi_fence(e);
     }
 }
@@ -592,8 +611,8 @@ __global__ __launch_bounds__((row_map<R, N, WPB>::THREADS)) SPSTD_WAVES_ATTR voi
 #else
         fe = f[e];
 #endif
-        if (v0) { vv.x = Vb[i0]; g.x = Rb[i0]; }
-        if (v1) { vv.y = Vb[i1]; g.y = Rb[i1]; }
+        if (v0) { vv.x = load_v(Vb + i0); g.x = Rb[i0]; }
+        if (v1) { vv.y = load_v(Vb + i1); g.y = Rb[i1]; }
         g.x = g.x + sa.x * v[0][e].x + va.x * vv.x * fe.x;
         g.y = g.y + sa.y * v[0][e].y + va.y * vv.y * fe.y;
         if (v0) Rb[i0] = g.x;
@@ -618,8 +637,8 @@ __global__ __launch_bounds__((row_map<R, N, WPB>::THREADS)) SPSTD_WAVES_ATTR voi
         const int i0 = o0 + C::T * e, i1 = o1 + C::T * e;
 #if SPSTD_X_RELOAD
         // psi_R here is the value this lane stored in the A epilogue
-        if (v0) Ib[i0] = Ib[i0] + vb.x * Vb[i0] * Rb[i0] + sb.x * v[0][e].x;
-        if (v1) Ib[i1] = Ib[i1] + vb.y * Vb[i1] * Rb[i1] + sb.y * v[0][e].y;
+        if (v0) Ib[i0] = Ib[i0] + vb.x * load_v(Vb + i0) * Rb[i0] + sb.x * v[0][e].x;
+        if (v1) Ib[i1] = Ib[i1] + vb.y * load_v(Vb + i1) * Rb[i1] + sb.y * v[0][e].y;
 #else
         if (v0) Ib[i0] = f[e].x + sb.x * v[0][e].x;
         if (v1) Ib[i1] = f[e].y + sb.y * v[0][e].y;
