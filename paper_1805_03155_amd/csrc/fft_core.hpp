@@ -213,11 +213,105 @@ __device__ __forceinline__ void twiddles_tail(const cpx<R>* __restrict__ tw, int
 // in the pencil; lds: LDS of pencil 0, pencil p at lds + p * lds_stride;
 // a pencil slice holds lds_size<N> reals (SPLIT) or twice that (re, im).
 // tw: table of w_N^t = exp(-2 pi i t / N), t = 0..N-1.
+// ---------------------------------------------------------------------------
+// Reorder before a radix-RL tail pass without LDS (gfx950 lane swaps).
+// After the last radix-16 pass, with S = N / (16 RL), lane j = m + S q
+// (m < S, q < RL) holds in register t = a + RL c (a < RL) the output that
+// the tail pass wants in lane m + S a, register (16/RL) q + c.  Each bit of
+// q is exchanged with the same bit of a by one swap of register pairs
+// between lanes D = S JS 2^s apart (JS: lane distance of neighbouring j),
+// v_permlane16_swap for D = 16 and v_permlane32_swap for D = 32: in the
+// lower lane the low register keeps its value and the high register
+// receives the partner's low register, in the upper lane the low register
+// receives the partner's high register.  A renaming of registers finishes
+// the reorder.
+// ---------------------------------------------------------------------------
+template <int D>
+__device__ __forceinline__ void swap_dwords(uint32_t& lo, uint32_t& hi) {
+    static_assert(D == 16 || D == 32, "lane swaps span 16 or 32 lanes");
+    if constexpr (D == 16) {
+        const auto r = __builtin_amdgcn_permlane16_swap(lo, hi, false, false);
+        lo = r[0];
+        hi = r[1];
+    } else {
+        const auto r = __builtin_amdgcn_permlane32_swap(lo, hi, false, false);
+        lo = r[0];
+        hi = r[1];
+    }
+}
+
+template <int D>
+__device__ __forceinline__ void swap_reals(float& lo, float& hi) {
+    uint32_t a = __float_as_uint(lo), b = __float_as_uint(hi);
+    swap_dwords<D>(a, b);
+    lo = __uint_as_float(a);
+    hi = __uint_as_float(b);
+}
+
+template <int D>
+__device__ __forceinline__ void swap_reals(double& lo, double& hi) {
+    const uint64_t a = (uint64_t)__double_as_longlong(lo), b = (uint64_t)__double_as_longlong(hi);
+    uint32_t a0 = (uint32_t)a, a1 = (uint32_t)(a >> 32), b0 = (uint32_t)b, b1 = (uint32_t)(b >> 32);
+    swap_dwords<D>(a0, b0);
+    swap_dwords<D>(a1, b1);
+    lo = __longlong_as_double((long long)(((uint64_t)a1 << 32) | a0));
+    hi = __longlong_as_double((long long)(((uint64_t)b1 << 32) | b0));
+}
+
+// Whether the tail reorder of an N-point pencil with lane distance JS runs
+// on lane swaps (every swap distance 16 or 32).
+template <int N, int JS>
+struct tail_swaps {
+    static constexpr int LOG = fft_shape<N>::LOG;
+    static constexpr int RL = 1 << (LOG % 4);
+    static constexpr int S = N / (16 * RL);
+    static constexpr int D0 = S * JS;
+    static constexpr bool OK = JS > 0 && RL > 1 && N / 16 <= 64 &&
+                               (RL == 2 ? (D0 == 16 || D0 == 32) : RL == 4 ? D0 == 16 : false);
+};
+
+template <typename R, int RL, int D0, int P>
+__device__ __forceinline__ void tail_reorder(cpx<R> (&v)[P][16]) {
+    constexpr int C = 16 / RL;
+#pragma unroll
+    for (int s = 0; (1 << s) < RL; ++s) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            if (r & (1 << s)) continue;
+            const int h = r | (1 << s);
+#pragma unroll
+            for (int p = 0; p < P; ++p) {
+                if (s == 0) {
+                    swap_reals<D0>(v[p][r].x, v[p][h].x);
+                    swap_reals<D0>(v[p][r].y, v[p][h].y);
+                } else {
+                    swap_reals<(D0 == 16 ? 32 : 16)>(v[p][r].x, v[p][h].x);
+                    swap_reals<(D0 == 16 ? 32 : 16)>(v[p][r].y, v[p][h].y);
+                }
+            }
+        }
+    }
+    // register q + RL c now holds what belongs in register c + C q
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+        cpx<R> t[16];
+#pragma unroll
+        for (int r = 0; r < 16; ++r) t[r] = v[p][r];
+#pragma unroll
+        for (int q = 0; q < RL; ++q)
+#pragma unroll
+            for (int c = 0; c < C; ++c) v[p][c + C * q] = t[q + RL * c];
+    }
+}
+
 // WAVE: the pencils lie inside one wavefront (T <= 64).
 // SPLIT: exchange the real parts, then the imaginary parts (half the LDS,
 // twice the barriers).
 // PRODUCTS: build the twiddles of a pass from two table reads.
-template <typename R, int N, bool INV, bool WAVE, bool SPLIT, bool PRODUCTS, int P>
+// JS: lane distance between neighbouring positions j of a pencil in the
+// wave (0: unknown); where tail_swaps<N, JS>::OK the reorder before the
+// tail pass uses lane swaps instead of LDS.
+template <typename R, int N, bool INV, bool WAVE, bool SPLIT, bool PRODUCTS, int P, int JS = 0>
 __device__ __forceinline__ void fft_pencils(cpx<R> (&v)[P][16], int j, R* lds, int lds_stride,
                                             const cpx<R>* __restrict__ tw) {
     constexpr int LOG = fft_shape<N>::LOG;
@@ -238,7 +332,7 @@ __device__ __forceinline__ void fft_pencils(cpx<R> (&v)[P][16], int j, R* lds, i
     for (int ps = 1; ps < NPASS; ++ps) {
         // scatter the previous radix-16 pass outputs (Ns = 16^(ps-1)),
         // gather the strided layout
-        {
+        auto exchange = [&]() {
             const int k = j % Ns;
             const int base = (j / Ns) * Ns * 16 + k;
             lds_sync<WAVE>();   // earlier reads of these slices are complete
@@ -299,6 +393,12 @@ __device__ __forceinline__ void fft_pencils(cpx<R> (&v)[P][16], int j, R* lds, i
                     for (int e = 0; e < 16; ++e) v[p][e].y = lre[lpad(j + T * e)];
                 }
             }
+        };
+        if constexpr (WAVE && tail_swaps<N, JS>::OK) {
+            if (ps == NPASS - 1) tail_reorder<R, tail_swaps<N, JS>::RL, tail_swaps<N, JS>::D0, P>(v);
+            else exchange();
+        } else {
+            exchange();
         }
         Ns *= 16;
         const bool last = (ps == NPASS - 1);

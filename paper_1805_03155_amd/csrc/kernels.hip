@@ -305,10 +305,10 @@ __global__ __launch_bounds__(64 * WPB) SPSTD_YZ_WAVES_ATTR void k_axis_acc(
         }
     }
     R* l0 = lds + (wave * C::PPW + p) * P * SL;
-    fft_pencils<R, N, false, true, TU::SPLIT, TU::PRODUCTS, P>(v, j, l0, SL, tw);
+    fft_pencils<R, N, false, true, TU::SPLIT, TU::PRODUCTS, P, C::PPW>(v, j, l0, SL, tw);
 #pragma unroll
     for (int q = 0; q < P; ++q) apply_k2<R, N>(v[q], j, nyq_zero);
-    fft_pencils<R, N, true, true, TU::SPLIT, TU::PRODUCTS, P>(v, j, l0, SL, tw);
+    fft_pencils<R, N, true, true, TU::SPLIT, TU::PRODUCTS, P, C::PPW>(v, j, l0, SL, tw);
     epi_begin();
     if (valid) {
 #pragma unroll
@@ -385,10 +385,10 @@ __global__ __launch_bounds__(64 * WPB) SPSTD_YZ_WAVES_ATTR void k_axis_ba(
     if constexpr (RL) reload_fence();
     R* l0 = lds + (wave * C::PPW + p) * P * SL;
     // B half of stage l: psi_I += sB T psi_R
-    fft_pencils<R, N, false, true, TU::SPLIT, TU::PRODUCTS, P>(v, j, l0, SL, tw);
+    fft_pencils<R, N, false, true, TU::SPLIT, TU::PRODUCTS, P, C::PPW>(v, j, l0, SL, tw);
 #pragma unroll
     for (int q = 0; q < P; ++q) apply_k2<R, N>(v[q], j, nyq_zero);
-    fft_pencils<R, N, true, true, TU::SPLIT, TU::PRODUCTS, P>(v, j, l0, SL, tw);
+    fft_pencils<R, N, true, true, TU::SPLIT, TU::PRODUCTS, P, C::PPW>(v, j, l0, SL, tw);
     epi_begin();
 #pragma unroll
     for (int e = 0; e < 16; ++e) {
@@ -408,10 +408,10 @@ __global__ __launch_bounds__(64 * WPB) SPSTD_YZ_WAVES_ATTR void k_axis_ba(
         epi_fence(e);
     }
     // A half of stage l + 1: psi_R += sA T psi_I(new)
-    fft_pencils<R, N, false, true, TU::SPLIT, TU::PRODUCTS, P>(v, j, l0, SL, tw);
+    fft_pencils<R, N, false, true, TU::SPLIT, TU::PRODUCTS, P, C::PPW>(v, j, l0, SL, tw);
 #pragma unroll
     for (int q = 0; q < P; ++q) apply_k2<R, N>(v[q], j, nyq_zero);
-    fft_pencils<R, N, true, true, TU::SPLIT, TU::PRODUCTS, P>(v, j, l0, SL, tw);
+    fft_pencils<R, N, true, true, TU::SPLIT, TU::PRODUCTS, P, C::PPW>(v, j, l0, SL, tw);
     epi_begin();
     if (valid) {
 #pragma unroll
@@ -532,9 +532,9 @@ __global__ __launch_bounds__((row_map<R, N, WPB>::THREADS)) SPSTD_WAVES_ATTR voi
     reload_fence();
 #endif
     R* l0 = lds + L.pin_block * M::SL;
-    fft_pencils<R, N, false, C::WAVE, M::SPLIT, TU::PRODUCTS, 1>(v, j, l0, M::SL, tw);
+    fft_pencils<R, N, false, C::WAVE, M::SPLIT, TU::PRODUCTS, 1, 1>(v, j, l0, M::SL, tw);
     apply_k2<R, N>(v[0], j, nyq_zero);
-    fft_pencils<R, N, true, C::WAVE, M::SPLIT, TU::PRODUCTS, 1>(v, j, l0, M::SL, tw);
+    fft_pencils<R, N, true, C::WAVE, M::SPLIT, TU::PRODUCTS, 1, 1>(v, j, l0, M::SL, tw);
     epi_begin();
     const R k0 = scale_of<R>(sc, inst0, kcol), p0 = scale_of<R>(sc, inst0, pcol);
     const R k1 = scale_of<R>(sc, inst1, kcol), p1 = scale_of<R>(sc, inst1, pcol);
@@ -594,9 +594,9 @@ __global__ __launch_bounds__((row_map<R, N, WPB>::THREADS)) SPSTD_WAVES_ATTR voi
 #endif
     R* l0 = lds + L.pin_block * M::SL;
     // A half: psi_R += T_x^A psi_I + p_A V psi_I
-    fft_pencils<R, N, false, C::WAVE, M::SPLIT, TU::PRODUCTS, 1>(v, j, l0, M::SL, tw);
+    fft_pencils<R, N, false, C::WAVE, M::SPLIT, TU::PRODUCTS, 1, 1>(v, j, l0, M::SL, tw);
     apply_k2<R, N>(v[0], j, nyq_zero);
-    fft_pencils<R, N, true, C::WAVE, M::SPLIT, TU::PRODUCTS, 1>(v, j, l0, M::SL, tw);
+    fft_pencils<R, N, true, C::WAVE, M::SPLIT, TU::PRODUCTS, 1, 1>(v, j, l0, M::SL, tw);
     epi_begin();
     const cpx<R> sa = {scale_of<R>(sc, inst0, SC_KXA), scale_of<R>(sc, inst1, SC_KXA)};
     const cpx<R> va = {scale_of<R>(sc, inst0, SC_PA), scale_of<R>(sc, inst1, SC_PA)};
@@ -628,9 +628,9 @@ __global__ __launch_bounds__((row_map<R, N, WPB>::THREADS)) SPSTD_WAVES_ATTR voi
     reload_fence();
 #endif
     // B half: psi_I += T_x^B psi_R(new) + p_B V psi_R(new)
-    fft_pencils<R, N, false, C::WAVE, M::SPLIT, TU::PRODUCTS, 1>(v, j, l0, M::SL, tw);
+    fft_pencils<R, N, false, C::WAVE, M::SPLIT, TU::PRODUCTS, 1, 1>(v, j, l0, M::SL, tw);
     apply_k2<R, N>(v[0], j, nyq_zero);
-    fft_pencils<R, N, true, C::WAVE, M::SPLIT, TU::PRODUCTS, 1>(v, j, l0, M::SL, tw);
+    fft_pencils<R, N, true, C::WAVE, M::SPLIT, TU::PRODUCTS, 1, 1>(v, j, l0, M::SL, tw);
     epi_begin();
 #pragma unroll
     for (int e = 0; e < 16; ++e) {
@@ -752,7 +752,7 @@ __global__ __launch_bounds__((row_map<R, N, SPSTD_WPB>::THREADS)) void k_energy_
             const R sg = (WALL && e >= 8) ? msign : (R)1;
             v[0][e] = valid ? cpx<R>{sg * psiR[q], sg * psiI[q]} : cpx<R>{(R)0, (R)0};
         }
-        fft_pencils<R, N, false, C::WAVE, M::SPLIT, TU::PRODUCTS, 1>(v, j, lds + pin * M::SL, M::SL, tw);
+        fft_pencils<R, N, false, C::WAVE, M::SPLIT, TU::PRODUCTS, 1, (ROWS ? 1 : C::PPW)>(v, j, lds + pin * M::SL, M::SL, tw);
 #pragma unroll
         for (int e = 0; e < 16; ++e) {
             const int kk = j + C::T * e;
@@ -814,9 +814,9 @@ __global__ __launch_bounds__((row_map<R, N, SPSTD_WPB>::THREADS)) void k_wall_ac
         v[0][e] = cpx<R>{ok0 ? sg * src[b0 + m] : (R)0, ok1 ? sg * src[b1 + m] : (R)0};
     }
     R* l0 = lds + pin * M::SL;
-    fft_pencils<R, N, false, C::WAVE, M::SPLIT, TU::PRODUCTS, 1>(v, j, l0, M::SL, tw);
+    fft_pencils<R, N, false, C::WAVE, M::SPLIT, TU::PRODUCTS, 1, (ROWS ? 1 : C::PPW)>(v, j, l0, M::SL, tw);
     apply_k2<R, N>(v[0], j, nyq_zero);
-    fft_pencils<R, N, true, C::WAVE, M::SPLIT, TU::PRODUCTS, 1>(v, j, l0, M::SL, tw);
+    fft_pencils<R, N, true, C::WAVE, M::SPLIT, TU::PRODUCTS, 1, (ROWS ? 1 : C::PPW)>(v, j, l0, M::SL, tw);
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
         const int64_t m = (int64_t)(j + C::T * e) * g.stride;

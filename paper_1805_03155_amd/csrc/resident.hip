@@ -97,9 +97,9 @@ __global__ __launch_bounds__((res_cfg<N>::THREADS)) void k_resident_1d(
                     cpx<R> v[1][16];
 #pragma unroll
                     for (int e = 0; e < 16; ++e) v[0][e] = src[e];
-                    fft_pencils<R, N, false, C::WAVE, true, true, 1>(v, j, l0, C::LS, tw);
+                    fft_pencils<R, N, false, C::WAVE, true, true, 1, 1>(v, j, l0, C::LS, tw);
                     k2_symbol<R, N>(v[0], j, nyq_zero);
-                    fft_pencils<R, N, true, C::WAVE, true, true, 1>(v, j, l0, C::LS, tw);
+                    fft_pencils<R, N, true, C::WAVE, true, true, 1, 1>(v, j, l0, C::LS, tw);
 #pragma unroll
                     for (int e = 0; e < 16; ++e) {
                         const int x = j + C::T * e;
@@ -159,9 +159,9 @@ __global__ __launch_bounds__((res_cfg<N>::THREADS)) void k_resident_1d(
                         const int x = j + C::T * e;
                         v[0][e] = cpx<R>{ha ? sa[x] : (R)0, hb ? sb[x] : (R)0};
                     }
-                    fft_pencils<R, N, false, C::WAVE, true, true, 1>(v, j, l0, C::LS, tw);
+                    fft_pencils<R, N, false, C::WAVE, true, true, 1, 1>(v, j, l0, C::LS, tw);
                     k2_symbol<R, N>(v[0], j, nyq_zero);
-                    fft_pencils<R, N, true, C::WAVE, true, true, 1>(v, j, l0, C::LS, tw);
+                    fft_pencils<R, N, true, C::WAVE, true, true, 1, 1>(v, j, l0, C::LS, tw);
 #pragma unroll
                     for (int e = 0; e < 16; ++e) {
                         const int x = j + C::T * e;

@@ -35,7 +35,7 @@ def alone(w, dt, steps, precision=spstd.FP64, flags=0):
     return r, i, ser
 
 
-@pytest.mark.parametrize("n", [16, 32, 256, 1024, 4096])
+@pytest.mark.parametrize("n", [16, 32, 256, 512, 1024, 4096])
 @pytest.mark.parametrize("prec", [spstd.FP64, spstd.FP32])
 def test_resident_kernel_matches_pass_kernels(n, prec):
     w = inst((n,), seed=n)

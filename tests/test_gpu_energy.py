@@ -35,7 +35,7 @@ def check(got, want, tol):
 
 
 @pytest.mark.parametrize("n", [(16,), (256,), (8192,), (16384,), (64, 32), (16, 1024),
-                               (32, 16, 16), (16, 64, 128)])
+                               (512, 16), (1024, 16), (32, 16, 16), (16, 64, 128)])
 @pytest.mark.parametrize("nyq", [spstd.NYQ_FULL, spstd.NYQ_ZERO])
 def test_energy_of_a_random_state(n, nyq):
     w = case(n, seed=len(n) * 1000 + n[0] + nyq)

@@ -78,7 +78,7 @@ def test_1d_lengths(n):
 
 
 @pytest.mark.parametrize("n", [(16, 16), (64, 32), (32, 128), (256, 16), (16, 512),
-                               (128, 1024)])
+                               (128, 1024), (512, 32), (1024, 16), (32, 64)])
 def test_2d_shapes(n):
     w = case(n, seed=sum(n), steps=8)
     dt = oracle.stable_dt(*w.coeffs, w.V, w.n, w.dx)
