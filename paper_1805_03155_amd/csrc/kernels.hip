@@ -25,9 +25,10 @@ bool row_len_ok(int64_t n) { return n >= 16 && n <= 16384 && (n & (n - 1)) == 0;
 // Build-time tuning switches (defaults are the measured choices):
 //   TW_PRODUCTS_*  twiddles of a pass from two table reads and products
 //   SPLIT_*        real-then-imaginary LDS exchange (half the LDS per wave);
-//                  SPLIT_XAB_F32 for the fused FP32 x pass, which is faster
-//                  with the joint exchange while the other FP32 passes gain
-//                  occupancy from the split one
+//                  the fused FP32 x pass takes the joint exchange below
+//                  SPLIT_XAB_F32_FROM points per row, the other FP32 passes
+//                  gain occupancy from the split one
+//   WPB, WPB_F64_256  waves per block of the pass kernels (wpb_of)
 //   BA_RELOAD_*    the stage-boundary y sweep re-reads psi_R for its second
 //                  epilogue instead of keeping it in registers (measured
 //                  slower: 106 -> 121 us FP64, 65 -> 68 us FP32 at 256^3)
@@ -95,6 +96,12 @@ bool row_len_ok(int64_t n) { return n >= 16 && n <= 16384 && (n & (n - 1)) == 0;
 #endif
 #ifndef SPSTD_WPB
 #define SPSTD_WPB 4
+#endif
+#ifndef SPSTD_WPB_F64_256
+#define SPSTD_WPB_F64_256 2
+#endif
+#ifndef SPSTD_SPLIT_XAB_F32_FROM
+#define SPSTD_SPLIT_XAB_F32_FROM 512
 #endif
 #ifndef SPSTD_EPI_CHUNK
 #define SPSTD_EPI_CHUNK 4
@@ -558,7 +565,9 @@ __global__ __launch_bounds__((row_map<R, N, WPB>::THREADS)) SPSTD_WAVES_ATTR voi
     R* __restrict__ psiR, R* __restrict__ psiI, const R* __restrict__ V,
     const cpx<R>* __restrict__ tw, RowGeom rg, ScaleRef sc, int nyq_zero) {
     using C = pencil_cfg<N>;
-    using M = row_map<R, N, WPB, tuning<R>::SPLIT_XAB>;
+    // FP32: the joint exchange up to 256-point rows, the split one beyond
+    // (512^2 batch 463 -> 428 us per step; 256^3 x pass 63 -> 75 us split)
+    using M = row_map<R, N, WPB, (sizeof(R) == 4 ? (N >= SPSTD_SPLIT_XAB_F32_FROM) : tuning<R>::SPLIT_XAB)>;
     using TU = tuning<R>;
     __shared__ R lds[M::LDS_REALS];
     const row_lane<R, N, WPB> L = row_coords<R, N, WPB>();
@@ -943,6 +952,16 @@ __global__ void k_fill0(int64_t n, R* __restrict__ y) {
 // ---------------------------------------------------------------------------
 constexpr int kWPB = SPSTD_WPB;   // waves per block of the wave-local passes
 
+// Waves per block of the hot pass kernels (y/z passes, the stage-boundary y
+// sweep, x passes): 2 for FP64 256-point pencils, where smaller blocks let
+// consecutive passes overlap their tails (graph-replayed 256^3 FP64 step
+// 2.72 -> 2.63 ms), SPSTD_WPB elsewhere (512^2 FP64 batch: 596 us per step
+// with 4, 692 with 2).
+template <typename R, int N>
+constexpr int wpb_of() {
+    return (sizeof(R) == 8 && N == 256) ? SPSTD_WPB_F64_256 : SPSTD_WPB;
+}
+
 template <typename R, int N>
 static hipError_t axis_acc_n(const R* src, R* dst, const void* tw, const AxisGeom& g, const ScaleRef& sc,
                              int col, int nyq_zero, hipStream_t st) {
@@ -951,8 +970,9 @@ static hipError_t axis_acc_n(const R* src, R* dst, const void* tw, const AxisGeo
     if (g.half_x % P) return hipErrorInvalidValue;
     const int64_t ngroups = g.half_x / P * g.n_outer;
     const int64_t waves = (ngroups + C::PPW - 1) / C::PPW;
-    const int64_t blocks = (waves + kWPB - 1) / kWPB;
-    hipLaunchKernelGGL((k_axis_acc<R, N, kWPB, P>), dim3((unsigned)blocks), dim3(64 * kWPB), 0, st,
+    constexpr int W = wpb_of<R, N>();
+    const int64_t blocks = (waves + W - 1) / W;
+    hipLaunchKernelGGL((k_axis_acc<R, N, W, P>), dim3((unsigned)blocks), dim3(64 * W), 0, st,
                        src, dst, (const cpx<R>*)tw, g, sc, col, nyq_zero);
     return hipGetLastError();
 }
@@ -965,8 +985,9 @@ static hipError_t axis_ba_n(R* psiR, R* psiI, const void* tw, const AxisGeom& g,
     if (g.half_x % P) return hipErrorInvalidValue;
     const int64_t ngroups = g.half_x / P * g.n_outer;
     const int64_t waves = (ngroups + C::PPW - 1) / C::PPW;
-    const int64_t blocks = (waves + kWPB - 1) / kWPB;
-    hipLaunchKernelGGL((k_axis_ba<R, N, kWPB, P>), dim3((unsigned)blocks), dim3(64 * kWPB), 0, st, psiR, psiI,
+    constexpr int W = wpb_of<R, N>();
+    const int64_t blocks = (waves + W - 1) / W;
+    hipLaunchKernelGGL((k_axis_ba<R, N, W, P>), dim3((unsigned)blocks), dim3(64 * W), 0, st, psiR, psiI,
                        (const cpx<R>*)tw, g, scB, scA, colB, colA, nyq_zero);
     return hipGetLastError();
 }
@@ -1004,14 +1025,15 @@ hipError_t launch_axis_acc(int64_t n, const R* src, R* dst, const void* tw, cons
 template <typename R, int N>
 static hipError_t x_acc_n(const R* src, R* dst, const R* V, const void* tw, const RowGeom& g,
                           const ScaleRef& sc, int kcol, int pcol, int nyq_zero, hipStream_t st) {
-    using M = row_map<R, N, kWPB>;
+    constexpr int W = wpb_of<R, N>();
+    using M = row_map<R, N, W>;
     const int64_t npen = (g.nrows + 1) / 2;
     const int64_t blocks = (npen + M::PPB - 1) / M::PPB;
     if (g.nrows % (2 * M::PPB) == 0)
-        hipLaunchKernelGGL((k_x_acc<R, N, kWPB, true>), dim3((unsigned)blocks), dim3(M::THREADS), 0, st,
+        hipLaunchKernelGGL((k_x_acc<R, N, W, true>), dim3((unsigned)blocks), dim3(M::THREADS), 0, st,
                            src, dst, V, (const cpx<R>*)tw, g, sc, kcol, pcol, nyq_zero);
     else
-        hipLaunchKernelGGL((k_x_acc<R, N, kWPB, false>), dim3((unsigned)blocks), dim3(M::THREADS), 0, st,
+        hipLaunchKernelGGL((k_x_acc<R, N, W, false>), dim3((unsigned)blocks), dim3(M::THREADS), 0, st,
                            src, dst, V, (const cpx<R>*)tw, g, sc, kcol, pcol, nyq_zero);
     return hipGetLastError();
 }
@@ -1019,14 +1041,15 @@ static hipError_t x_acc_n(const R* src, R* dst, const R* V, const void* tw, cons
 template <typename R, int N>
 static hipError_t x_ab_n(R* psiR, R* psiI, const R* V, const void* tw, const RowGeom& g,
                          const ScaleRef& sc, int nyq_zero, hipStream_t st) {
-    using M = row_map<R, N, kWPB>;
+    constexpr int W = wpb_of<R, N>();
+    using M = row_map<R, N, W>;
     const int64_t npen = (g.nrows + 1) / 2;
     const int64_t blocks = (npen + M::PPB - 1) / M::PPB;
     if (g.nrows % (2 * M::PPB) == 0)
-        hipLaunchKernelGGL((k_x_ab<R, N, kWPB, true>), dim3((unsigned)blocks), dim3(M::THREADS), 0, st,
+        hipLaunchKernelGGL((k_x_ab<R, N, W, true>), dim3((unsigned)blocks), dim3(M::THREADS), 0, st,
                            psiR, psiI, V, (const cpx<R>*)tw, g, sc, nyq_zero);
     else
-        hipLaunchKernelGGL((k_x_ab<R, N, kWPB, false>), dim3((unsigned)blocks), dim3(M::THREADS), 0, st,
+        hipLaunchKernelGGL((k_x_ab<R, N, W, false>), dim3((unsigned)blocks), dim3(M::THREADS), 0, st,
                            psiR, psiI, V, (const cpx<R>*)tw, g, sc, nyq_zero);
     return hipGetLastError();
 }
