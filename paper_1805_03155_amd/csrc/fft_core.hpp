@@ -332,7 +332,14 @@ __device__ __forceinline__ void fft_pencils(cpx<R> (&v)[P][16], int j, R* lds, i
     for (int ps = 1; ps < NPASS; ++ps) {
         // scatter the previous radix-16 pass outputs (Ns = 16^(ps-1)),
         // gather the strided layout
-        auto exchange = [&]() {
+        bool swapped = false;
+        if constexpr (WAVE && tail_swaps<N, JS>::OK) {
+            if (ps == NPASS - 1) {
+                tail_reorder<R, tail_swaps<N, JS>::RL, tail_swaps<N, JS>::D0, P>(v);
+                swapped = true;
+            }
+        }
+        if (!swapped) {
             const int k = j % Ns;
             const int base = (j / Ns) * Ns * 16 + k;
             lds_sync<WAVE>();   // earlier reads of these slices are complete
@@ -393,12 +400,6 @@ __device__ __forceinline__ void fft_pencils(cpx<R> (&v)[P][16], int j, R* lds, i
                     for (int e = 0; e < 16; ++e) v[p][e].y = lre[lpad(j + T * e)];
                 }
             }
-        };
-        if constexpr (WAVE && tail_swaps<N, JS>::OK) {
-            if (ps == NPASS - 1) tail_reorder<R, tail_swaps<N, JS>::RL, tail_swaps<N, JS>::D0, P>(v);
-            else exchange();
-        } else {
-            exchange();
         }
         Ns *= 16;
         const bool last = (ps == NPASS - 1);
