@@ -43,7 +43,7 @@ static BatchLayout batch_layout(const spstd_batch_desc* d) {
     L.V = off; off += fb;
     for (int a = 0; a < 3; ++a) {
         L.tw[a] = off;
-        if (a < d->ndim) off += align256((size_t)d->n[a] * 2 * esz);
+        if (a < d->ndim) off += align256((size_t)d->n[a] * 2 * sizeof(double));
     }
     L.scales = off; off += align256(cap * (size_t)d->m * SC_COLS * esz);
     L.pidx = off; off += align256(cap * np * sizeof(int64_t));
@@ -455,16 +455,10 @@ spstd_status spstd_batch_create(const spstd_batch_desc* d, void* d_workspace, si
     if (e == hipSuccess) e = hipMemcpyAsync(b->ws + L.counter, cnt.data(), cnt.size() * sizeof(int64_t),
                                             hipMemcpyHostToDevice, b->st);
     for (int a = 0; a < d->ndim && e == hipSuccess; ++a) {
+        // FP64 in every precision: the kernels round each twiddle once
         std::vector<double> t = twiddles(d->n[a]);
-        if (b->esz == 8) {
-            e = hipMemcpyAsync(b->ws + L.tw[a], t.data(), t.size() * 8, hipMemcpyHostToDevice, b->st);
-            if (e == hipSuccess) e = hipStreamSynchronize(b->st);
-        } else {
-            std::vector<float> f(t.size());
-            for (size_t i = 0; i < t.size(); ++i) f[i] = (float)t[i];
-            e = hipMemcpyAsync(b->ws + L.tw[a], f.data(), f.size() * 4, hipMemcpyHostToDevice, b->st);
-            if (e == hipSuccess) e = hipStreamSynchronize(b->st);
-        }
+        e = hipMemcpyAsync(b->ws + L.tw[a], t.data(), t.size() * 8, hipMemcpyHostToDevice, b->st);
+        if (e == hipSuccess) e = hipStreamSynchronize(b->st);
     }
     if (e == hipSuccess) e = hipStreamSynchronize(b->st);
     if (e != hipSuccess) {

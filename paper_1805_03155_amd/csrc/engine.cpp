@@ -566,16 +566,10 @@ static spstd_status plan_init(Plan* p, const double* V, const double* psiR0, con
     if ((s = upload<R>(p, p->L.psiI, psiI0)) != SPSTD_OK) return s;
     if ((s = upload<R>(p, p->L.V, V)) != SPSTD_OK) return s;
     for (int a = 0; a < p->d.ndim; ++a) {
+        // FP64 in every precision: the kernels round each twiddle once
         std::vector<double> t = twiddles(transform_len(p->d, a));
-        if (sizeof(R) == 8) {
-            HIPCHK(hipMemcpyAsync(p->ws + p->L.tw[a], t.data(), t.size() * 8, hipMemcpyHostToDevice, p->st));
-            HIPCHK(hipStreamSynchronize(p->st));
-        } else {
-            std::vector<float> f(t.size());
-            for (size_t i = 0; i < t.size(); ++i) f[i] = (float)t[i];
-            HIPCHK(hipMemcpyAsync(p->ws + p->L.tw[a], f.data(), f.size() * 4, hipMemcpyHostToDevice, p->st));
-            HIPCHK(hipStreamSynchronize(p->st));
-        }
+        HIPCHK(hipMemcpyAsync(p->ws + p->L.tw[a], t.data(), t.size() * 8, hipMemcpyHostToDevice, p->st));
+        HIPCHK(hipStreamSynchronize(p->st));
     }
     {
         // stage rows (A coefficient c_l dt, B coefficient -d_l dt), then the RK4 row (+1, -1)

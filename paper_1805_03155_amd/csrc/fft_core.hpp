@@ -164,45 +164,34 @@ __device__ __forceinline__ void lds_sync() {
     }
 }
 
-// Twiddles w_N^{r*step}, r = 0..15, of one radix-16 pass.  Either 15
-// table reads, or (PRODUCTS) two reads, w^step and w^{4 step}, and the other
-// powers as products w^{a step} * w^{4 b step} (r = a + 4b, a, b < 4): at
-// most four roundings on top of the tabulated values.
-template <typename R, bool PRODUCTS>
-__device__ __forceinline__ void twiddles16(const cpx<R>* __restrict__ tw, int step, cpx<R> (&w)[16]) {
-    w[0] = cpx<R>{(R)1, (R)0};
-    if constexpr (!PRODUCTS) {
-#pragma unroll
-        for (int r = 1; r < 16; ++r) w[r] = tw[r * step];
-    } else {
-        const cpx<R> t1 = tw[step], t4 = tw[4 * step];
-        const cpx<R> t2 = cmul(t1, t1), t3 = cmul(t2, t1);
-        const cpx<R> t8 = cmul(t4, t4), t12 = cmul(t8, t4);
-        const cpx<R> lo[4] = {w[0], t1, t2, t3};
-        const cpx<R> hi[4] = {w[0], t4, t8, t12};
-#pragma unroll
-        for (int r = 1; r < 16; ++r) w[r] = (r >> 2) == 0 ? lo[r & 3] : (r & 3) == 0 ? hi[r >> 2] : cmul(lo[r & 3], hi[r >> 2]);
-    }
+
+// Twiddles are generated in FP64 in every precision: the table holds
+// exp(-2 pi i t / N) in FP64 (from long-double cos/sin), any products of
+// table entries are formed in FP64, and each twiddle is rounded once to the
+// run precision where it is used.
+template <typename R>
+__device__ __forceinline__ cpx<R> to_run(cpx<double> a) {
+    return cpx<R>{(R)a.x, (R)a.y};
 }
 
 // Twiddles w_N^{r*b}, r < RL, of the tail pass (RL = 2, 4, 8).
 template <typename R, int RL, bool PRODUCTS>
-__device__ __forceinline__ void twiddles_tail(const cpx<R>* __restrict__ tw, int b, cpx<R> (&w)[8]) {
+__device__ __forceinline__ void twiddles_tail(const cpx<double>* __restrict__ tw, int b, cpx<R> (&w)[8]) {
     w[0] = cpx<R>{(R)1, (R)0};
     if constexpr (!PRODUCTS || RL == 2) {
 #pragma unroll
-        for (int r = 1; r < RL; ++r) w[r] = tw[r * b];
+        for (int r = 1; r < RL; ++r) w[r] = to_run<R>(tw[r * b]);
     } else {
-        const cpx<R> t1 = tw[b];
-        w[1] = t1;
-        w[2] = cmul(t1, t1);
-        w[3] = cmul(w[2], t1);
+        const cpx<double> t1 = tw[b], t2 = cmul(t1, t1), t3 = cmul(t2, t1);
+        w[1] = to_run<R>(t1);
+        w[2] = to_run<R>(t2);
+        w[3] = to_run<R>(t3);
         if constexpr (RL == 8) {
-            const cpx<R> t4 = tw[4 * b];
-            w[4] = t4;
-            w[5] = cmul(t1, t4);
-            w[6] = cmul(w[2], t4);
-            w[7] = cmul(w[3], t4);
+            const cpx<double> t4 = tw[4 * b];
+            w[4] = to_run<R>(t4);
+            w[5] = to_run<R>(cmul(t1, t4));
+            w[6] = to_run<R>(cmul(t2, t4));
+            w[7] = to_run<R>(cmul(t3, t4));
         }
     }
 }
@@ -212,7 +201,7 @@ __device__ __forceinline__ void twiddles_tail(const cpx<R>* __restrict__ tw, int
 // v[p]: the lane's 16 values of pencil p in strided layout; j: lane position
 // in the pencil; lds: LDS of pencil 0, pencil p at lds + p * lds_stride;
 // a pencil slice holds lds_size<N> reals (SPLIT) or twice that (re, im).
-// tw: table of w_N^t = exp(-2 pi i t / N), t = 0..N-1.
+// tw: FP64 table of w_N^t = exp(-2 pi i t / N), t = 0..N-1.
 // ---------------------------------------------------------------------------
 // Reorder before a radix-RL tail pass without LDS (gfx950 lane swaps).
 // After the last radix-16 pass, with S = N / (16 RL), lane j = m + S q
@@ -313,7 +302,7 @@ __device__ __forceinline__ void tail_reorder(cpx<R> (&v)[P][16]) {
 // tail pass uses lane swaps instead of LDS.
 template <typename R, int N, bool INV, bool WAVE, bool SPLIT, bool PRODUCTS, int P, int JS = 0>
 __device__ __forceinline__ void fft_pencils(cpx<R> (&v)[P][16], int j, R* lds, int lds_stride,
-                                            const cpx<R>* __restrict__ tw) {
+                                            const cpx<double>* __restrict__ tw) {
     constexpr int LOG = fft_shape<N>::LOG;
     constexpr int T = N / 16;
     constexpr int NP16 = LOG / 4;            // radix-16 passes
@@ -409,23 +398,23 @@ __device__ __forceinline__ void fft_pencils(cpx<R> (&v)[P][16], int j, R* lds, i
             const int k = j % Ns;
             const int step = k * (N / (16 * Ns));
             if constexpr (PRODUCTS) {
-                // w^{a step} w^{4 b step}, r = a + 4b, formed where used
-                const cpx<R> t1 = tw[step], t4 = tw[4 * step];
-                const cpx<R> t2 = cmul(t1, t1), t3 = cmul(t2, t1);
-                const cpx<R> t8 = cmul(t4, t4), t12 = cmul(t8, t4);
+                // w^{a step} w^{4 b step}, r = a + 4b, formed in FP64 where used
+                const cpx<double> t1 = tw[step], t4 = tw[4 * step];
+                const cpx<double> t2 = cmul(t1, t1), t3 = cmul(t2, t1);
+                const cpx<double> t8 = cmul(t4, t4), t12 = cmul(t8, t4);
 #pragma unroll
                 for (int r = 1; r < 16; ++r) {
                     const int a = r & 3, b = r >> 2;
-                    const cpx<R> lo = a == 1 ? t1 : a == 2 ? t2 : t3;
-                    const cpx<R> hi = b == 1 ? t4 : b == 2 ? t8 : t12;
-                    const cpx<R> w = b == 0 ? lo : a == 0 ? hi : cmul(lo, hi);
+                    const cpx<double> lo = a == 1 ? t1 : a == 2 ? t2 : t3;
+                    const cpx<double> hi = b == 1 ? t4 : b == 2 ? t8 : t12;
+                    const cpx<R> w = to_run<R>(b == 0 ? lo : a == 0 ? hi : cmul(lo, hi));
 #pragma unroll
                     for (int p = 0; p < P; ++p) v[p][r] = INV ? cmulc(v[p][r], w) : cmul(v[p][r], w);
                 }
             } else {
 #pragma unroll
                 for (int r = 1; r < 16; ++r) {
-                    const cpx<R> w = tw[r * step];
+                    const cpx<R> w = to_run<R>(tw[r * step]);
 #pragma unroll
                     for (int p = 0; p < P; ++p) v[p][r] = INV ? cmulc(v[p][r], w) : cmul(v[p][r], w);
                 }

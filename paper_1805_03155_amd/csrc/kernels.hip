@@ -23,7 +23,9 @@ bool axis_len_ok(int64_t n) { return n >= 16 && n <= 1024 && (n & (n - 1)) == 0;
 bool row_len_ok(int64_t n) { return n >= 16 && n <= 16384 && (n & (n - 1)) == 0; }
 
 // Build-time tuning switches (defaults are the measured choices):
-//   TW_PRODUCTS_*  twiddles of a pass from two table reads and products
+//   TW_PRODUCTS_*  twiddles of a pass from two table reads and FP64 products
+//                  instead of one table read per twiddle (FP32 256^3 graph
+//                  step 1.58 -> 1.44 ms, FP32 512^2 batch 428 -> 319 us)
 //   SPLIT_*        real-then-imaginary LDS exchange (half the LDS per wave);
 //                  the fused FP32 x pass takes the joint exchange below
 //                  SPLIT_XAB_F32_FROM points per row, the other FP32 passes
@@ -53,7 +55,7 @@ bool row_len_ok(int64_t n) { return n >= 16 && n <= 16384 && (n & (n - 1)) == 0;
 #define SPSTD_TW_PRODUCTS_F64 1
 #endif
 #ifndef SPSTD_TW_PRODUCTS_F32
-#define SPSTD_TW_PRODUCTS_F32 0
+#define SPSTD_TW_PRODUCTS_F32 1
 #endif
 #ifndef SPSTD_SPLIT_F64
 #define SPSTD_SPLIT_F64 1
@@ -271,7 +273,7 @@ __device__ __forceinline__ void add_group(R* dst, const cpx<R> (&v)[P][16], int 
 // ---------------------------------------------------------------------------
 template <typename R, int N, int WPB, int P>
 __global__ __launch_bounds__(64 * WPB) SPSTD_YZ_WAVES_ATTR void k_axis_acc(
-    const R* __restrict__ src, R* __restrict__ dst, const cpx<R>* __restrict__ tw, AxisGeom g,
+    const R* __restrict__ src, R* __restrict__ dst, const cpx<double>* __restrict__ tw, AxisGeom g,
     ScaleRef sc, int col, int nyq_zero) {
     using C = pencil_cfg<N>;
     using TU = tuning<R>;
@@ -346,7 +348,7 @@ __global__ __launch_bounds__(64 * WPB) SPSTD_YZ_WAVES_ATTR void k_axis_acc(
 // ---------------------------------------------------------------------------
 template <typename R, int N, int WPB, int P>
 __global__ __launch_bounds__(64 * WPB) SPSTD_YZ_WAVES_ATTR void k_axis_ba(
-    R* __restrict__ psiR, R* __restrict__ psiI, const cpx<R>* __restrict__ tw, AxisGeom g,
+    R* __restrict__ psiR, R* __restrict__ psiI, const cpx<double>* __restrict__ tw, AxisGeom g,
     ScaleRef scB, ScaleRef scA, int colB, int colA, int nyq_zero) {
     using C = pencil_cfg<N>;
     using TU = tuning<R>;
@@ -498,7 +500,7 @@ __device__ __forceinline__ row_lane<R, N, WPB> row_coords() {
 template <typename R, int N, int WPB, bool FULL>
 __global__ __launch_bounds__((row_map<R, N, WPB>::THREADS)) SPSTD_WAVES_ATTR void k_x_acc(
     const R* __restrict__ src, R* __restrict__ dst, const R* __restrict__ V,
-    const cpx<R>* __restrict__ tw, RowGeom rg, ScaleRef sc, int kcol, int pcol, int nyq_zero) {
+    const cpx<double>* __restrict__ tw, RowGeom rg, ScaleRef sc, int kcol, int pcol, int nyq_zero) {
     using C = pencil_cfg<N>;
     using M = row_map<R, N, WPB>;
     using TU = tuning<R>;
@@ -563,7 +565,7 @@ __global__ __launch_bounds__((row_map<R, N, WPB>::THREADS)) SPSTD_WAVES_ATTR voi
 template <typename R, int N, int WPB, bool FULL>
 __global__ __launch_bounds__((row_map<R, N, WPB>::THREADS)) SPSTD_WAVES_ATTR void k_x_ab(
     R* __restrict__ psiR, R* __restrict__ psiI, const R* __restrict__ V,
-    const cpx<R>* __restrict__ tw, RowGeom rg, ScaleRef sc, int nyq_zero) {
+    const cpx<double>* __restrict__ tw, RowGeom rg, ScaleRef sc, int nyq_zero) {
     using C = pencil_cfg<N>;
     // FP32: the joint exchange up to 256-point rows, the split one beyond
     // (512^2 batch 463 -> 428 us per step; 256^3 x pass 63 -> 75 us split)
@@ -731,7 +733,7 @@ __device__ __forceinline__ int line_pos(int j, int e) {
 
 template <typename R, int N, bool ROWS, bool WALL>
 __global__ __launch_bounds__((row_map<R, N, SPSTD_WPB>::THREADS)) void k_energy_axis(
-    const R* __restrict__ psiR, const R* __restrict__ psiI, const cpx<R>* __restrict__ tw,
+    const R* __restrict__ psiR, const R* __restrict__ psiI, const cpx<double>* __restrict__ tw,
     EnergyGeom g, int nyq_zero, R msign, double* __restrict__ partials) {
     using C = pencil_cfg<N>;
     using M = row_map<R, N, SPSTD_WPB>;
@@ -790,7 +792,7 @@ __global__ __launch_bounds__((row_map<R, N, SPSTD_WPB>::THREADS)) void k_energy_
 template <typename R, int N, bool ROWS>
 __global__ __launch_bounds__((row_map<R, N, SPSTD_WPB>::THREADS)) void k_wall_acc(
     const R* __restrict__ src, R* __restrict__ dst, const R* __restrict__ V,
-    const cpx<R>* __restrict__ tw, EnergyGeom g, int64_t npts, ScaleRef sc, int kcol, int pcol,
+    const cpx<double>* __restrict__ tw, EnergyGeom g, int64_t npts, ScaleRef sc, int kcol, int pcol,
     int nyq_zero, R msign) {
     using C = pencil_cfg<N>;
     using M = row_map<R, N, SPSTD_WPB>;
@@ -973,7 +975,7 @@ static hipError_t axis_acc_n(const R* src, R* dst, const void* tw, const AxisGeo
     constexpr int W = wpb_of<R, N>();
     const int64_t blocks = (waves + W - 1) / W;
     hipLaunchKernelGGL((k_axis_acc<R, N, W, P>), dim3((unsigned)blocks), dim3(64 * W), 0, st,
-                       src, dst, (const cpx<R>*)tw, g, sc, col, nyq_zero);
+                       src, dst, (const cpx<double>*)tw, g, sc, col, nyq_zero);
     return hipGetLastError();
 }
 
@@ -988,7 +990,7 @@ static hipError_t axis_ba_n(R* psiR, R* psiI, const void* tw, const AxisGeom& g,
     constexpr int W = wpb_of<R, N>();
     const int64_t blocks = (waves + W - 1) / W;
     hipLaunchKernelGGL((k_axis_ba<R, N, W, P>), dim3((unsigned)blocks), dim3(64 * W), 0, st, psiR, psiI,
-                       (const cpx<R>*)tw, g, scB, scA, colB, colA, nyq_zero);
+                       (const cpx<double>*)tw, g, scB, scA, colB, colA, nyq_zero);
     return hipGetLastError();
 }
 
@@ -1031,10 +1033,10 @@ static hipError_t x_acc_n(const R* src, R* dst, const R* V, const void* tw, cons
     const int64_t blocks = (npen + M::PPB - 1) / M::PPB;
     if (g.nrows % (2 * M::PPB) == 0)
         hipLaunchKernelGGL((k_x_acc<R, N, W, true>), dim3((unsigned)blocks), dim3(M::THREADS), 0, st,
-                           src, dst, V, (const cpx<R>*)tw, g, sc, kcol, pcol, nyq_zero);
+                           src, dst, V, (const cpx<double>*)tw, g, sc, kcol, pcol, nyq_zero);
     else
         hipLaunchKernelGGL((k_x_acc<R, N, W, false>), dim3((unsigned)blocks), dim3(M::THREADS), 0, st,
-                           src, dst, V, (const cpx<R>*)tw, g, sc, kcol, pcol, nyq_zero);
+                           src, dst, V, (const cpx<double>*)tw, g, sc, kcol, pcol, nyq_zero);
     return hipGetLastError();
 }
 
@@ -1047,10 +1049,10 @@ static hipError_t x_ab_n(R* psiR, R* psiI, const R* V, const void* tw, const Row
     const int64_t blocks = (npen + M::PPB - 1) / M::PPB;
     if (g.nrows % (2 * M::PPB) == 0)
         hipLaunchKernelGGL((k_x_ab<R, N, W, true>), dim3((unsigned)blocks), dim3(M::THREADS), 0, st,
-                           psiR, psiI, V, (const cpx<R>*)tw, g, sc, nyq_zero);
+                           psiR, psiI, V, (const cpx<double>*)tw, g, sc, nyq_zero);
     else
         hipLaunchKernelGGL((k_x_ab<R, N, W, false>), dim3((unsigned)blocks), dim3(M::THREADS), 0, st,
-                           psiR, psiI, V, (const cpx<R>*)tw, g, sc, nyq_zero);
+                           psiR, psiI, V, (const cpx<double>*)tw, g, sc, nyq_zero);
     return hipGetLastError();
 }
 
@@ -1138,7 +1140,7 @@ static hipError_t energy_axis_n(const R* psiR, const R* psiI, const void* tw, co
     if (b < 1) b = 1;
     *nblocks = (int)b;
     const R ms = wall == WALL_NEUMANN ? (R)1 : (R)-1;
-    const cpx<R>* t = (const cpx<R>*)tw;
+    const cpx<double>* t = (const cpx<double>*)tw;
 #define SPSTD_ENERGY_LAUNCH(ROWS_, WALL_)                                                              \
     hipLaunchKernelGGL((k_energy_axis<R, N, ROWS_, WALL_>), dim3((unsigned)b), dim3(M::THREADS), 0, st, \
                        psiR, psiI, t, g, nyq_zero, ms, partials)
@@ -1173,10 +1175,10 @@ static hipError_t wall_acc_n(const R* src, R* dst, const R* V, const void* tw, c
     const R ms = wall == WALL_NEUMANN ? (R)1 : (R)-1;
     if (rows)
         hipLaunchKernelGGL((k_wall_acc<R, N, true>), dim3((unsigned)b), dim3(M::THREADS), 0, st, src, dst, V,
-                           (const cpx<R>*)tw, g, npts, sc, kcol, pcol, nyq_zero, ms);
+                           (const cpx<double>*)tw, g, npts, sc, kcol, pcol, nyq_zero, ms);
     else if constexpr (pencil_cfg<N>::WAVE)
         hipLaunchKernelGGL((k_wall_acc<R, N, false>), dim3((unsigned)b), dim3(M::THREADS), 0, st, src, dst, V,
-                           (const cpx<R>*)tw, g, npts, sc, kcol, pcol, nyq_zero, ms);
+                           (const cpx<double>*)tw, g, npts, sc, kcol, pcol, nyq_zero, ms);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();

@@ -53,7 +53,7 @@ __device__ __forceinline__ void k2_symbol(cpx<R> (&v)[16], int j, int nyq_zero) 
 template <typename R, int N, bool GS>
 __global__ __launch_bounds__((res_cfg<N>::THREADS)) void k_resident_1d(
     const ResidentInst<R>* __restrict__ inst, int ninst, int m, int64_t nsteps, int nyq_zero,
-    const cpx<R>* __restrict__ tw) {
+    const cpx<double>* __restrict__ tw) {
     using C = res_cfg<N>;
     __shared__ R lds[C::LDS_REALS];
     int j, gib;
@@ -208,7 +208,7 @@ static hipError_t res_n(const ResidentInst<R>* inst, int ninst, int m, int64_t n
     const int groups = (ninst + 1) / 2;
     const int blocks = (groups + C::GPB - 1) / C::GPB;
     hipLaunchKernelGGL((k_resident_1d<R, N, (N > 4096)>), dim3(blocks), dim3(C::THREADS), 0, st, inst,
-                       ninst, m, nsteps, nyq_zero, (const cpx<R>*)tw);
+                       ninst, m, nsteps, nyq_zero, (const cpx<double>*)tw);
     return hipGetLastError();
 }
 
