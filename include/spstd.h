@@ -3,9 +3,11 @@
  *
  * The engine advances the time-dependent Schroedinger equation
  *     i hbar d(psi)/dt = -(hbar^2 / 2 m*) Laplacian psi + V(r) psi      (Eq. 1)
- * on a periodic, collocated grid (Eq. 5-6) with psi = psi_R + i psi_I
- * (Eq. 2-4), the Fourier pseudospectral second derivative (Eq. 7-10) and the
- * partitioned symplectic stage update (Eq. 13-18) of Shen, Sha, Kuang, Hu,
+ * on a collocated grid (Eq. 5-6), periodic along each axis or between
+ * Dirichlet or Neumann walls (Sec. 2.2), with psi = psi_R + i psi_I
+ * (Eq. 2-4), the pseudospectral second derivative (Eq. 7-10; sine or cosine
+ * modes between walls) and the partitioned symplectic stage update
+ * (Eq. 13-18) of Shen, Sha, Kuang, Hu,
  * Huang and Wu, "Symplectic Pseudospectral Time-Domain Scheme for Solving
  * Time-Dependent Schroedinger Equation" (arXiv:1805.03155).  Eigenvalues are
  * read from the time spectrum of probe-point series (Sec. 3, Tables 2-4).

@@ -49,7 +49,6 @@ struct Plan {
     char* ws;
     Layout L;
     hipStream_t st;
-    int64_t twlen[3];
     hipGraphExec_t graph;
     bool graph_ready;
     bool eig_on = false;
