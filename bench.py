@@ -70,8 +70,11 @@ def run_precision(w, prec, steps, warmup):
     import torch
     from paper_1805_03155_amd import spstd
     code = spstd.FP64 if prec == "fp64" else spstd.FP32
+    torch.cuda.synchronize()
+    s0 = time.perf_counter()
     p = spstd.plan_from_workload(w, precision=code, nsteps_max=steps + warmup,
                                  flags=spstd.TIMING)
+    setup_s = time.perf_counter() - s0   # host arrays in, over PCIe (not in the timed region)
     st = p.info()
     npts = w.npoints
     su_per_step = npts * st.substeps_per_step / 2.0
@@ -85,7 +88,9 @@ def run_precision(w, prec, steps, warmup):
     times = p.pass_times()
     el = t1 - t0
     info = p.info()
-    _, st2 = p.run(0)                    # norm check (raises on NaN/Inf)
+    r0 = time.perf_counter()
+    _, st2 = p.run(0)                    # norm check (raises on NaN/Inf), probe series out
+    readback_s = time.perf_counter() - r0
     log(f"{prec}: {steps} steps in {el:.3f} s, norm drift {st2.norm / st2.norm0 - 1:.2e}")
     kinds = {k: v for k, v in times.items() if v[0] > 0}
     dom = max(kinds, key=lambda k: kinds[k][1])
@@ -109,7 +114,9 @@ def run_precision(w, prec, steps, warmup):
     torch.cuda.synchronize()
     g1 = time.perf_counter()
     del q
-    return {"value": su_per_step * steps / el, "ms_per_step": el / steps * 1e3,
+    pcie = {"plan_setup_s": setup_s, "readback_s": readback_s,
+            "value_including_transfers": su_per_step * steps / (el + setup_s + readback_s)}
+    return {"value": su_per_step * steps / el, "ms_per_step": el / steps * 1e3, "host_transfers": pcie,
             "roofline": roof, "kernels": per_kernel, "dt": info.dt,
             "graph_mode": {"value": su_per_step * steps / (g1 - g0),
                            "ms_per_step": (g1 - g0) / steps * 1e3},
@@ -341,11 +348,12 @@ def main():
         "cpu_baseline": cpu,
         "kernels": r64["kernels"],
         "graph_mode": r64["graph_mode"],
+        "host_transfers": r64["host_transfers"],
         "batching": batch,
         "serving": serving,
         "fp32": {"value": r32["value"], "ms_per_step": r32["ms_per_step"], "dtype": "f32",
                  "roofline": r32["roofline"], "kernels": r32["kernels"],
-                 "graph_mode": r32["graph_mode"],
+                 "graph_mode": r32["graph_mode"], "host_transfers": r32["host_transfers"],
                  "speedup_vs_fp64": r32["value"] / r64["value"]},
     }
     print(json.dumps(line), flush=True)
