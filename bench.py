@@ -146,9 +146,14 @@ def batching_leg(count, steps, seed=0):
     from paper_1805_03155_amd import workloads as W
     inst = W.batch_instances(count=count, seed=seed, steps=steps)
     _, st = batching.run_instances(inst, steps, precision=spstd.FP32)
+    # schedules the autotuner chose, counted over the shape groups
+    picks = {}
+    for sched, wpb in st["schedules"].values():
+        k = "resident" if sched == "resident" else f"passes_{wpb}_waves"
+        picks[k] = picks.get(k, 0) + 1
     return {"value": st["stage_updates_per_s"], "unit": "stage updates/s", "instances": count,
             "steps": steps, "points": st["points"], "elapsed_s": st["elapsed_s"],
-            "shape_groups": len(st["groups"]), "dtype": "f32 fields, f64 probes"}
+            "shape_groups": len(st["groups"]), "schedules": picks, "dtype": "f32 fields, f64 probes"}
 
 
 def serving_leg(count, rate, steps, seed=0, budget_gb=64):

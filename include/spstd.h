@@ -321,11 +321,17 @@ typedef struct spstd_batch_s *spstd_batch_t;
  *   flags         SPSTD_ALLOW_UNSTABLE, SPSTD_NO_RESIDENT, SPSTD_AUTOTUNE.
  *                 A 1D batch of up to 16384 points has two schedules: the
  *                 resident kernel (whole step chunks in one launch) or the
- *                 pass kernels replayed as step graphs.  SPSTD_AUTOTUNE runs
- *                 both for a few steps on the empty batch at creation (every
- *                 slot stepping a zero state at a nominal dt), keeps the
- *                 faster, and remembers the choice for this (shape,
- *                 precision, capacity) for the rest of the process.
+ *                 pass kernels replayed as step graphs.  The pass kernels
+ *                 run 2 or 4 waves per block.  SPSTD_AUTOTUNE runs every
+ *                 candidate (resident where it applies; passes at 2 and at
+ *                 4 waves per block) for a few steps on the empty batch at
+ *                 creation (every slot stepping a zero state at a nominal
+ *                 dt), keeps the fastest, and remembers the choice for this
+ *                 (shape, precision, capacity) for the rest of the process.
+ *   waves_per_block  block size of the pass kernels in 64-lane waves: 0
+ *                 for the built-in choice per precision and length, or 2 or
+ *                 4 (rows longer than 1024 points run one pencil per block
+ *                 whatever it says).  SPSTD_AUTOTUNE overrides it.
  */
 typedef struct spstd_batch_desc {
     int ndim;
@@ -338,6 +344,7 @@ typedef struct spstd_batch_desc {
     int nprobes;
     int64_t nsteps_max;
     uint32_t flags;
+    int waves_per_block;
 } spstd_batch_desc;
 
 /* Exact device workspace size of a batch.  Pure host computation. */
@@ -385,10 +392,12 @@ spstd_status spstd_batch_read(spstd_batch_t batch, int slot, double *probes_out,
 spstd_status spstd_batch_release(spstd_batch_t batch, int slot);
 
 /* The schedule in use: *resident = 1 for the resident 1D kernel, 0 for the
- * pass kernels; *tuned_us = the measured microseconds per step of each
- * schedule at creation ([resident, passes]; 0 where not measured; may be
- * NULL). */
-spstd_status spstd_batch_schedule(spstd_batch_t batch, int *resident, double *tuned_us);
+ * pass kernels; *waves_per_block = the pass kernels' block size in waves (0:
+ * the built-in choice; may be NULL); tuned_us[0..2] = the measured
+ * microseconds per step at creation of [resident, passes at 2 waves/block,
+ * passes at 4 waves/block] (0 where not measured; may be NULL). */
+spstd_status spstd_batch_schedule(spstd_batch_t batch, int *resident, int *waves_per_block,
+                                  double *tuned_us);
 
 /* Slot state: active flag, steps since its load, time step. */
 spstd_status spstd_batch_slot_info(spstd_batch_t batch, int slot, int *active, int64_t *steps_done,

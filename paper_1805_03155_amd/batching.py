@@ -53,6 +53,6 @@ def run_instances(instances, steps, precision=spstd.FP32, coeffs=None, nprobes=1
     su = sum(np.prod(w.n) for w in instances) * steps * subs / 2.0
     stats = {"elapsed_s": el, "stage_updates": su, "stage_updates_per_s": su / el,
              "groups": {str(k): len(v[2]) for k, v in batches.items()},
-             "schedules": {str(k): v[0].schedule()[0] for k, v in batches.items()},
+             "schedules": {str(k): v[0].schedule()[:2] for k, v in batches.items()},
              "points": int(sum(np.prod(w.n) for w in instances))}
     return results, stats

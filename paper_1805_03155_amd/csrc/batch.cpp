@@ -77,7 +77,8 @@ struct Batch {
     int nres = 0;               // active slots in the resident table
     hipGraphExec_t graph;
     bool graph_ready = false;
-    double tuned_us[2] = {0.0, 0.0};   // [resident, passes] per step at creation
+    int wpb = 0;                // waves per block of the pass kernels (0: built-in choice)
+    double tuned_us[3] = {0.0, 0.0, 0.0};   // [resident, passes at 2 and 4 waves/block] per step
     std::string err;
 };
 
@@ -110,13 +111,14 @@ static spstd_status validate_batch(const spstd_batch_desc* d) {
     if (d->capacity < 1 || d->capacity > (1 << 20)) return SPSTD_ERR_ARG;
     if (d->nprobes < 0 || d->nprobes > kResMaxProbes) return SPSTD_ERR_ARG;
     if (d->nsteps_max < 0) return SPSTD_ERR_ARG;
+    if (d->waves_per_block != 0 && d->waves_per_block != 2 && d->waves_per_block != 4) return SPSTD_ERR_ARG;
     return SPSTD_OK;
 }
 
 template <typename R>
 static hipError_t batch_axis(Batch* b, int a, const R* src, R* dst, const ScaleRef& sc, int col) {
     return launch_axis_acc<R>(b->d.n[a], src, dst, b->ws + b->L.tw[a],
-                              axis_geom_of_n(b->d.ndim, b->d.n, a, b->d.capacity), sc, col, b->d.nyquist, b->st);
+                              axis_geom_of_n(b->d.ndim, b->d.n, a, b->d.capacity), sc, col, b->d.nyquist, b->st, b->wpb);
 }
 
 template <typename R>
@@ -140,7 +142,7 @@ static hipError_t batch_step_once(Batch* b) {
                 const ScaleRef so{b->ws + b->L.scales, b->d.m, owed};
                 e = launch_axis_ba<R>(b->d.n[1], pr, pi, b->ws + b->L.tw[1],
                                       axis_geom_of_n(b->d.ndim, b->d.n, 1, b->d.capacity), so, sc, SC_KYB, SC_KYA,
-                                      b->d.nyquist, b->st);
+                                      b->d.nyquist, b->st, b->wpb);
             } else {
                 if (owed >= 0) {
                     const ScaleRef so{b->ws + b->L.scales, b->d.m, owed};
@@ -152,9 +154,9 @@ static hipError_t batch_step_once(Batch* b) {
             if (a && e == hipSuccess && b->d.ndim == 3) e = batch_axis<R>(b, 2, pi, pr, sc, SC_KZA);
         }
         if (e != hipSuccess) break;
-        if (a && bb) e = launch_x_ab<R>(nx, pr, pi, V, twx, rg, sc, b->d.nyquist, b->st);
-        else if (a) e = launch_x_acc<R>(nx, pi, pr, V, twx, rg, sc, SC_KXA, SC_PA, b->d.nyquist, b->st);
-        else if (bb) e = launch_x_acc<R>(nx, pr, pi, V, twx, rg, sc, SC_KXB, SC_PB, b->d.nyquist, b->st);
+        if (a && bb) e = launch_x_ab<R>(nx, pr, pi, V, twx, rg, sc, b->d.nyquist, b->st, b->wpb);
+        else if (a) e = launch_x_acc<R>(nx, pi, pr, V, twx, rg, sc, SC_KXA, SC_PA, b->d.nyquist, b->st, b->wpb);
+        else if (bb) e = launch_x_acc<R>(nx, pr, pi, V, twx, rg, sc, SC_KXB, SC_PB, b->d.nyquist, b->st, b->wpb);
         if (e != hipSuccess) break;
         if (bb && b->d.ndim >= 2) {
             if (b->d.ndim == 3) e = batch_axis<R>(b, 2, pr, pi, sc, SC_KZB);
@@ -263,12 +265,18 @@ static spstd_status batch_step_t(Batch* b, int64_t n) {
 }
 
 // ---------------------------------------------------------------------------
-// Schedule autotuner for 1D batches: resident kernel against pass-kernel
-// graphs, timed on the empty batch (every slot stepping a zero state with the
-// scales of a nominal instance) and remembered per (n, precision, capacity).
+// Schedule autotuner: the resident kernel (1D batches that fit it) against
+// the pass kernels with 2 and with 4 waves per block, timed on the empty
+// batch (every slot stepping a zero state with the scales of a nominal
+// instance) and remembered per (shape, precision, capacity).
 // ---------------------------------------------------------------------------
+struct TuneResult {
+    bool resident;
+    int wpb;
+    double us[3];
+};
 static std::mutex g_tune_mu;
-static std::map<std::tuple<int64_t, size_t, int>, std::pair<bool, std::pair<double, double>>> g_tune;
+static std::map<std::tuple<int64_t, int64_t, int64_t, size_t, int>, TuneResult> g_tune;
 
 template <typename R>
 static spstd_status time_steps(Batch* b, int64_t warm, int64_t n, double* us) {
@@ -296,27 +304,34 @@ static spstd_status time_steps(Batch* b, int64_t warm, int64_t n, double* us) {
     return s;
 }
 
+// Drop the captured pass graph (its launches carry the old block size).
+static void drop_graph(Batch* b) {
+    if (b->graph_ready) (void)hipGraphExecDestroy(b->graph);
+    b->graph_ready = false;
+}
+
 template <typename R>
 static spstd_status batch_autotune(Batch* b) {
-    const auto key = std::make_tuple(b->d.n[0], b->esz, b->d.capacity);
+    const auto key = std::make_tuple(b->d.n[0], b->d.n[1], b->d.n[2], b->esz, b->d.capacity);
     {
         std::lock_guard<std::mutex> g(g_tune_mu);
         auto it = g_tune.find(key);
         if (it != g_tune.end()) {
-            b->resident = it->second.first;
-            b->tuned_us[0] = it->second.second.first;
-            b->tuned_us[1] = it->second.second.second;
+            b->resident = it->second.resident;
+            b->wpb = it->second.wpb;
+            for (int k = 0; k < 3; ++k) b->tuned_us[k] = it->second.us[k];
             return SPSTD_OK;
         }
     }
     // nominal instance: dx = hbar = m* = 1, V = 0, dt = 0.5 x_max / rho
     spstd_desc one{};
-    one.ndim = 1;
-    one.n[0] = b->d.n[0];
-    one.n[1] = one.n[2] = 1;
-    one.dx[0] = one.dx[1] = one.dx[2] = 1.0;
+    one.ndim = b->d.ndim;
+    for (int a = 0; a < 3; ++a) {
+        one.n[a] = b->d.n[a];
+        one.dx[a] = 1.0;
+    }
     one.hbar = one.mass = 1.0;
-    const double dt = 0.5 * b->xmax / (0.5 * kPi * kPi);
+    const double dt = 0.5 * b->xmax / (0.5 * kPi * kPi * (double)b->d.ndim);
     std::vector<double> rows((size_t)b->d.m * SC_COLS);
     for (int l = 0; l < b->d.m; ++l) scale_row(one, b->c[l] * dt, -b->dd[l] * dt, &rows[(size_t)l * SC_COLS]);
     std::vector<R> rr(rows.size() * (size_t)b->d.capacity);
@@ -337,14 +352,27 @@ static spstd_status batch_autotune(Batch* b) {
         for (int q = 0; q < b->d.nprobes; ++q) sl.probe_idx[q] = 0;
     }
     const int64_t trial = 2 * kBatchGraphChunk;
-    double us[2] = {0.0, 0.0};
-    b->resident = true;
-    b->rtab_dirty = true;
-    spstd_status s = time_steps<R>(b, kBatchGraphChunk, trial, &us[0]);
-    if (s == SPSTD_OK) {
-        b->resident = false;
-        s = time_steps<R>(b, kBatchGraphChunk, trial, &us[1]);
+    double us[3] = {0.0, 0.0, 0.0};
+    spstd_status s = SPSTD_OK;
+    const bool can_resident = b->resident;
+    if (can_resident) {
+        b->rtab_dirty = true;
+        s = time_steps<R>(b, kBatchGraphChunk, trial, &us[0]);
     }
+    b->resident = false;
+    // block size matters only where pencils of a wave share a block: every
+    // y/z length does, x rows do up to 1024 points
+    const bool both = b->d.ndim >= 2 || b->d.n[0] <= 1024;
+    for (int k = 0; k < 2 && s == SPSTD_OK; ++k) {
+        if (k == 1 && !both) {
+            us[2] = us[1];
+            break;
+        }
+        drop_graph(b);
+        b->wpb = k == 0 ? 2 : 4;
+        s = time_steps<R>(b, kBatchGraphChunk, trial, &us[1 + k]);
+    }
+    drop_graph(b);
     // back to an empty batch: zero scales, counters and active flags (the
     // fields stayed zero: a zero state steps to zero)
     std::vector<R> zr(rr.size(), (R)0);
@@ -357,11 +385,12 @@ static spstd_status batch_autotune(Batch* b) {
     for (Slot& sl : b->slots) sl = Slot{};
     b->rtab_dirty = true;
     if (s != SPSTD_OK) return s;
-    b->resident = us[0] <= us[1];
-    b->tuned_us[0] = us[0];
-    b->tuned_us[1] = us[1];
+    b->wpb = (both && us[2] < us[1]) ? 4 : 2;
+    const double pass_us = us[b->wpb == 4 ? 2 : 1];
+    b->resident = can_resident && us[0] <= pass_us;
+    for (int k = 0; k < 3; ++k) b->tuned_us[k] = us[k];
     std::lock_guard<std::mutex> g(g_tune_mu);
-    g_tune[key] = std::make_pair(b->resident, std::make_pair(us[0], us[1]));
+    g_tune[key] = TuneResult{b->resident, b->wpb, {us[0], us[1], us[2]}};
     return SPSTD_OK;
 }
 
@@ -429,6 +458,7 @@ spstd_status spstd_batch_create(const spstd_batch_desc* d, void* d_workspace, si
     b->st = (hipStream_t)stream;
     b->slots.resize(d->capacity);
     b->resident = d->ndim == 1 && resident_len_ok(d->n[0]) && !(d->flags & SPSTD_NO_RESIDENT);
+    b->wpb = d->waves_per_block;
     // zero fields and scales, twiddles, probe slots inactive
     hipError_t e = hipSuccess;
     const size_t fb = (size_t)d->capacity * b->npts;
@@ -465,10 +495,10 @@ spstd_status spstd_batch_create(const spstd_batch_desc* d, void* d_workspace, si
         delete b;
         return SPSTD_ERR_DEVICE;
     }
-    if (b->resident && (d->flags & SPSTD_AUTOTUNE)) {
+    if (d->flags & SPSTD_AUTOTUNE) {
         s = (b->esz == 8) ? batch_autotune<double>(b) : batch_autotune<float>(b);
         if (s != SPSTD_OK) {
-            if (b->graph_ready) (void)hipGraphExecDestroy(b->graph);
+            drop_graph(b);
             delete b;
             return s;
         }
@@ -477,13 +507,12 @@ spstd_status spstd_batch_create(const spstd_batch_desc* d, void* d_workspace, si
     return SPSTD_OK;
 }
 
-spstd_status spstd_batch_schedule(spstd_batch_t b, int* resident, double* tuned_us) {
+spstd_status spstd_batch_schedule(spstd_batch_t b, int* resident, int* waves_per_block, double* tuned_us) {
     if (!b || !resident) return SPSTD_ERR_ARG;
     *resident = b->resident ? 1 : 0;
-    if (tuned_us) {
-        tuned_us[0] = b->tuned_us[0];
-        tuned_us[1] = b->tuned_us[1];
-    }
+    if (waves_per_block) *waves_per_block = b->wpb;
+    if (tuned_us)
+        for (int k = 0; k < 3; ++k) tuned_us[k] = b->tuned_us[k];
     return SPSTD_OK;
 }
 

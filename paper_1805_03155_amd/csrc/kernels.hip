@@ -14,6 +14,8 @@
 //   x: psi_R += c_l dt (T_x psi_I + V psi_I / hbar), then on the same rows
 //      psi_I -= d_l dt (T_x psi_R + V psi_R / hbar)       (fused A and B)
 //   y: psi_I -= d_l dt T_y psi_R          z: psi_I -= d_l dt T_z psi_R
+#include <type_traits>
+
 #include "fft_core.hpp"
 #include "kernels.hpp"
 
@@ -964,15 +966,27 @@ constexpr int wpb_of() {
     return (sizeof(R) == 8 && N == 256) ? SPSTD_WPB_F64_256 : SPSTD_WPB;
 }
 
-template <typename R, int N>
-static hipError_t axis_acc_n(const R* src, R* dst, const void* tw, const AxisGeom& g, const ScaleRef& sc,
-                             int col, int nyq_zero, hipStream_t st) {
+// Pass launch with W waves per block; the block size is a runtime choice
+// (wpb: 0 for wpb_of, else 2 or 4) made by the batch autotuner.  Rows longer
+// than 1024 points run one pencil per block and ignore it.
+template <int N, typename F>
+static hipError_t with_wpb(int wpb, F&& f) {
+    if constexpr (pencil_cfg<N>::WAVE) {
+        if (wpb == 2) return f(std::integral_constant<int, 2>{});
+        if (wpb == 4) return f(std::integral_constant<int, 4>{});
+    }
+    return f(std::integral_constant<int, 0>{});
+}
+
+template <typename R, int N, int W0>
+static hipError_t axis_acc_nw(const R* src, R* dst, const void* tw, const AxisGeom& g, const ScaleRef& sc,
+                              int col, int nyq_zero, hipStream_t st) {
     using C = pencil_cfg<N>;
     constexpr int P = tuning<R>::YZ_PPL;
+    constexpr int W = W0 ? W0 : wpb_of<R, N>();
     if (g.half_x % P) return hipErrorInvalidValue;
     const int64_t ngroups = g.half_x / P * g.n_outer;
     const int64_t waves = (ngroups + C::PPW - 1) / C::PPW;
-    constexpr int W = wpb_of<R, N>();
     const int64_t blocks = (waves + W - 1) / W;
     hipLaunchKernelGGL((k_axis_acc<R, N, W, P>), dim3((unsigned)blocks), dim3(64 * W), 0, st,
                        src, dst, (const cpx<double>*)tw, g, sc, col, nyq_zero);
@@ -980,54 +994,70 @@ static hipError_t axis_acc_n(const R* src, R* dst, const void* tw, const AxisGeo
 }
 
 template <typename R, int N>
-static hipError_t axis_ba_n(R* psiR, R* psiI, const void* tw, const AxisGeom& g, const ScaleRef& scB,
-                            const ScaleRef& scA, int colB, int colA, int nyq_zero, hipStream_t st) {
+static hipError_t axis_acc_n(const R* src, R* dst, const void* tw, const AxisGeom& g, const ScaleRef& sc,
+                             int col, int nyq_zero, hipStream_t st, int wpb) {
+    return with_wpb<N>(wpb, [&](auto w) {
+        return axis_acc_nw<R, N, decltype(w)::value>(src, dst, tw, g, sc, col, nyq_zero, st);
+    });
+}
+
+template <typename R, int N, int W0>
+static hipError_t axis_ba_nw(R* psiR, R* psiI, const void* tw, const AxisGeom& g, const ScaleRef& scB,
+                             const ScaleRef& scA, int colB, int colA, int nyq_zero, hipStream_t st) {
     using C = pencil_cfg<N>;
     constexpr int P = tuning<R>::YZ_PPL;
+    constexpr int W = W0 ? W0 : wpb_of<R, N>();
     if (g.half_x % P) return hipErrorInvalidValue;
     const int64_t ngroups = g.half_x / P * g.n_outer;
     const int64_t waves = (ngroups + C::PPW - 1) / C::PPW;
-    constexpr int W = wpb_of<R, N>();
     const int64_t blocks = (waves + W - 1) / W;
     hipLaunchKernelGGL((k_axis_ba<R, N, W, P>), dim3((unsigned)blocks), dim3(64 * W), 0, st, psiR, psiI,
                        (const cpx<double>*)tw, g, scB, scA, colB, colA, nyq_zero);
     return hipGetLastError();
 }
 
+template <typename R, int N>
+static hipError_t axis_ba_n(R* psiR, R* psiI, const void* tw, const AxisGeom& g, const ScaleRef& scB,
+                            const ScaleRef& scA, int colB, int colA, int nyq_zero, hipStream_t st, int wpb) {
+    return with_wpb<N>(wpb, [&](auto w) {
+        return axis_ba_nw<R, N, decltype(w)::value>(psiR, psiI, tw, g, scB, scA, colB, colA, nyq_zero, st);
+    });
+}
+
 template <typename R>
 hipError_t launch_axis_ba(int64_t n, R* psiR, R* psiI, const void* tw, const AxisGeom& g, const ScaleRef& scB,
-                          const ScaleRef& scA, int colB, int colA, int nyq_zero, hipStream_t st) {
+                          const ScaleRef& scA, int colB, int colA, int nyq_zero, hipStream_t st, int wpb) {
     switch (n) {
-        case 16: return axis_ba_n<R, 16>(psiR, psiI, tw, g, scB, scA, colB, colA, nyq_zero, st);
-        case 32: return axis_ba_n<R, 32>(psiR, psiI, tw, g, scB, scA, colB, colA, nyq_zero, st);
-        case 64: return axis_ba_n<R, 64>(psiR, psiI, tw, g, scB, scA, colB, colA, nyq_zero, st);
-        case 128: return axis_ba_n<R, 128>(psiR, psiI, tw, g, scB, scA, colB, colA, nyq_zero, st);
-        case 256: return axis_ba_n<R, 256>(psiR, psiI, tw, g, scB, scA, colB, colA, nyq_zero, st);
-        case 512: return axis_ba_n<R, 512>(psiR, psiI, tw, g, scB, scA, colB, colA, nyq_zero, st);
-        case 1024: return axis_ba_n<R, 1024>(psiR, psiI, tw, g, scB, scA, colB, colA, nyq_zero, st);
+        case 16: return axis_ba_n<R, 16>(psiR, psiI, tw, g, scB, scA, colB, colA, nyq_zero, st, wpb);
+        case 32: return axis_ba_n<R, 32>(psiR, psiI, tw, g, scB, scA, colB, colA, nyq_zero, st, wpb);
+        case 64: return axis_ba_n<R, 64>(psiR, psiI, tw, g, scB, scA, colB, colA, nyq_zero, st, wpb);
+        case 128: return axis_ba_n<R, 128>(psiR, psiI, tw, g, scB, scA, colB, colA, nyq_zero, st, wpb);
+        case 256: return axis_ba_n<R, 256>(psiR, psiI, tw, g, scB, scA, colB, colA, nyq_zero, st, wpb);
+        case 512: return axis_ba_n<R, 512>(psiR, psiI, tw, g, scB, scA, colB, colA, nyq_zero, st, wpb);
+        case 1024: return axis_ba_n<R, 1024>(psiR, psiI, tw, g, scB, scA, colB, colA, nyq_zero, st, wpb);
         default: return hipErrorInvalidValue;
     }
 }
 
 template <typename R>
 hipError_t launch_axis_acc(int64_t n, const R* src, R* dst, const void* tw, const AxisGeom& g,
-                           const ScaleRef& sc, int col, int nyq_zero, hipStream_t st) {
+                           const ScaleRef& sc, int col, int nyq_zero, hipStream_t st, int wpb) {
     switch (n) {
-        case 16: return axis_acc_n<R, 16>(src, dst, tw, g, sc, col, nyq_zero, st);
-        case 32: return axis_acc_n<R, 32>(src, dst, tw, g, sc, col, nyq_zero, st);
-        case 64: return axis_acc_n<R, 64>(src, dst, tw, g, sc, col, nyq_zero, st);
-        case 128: return axis_acc_n<R, 128>(src, dst, tw, g, sc, col, nyq_zero, st);
-        case 256: return axis_acc_n<R, 256>(src, dst, tw, g, sc, col, nyq_zero, st);
-        case 512: return axis_acc_n<R, 512>(src, dst, tw, g, sc, col, nyq_zero, st);
-        case 1024: return axis_acc_n<R, 1024>(src, dst, tw, g, sc, col, nyq_zero, st);
+        case 16: return axis_acc_n<R, 16>(src, dst, tw, g, sc, col, nyq_zero, st, wpb);
+        case 32: return axis_acc_n<R, 32>(src, dst, tw, g, sc, col, nyq_zero, st, wpb);
+        case 64: return axis_acc_n<R, 64>(src, dst, tw, g, sc, col, nyq_zero, st, wpb);
+        case 128: return axis_acc_n<R, 128>(src, dst, tw, g, sc, col, nyq_zero, st, wpb);
+        case 256: return axis_acc_n<R, 256>(src, dst, tw, g, sc, col, nyq_zero, st, wpb);
+        case 512: return axis_acc_n<R, 512>(src, dst, tw, g, sc, col, nyq_zero, st, wpb);
+        case 1024: return axis_acc_n<R, 1024>(src, dst, tw, g, sc, col, nyq_zero, st, wpb);
         default: return hipErrorInvalidValue;
     }
 }
 
-template <typename R, int N>
-static hipError_t x_acc_n(const R* src, R* dst, const R* V, const void* tw, const RowGeom& g,
-                          const ScaleRef& sc, int kcol, int pcol, int nyq_zero, hipStream_t st) {
-    constexpr int W = wpb_of<R, N>();
+template <typename R, int N, int W0>
+static hipError_t x_acc_nw(const R* src, R* dst, const R* V, const void* tw, const RowGeom& g,
+                           const ScaleRef& sc, int kcol, int pcol, int nyq_zero, hipStream_t st) {
+    constexpr int W = W0 ? W0 : wpb_of<R, N>();
     using M = row_map<R, N, W>;
     const int64_t npen = (g.nrows + 1) / 2;
     const int64_t blocks = (npen + M::PPB - 1) / M::PPB;
@@ -1041,9 +1071,17 @@ static hipError_t x_acc_n(const R* src, R* dst, const R* V, const void* tw, cons
 }
 
 template <typename R, int N>
-static hipError_t x_ab_n(R* psiR, R* psiI, const R* V, const void* tw, const RowGeom& g,
-                         const ScaleRef& sc, int nyq_zero, hipStream_t st) {
-    constexpr int W = wpb_of<R, N>();
+static hipError_t x_acc_n(const R* src, R* dst, const R* V, const void* tw, const RowGeom& g,
+                          const ScaleRef& sc, int kcol, int pcol, int nyq_zero, hipStream_t st, int wpb) {
+    return with_wpb<N>(wpb, [&](auto w) {
+        return x_acc_nw<R, N, decltype(w)::value>(src, dst, V, tw, g, sc, kcol, pcol, nyq_zero, st);
+    });
+}
+
+template <typename R, int N, int W0>
+static hipError_t x_ab_nw(R* psiR, R* psiI, const R* V, const void* tw, const RowGeom& g,
+                          const ScaleRef& sc, int nyq_zero, hipStream_t st) {
+    constexpr int W = W0 ? W0 : wpb_of<R, N>();
     using M = row_map<R, N, W>;
     const int64_t npen = (g.nrows + 1) / 2;
     const int64_t blocks = (npen + M::PPB - 1) / M::PPB;
@@ -1054,6 +1092,14 @@ static hipError_t x_ab_n(R* psiR, R* psiI, const R* V, const void* tw, const Row
         hipLaunchKernelGGL((k_x_ab<R, N, W, false>), dim3((unsigned)blocks), dim3(M::THREADS), 0, st,
                            psiR, psiI, V, (const cpx<double>*)tw, g, sc, nyq_zero);
     return hipGetLastError();
+}
+
+template <typename R, int N>
+static hipError_t x_ab_n(R* psiR, R* psiI, const R* V, const void* tw, const RowGeom& g,
+                         const ScaleRef& sc, int nyq_zero, hipStream_t st, int wpb) {
+    return with_wpb<N>(wpb, [&](auto w) {
+        return x_ab_nw<R, N, decltype(w)::value>(psiR, psiI, V, tw, g, sc, nyq_zero, st);
+    });
 }
 
 #define SPSTD_ROW_CASES(F, ...)                         \
@@ -1075,14 +1121,14 @@ static hipError_t x_ab_n(R* psiR, R* psiI, const R* V, const void* tw, const Row
 template <typename R>
 hipError_t launch_x_acc(int64_t nx, const R* src, R* dst, const R* V, const void* tw,
                         const RowGeom& g, const ScaleRef& sc, int kcol, int pcol, int nyq_zero,
-                        hipStream_t st) {
-    SPSTD_ROW_CASES(x_acc_n, src, dst, V, tw, g, sc, kcol, pcol, nyq_zero, st)
+                        hipStream_t st, int wpb) {
+    SPSTD_ROW_CASES(x_acc_n, src, dst, V, tw, g, sc, kcol, pcol, nyq_zero, st, wpb)
 }
 
 template <typename R>
 hipError_t launch_x_ab(int64_t nx, R* psiR, R* psiI, const R* V, const void* tw,
-                       const RowGeom& g, const ScaleRef& sc, int nyq_zero, hipStream_t st) {
-    SPSTD_ROW_CASES(x_ab_n, psiR, psiI, V, tw, g, sc, nyq_zero, st)
+                       const RowGeom& g, const ScaleRef& sc, int nyq_zero, hipStream_t st, int wpb) {
+    SPSTD_ROW_CASES(x_ab_n, psiR, psiI, V, tw, g, sc, nyq_zero, st, wpb)
 }
 
 template <typename R>
@@ -1256,15 +1302,15 @@ hipError_t launch_fill0(int64_t n, R* y, hipStream_t st) {
 
 #define SPSTD_INSTANTIATE(R)                                                                    \
     template hipError_t launch_axis_acc<R>(int64_t, const R*, R*, const void*, const AxisGeom&, \
-                                           const ScaleRef&, int, int, hipStream_t);             \
+                                           const ScaleRef&, int, int, hipStream_t, int);        \
     template hipError_t launch_axis_ba<R>(int64_t, R*, R*, const void*, const AxisGeom&,        \
                                           const ScaleRef&, const ScaleRef&, int, int, int,      \
-                                          hipStream_t);                                         \
+                                          hipStream_t, int);                                    \
     template hipError_t launch_x_acc<R>(int64_t, const R*, R*, const R*, const void*,           \
                                         const RowGeom&, const ScaleRef&, int, int, int,         \
-                                        hipStream_t);                                           \
+                                        hipStream_t, int);                                      \
     template hipError_t launch_x_ab<R>(int64_t, R*, R*, const R*, const void*, const RowGeom&,  \
-                                       const ScaleRef&, int, hipStream_t);                      \
+                                       const ScaleRef&, int, hipStream_t, int);                 \
     template hipError_t launch_probe_batch<R>(const R*, const R*, int64_t, const int64_t*, int, \
                                               const int*, int, double*, int64_t*, int64_t,      \
                                               hipStream_t);                                     \

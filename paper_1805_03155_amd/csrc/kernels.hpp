@@ -40,6 +40,10 @@ struct ScaleRef {
     int l;             // stage of this pass
 };
 
+// The pass launchers (y/z passes, stage-boundary sweep, x passes) take the
+// waves per block as a last argument: 0 for the built-in choice per
+// precision and length, or 2 or 4 (the batch autotuner's candidates).
+
 // Supported pencil lengths.
 bool axis_len_ok(int64_t n);   // y/z passes: 16..1024
 bool row_len_ok(int64_t n);    // x pass:     16..16384
@@ -48,27 +52,27 @@ bool row_len_ok(int64_t n);    // x pass:     16..16384
 template <typename R>
 hipError_t launch_axis_acc(int64_t n, const R* src, R* dst, const void* tw,
                            const AxisGeom& g, const ScaleRef& sc, int col, int nyq_zero,
-                           hipStream_t st);
+                           hipStream_t st, int wpb = 0);
 
 // One sweep of y (or z) pencils at a stage boundary:
 //   psiI += sB T psiR  (column colB of stage scB.l), then
 //   psiR += sA T psiI  (column colA of stage scA.l), T the bare axis operator.
 template <typename R>
 hipError_t launch_axis_ba(int64_t n, R* psiR, R* psiI, const void* tw, const AxisGeom& g, const ScaleRef& scB,
-                          const ScaleRef& scA, int colB, int colA, int nyq_zero, hipStream_t st);
+                          const ScaleRef& scA, int colB, int colA, int nyq_zero, hipStream_t st, int wpb = 0);
 
 // dst += k * IFFT_x(ks^2 FFT_x(src)) + p * V * src with (k, p) of columns
 // (kcol, pcol): one half-stage along x.
 template <typename R>
 hipError_t launch_x_acc(int64_t nx, const R* src, R* dst, const R* V,
                         const void* tw, const RowGeom& g, const ScaleRef& sc,
-                        int kcol, int pcol, int nyq_zero, hipStream_t st);
+                        int kcol, int pcol, int nyq_zero, hipStream_t st, int wpb = 0);
 
 // Fused A and B halves along x (columns SC_KXA, SC_PA, SC_KXB, SC_PB):
 //   psi_R += T_x^A psi_I + p_A V psi_I;  then  psi_I += T_x^B psi_R + p_B V psi_R
 template <typename R>
 hipError_t launch_x_ab(int64_t nx, R* psiR, R* psiI, const R* V, const void* tw,
-                       const RowGeom& g, const ScaleRef& sc, int nyq_zero, hipStream_t st);
+                       const RowGeom& g, const ScaleRef& sc, int nyq_zero, hipStream_t st, int wpb = 0);
 
 // Batched probe samples: for every instance i < ninst with active[i],
 // out_i[slot][p] = (psiR[i*npts + idx[i*P + p]], psiI[...]) as doubles,

@@ -23,7 +23,7 @@ ALLOW_UNSTABLE = 0x1
 EAGER = 0x2          # no step-chunk graphs
 TIMING = 0x4         # pass kernels bracketed by HIP events (pass_times)
 NO_RESIDENT = 0x8    # 1D plans use the pass kernels, not the resident kernel
-AUTOTUNE = 0x10      # batches: time both 1D schedules at creation, keep the faster
+AUTOTUNE = 0x10      # batches: time the candidate schedules at creation, keep the fastest
 PASS_KINDS = ("y", "z", "xab", "x", "yba")
 MAX_PROBES = 64
 
@@ -54,7 +54,8 @@ class Desc(ctypes.Structure):
 class BatchDesc(ctypes.Structure):
     _fields_ = [("ndim", c_int), ("n", c_i64 * 3), ("precision", c_int), ("m", c_int),
                 ("c", P(c_d)), ("d", P(c_d)), ("nyquist", c_int), ("capacity", c_int),
-                ("nprobes", c_int), ("nsteps_max", c_i64), ("flags", c_u32)]
+                ("nprobes", c_int), ("nsteps_max", c_i64), ("flags", c_u32),
+                ("waves_per_block", c_int)]
 
 
 class Stats(ctypes.Structure):
@@ -109,7 +110,7 @@ def lib():
         L.spstd_batch_read.argtypes = [vp, c_int, pd, pd, pd, pi64]
         L.spstd_batch_release.argtypes = [vp, c_int]
         L.spstd_batch_slot_info.argtypes = [vp, c_int, P(c_int), pi64, pd]
-        L.spstd_batch_schedule.argtypes = [vp, P(c_int), pd]
+        L.spstd_batch_schedule.argtypes = [vp, P(c_int), P(c_int), pd]
         L.spstd_batch_destroy.argtypes = [vp]
         L.spstd_batch_last_error.argtypes = [vp]
         L.spstd_batch_last_error.restype = ctypes.c_char_p
@@ -338,7 +339,7 @@ def plan_from_workload(w, precision=FP64, method=SYMPLECTIC, dt=0.0, nsteps_max=
 
 
 def make_batch_desc(n, coeffs, capacity, nprobes=1, nsteps_max=0, precision=FP64,
-                    nyquist=NYQ_FULL, flags=0):
+                    nyquist=NYQ_FULL, flags=0, wpb=0):
     c, d = coeffs
     desc = BatchDesc()
     desc.ndim = len(n)
@@ -349,6 +350,7 @@ def make_batch_desc(n, coeffs, capacity, nprobes=1, nsteps_max=0, precision=FP64
     desc.c, desc.d = _dp(ca), _dp(da)
     desc.nyquist, desc.capacity, desc.nprobes = nyquist, int(capacity), int(nprobes)
     desc.nsteps_max, desc.flags = int(nsteps_max), flags
+    desc.waves_per_block = int(wpb)
     desc._keep = [ca, da]
     return desc
 
@@ -363,10 +365,10 @@ class Batch:
     """Slots of independent instances of one shape, stepped together."""
 
     def __init__(self, n, coeffs, capacity, nprobes=1, nsteps_max=0, precision=FP64,
-                 nyquist=NYQ_FULL, flags=0, device="cuda", stream=None):
+                 nyquist=NYQ_FULL, flags=0, device="cuda", stream=None, wpb=0):
         import torch
         self.desc = make_batch_desc(n, coeffs, capacity, nprobes, nsteps_max, precision,
-                                    nyquist, flags)
+                                    nyquist, flags, wpb)
         self.n = tuple(n)
         self.npoints = int(np.prod(n))
         self.nprobes = int(nprobes)
@@ -412,12 +414,13 @@ class Batch:
         _check(lib().spstd_batch_step(self.h, int(nsteps)), batch=self.h)
 
     def schedule(self):
-        """("resident" or "passes", measured us/step [resident, passes] at
-        creation, zeros where not tuned)."""
-        r = c_int()
-        us = np.zeros(2)
-        _check(lib().spstd_batch_schedule(self.h, ctypes.byref(r), _dp(us)))
-        return ("resident" if r.value else "passes"), (float(us[0]), float(us[1]))
+        """("resident" or "passes", pass-kernel waves per block (0: built-in),
+        measured us/step at creation of (resident, passes at 2 waves/block,
+        passes at 4), zeros where not tuned)."""
+        r, w = c_int(), c_int()
+        us = np.zeros(3)
+        _check(lib().spstd_batch_schedule(self.h, ctypes.byref(r), ctypes.byref(w), _dp(us)))
+        return ("resident" if r.value else "passes"), w.value, tuple(float(u) for u in us)
 
     def slot_info(self, slot):
         a, s, dt = c_int(), c_i64(), c_d()

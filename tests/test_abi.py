@@ -86,6 +86,17 @@ def test_bad_descriptors_rejected(bad):
     assert ei.value.code == 1
 
 
+@pytest.mark.parametrize("wpb,ok", [(0, True), (2, True), (4, True), (3, False), (8, False)])
+def test_batch_block_size_is_validated(wpb, ok):
+    d = spstd.make_batch_desc((32, 16), W.PAPER, 4, wpb=wpb)
+    if ok:
+        assert spstd.batch_workspace_size(d) > 4 * 3 * 32 * 16 * 8
+    else:
+        with pytest.raises(spstd.SpstdError) as ei:
+            spstd.batch_workspace_size(d)
+        assert ei.value.code == 1
+
+
 def test_spectrum_matches_oracle_extraction():
     w = W.finite_well_1d(seed=2, steps=8000)
     c, d = w.coeffs

@@ -116,21 +116,28 @@ def test_batch_release_and_reload_slot():
         b.load(1, w0.dx, w0.V, w0.psiR, w0.psiI, w0.probes)   # slot busy
 
 
-@pytest.mark.parametrize("n,prec", [(512, spstd.FP64), (8192, spstd.FP64), (2048, spstd.FP32)])
+@pytest.mark.parametrize("n,prec", [((512,), spstd.FP64), ((8192,), spstd.FP64), ((2048,), spstd.FP32),
+                                    ((64, 32), spstd.FP64), ((32, 16, 16), spstd.FP32),
+                                    ((64, 64, 64), spstd.FP64)])
 def test_autotuned_batch_starts_empty_and_matches_alone(n, prec):
     steps = 40
-    b = spstd.Batch((n,), W.PAPER, capacity=3, nprobes=2, nsteps_max=steps, precision=prec,
+    b = spstd.Batch(n, W.PAPER, capacity=3, nprobes=2, nsteps_max=steps, precision=prec,
                     flags=spstd.AUTOTUNE)
-    sched, us = b.schedule()
-    assert us[0] > 0 and us[1] > 0
-    assert sched == ("resident" if us[0] <= us[1] else "passes")
+    sched, wpb, us = b.schedule()
+    # resident candidate only for 1D; passes always timed at both block sizes
+    # (equal where rows longer than 1024 points make the size moot)
+    assert (us[0] > 0) == (len(n) == 1) and us[1] > 0 and us[2] > 0
+    if len(n) == 1 and n[0] > 1024:
+        assert us[1] == us[2]
+    assert wpb == (4 if us[2] < us[1] else 2)
+    assert sched == ("resident" if len(n) == 1 and us[0] <= us[1 if wpb == 2 else 2] else "passes")
     # the same key again: the remembered choice, no new timing
-    b2 = spstd.Batch((n,), W.PAPER, capacity=3, nprobes=2, nsteps_max=steps, precision=prec,
+    b2 = spstd.Batch(n, W.PAPER, capacity=3, nprobes=2, nsteps_max=steps, precision=prec,
                      flags=spstd.AUTOTUNE)
-    assert b2.schedule() == (sched, us)
+    assert b2.schedule() == (sched, wpb, us)
     for s in range(3):
         assert b.slot_info(s)[0] is False
-    ws = {s: inst((n,), seed=300 + s, nprobes=2) for s in (0, 2)}
+    ws = {s: inst(n, seed=300 + s, nprobes=2) for s in (0, 2)}
     dts = {}
     for s, w in ws.items():
         dts[s] = 0.9 * oracle.stable_dt(*w.coeffs, w.V, w.n, w.dx)
@@ -143,3 +150,19 @@ def test_autotuned_batch_starts_empty_and_matches_alone(n, prec):
         ra, ia, sa = alone(w, dts[s], steps, prec)
         assert rel(np.concatenate([r, i]), np.concatenate([ra, ia])) < tol
         assert rel(ser, sa) < tol
+
+
+@pytest.mark.parametrize("wpb", [2, 4])
+def test_forced_block_sizes_match_the_oracle(wpb):
+    # both block sizes give the oracle's result (the autotuner may pick either)
+    n = (32, 16, 64)
+    w = inst(n, seed=77)
+    dt = oracle.stable_dt(*w.coeffs, w.V, w.n, w.dx)
+    b = spstd.Batch(n, W.PAPER, capacity=2, nprobes=1, nsteps_max=20, wpb=wpb)
+    assert b.schedule()[1] == wpb
+    b.load(1, w.dx, w.V, w.psiR, w.psiI, w.probes, dt=dt)
+    b.step(20)
+    ser, r, i, _ = b.read(1)
+    ro, io, so, _ = oracle.run(w.psiR, w.psiI, w.V, w.n, w.dx, *w.coeffs, dt, 20, w.probes)
+    assert rel(np.concatenate([r, i]), np.concatenate([ro, io])) <= 1e-12
+    assert rel(ser, so) <= 1e-12
