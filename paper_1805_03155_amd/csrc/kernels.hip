@@ -47,6 +47,20 @@ bool row_len_ok(int64_t n) { return n >= 16 && n <= 16384 && (n & (n - 1)) == 0;
 //   YZ_PPL_F32     complex pencils per lane group in FP32 y/z passes
 //   EPI_CHUNK      epilogue elements scheduled together (caps the loads in
 //                  flight, and with them the registers)
+//   YZ_ACC_WAVES_*, YZ_BA_WAVES_F32, X_AB_WAVES_F32  minimum waves per SIMD of
+//                  the 256-point passes (yz_acc_waves and its kin).  Taken:
+//                  4 for the FP32 y/z pass.  Measured slower: 4 for the FP64
+//                  y/z pass (spills; z 70.5 -> 103 us), 3 or 4 for the FP32
+//                  boundary sweep (spills), 4 for the FP32 fused x pass
+//                  (54.7 -> 55.4 us); fewer FP64 y/z blocks per CU (4 or 2,
+//                  by unused dynamic LDS) slower too (z 70.5 -> 75.9, 99 us)
+//   YZ_EPI_BATCH_* y/z pass epilogues read YZ_CHUNK elements of the
+//                  accumulated field before writing any of them (element by
+//                  element, each read waits for the previous write: the
+//                  compiler cannot prove that the elements of one pencil are
+//                  distinct).  FP32 256^3: z 41.8 -> 41.3 us, boundary sweep
+//                  59.5 -> 58.1 us; FP64 slower (z 71.0 -> 73.3 us, sweep
+//                  98.6 -> 102.4 us); 8 or 16 reads at once slower in both
 //   EPI_FENCE      keep epilogue loads from being hoisted into the inverse
 //                  transform
 //   YZ_ORDER       0: consecutive blocks take neighbouring x column groups of
@@ -110,6 +124,27 @@ bool row_len_ok(int64_t n) { return n >= 16 && n <= 16384 && (n & (n - 1)) == 0;
 #ifndef SPSTD_EPI_CHUNK
 #define SPSTD_EPI_CHUNK 4
 #endif
+#ifndef SPSTD_YZ_ACC_WAVES_F32
+#define SPSTD_YZ_ACC_WAVES_F32 4
+#endif
+#ifndef SPSTD_YZ_ACC_WAVES_F64
+#define SPSTD_YZ_ACC_WAVES_F64 0
+#endif
+#ifndef SPSTD_YZ_BA_WAVES_F32
+#define SPSTD_YZ_BA_WAVES_F32 0
+#endif
+#ifndef SPSTD_X_AB_WAVES_F32
+#define SPSTD_X_AB_WAVES_F32 0
+#endif
+#ifndef SPSTD_YZ_EPI_BATCH_F64
+#define SPSTD_YZ_EPI_BATCH_F64 0
+#endif
+#ifndef SPSTD_YZ_EPI_BATCH_F32
+#define SPSTD_YZ_EPI_BATCH_F32 1
+#endif
+#ifndef SPSTD_YZ_CHUNK
+#define SPSTD_YZ_CHUNK 4
+#endif
 #ifndef SPSTD_EPI_FENCE
 #define SPSTD_EPI_FENCE 1
 #endif
@@ -122,11 +157,6 @@ bool row_len_ok(int64_t n) { return n >= 16 && n <= 16384 && (n & (n - 1)) == 0;
 #else
 #define SPSTD_WAVES_ATTR
 #endif
-#if SPSTD_YZ_MIN_WAVES > 0
-#define SPSTD_YZ_WAVES_ATTR __attribute__((amdgpu_waves_per_eu(SPSTD_YZ_MIN_WAVES)))
-#else
-#define SPSTD_YZ_WAVES_ATTR SPSTD_WAVES_ATTR
-#endif
 
 template <typename R>
 struct tuning;
@@ -138,6 +168,7 @@ struct tuning<double> {
     static constexpr int YZ_PPL = SPSTD_YZ_PPL_F64;
     static constexpr bool BA_RELOAD = SPSTD_BA_RELOAD_F64;
     static constexpr bool V_NT = SPSTD_V_NT_F64;
+    static constexpr bool EPI_BATCH = SPSTD_YZ_EPI_BATCH_F64;
 };
 template <>
 struct tuning<float> {
@@ -147,7 +178,29 @@ struct tuning<float> {
     static constexpr int YZ_PPL = SPSTD_YZ_PPL_F32;
     static constexpr bool BA_RELOAD = SPSTD_BA_RELOAD_F32;
     static constexpr bool V_NT = SPSTD_V_NT_F32;
+    static constexpr bool EPI_BATCH = SPSTD_YZ_EPI_BATCH_F32;
 };
+
+// Minimum waves per SIMD requested for the 256-point pass kernels (a value
+// of 0 leaves the general setting).  A 256^3 FP32 y/z pass is 16 waves per
+// CU: at 137 registers three waves per SIMD fit, which leaves a second round
+// a third full; capped at 128 registers all 16 run at once (z 41.4 -> 35.6
+// us).
+template <typename R, int N>
+constexpr int yz_acc_waves() {
+    const int k = N != 256 ? 0 : sizeof(R) == 4 ? SPSTD_YZ_ACC_WAVES_F32 : SPSTD_YZ_ACC_WAVES_F64;
+    return k > 0 ? k : SPSTD_YZ_MIN_WAVES > 0 ? SPSTD_YZ_MIN_WAVES : SPSTD_MIN_WAVES > 0 ? SPSTD_MIN_WAVES : 1;
+}
+template <typename R, int N>
+constexpr int yz_ba_waves() {
+    const int k = N != 256 ? 0 : sizeof(R) == 4 ? SPSTD_YZ_BA_WAVES_F32 : 0;
+    return k > 0 ? k : SPSTD_YZ_MIN_WAVES > 0 ? SPSTD_YZ_MIN_WAVES : SPSTD_MIN_WAVES > 0 ? SPSTD_MIN_WAVES : 1;
+}
+template <typename R, int N>
+constexpr int x_ab_waves() {
+    const int k = N != 256 ? 0 : sizeof(R) == 4 ? SPSTD_X_AB_WAVES_F32 : 0;
+    return k > 0 ? k : SPSTD_MIN_WAVES > 0 ? SPSTD_MIN_WAVES : 1;
+}
 
 // The potential is read once per x pass.  In FP64 the three fields of a
 // 256^3 grid (403 MB) exceed the 256 MB last-level cache, and reading V
@@ -267,6 +320,17 @@ __device__ __forceinline__ void add_group(R* dst, const cpx<R> (&v)[P][16], int 
     *q = a;
 }
 
+// a += s * (the P complex values of element e), as one vector of 2P reals
+template <typename R, int P>
+__device__ __forceinline__ void add_vec(typename vec_of<R, P>::type& a, const cpx<R> (&v)[P][16], int e, R s) {
+    if constexpr (P == 1) {
+        a.x += s * v[0][e].x; a.y += s * v[0][e].y;
+    } else {
+        a.x += s * v[0][e].x; a.y += s * v[0][e].y;
+        a.z += s * v[1][e].x; a.w += s * v[1][e].y;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // y / z pass: dst += T_axis src.  A lane group carries P complex pencils
 // (2P neighbouring x columns, one vector load per element).  Lane l of a
@@ -274,7 +338,7 @@ __device__ __forceinline__ void add_group(R* dst, const cpx<R> (&v)[P][16], int 
 // neighbouring columns), position j = l / PPW.
 // ---------------------------------------------------------------------------
 template <typename R, int N, int WPB, int P>
-__global__ __launch_bounds__(64 * WPB) SPSTD_YZ_WAVES_ATTR void k_axis_acc(
+__global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(yz_acc_waves<R, N>()))) void k_axis_acc(
     const R* __restrict__ src, R* __restrict__ dst, const cpx<double>* __restrict__ tw, AxisGeom g,
     ScaleRef sc, int col, int nyq_zero) {
     using C = pencil_cfg<N>;
@@ -330,10 +394,28 @@ __global__ __launch_bounds__(64 * WPB) SPSTD_YZ_WAVES_ATTR void k_axis_acc(
                 v[q][e].y *= scale;
             }
         }
+        if constexpr (TU::EPI_BATCH && !SPSTD_YZ_NT) {
+            using V = typename vec_of<R, P>::type;
+            constexpr int CH = SPSTD_YZ_CHUNK;
 #pragma unroll
-        for (int e = 0; e < 16; ++e) {
-            add_group<R, P>(dst + base + (int64_t)(j + C::T * e) * g.stride, v, e);
-            epi_fence(e);
+            for (int e0 = 0; e0 < 16; e0 += CH) {
+                V a[CH];
+#pragma unroll
+                for (int k = 0; k < CH; ++k)
+                    a[k] = *reinterpret_cast<const V*>(dst + base + (int64_t)(j + C::T * (e0 + k)) * g.stride);
+#pragma unroll
+                for (int k = 0; k < CH; ++k) {
+                    add_vec<R, P>(a[k], v, e0 + k, (R)1);
+                    *reinterpret_cast<V*>(dst + base + (int64_t)(j + C::T * (e0 + k)) * g.stride) = a[k];
+                }
+                __builtin_amdgcn_sched_barrier(0);
+            }
+        } else {
+#pragma unroll
+            for (int e = 0; e < 16; ++e) {
+                add_group<R, P>(dst + base + (int64_t)(j + C::T * e) * g.stride, v, e);
+                epi_fence(e);
+            }
         }
     }
 }
@@ -349,7 +431,7 @@ __global__ __launch_bounds__(64 * WPB) SPSTD_YZ_WAVES_ATTR void k_axis_acc(
 // FP64 against 48 B for the two passes it replaces).
 // ---------------------------------------------------------------------------
 template <typename R, int N, int WPB, int P>
-__global__ __launch_bounds__(64 * WPB) SPSTD_YZ_WAVES_ATTR void k_axis_ba(
+__global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(yz_ba_waves<R, N>()))) void k_axis_ba(
     R* __restrict__ psiR, R* __restrict__ psiI, const cpx<double>* __restrict__ tw, AxisGeom g,
     ScaleRef scB, ScaleRef scA, int colB, int colA, int nyq_zero) {
     using C = pencil_cfg<N>;
@@ -401,22 +483,43 @@ __global__ __launch_bounds__(64 * WPB) SPSTD_YZ_WAVES_ATTR void k_axis_ba(
     for (int q = 0; q < P; ++q) apply_k2<R, N>(v[q], j, nyq_zero);
     fft_pencils<R, N, true, true, TU::SPLIT, TU::PRODUCTS, P, C::PPW>(v, j, l0, SL, tw);
     epi_begin();
+    if constexpr (TU::EPI_BATCH) {
+        constexpr int CH = SPSTD_YZ_CHUNK;
 #pragma unroll
-    for (int e = 0; e < 16; ++e) {
-        V a{};
-        V* q = reinterpret_cast<V*>(psiI + base + (int64_t)(j + C::T * e) * g.stride);
-        if (valid) a = *q;
-        if constexpr (P == 1) {
-            a.x += sB * v[0][e].x; a.y += sB * v[0][e].y;
-            v[0][e] = cpx<R>{a.x, a.y};
-        } else {
-            a.x += sB * v[0][e].x; a.y += sB * v[0][e].y;
-            a.z += sB * v[1][e].x; a.w += sB * v[1][e].y;
-            v[0][e] = cpx<R>{a.x, a.y};
-            v[1][e] = cpx<R>{a.z, a.w};
+        for (int e0 = 0; e0 < 16; e0 += CH) {
+            V a[CH];
+#pragma unroll
+            for (int k = 0; k < CH; ++k) {
+                a[k] = V{};
+                if (valid) a[k] = *reinterpret_cast<const V*>(psiI + base + (int64_t)(j + C::T * (e0 + k)) * g.stride);
+            }
+#pragma unroll
+            for (int k = 0; k < CH; ++k) {
+                add_vec<R, P>(a[k], v, e0 + k, sB);
+                v[0][e0 + k] = cpx<R>{a[k].x, a[k].y};
+                if constexpr (P == 2) v[1][e0 + k] = cpx<R>{a[k].z, a[k].w};
+                if (valid) *reinterpret_cast<V*>(psiI + base + (int64_t)(j + C::T * (e0 + k)) * g.stride) = a[k];
+            }
+            __builtin_amdgcn_sched_barrier(0);
         }
-        if (valid) *q = a;
-        epi_fence(e);
+    } else {
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+            V a{};
+            V* q = reinterpret_cast<V*>(psiI + base + (int64_t)(j + C::T * e) * g.stride);
+            if (valid) a = *q;
+            if constexpr (P == 1) {
+                a.x += sB * v[0][e].x; a.y += sB * v[0][e].y;
+                v[0][e] = cpx<R>{a.x, a.y};
+            } else {
+                a.x += sB * v[0][e].x; a.y += sB * v[0][e].y;
+                a.z += sB * v[1][e].x; a.w += sB * v[1][e].y;
+                v[0][e] = cpx<R>{a.x, a.y};
+                v[1][e] = cpx<R>{a.z, a.w};
+            }
+            if (valid) *q = a;
+            epi_fence(e);
+        }
     }
     // A half of stage l + 1: psi_R += sA T psi_I(new)
     fft_pencils<R, N, false, true, TU::SPLIT, TU::PRODUCTS, P, C::PPW>(v, j, l0, SL, tw);
@@ -565,7 +668,7 @@ __global__ __launch_bounds__((row_map<R, N, WPB>::THREADS)) SPSTD_WAVES_ATTR voi
 }
 
 template <typename R, int N, int WPB, bool FULL>
-__global__ __launch_bounds__((row_map<R, N, WPB>::THREADS)) SPSTD_WAVES_ATTR void k_x_ab(
+__global__ __launch_bounds__((row_map<R, N, WPB>::THREADS)) __attribute__((amdgpu_waves_per_eu(x_ab_waves<R, N>()))) void k_x_ab(
     R* __restrict__ psiR, R* __restrict__ psiI, const R* __restrict__ V,
     const cpx<double>* __restrict__ tw, RowGeom rg, ScaleRef sc, int nyq_zero) {
     using C = pencil_cfg<N>;
