@@ -3,6 +3,7 @@
 // probe recording, norms, checkpoints and the RK4 comparison integrator.
 #include <hip/hip_runtime.h>
 
+#include <array>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -54,46 +55,62 @@ struct Plan {
     bool eig_on = false;
     EigParams eig{};
     std::string err;
-    // SPSTD_TIMING: event pairs around pass launches and their kinds
+    // SPSTD_TIMING: events recorded on the stream in order, and the (start,
+    // end, kind) of each timed pass; ev_open: the last event ends a timed
+    // pass and nothing was enqueued after it, so it also starts the next one
     std::vector<hipEvent_t> ev_pool;
-    std::vector<int> ev_kind;
+    std::vector<std::array<int, 3>> ev_span;
     size_t ev_used = 0;
+    bool ev_open = false;
     int64_t acc_n[SPSTD_NPASS_KINDS] = {0};
     double acc_ms[SPSTD_NPASS_KINDS] = {0.0};
 };
 
+// Record the next event of the pool on the plan's stream; -1 if none.
+static int ev_record(Plan* p) {
+    if (p->ev_used == p->ev_pool.size()) {
+        // timing only: no system-scope fence (cache write-back and
+        // invalidate) when an event completes, which would otherwise cost
+        // every bracketed pass a few microseconds
+        hipEvent_t a;
+        if (hipEventCreateWithFlags(&a, hipEventDisableSystemFence) != hipSuccess) return -1;
+        p->ev_pool.push_back(a);
+    }
+    const int k = (int)p->ev_used;
+    if (hipEventRecord(p->ev_pool[k], p->st) != hipSuccess) return -1;
+    ++p->ev_used;
+    return k;
+}
+
+// Work enqueued outside a timed pass: the next pass records its own start.
+static void ev_break(Plan* p) { p->ev_open = false; }
+
 // Brackets one pass launch with HIP events on the plan's stream when the
 // plan times its passes (timing plans launch eagerly, never from a graph).
+// Back-to-back passes share the event between them.
 struct PassTimer {
     Plan* p;
-    int slot;
-    PassTimer(Plan* pl, int kind) : p(pl), slot(-1) {
+    int start, kind;
+    PassTimer(Plan* pl, int k) : p(pl), start(-1), kind(k) {
         if (!(p->d.flags & SPSTD_TIMING)) return;
-        if (p->ev_used + 2 > p->ev_pool.size()) {
-            hipEvent_t a, b;
-            if (hipEventCreate(&a) != hipSuccess) return;
-            if (hipEventCreate(&b) != hipSuccess) { (void)hipEventDestroy(a); return; }
-            p->ev_pool.push_back(a);
-            p->ev_pool.push_back(b);
-        }
-        slot = (int)p->ev_used;
-        p->ev_used += 2;
-        p->ev_kind.push_back(kind);
-        (void)hipEventRecord(p->ev_pool[slot], p->st);
+        start = p->ev_open ? (int)p->ev_used - 1 : ev_record(p);
     }
     ~PassTimer() {
-        if (slot >= 0) (void)hipEventRecord(p->ev_pool[slot + 1], p->st);
+        if (start < 0) return;
+        const int end = ev_record(p);
+        p->ev_open = end >= 0;
+        if (end >= 0) p->ev_span.push_back({start, end, kind});
     }
 };
 
-// Add the durations of completed event pairs to the per-kind totals.
-static hipError_t harvest(Plan* p, const std::vector<hipEvent_t>& ev, const std::vector<int>& kind) {
-    for (size_t i = 0; i < kind.size(); ++i) {
+// Add the durations of completed passes to the per-kind totals.
+static hipError_t harvest(Plan* p) {
+    for (const auto& sp : p->ev_span) {
         float t = 0.0f;
-        hipError_t e = hipEventElapsedTime(&t, ev[2 * i], ev[2 * i + 1]);
+        hipError_t e = hipEventElapsedTime(&t, p->ev_pool[sp[0]], p->ev_pool[sp[1]]);
         if (e != hipSuccess) return e;
-        p->acc_n[kind[i]] += 1;
-        p->acc_ms[kind[i]] += t;
+        p->acc_n[sp[2]] += 1;
+        p->acc_ms[sp[2]] += t;
     }
     return hipSuccess;
 }
@@ -368,6 +385,7 @@ static hipError_t apply_K(Plan* p, const R* src, R* kout, double coef) {
     const ScaleRef sc{p->ws + p->L.scales, p->d.m + 1, p->d.m};
     const int ab = coef > 0.0 ? 0 : 1;
     hipError_t e = launch_fill0<R>(p->N, kout, p->st);
+    ev_break(p);
     if (p->d.laplacian == SPSTD_LAP_FD3) return e == hipSuccess ? fd_half<R>(p, src, kout, sc, ab) : e;
     if (e == hipSuccess) e = yz_passes<R>(p, src, kout, sc, ab);
     PassTimer tm(p, SPSTD_PASS_X);
@@ -402,9 +420,11 @@ static hipError_t enqueue_rk4_step(Plan* p) {
             if (e == hipSuccess) e = launch_xpay<R>(N, pr, nxt[s] * dt, kR, yR, p->st);
             if (e == hipSuccess) e = launch_xpay<R>(N, pi, nxt[s] * dt, kI, yI, p->st);
         }
+        ev_break(p);
     }
     if (e == hipSuccess) e = launch_axpby<R>(N, dt / 6.0, aR, 1.0, pr, p->st);
     if (e == hipSuccess) e = launch_axpby<R>(N, dt / 6.0, aI, 1.0, pi, p->st);
+    ev_break(p);
     return e;
 }
 
@@ -447,6 +467,7 @@ template <typename R>
 static hipError_t enqueue_steps_eager(Plan* p, int64_t n) {
     hipError_t e = hipSuccess;
     for (int64_t s = 0; s < n && e == hipSuccess; ++s) {
+        ev_break(p);
         e = (p->d.method == SPSTD_RK4) ? enqueue_rk4_step<R>(p) : enqueue_symplectic_step<R>(p);
         if (e == hipSuccess && p->d.nprobes > 0)
             e = launch_probe<R>(F<R>(p, p->L.psiR), F<R>(p, p->L.psiI),
@@ -458,6 +479,7 @@ static hipError_t enqueue_steps_eager(Plan* p, int64_t n) {
             e = launch_eig_acc<R>(F<R>(p, p->L.psiR), F<R>(p, p->L.psiI), p->N, p->eig, p->st);
             if (e == hipSuccess) e = launch_count_tick(reinterpret_cast<int64_t*>(p->ws + p->L.ecount), p->st);
         }
+        ev_break(p);
     }
     return e;
 }
@@ -877,13 +899,14 @@ spstd_status spstd_pass_times(spstd_plan_t p, int64_t* launches, double* total_m
         p->err = hipGetErrorString(e);
         return SPSTD_ERR_DEVICE;
     }
-    e = harvest(p, p->ev_pool, p->ev_kind);
+    e = harvest(p);
     if (e != hipSuccess) {
         p->err = hipGetErrorString(e);
         return SPSTD_ERR_DEVICE;
     }
-    p->ev_kind.clear();
+    p->ev_span.clear();
     p->ev_used = 0;
+    p->ev_open = false;
     for (int k = 0; k < SPSTD_NPASS_KINDS; ++k) {
         if (launches) launches[k] = p->acc_n[k];
         if (total_ms) total_ms[k] = p->acc_ms[k];
