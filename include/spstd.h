@@ -288,7 +288,9 @@ enum { SPSTD_PASS_Y = 0, SPSTD_PASS_Z = 1, SPSTD_PASS_XAB = 2, SPSTD_PASS_X = 3,
  * plan's stream and returns, for each kind k < SPSTD_NPASS_KINDS, the number
  * of launches since the previous call (launches[k]), their summed duration
  * in milliseconds measured with HIP events recorded on the plan's stream
- * around each launch (total_ms[k]), and the algorithmic HBM bytes of one
+ * around each launch (total_ms[k]; the events carry no system-scope fence,
+ * and one event ends a launch and starts the next when nothing else was
+ * enqueued between them), and the algorithmic HBM bytes of one
  * launch (bytes_per_launch[k]: every field read once and every field written
  * once).  Host arrays of SPSTD_NPASS_KINDS entries; any may be NULL.
  * SPSTD_ERR_ARG if the plan was made without SPSTD_TIMING.
