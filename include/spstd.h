@@ -56,8 +56,9 @@ enum { SPSTD_LAP_SPECTRAL = 0, SPSTD_LAP_FD3 = 1 };  /* spatial second derivativ
                                                         instead of replaying step-chunk graphs */
 #define SPSTD_TIMING 0x4u                            /* flags: eager launches, each pass kernel
                                                         bracketed by HIP events (spstd_pass_times) */
-#define SPSTD_NO_RESIDENT 0x8u                       /* flags: 1D plans use the pass kernels
-                                                        even where the resident kernel applies */
+#define SPSTD_NO_RESIDENT 0x8u                       /* flags: 1D plans (and small 2D batches)
+                                                        use the pass kernels even where a
+                                                        resident kernel applies */
 #define SPSTD_AUTOTUNE 0x10u                         /* batch flags: time the candidate schedules
                                                         at creation and keep the faster */
 #define SPSTD_MAX_STAGES 16
@@ -321,9 +322,11 @@ typedef struct spstd_batch_s *spstd_batch_t;
  *   nprobes       probe points per slot, 0..8.
  *   nsteps_max    probe samples kept per slot after sample 0.
  *   flags         SPSTD_ALLOW_UNSTABLE, SPSTD_NO_RESIDENT, SPSTD_AUTOTUNE.
- *                 A 1D batch of up to 16384 points has two schedules: the
- *                 resident kernel (whole step chunks in one launch) or the
- *                 pass kernels replayed as step graphs.  The pass kernels
+ *                 A 1D batch of up to 16384 points, or a 2D batch of n_x,
+ *                 n_y in {16, 32, 64}, has two schedules: the resident
+ *                 kernel (whole step chunks in one launch; a 2D instance
+ *                 lives in one workgroup's LDS) or the pass kernels
+ *                 replayed as step graphs.  The pass kernels
  *                 run 2 or 4 waves per block.  SPSTD_AUTOTUNE runs every
  *                 candidate (resident where it applies; passes at 2 and at
  *                 4 waves per block) for a few steps on the empty batch at

@@ -4,8 +4,9 @@
 // every directional pass of a stage is one launch over all slots; each slot
 // has its own row of the scale table (its dt, spacing, m* and hbar), its own
 // probe points, probe buffer and step counter.  Free slots hold zero fields
-// and zero scales, so they stay zero.  Short 1D batches run the resident
-// kernel (one launch per spstd_batch_step call for every active slot).
+// and zero scales, so they stay zero.  Short 1D batches and 2D batches of
+// up to 64 x 64 points run a resident kernel (one launch per
+// spstd_batch_step call for every active slot).
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -219,12 +220,18 @@ static spstd_status upload_rtab(Batch* b) {
         I.capacity = b->d.nsteps_max + 1;
         I.nprobes = b->d.nprobes;
         for (int q = 0; q < b->d.nprobes; ++q) I.probe_idx[q] = s.probe_idx[q];
-        const double k1 = k1base / ((double)b->d.n[0] * s.dx[0]);
-        const double kin = s.hbar / (2.0 * s.mass) * k1 * k1 / (double)b->d.n[0];
+        // kinetic scale per axis: (hbar/2m*) (2 pi/L)^2 / N for the bare k^2
+        double kin[2] = {0.0, 0.0};
+        for (int ax = 0; ax < b->d.ndim && ax < 2; ++ax) {
+            const double k1 = k1base / ((double)b->d.n[ax] * s.dx[ax]);
+            kin[ax] = s.hbar / (2.0 * s.mass) * k1 * k1 / (double)b->d.n[ax];
+        }
         for (int l = 0; l < b->d.m; ++l) {
             const double a = b->c[l] * s.dt, bb = -b->dd[l] * s.dt;
-            I.kin[2 * l] = (R)(a * kin);
-            I.kin[2 * l + 1] = (R)(bb * kin);
+            I.kin[2 * l] = (R)(a * kin[0]);
+            I.kin[2 * l + 1] = (R)(bb * kin[0]);
+            I.kin_y[2 * l] = (R)(a * kin[1]);
+            I.kin_y[2 * l + 1] = (R)(bb * kin[1]);
             I.pot[2 * l] = (R)(a / s.hbar);
             I.pot[2 * l + 1] = (R)(bb / s.hbar);
         }
@@ -247,9 +254,15 @@ static spstd_status batch_step_t(Batch* b, int64_t n) {
             spstd_status s = upload_rtab<R>(b);
             if (s != SPSTD_OK) return s;
         }
-        if (b->nres > 0 && n > 0)
-            BCHK(launch_resident_1d<R>(b->d.n[0], reinterpret_cast<const ResidentInst<R>*>(b->ws + b->L.rinst),
-                                       b->nres, b->d.m, n, b->d.nyquist, b->ws + b->L.tw[0], b->st));
+        const ResidentInst<R>* tab = reinterpret_cast<const ResidentInst<R>*>(b->ws + b->L.rinst);
+        if (b->nres > 0 && n > 0) {
+            if (b->d.ndim == 1)
+                BCHK(launch_resident_1d<R>(b->d.n[0], tab, b->nres, b->d.m, n, b->d.nyquist, b->ws + b->L.tw[0],
+                                           b->st));
+            else
+                BCHK(launch_resident_2d<R>(b->d.n[0], b->d.n[1], tab, b->nres, b->d.m, n, b->d.nyquist,
+                                           b->ws + b->L.tw[0], b->ws + b->L.tw[1], b->st));
+        }
         return SPSTD_OK;
     }
     int64_t left = n;
@@ -265,7 +278,7 @@ static spstd_status batch_step_t(Batch* b, int64_t n) {
 }
 
 // ---------------------------------------------------------------------------
-// Schedule autotuner: the resident kernel (1D batches that fit it) against
+// Schedule autotuner: the resident kernel (batches that fit it) against
 // the pass kernels with 2 and with 4 waves per block, timed on the empty
 // batch (every slot stepping a zero state with the scales of a nominal
 // instance) and remembered per (shape, precision, capacity).
@@ -457,7 +470,8 @@ spstd_status spstd_batch_create(const spstd_batch_desc* d, void* d_workspace, si
     b->L = L;
     b->st = (hipStream_t)stream;
     b->slots.resize(d->capacity);
-    b->resident = d->ndim == 1 && resident_len_ok(d->n[0]) && !(d->flags & SPSTD_NO_RESIDENT);
+    b->resident = ((d->ndim == 1 && resident_len_ok(d->n[0])) || (d->ndim == 2 && resident2d_ok(d->n[0], d->n[1]))) &&
+                  !(d->flags & SPSTD_NO_RESIDENT);
     b->wpb = d->waves_per_block;
     // zero fields and scales, twiddles, probe slots inactive
     hipError_t e = hipSuccess;

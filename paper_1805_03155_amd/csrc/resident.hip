@@ -199,7 +199,158 @@ __global__ __launch_bounds__((res_cfg<N>::THREADS)) void k_resident_1d(
     }
 }
 
+// ---------------------------------------------------------------------------
+// Resident 2D kernel: one workgroup per instance of NX by NY points (x
+// fastest), psi_R and psi_I in LDS for the whole launch.  A substep is
+//   g += kin_x T_x f + pot V f   (x phase: lane groups on row pairs 2q, 2q+1
+//                                 packed as one complex pencil)
+//   g += kin_y T_y f             (y phase: lane groups on column pairs)
+// with f the source and g the destination field of Eq. (18) (A: f = psi_I,
+// g = psi_R; B: f = psi_R, g = psi_I, kin and pot from -d_l dt), each phase
+// a forward transform, the bare k^2 (bin index squared) and an inverse
+// transform along its axis, separated by workgroup barriers.  f is not
+// written within a substep; every element of g is written by one lane per
+// phase.  After every step thread 0 records the probe samples (FP64).
+// ---------------------------------------------------------------------------
+template <int NX, int NY>
+struct res2_cfg {
+    static constexpr int TX = NX / 16, TY = NY / 16;   // lanes per pencil
+    static constexpr int NPT = NX * NY;
+    static constexpr int LANES = NPT / 32;             // lanes busy in either phase
+    static constexpr int THREADS = LANES < 64 ? 64 : LANES;
+    static constexpr int GX = THREADS / TX, GY = THREADS / TY;   // lane groups per phase
+    static constexpr int SX = NX == 16 ? 0 : GX * lds_size<NX>::value;
+    static constexpr int SY = NY == 16 ? 0 : GY * lds_size<NY>::value;
+    static constexpr int SCR = (SX > SY ? SX : SY) > 0 ? (SX > SY ? SX : SY) : 1;
+};
+
+template <typename R, int NX, int NY>
+__global__ __launch_bounds__((res2_cfg<NX, NY>::THREADS)) void k_resident_2d(
+    const ResidentInst<R>* __restrict__ inst, int ninst, int m, int64_t nsteps, int nyq_zero,
+    const cpx<double>* __restrict__ twx, const cpx<double>* __restrict__ twy) {
+    using C = res2_cfg<NX, NY>;
+    __shared__ R sR[C::NPT];
+    __shared__ R sI[C::NPT];
+    __shared__ R scr[C::SCR];
+    if ((int)blockIdx.x >= ninst) return;   // uniform over the workgroup
+    const ResidentInst<R>* I = inst + blockIdx.x;
+    const int t = threadIdx.x;
+    for (int k = t; k < C::NPT; k += C::THREADS) {
+        sR[k] = I->psiR[k];
+        sI[k] = I->psiI[k];
+    }
+    const R* __restrict__ V = I->V;
+    const int64_t slot0 = *I->counter;
+    // x phase: row pair qx, position jx; y phase: column pair qy, position jy
+    const int jx = t % C::TX, qx = t / C::TX;
+    const int jy = t % C::TY, qy = t / C::TY;
+    const bool hx = qx < NY / 2, hy = qy < NX / 2;
+    R* lx = scr + (NX == 16 ? 0 : qx * lds_size<NX>::value);
+    R* ly = scr + (NY == 16 ? 0 : qy * lds_size<NY>::value);
+    __syncthreads();
+    for (int64_t s = 0; s < nsteps; ++s) {
+        for (int l = 0; l < m; ++l) {
+            for (int half = 0; half < 2; ++half) {
+                const R kx = I->kin[2 * l + half], ky = I->kin_y[2 * l + half], pt = I->pot[2 * l + half];
+                if (kx == (R)0 && ky == (R)0 && pt == (R)0) continue;   // uniform
+                const R* f = half == 0 ? sI : sR;
+                R* g = half == 0 ? sR : sI;
+                cpx<R> v[1][16];
+#pragma unroll
+                for (int e = 0; e < 16; ++e) {
+                    const int k0 = 2 * qx * NX + jx + C::TX * e;
+                    v[0][e] = hx ? cpx<R>{f[k0], f[k0 + NX]} : cpx<R>{(R)0, (R)0};
+                }
+                fft_pencils<R, NX, false, true, true, true, 1, 1>(v, jx, lx, lds_size<NX>::value, twx);
+                k2_symbol<R, NX>(v[0], jx, nyq_zero);
+                fft_pencils<R, NX, true, true, true, true, 1, 1>(v, jx, lx, lds_size<NX>::value, twx);
+                if (hx) {
+#pragma unroll
+                    for (int e = 0; e < 16; ++e) {
+                        const int k0 = 2 * qx * NX + jx + C::TX * e, k1 = k0 + NX;
+                        g[k0] += kx * v[0][e].x + pt * V[k0] * f[k0];
+                        g[k1] += kx * v[0][e].y + pt * V[k1] * f[k1];
+                    }
+                }
+                __syncthreads();
+#pragma unroll
+                for (int e = 0; e < 16; ++e) {
+                    const int k0 = (jy + C::TY * e) * NX + 2 * qy;
+                    v[0][e] = hy ? cpx<R>{f[k0], f[k0 + 1]} : cpx<R>{(R)0, (R)0};
+                }
+                fft_pencils<R, NY, false, true, true, true, 1, 1>(v, jy, ly, lds_size<NY>::value, twy);
+                k2_symbol<R, NY>(v[0], jy, nyq_zero);
+                fft_pencils<R, NY, true, true, true, true, 1, 1>(v, jy, ly, lds_size<NY>::value, twy);
+                if (hy) {
+#pragma unroll
+                    for (int e = 0; e < 16; ++e) {
+                        const int k0 = (jy + C::TY * e) * NX + 2 * qy;
+                        g[k0] += ky * v[0][e].x;
+                        g[k0 + 1] += ky * v[0][e].y;
+                    }
+                }
+                __syncthreads();
+            }
+        }
+        if (t == 0) {
+            const int64_t slot = slot0 + s;
+            for (int q = 0; q < I->nprobes && slot < I->capacity; ++q) {
+                const int64_t pidx = I->probe_idx[q];
+                I->probes[(slot * I->nprobes + q) * 2 + 0] = (double)sR[pidx];
+                I->probes[(slot * I->nprobes + q) * 2 + 1] = (double)sI[pidx];
+            }
+        }
+        // the next step writes the fields thread 0 has just sampled
+        __syncthreads();
+    }
+    for (int k = t; k < C::NPT; k += C::THREADS) {
+        I->psiR[k] = sR[k];
+        I->psiI[k] = sI[k];
+    }
+    if (t == 0) *I->counter = slot0 + nsteps;
+}
+
 bool resident_len_ok(int64_t n) { return n >= 16 && (n & (n - 1)) == 0 && n <= 16384; }
+
+bool resident2d_ok(int64_t nx, int64_t ny) {
+    return (nx == 16 || nx == 32 || nx == 64) && (ny == 16 || ny == 32 || ny == 64);
+}
+
+template <typename R, int NX, int NY>
+static hipError_t res2_n(const ResidentInst<R>* inst, int ninst, int m, int64_t nsteps, int nyq_zero,
+                         const void* twx, const void* twy, hipStream_t st) {
+    hipLaunchKernelGGL((k_resident_2d<R, NX, NY>), dim3(ninst), dim3(res2_cfg<NX, NY>::THREADS), 0, st, inst,
+                       ninst, m, nsteps, nyq_zero, (const cpx<double>*)twx, (const cpx<double>*)twy);
+    return hipGetLastError();
+}
+
+template <typename R, int NX>
+static hipError_t res2_x(int64_t ny, const ResidentInst<R>* inst, int ninst, int m, int64_t nsteps, int nyq_zero,
+                         const void* twx, const void* twy, hipStream_t st) {
+    switch (ny) {
+        case 16: return res2_n<R, NX, 16>(inst, ninst, m, nsteps, nyq_zero, twx, twy, st);
+        case 32: return res2_n<R, NX, 32>(inst, ninst, m, nsteps, nyq_zero, twx, twy, st);
+        case 64: return res2_n<R, NX, 64>(inst, ninst, m, nsteps, nyq_zero, twx, twy, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <typename R>
+hipError_t launch_resident_2d(int64_t nx, int64_t ny, const ResidentInst<R>* inst, int ninst, int m,
+                              int64_t nsteps, int nyq_zero, const void* twx, const void* twy, hipStream_t st) {
+    if (ninst < 1 || m < 1 || m > kResMaxSubsteps / 2 || nsteps < 0) return hipErrorInvalidValue;
+    switch (nx) {
+        case 16: return res2_x<R, 16>(ny, inst, ninst, m, nsteps, nyq_zero, twx, twy, st);
+        case 32: return res2_x<R, 32>(ny, inst, ninst, m, nsteps, nyq_zero, twx, twy, st);
+        case 64: return res2_x<R, 64>(ny, inst, ninst, m, nsteps, nyq_zero, twx, twy, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template hipError_t launch_resident_2d<double>(int64_t, int64_t, const ResidentInst<double>*, int, int, int64_t,
+                                               int, const void*, const void*, hipStream_t);
+template hipError_t launch_resident_2d<float>(int64_t, int64_t, const ResidentInst<float>*, int, int, int64_t,
+                                              int, const void*, const void*, hipStream_t);
 
 template <typename R, int N>
 static hipError_t res_n(const ResidentInst<R>* inst, int ninst, int m, int64_t nsteps, int nyq_zero,

@@ -1,4 +1,4 @@
-// Resident 1D kernel: instance table and launcher (host-callable C++).
+// Resident kernels (1D, small 2D): instance table and launchers (host-callable C++).
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -23,14 +23,24 @@ struct ResidentInst {
     int64_t probe_idx[kResMaxProbes];
     R kin[kResMaxSubsteps];   // substep 2l (A) and 2l+1 (B): coef dt (hbar/2m*) (2 pi/L)^2 / N
     R pot[kResMaxSubsteps];   // substep 2l (A) and 2l+1 (B): coef dt / hbar
+    R kin_y[kResMaxSubsteps]; // 2D instances: kin of the y axis (L_y, N_y); kin is then the x axis's
 };
 
 bool resident_len_ok(int64_t n);
+// 2D grids the resident kernel holds whole in LDS: n_x, n_y in {16, 32, 64}.
+bool resident2d_ok(int64_t nx, int64_t ny);
 
 // Advance every instance of the table (all of length n) by nsteps steps of
 // m stages.  tw: twiddle table w_n^t, t < n, in the run precision.
 template <typename R>
 hipError_t launch_resident_1d(int64_t n, const ResidentInst<R>* inst, int ninst, int m, int64_t nsteps,
                               int nyq_zero, const void* tw, hipStream_t st);
+
+// The same for 2D instances of nx by ny points (x fastest), one workgroup
+// per instance with the state in LDS.  twx, twy: twiddle tables of the two
+// axes (FP64).
+template <typename R>
+hipError_t launch_resident_2d(int64_t nx, int64_t ny, const ResidentInst<R>* inst, int ninst, int m,
+                              int64_t nsteps, int nyq_zero, const void* twx, const void* twy, hipStream_t st);
 
 }  // namespace spstd

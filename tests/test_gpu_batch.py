@@ -28,6 +28,13 @@ def inst(n, seed, nprobes=1):
                       rng.standard_normal(N), rng.integers(0, N, nprobes).astype(np.int64), 0, W.PAPER)
 
 
+def resident_ok(n):
+    """Shapes a batch can run with a resident kernel."""
+    if len(n) == 1:
+        return 16 <= n[0] <= 16384
+    return len(n) == 2 and n[0] in (16, 32, 64) and n[1] in (16, 32, 64)
+
+
 def alone(w, dt, steps, precision=spstd.FP64, flags=0):
     p = spstd.plan_from_workload(w, dt=dt, nsteps_max=steps, precision=precision, flags=flags)
     ser, _ = p.run(steps)
@@ -124,13 +131,14 @@ def test_autotuned_batch_starts_empty_and_matches_alone(n, prec):
     b = spstd.Batch(n, W.PAPER, capacity=3, nprobes=2, nsteps_max=steps, precision=prec,
                     flags=spstd.AUTOTUNE)
     sched, wpb, us = b.schedule()
-    # resident candidate only for 1D; passes always timed at both block sizes
-    # (equal where rows longer than 1024 points make the size moot)
-    assert (us[0] > 0) == (len(n) == 1) and us[1] > 0 and us[2] > 0
+    # resident candidate only where a resident kernel applies; passes always
+    # timed at both block sizes (equal where rows longer than 1024 points
+    # make the size moot)
+    assert (us[0] > 0) == resident_ok(n) and us[1] > 0 and us[2] > 0
     if len(n) == 1 and n[0] > 1024:
         assert us[1] == us[2]
     assert wpb == (4 if us[2] < us[1] else 2)
-    assert sched == ("resident" if len(n) == 1 and us[0] <= us[1 if wpb == 2 else 2] else "passes")
+    assert sched == ("resident" if resident_ok(n) and us[0] <= us[1 if wpb == 2 else 2] else "passes")
     # the same key again: the remembered choice, no new timing
     b2 = spstd.Batch(n, W.PAPER, capacity=3, nprobes=2, nsteps_max=steps, precision=prec,
                      flags=spstd.AUTOTUNE)
@@ -166,3 +174,41 @@ def test_forced_block_sizes_match_the_oracle(wpb):
     ro, io, so, _ = oracle.run(w.psiR, w.psiI, w.V, w.n, w.dx, *w.coeffs, dt, 20, w.probes)
     assert rel(np.concatenate([r, i]), np.concatenate([ro, io])) <= 1e-12
     assert rel(ser, so) <= 1e-12
+
+
+@pytest.mark.parametrize("n", [(16, 16), (32, 64), (64, 16), (64, 64)])
+@pytest.mark.parametrize("prec", [spstd.FP64, spstd.FP32])
+def test_resident_2d_matches_pass_kernels_and_oracle(n, prec):
+    # small 2D instances held in one workgroup's LDS against the pass-kernel
+    # schedule of the same batch, and (FP64) against the oracle
+    steps = 30
+    ws = [inst(n, seed=700 + k, nprobes=2) for k in range(3)]
+    res = spstd.Batch(n, W.PAPER, capacity=3, nprobes=2, nsteps_max=steps, precision=prec)
+    split = spstd.Batch(n, W.PAPER, capacity=3, nprobes=2, nsteps_max=steps, precision=prec)
+    pas = spstd.Batch(n, W.PAPER, capacity=3, nprobes=2, nsteps_max=steps, precision=prec,
+                      flags=spstd.NO_RESIDENT)
+    assert res.schedule()[0] == "resident" and pas.schedule()[0] == "passes"
+    dts = []
+    for k, w in enumerate(ws):
+        dt = 0.9 * oracle.stable_dt(*w.coeffs, w.V, w.n, w.dx)
+        dts.append(dt)
+        for b in (res, split, pas):
+            b.load(k, w.dx, w.V, w.psiR, w.psiI, w.probes, dt=dt)
+    res.step(steps)
+    split.step(11)
+    split.step(steps - 11)
+    pas.step(steps)
+    tol = 1e-13 if prec == spstd.FP64 else 2e-5
+    for k, w in enumerate(ws):
+        s1, r1, i1, c1 = res.read(k)
+        s2, r2, i2, c2 = pas.read(k)
+        s3, r3, i3, c3 = split.read(k)
+        assert c1 == c2 == c3 == steps
+        # one launch or two: the same arithmetic
+        assert np.array_equal(r1, r3) and np.array_equal(i1, i3) and np.array_equal(s1, s3)
+        assert rel(np.concatenate([r1, i1]), np.concatenate([r2, i2])) < tol
+        assert rel(s1, s2) < tol
+        if prec == spstd.FP64:
+            ro, io, so, _ = oracle.run(w.psiR, w.psiI, w.V, w.n, w.dx, *w.coeffs, dts[k], steps, w.probes)
+            assert rel(np.concatenate([r1, i1]), np.concatenate([ro, io])) <= 1e-12
+            assert rel(s1, so) <= 1e-12
