@@ -396,7 +396,7 @@ spstd_status spstd_batch_read(spstd_batch_t batch, int slot, double *probes_out,
 /* Free a slot (its fields and scales are cleared).  Synchronises. */
 spstd_status spstd_batch_release(spstd_batch_t batch, int slot);
 
-/* The schedule in use: *resident = 1 for the resident 1D kernel, 0 for the
+/* The schedule in use: *resident = 1 for a resident kernel, 0 for the
  * pass kernels; *waves_per_block = the pass kernels' block size in waves (0:
  * the built-in choice; may be NULL); tuned_us[0..2] = the measured
  * microseconds per step at creation of [resident, passes at 2 waves/block,

@@ -10,7 +10,7 @@ namespace spstd {
 constexpr int kResMaxProbes = 8;
 constexpr int kResMaxSubsteps = 32;   // 2 * SPSTD_MAX_STAGES
 
-// One 1D instance advanced by the resident kernel (device-resident table).
+// One instance advanced by a resident kernel (device-resident table).
 template <typename R>
 struct ResidentInst {
     const R* V;            // N potential values
