@@ -54,6 +54,15 @@ bool row_len_ok(int64_t n) { return n >= 16 && n <= 16384 && (n & (n - 1)) == 0;
 //                  boundary sweep (spills), 4 for the FP32 fused x pass
 //                  (54.7 -> 55.4 us); fewer FP64 y/z blocks per CU (4 or 2,
 //                  by unused dynamic LDS) slower too (z 70.5 -> 75.9, 99 us)
+//   BA_PPL_F32, BA_PPL_F32_LONG  complex pencils per lane group in the FP32
+//                  stage-boundary sweep up to 256 and from 512 points: one
+//                  (142 registers, three waves per SIMD) against two (248,
+//                  two waves) at 256: 256^3 sweep 59.1 -> 55.0 us; two at
+//                  512 (a 512^2 batch of 49: 316 against 352 us per step).
+//                  Reading psi_I together with psi_R at the start instead
+//                  of after the first transform pair was slower in both
+//                  precisions (FP32 58.9, with psi_R re-read and four waves
+//                  62.2; FP64 98.2 -> 124.4 us with psi_R re-read)
 //   YZ_EPI_BATCH_* y/z pass epilogues read YZ_CHUNK elements of the
 //                  accumulated field before writing any of them (element by
 //                  element, each read waits for the previous write: the
@@ -136,6 +145,12 @@ bool row_len_ok(int64_t n) { return n >= 16 && n <= 16384 && (n & (n - 1)) == 0;
 #ifndef SPSTD_X_AB_WAVES_F32
 #define SPSTD_X_AB_WAVES_F32 0
 #endif
+#ifndef SPSTD_BA_PPL_F32
+#define SPSTD_BA_PPL_F32 1
+#endif
+#ifndef SPSTD_BA_PPL_F32_LONG
+#define SPSTD_BA_PPL_F32_LONG 2
+#endif
 #ifndef SPSTD_YZ_EPI_BATCH_F64
 #define SPSTD_YZ_EPI_BATCH_F64 0
 #endif
@@ -169,6 +184,7 @@ struct tuning<double> {
     static constexpr bool BA_RELOAD = SPSTD_BA_RELOAD_F64;
     static constexpr bool V_NT = SPSTD_V_NT_F64;
     static constexpr bool EPI_BATCH = SPSTD_YZ_EPI_BATCH_F64;
+    static constexpr int BA_PPL = 1;
 };
 template <>
 struct tuning<float> {
@@ -179,6 +195,7 @@ struct tuning<float> {
     static constexpr bool BA_RELOAD = SPSTD_BA_RELOAD_F32;
     static constexpr bool V_NT = SPSTD_V_NT_F32;
     static constexpr bool EPI_BATCH = SPSTD_YZ_EPI_BATCH_F32;
+    static constexpr int BA_PPL = SPSTD_BA_PPL_F32;
 };
 
 // Minimum waves per SIMD requested for the 256-point pass kernels (a value
@@ -1108,7 +1125,7 @@ template <typename R, int N, int W0>
 static hipError_t axis_ba_nw(R* psiR, R* psiI, const void* tw, const AxisGeom& g, const ScaleRef& scB,
                              const ScaleRef& scA, int colB, int colA, int nyq_zero, hipStream_t st) {
     using C = pencil_cfg<N>;
-    constexpr int P = tuning<R>::YZ_PPL;
+    constexpr int P = (sizeof(R) == 4 && N >= 512) ? SPSTD_BA_PPL_F32_LONG : tuning<R>::BA_PPL;
     constexpr int W = W0 ? W0 : wpb_of<R, N>();
     if (g.half_x % P) return hipErrorInvalidValue;
     const int64_t ngroups = g.half_x / P * g.n_outer;
