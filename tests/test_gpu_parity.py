@@ -192,3 +192,46 @@ def test_error_paths():
     with pytest.raises(spstd.SpstdError) as ei:
         p.run(11)
     assert ei.value.code == 6
+
+
+@pytest.mark.parametrize("n", [(64,), (32, 16), (16, 32, 16)])
+@pytest.mark.parametrize("flags", [0, spstd.NO_RESIDENT | spstd.EAGER])
+def test_degenerate_runs(n, flags):
+    # zero steps: the initial sample only and the state untouched
+    w = case(n, seed=3)
+    N = int(np.prod(n))
+    w.probes = np.array([0, N - 1], np.int64)           # first and last grid point
+    dt = oracle.stable_dt(*w.coeffs, w.V, w.n, w.dx)
+    p = spstd.plan_from_workload(w, dt=dt, nsteps_max=5, flags=flags)
+    ser, _ = p.run(0)
+    assert ser.shape == (1, 2, 2)
+    assert np.array_equal(ser[0, :, 0], w.psiR[[0, N - 1]]) and np.array_equal(ser[0, :, 1], w.psiI[[0, N - 1]])
+    r, i, step = p.get_state()
+    assert step == 0 and np.array_equal(r, w.psiR) and np.array_equal(i, w.psiI)
+    # probes at the ends of the grid follow the oracle over a few steps
+    ser, _ = p.run(5)
+    ro, io, so = oracle_run(w, dt, 5)
+    assert rel(ser, so) <= 1e-12
+    # no probes: the run still advances the state
+    w0 = case(n, seed=3)
+    w0.probes = np.zeros(0, np.int64)
+    q = spstd.plan_from_workload(w0, dt=dt, nsteps_max=5, flags=flags)
+    q.run(5)
+    r, i, step = q.get_state()
+    assert step == 5
+    assert rel(np.concatenate([r, i]), np.concatenate([ro, io])) <= 1e-12
+    # the zero state stays exactly zero; a zero potential with psi_I absent
+    w0.psiR = np.zeros(N)
+    w0.psiI = np.zeros(N)
+    z = spstd.plan_from_workload(w0, dt=dt, nsteps_max=5, flags=flags)
+    z.run(5)
+    r, i, _ = z.get_state()
+    assert not r.any() and not i.any()
+    wv = case(n, seed=4)
+    wv.V = np.zeros(N)
+    desc = spstd.make_desc(wv.n, wv.dx, *wv.coeffs, dt=dt, probes=wv.probes, flags=flags)
+    pv = spstd.Plan(desc, wv.V, wv.psiR, None, nsteps_max=5)
+    pv.run(5)
+    r, i, _ = pv.get_state()
+    ro, io, _, _ = oracle.run(wv.psiR, np.zeros(N), wv.V, wv.n, wv.dx, *wv.coeffs, dt, 5, wv.probes)
+    assert rel(np.concatenate([r, i]), np.concatenate([ro, io])) <= 1e-12
