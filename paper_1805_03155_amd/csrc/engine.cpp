@@ -197,8 +197,9 @@ static Layout layout_of(const spstd_desc* d, int64_t nsteps_max) {
         if (d->method == SPSTD_RK4) off += fb;
     }
     for (int a = 0; a < 3; ++a) {
+        // FP64 twiddle tables in every precision
         L.tw[a] = off;
-        if (a < d->ndim) off += align256((size_t)transform_len(*d, a) * 2 * esz);
+        if (a < d->ndim) off += align256((size_t)transform_len(*d, a) * 2 * sizeof(double));
     }
     L.pidx = off; off += align256(sizeof(int64_t) * (size_t)(d->nprobes > 0 ? d->nprobes : 1));
     L.probes = off;
@@ -589,6 +590,11 @@ static spstd_status plan_init(Plan* p, const double* V, const double* psiR0, con
     for (int a = 0; a < p->d.ndim; ++a) {
         // FP64 in every precision: the kernels round each twiddle once
         std::vector<double> t = twiddles(transform_len(p->d, a));
+        const size_t room = (a < 2 ? p->L.tw[a + 1] : p->L.pidx) - p->L.tw[a];
+        if (t.size() * 8 > room) {
+            p->err = "twiddle table larger than its workspace region";
+            return SPSTD_ERR_WORKSPACE;
+        }
         HIPCHK(hipMemcpyAsync(p->ws + p->L.tw[a], t.data(), t.size() * 8, hipMemcpyHostToDevice, p->st));
         HIPCHK(hipStreamSynchronize(p->st));
     }

@@ -69,6 +69,11 @@ def test_workspace_size_grows_with_probe_capacity_and_precision():
     assert b - a >= 9990 * 3 * 2 * 8 - 256      # 256-byte alignment of the buffer
     assert spstd.workspace_size(d32, 10) < a
     assert a >= 3 * 32 ** 3 * 8
+    # twiddle tables are FP64 (16 B per entry) in both precisions
+    for prec, esz in ((spstd.FP64, 8), (spstd.FP32, 4)):
+        for n in ((16384,), (1024, 512), (64, 32, 1024)):
+            d = spstd.make_desc(n, (0.1,) * len(n), *W.PAPER, precision=prec)
+            assert spstd.workspace_size(d, 0) >= 3 * int(np.prod(n)) * esz + 16 * sum(n)
 
 
 @pytest.mark.parametrize("bad", [dict(n=(24,), dx=(0.1,)), dict(n=(16, 2048), dx=(0.1, 0.1)),
