@@ -56,9 +56,9 @@ enum { SPSTD_LAP_SPECTRAL = 0, SPSTD_LAP_FD3 = 1 };  /* spatial second derivativ
                                                         instead of replaying step-chunk graphs */
 #define SPSTD_TIMING 0x4u                            /* flags: eager launches, each pass kernel
                                                         bracketed by HIP events (spstd_pass_times) */
-#define SPSTD_NO_RESIDENT 0x8u                       /* flags: 1D plans (and small 2D batches)
-                                                        use the pass kernels even where a
-                                                        resident kernel applies */
+#define SPSTD_NO_RESIDENT 0x8u                       /* flags: 1D and small 2D plans and
+                                                        batches use the pass kernels even
+                                                        where a resident kernel applies */
 #define SPSTD_AUTOTUNE 0x10u                         /* batch flags: time the candidate schedules
                                                         at creation and keep the faster */
 #define SPSTD_MAX_STAGES 16

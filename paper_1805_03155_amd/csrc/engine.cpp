@@ -431,13 +431,14 @@ static hipError_t enqueue_rk4_step(Plan* p) {
 
 static bool uses_resident(const Plan* p) {
     const spstd_desc& d = p->d;
-    return d.ndim == 1 && d.bc[0] == SPSTD_BC_PERIODIC && d.laplacian == SPSTD_LAP_SPECTRAL && d.neig == 0 &&
-           d.method == SPSTD_SYMPLECTIC && resident_len_ok(d.n[0]) &&
-           d.nprobes <= kResMaxProbes && d.m <= SPSTD_MAX_STAGES &&
+    const bool shape = (d.ndim == 1 && resident_len_ok(d.n[0])) ||
+                       (d.ndim == 2 && resident2d_ok(d.n[0], d.n[1]) && d.bc[1] == SPSTD_BC_PERIODIC);
+    return shape && d.bc[0] == SPSTD_BC_PERIODIC && d.laplacian == SPSTD_LAP_SPECTRAL && d.neig == 0 &&
+           d.method == SPSTD_SYMPLECTIC && d.nprobes <= kResMaxProbes && d.m <= SPSTD_MAX_STAGES &&
            !(d.flags & (SPSTD_NO_RESIDENT | SPSTD_TIMING));
 }
 
-// The resident kernel's one-entry instance table for a 1D plan.
+// The resident kernel's one-entry instance table for a 1D or small 2D plan.
 template <typename R>
 static spstd_status upload_resident_inst(Plan* p) {
     ResidentInst<R> I{};
@@ -449,13 +450,18 @@ static spstd_status upload_resident_inst(Plan* p) {
     I.capacity = p->nsteps_max + 1;
     I.nprobes = p->d.nprobes;
     for (int q = 0; q < p->d.nprobes; ++q) I.probe_idx[q] = p->probe_idx[q];
-    const double L = (double)p->d.n[0] * p->d.dx[0];
-    const double k1 = 2.0 * kPi / L;
-    const double kin = p->d.hbar / (2.0 * p->d.mass) * k1 * k1 / (double)p->d.n[0];
+    // kinetic scale per axis: (hbar/2m*) (2 pi/L)^2 / N for the bare k^2
+    double kin[2] = {0.0, 0.0};
+    for (int ax = 0; ax < p->d.ndim && ax < 2; ++ax) {
+        const double k1 = 2.0 * kPi / ((double)p->d.n[ax] * p->d.dx[ax]);
+        kin[ax] = p->d.hbar / (2.0 * p->d.mass) * k1 * k1 / (double)p->d.n[ax];
+    }
     for (int l = 0; l < p->d.m; ++l) {
         const double a = p->c[l] * p->dt, b = -p->dd[l] * p->dt;
-        I.kin[2 * l] = (R)(a * kin);
-        I.kin[2 * l + 1] = (R)(b * kin);
+        I.kin[2 * l] = (R)(a * kin[0]);
+        I.kin[2 * l + 1] = (R)(b * kin[0]);
+        I.kin_y[2 * l] = (R)(a * kin[1]);
+        I.kin_y[2 * l + 1] = (R)(b * kin[1]);
         I.pot[2 * l] = (R)(a / p->d.hbar);
         I.pot[2 * l + 1] = (R)(b / p->d.hbar);
     }
@@ -513,9 +519,12 @@ static spstd_status build_graph(Plan* p) {
 template <typename R>
 static spstd_status enqueue_steps(Plan* p, int64_t n) {
     if (uses_resident(p)) {
-        if (n > 0)
-            HIPCHK(launch_resident_1d<R>(p->d.n[0], reinterpret_cast<const ResidentInst<R>*>(p->ws + p->L.rinst),
-                                         1, p->d.m, n, p->d.nyquist, p->ws + p->L.tw[0], p->st));
+        const ResidentInst<R>* tab = reinterpret_cast<const ResidentInst<R>*>(p->ws + p->L.rinst);
+        if (n > 0 && p->d.ndim == 1)
+            HIPCHK(launch_resident_1d<R>(p->d.n[0], tab, 1, p->d.m, n, p->d.nyquist, p->ws + p->L.tw[0], p->st));
+        else if (n > 0)
+            HIPCHK(launch_resident_2d<R>(p->d.n[0], p->d.n[1], tab, 1, p->d.m, n, p->d.nyquist, p->ws + p->L.tw[0],
+                                         p->ws + p->L.tw[1], p->st));
         return SPSTD_OK;
     }
     const bool use_graph = !(p->d.flags & (SPSTD_EAGER | SPSTD_TIMING)) && n >= kGraphChunk;

@@ -22,7 +22,7 @@ LAP_SPECTRAL, LAP_FD3 = 0, 1
 ALLOW_UNSTABLE = 0x1
 EAGER = 0x2          # no step-chunk graphs
 TIMING = 0x4         # pass kernels bracketed by HIP events (pass_times)
-NO_RESIDENT = 0x8    # 1D plans and small 2D batches use the pass kernels, not a resident kernel
+NO_RESIDENT = 0x8    # 1D and small 2D plans/batches use the pass kernels, not a resident kernel
 AUTOTUNE = 0x10      # batches: time the candidate schedules at creation, keep the fastest
 PASS_KINDS = ("y", "z", "xab", "x", "yba")
 MAX_PROBES = 64

@@ -235,3 +235,27 @@ def test_degenerate_runs(n, flags):
     r, i, _ = pv.get_state()
     ro, io, _, _ = oracle.run(wv.psiR, np.zeros(N), wv.V, wv.n, wv.dx, *wv.coeffs, dt, 5, wv.probes)
     assert rel(np.concatenate([r, i]), np.concatenate([ro, io])) <= 1e-12
+
+
+@pytest.mark.parametrize("n", [(16, 16), (64, 32), (32, 64), (64, 64)])
+@pytest.mark.parametrize("prec", [spstd.FP64, spstd.FP32])
+def test_small_2d_plans_resident_vs_passes(n, prec):
+    # small periodic 2D plans run the LDS-resident kernel; the pass kernels
+    # give the same run, and a resumed run continues bitwise
+    steps = 30
+    w = case(n, seed=sum(n) + 7, steps=steps)
+    dt = oracle.stable_dt(*w.coeffs, w.V, w.n, w.dx)
+    a = gpu_run(w, dt, steps, precision=prec)
+    b = gpu_run(w, dt, steps, precision=prec, flags=spstd.NO_RESIDENT)
+    tol = 1e-13 if prec == spstd.FP64 else 2e-5
+    assert rel(np.concatenate(a[:2]), np.concatenate(b[:2])) < tol
+    assert rel(a[2], b[2]) < tol
+    p = spstd.plan_from_workload(w, dt=dt, nsteps_max=steps, precision=prec)
+    p.run(11)
+    r, i, s = p.get_state()
+    q = spstd.plan_from_workload(w, dt=dt, nsteps_max=steps, precision=prec)
+    q.set_state(r, i, s)
+    ser, _ = q.run(steps - 11)
+    r2, i2, _ = q.get_state()
+    assert np.array_equal(r2, a[0]) and np.array_equal(i2, a[1])
+    assert np.array_equal(ser[s:], a[2][s:])
