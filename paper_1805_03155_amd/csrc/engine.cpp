@@ -3,6 +3,7 @@
 // probe recording, norms, checkpoints and the RK4 comparison integrator.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <array>
 #include <cmath>
 #include <cstdio>
@@ -24,8 +25,12 @@ static const double kRK4Edge = 2.8284271247461900976;
 // ---------------------------------------------------------------------------
 // plan
 // ---------------------------------------------------------------------------
+// Rows of a plan's scale table: one per stage, the RK4 row, and the row of a
+// merged step boundary.
+static int scale_rows(const spstd_desc& d) { return d.m + 2; }
+
 struct Layout {
-    size_t psiR, psiI, V, rk[6], tw[3], pidx, probes, counter, partials, rinst, scales, eig, ecount, total;
+    size_t psiR, psiI, V, rk[6], tw[3], pidx, probes, counter, psave, partials, rinst, scales, eig, ecount, total;
 };
 
 static const int kNormBlocks = 256;
@@ -205,11 +210,13 @@ static Layout layout_of(const spstd_desc* d, int64_t nsteps_max) {
     L.probes = off;
     off += align256(sizeof(double) * 2 * (size_t)(d->nprobes > 0 ? d->nprobes : 1) * (size_t)(nsteps_max + 1));
     L.counter = off; off += 256;
+    // probe values saved around a merged step boundary: psi_R before, psi_I
+    L.psave = off; off += align256(sizeof(double) * 2 * SPSTD_MAX_PROBES);
     // norm partials, then the energy sums: kinetic per axis, potential, norm
     L.partials = off; off += align256(sizeof(double) * kNormBlocks * 6);
     L.rinst = off; off += align256(sizeof(ResidentInst<double>));
     // per-stage pass scales, then one row for the RK4 operator applications
-    L.scales = off; off += align256((size_t)(d->m + 1) * SC_COLS * esz);
+    L.scales = off; off += align256((size_t)scale_rows(*d) * SC_COLS * esz);
     // eigenstate accumulators: neig complex FP64 fields, then their step count
     L.eig = off; off += align256((size_t)d->neig * 2 * (size_t)N * sizeof(double));
     L.ecount = off; off += 256;
@@ -306,14 +313,50 @@ static hipError_t x_half(Plan* p, const R* src, R* dst, const ScaleRef& sc, int 
     return launch_x_acc<R>(p->d.n[0], src, dst, V, twx, rg, sc, kcol, pcol, p->d.nyquist, p->st);
 }
 
+// When the last stage of the set has no B half (d_m = 0), the A half that
+// ends a step and the A half that opens the next one act on psi_R with the
+// same psi_I (Eq. 18), so consecutive steps of one enqueue share them as a
+// single A half with coefficient c_m + c_1 (the scale row after the RK4
+// row), fused with the B half of stage 1.  The boundary state is never
+// formed; its probe samples are interpolated from psi_R around the merged
+// half (probes.hip).  Not with eigenstate sums (they need every step's
+// state) or the difference operator.
+static bool merges_steps(const Plan* p) {
+    const spstd_desc& d = p->d;
+    if (d.method != SPSTD_SYMPLECTIC || d.laplacian != SPSTD_LAP_SPECTRAL || p->eig_on || d.m < 2) return false;
+    const double cl = p->c[d.m - 1], c1 = p->c[0];
+    return p->dd[d.m - 1] == 0.0 && cl != 0.0 && c1 != 0.0 && cl + c1 != 0.0;
+}
+
+// Probe samples and eigenstate sums of a completed step.
 template <typename R>
-static hipError_t enqueue_symplectic_step(Plan* p) {
+static hipError_t step_end(Plan* p) {
+    hipError_t e = hipSuccess;
+    if (p->d.nprobes > 0)
+        e = launch_probe<R>(F<R>(p, p->L.psiR), F<R>(p, p->L.psiI), reinterpret_cast<const int64_t*>(p->ws + p->L.pidx),
+                            p->d.nprobes, reinterpret_cast<double*>(p->ws + p->L.probes),
+                            reinterpret_cast<int64_t*>(p->ws + p->L.counter), p->nsteps_max + 1, p->st);
+    if (e == hipSuccess && p->eig_on) {
+        e = launch_eig_acc<R>(F<R>(p, p->L.psiR), F<R>(p, p->L.psiI), p->N, p->eig, p->st);
+        if (e == hipSuccess) e = launch_count_tick(reinterpret_cast<int64_t*>(p->ws + p->L.ecount), p->st);
+    }
+    ev_break(p);
+    return e;
+}
+
+// k symplectic steps, each followed by its probe samples; with merge,
+// consecutive steps share their boundary A half (merges_steps).
+template <typename R>
+static hipError_t enqueue_symplectic_steps(Plan* p, int64_t k, bool merge) {
     R* pr = F<R>(p, p->L.psiR);
     R* pi = F<R>(p, p->L.psiI);
     const R* V = F<R>(p, p->L.V);
     const RowGeom rg{p->N / p->d.n[0], p->N / p->d.n[0]};
     const int64_t nx = p->d.n[0];
     const void* twx = p->ws + p->L.tw[0];
+    const int m = p->d.m, rows = scale_rows(p->d);
+    const int64_t* pidx = reinterpret_cast<const int64_t*>(p->ws + p->L.pidx);
+    double* save = reinterpret_cast<double*>(p->ws + p->L.psave);
     hipError_t e = hipSuccess;
     // The B half ends with the pass along axis fa (y, or z with
     // SPSTD_FUSE_AXIS=2) and the A half starts with it, so the pass owed by
@@ -322,60 +365,101 @@ static hipError_t enqueue_symplectic_step(Plan* p) {
     // on its own: the probes sample the completed step.
     const int fa = p->d.ndim == 3 ? SPSTD_FUSE_AXIS : 1, oa = 3 - fa;
     const bool fuse = p->d.ndim >= 2 && !walled(p, fa);
-    int owed = -1;   // stage whose B half still owes its pass along fa
-    auto owed_pass = [&](int stage) -> hipError_t {
-        const ScaleRef so{p->ws + p->L.scales, p->d.m + 1, stage};
+    int owed = -1;   // scale row whose B half still owes its pass along fa
+    auto owed_pass = [&](int row) -> hipError_t {
+        const ScaleRef so{p->ws + p->L.scales, rows, row};
         return axis_pass<R>(p, fa, pr, pi, so, SC_KXB + fa);
     };
-    for (int l = 0; l < p->d.m && e == hipSuccess; ++l) {
-        const bool a = p->c[l] != 0.0, b = p->dd[l] != 0.0;
-        const ScaleRef sc{p->ws + p->L.scales, p->d.m + 1, l};
+    // one stage: A half (a) with row's A columns, B half (b) with its B
+    // columns; boundary: a merged step boundary, whose probe samples are
+    // taken around it
+    auto stage = [&](int row, bool a, bool b, bool boundary) -> hipError_t {
+        const ScaleRef sc{p->ws + p->L.scales, rows, row};
+        const bool smp = boundary && p->d.nprobes > 0;
+        hipError_t r = hipSuccess;
         if (p->d.laplacian == SPSTD_LAP_FD3) {
-            if (a) e = fd_half<R>(p, pi, pr, sc, 0);
-            if (b && e == hipSuccess) e = fd_half<R>(p, pr, pi, sc, 1);
-            continue;
+            if (a) r = fd_half<R>(p, pi, pr, sc, 0);
+            if (b && r == hipSuccess) r = fd_half<R>(p, pr, pi, sc, 1);
+            return r;
+        }
+        if (smp) {
+            // psi_R before the merged A half (B passes leave it alone)
+            r = launch_probe_save<R>(pr, pidx, p->d.nprobes, save, p->st);
+            ev_break(p);
+            if (r != hipSuccess) return r;
         }
         if (a && owed >= 0) {
-            const ScaleRef so{p->ws + p->L.scales, p->d.m + 1, owed};
+            const ScaleRef so{p->ws + p->L.scales, rows, owed};
             {
                 PassTimer tm(p, SPSTD_PASS_YBA);
-                e = launch_axis_ba<R>(p->d.n[fa], pr, pi, p->ws + p->L.tw[fa], axis_geom_of(p->d, fa, 1), so, sc,
+                r = launch_axis_ba<R>(p->d.n[fa], pr, pi, p->ws + p->L.tw[fa], axis_geom_of(p->d, fa, 1), so, sc,
                                       SC_KXB + fa, SC_KXA + fa, p->d.nyquist, p->st);
             }
             owed = -1;
-            if (e == hipSuccess && p->d.ndim == 3) e = axis_pass<R>(p, oa, pi, pr, sc, SC_KXA + oa);
+            if (r == hipSuccess && p->d.ndim == 3) r = axis_pass<R>(p, oa, pi, pr, sc, SC_KXA + oa);
         } else {
             if (owed >= 0) {
-                e = owed_pass(owed);
+                r = owed_pass(owed);
                 owed = -1;
             }
-            if (a && e == hipSuccess) e = yz_passes<R>(p, pi, pr, sc, 0);
+            if (a && r == hipSuccess) r = yz_passes<R>(p, pi, pr, sc, 0);
         }
-        if (e != hipSuccess) break;
+        if (r != hipSuccess) return r;
+        if (smp) {
+            // psi_I of the boundary state: every B pass before it is done
+            r = launch_probe_save<R>(pi, pidx, p->d.nprobes, save + SPSTD_MAX_PROBES, p->st);
+            ev_break(p);
+            if (r != hipSuccess) return r;
+        }
         if (a && b && !walled(p, 0)) {
             PassTimer tm(p, SPSTD_PASS_XAB);
-            e = launch_x_ab<R>(nx, pr, pi, V, twx, rg, sc, p->d.nyquist, p->st);
+            r = launch_x_ab<R>(nx, pr, pi, V, twx, rg, sc, p->d.nyquist, p->st);
         } else {
             if (a) {
                 PassTimer tm(p, SPSTD_PASS_X);
-                e = x_half<R>(p, pi, pr, sc, SC_KXA, SC_PA);
+                r = x_half<R>(p, pi, pr, sc, SC_KXA, SC_PA);
             }
-            if (b && e == hipSuccess) {
+            if (b && r == hipSuccess) {
                 PassTimer tm(p, SPSTD_PASS_X);
-                e = x_half<R>(p, pr, pi, sc, SC_KXB, SC_PB);
+                r = x_half<R>(p, pr, pi, sc, SC_KXB, SC_PB);
             }
         }
-        if (e != hipSuccess) break;
+        if (r != hipSuccess) return r;
+        if (smp) {
+            const double w = p->c[m - 1] / (p->c[m - 1] + p->c[0]);
+            r = launch_probe_merged<R>(pr, pidx, p->d.nprobes, save, save + SPSTD_MAX_PROBES, w,
+                                       reinterpret_cast<double*>(p->ws + p->L.probes),
+                                       reinterpret_cast<int64_t*>(p->ws + p->L.counter), p->nsteps_max + 1, p->st);
+            ev_break(p);
+            if (r != hipSuccess) return r;
+        }
         if (b) {
             if (fuse) {
-                if (p->d.ndim == 3) e = axis_pass<R>(p, oa, pr, pi, sc, SC_KXB + oa);
-                owed = l;
+                if (p->d.ndim == 3) r = axis_pass<R>(p, oa, pr, pi, sc, SC_KXB + oa);
+                owed = row;
             } else {
-                e = yz_passes<R>(p, pr, pi, sc, 1);
+                r = yz_passes<R>(p, pr, pi, sc, 1);
             }
         }
+        return r;
+    };
+    for (int64_t s = 0; s < k && e == hipSuccess; ++s) {
+        const bool head = merge && s > 0;        // stage 1's A half ran at the boundary before
+        const bool tail = merge && s + 1 < k;    // the last A half runs merged with the next
+        ev_break(p);
+        for (int l = head ? 1 : 0; l < m && e == hipSuccess; ++l) {
+            if (l == m - 1 && tail)
+                e = stage(m + 1, true, p->dd[0] != 0.0, true);
+            else
+                e = stage(l, p->c[l] != 0.0, p->dd[l] != 0.0, false);
+        }
+        if (e != hipSuccess || tail) continue;
+        if (owed >= 0) {
+            e = owed_pass(owed);
+            owed = -1;
+        }
+        if (e == hipSuccess) e = step_end<R>(p);
     }
-    if (e == hipSuccess && owed >= 0) e = owed_pass(owed);
     return e;
 }
 
@@ -383,7 +467,7 @@ static hipError_t enqueue_symplectic_step(Plan* p) {
 // the scale table holds coefficient +1 in its A columns and -1 in its B columns
 template <typename R>
 static hipError_t apply_K(Plan* p, const R* src, R* kout, double coef) {
-    const ScaleRef sc{p->ws + p->L.scales, p->d.m + 1, p->d.m};
+    const ScaleRef sc{p->ws + p->L.scales, scale_rows(p->d), p->d.m};
     const int ab = coef > 0.0 ? 0 : 1;
     hipError_t e = launch_fill0<R>(p->N, kout, p->st);
     ev_break(p);
@@ -473,20 +557,18 @@ static spstd_status upload_resident_inst(Plan* p) {
 template <typename R>
 static hipError_t enqueue_steps_eager(Plan* p, int64_t n) {
     hipError_t e = hipSuccess;
+    if (p->d.method == SPSTD_SYMPLECTIC) {
+        // in chunks of the graph's length, so that eager and graph-replayed
+        // runs merge the same step boundaries
+        const bool merge = merges_steps(p);
+        for (int64_t done = 0; done < n && e == hipSuccess; done += kGraphChunk)
+            e = enqueue_symplectic_steps<R>(p, std::min<int64_t>(kGraphChunk, n - done), merge);
+        return e;
+    }
     for (int64_t s = 0; s < n && e == hipSuccess; ++s) {
         ev_break(p);
-        e = (p->d.method == SPSTD_RK4) ? enqueue_rk4_step<R>(p) : enqueue_symplectic_step<R>(p);
-        if (e == hipSuccess && p->d.nprobes > 0)
-            e = launch_probe<R>(F<R>(p, p->L.psiR), F<R>(p, p->L.psiI),
-                                reinterpret_cast<const int64_t*>(p->ws + p->L.pidx), p->d.nprobes,
-                                reinterpret_cast<double*>(p->ws + p->L.probes),
-                                reinterpret_cast<int64_t*>(p->ws + p->L.counter), p->nsteps_max + 1,
-                                p->st);
-        if (e == hipSuccess && p->eig_on) {
-            e = launch_eig_acc<R>(F<R>(p, p->L.psiR), F<R>(p, p->L.psiI), p->N, p->eig, p->st);
-            if (e == hipSuccess) e = launch_count_tick(reinterpret_cast<int64_t*>(p->ws + p->L.ecount), p->st);
-        }
-        ev_break(p);
+        e = enqueue_rk4_step<R>(p);
+        if (e == hipSuccess) e = step_end<R>(p);
     }
     return e;
 }
@@ -608,12 +690,17 @@ static spstd_status plan_init(Plan* p, const double* V, const double* psiR0, con
         HIPCHK(hipStreamSynchronize(p->st));
     }
     {
-        // stage rows (A coefficient c_l dt, B coefficient -d_l dt), then the RK4 row (+1, -1)
-        const int rows = p->d.m + 1;
+        // stage rows (A coefficient c_l dt, B coefficient -d_l dt), the RK4
+        // row (+1, -1), then the merged step-boundary row: A (c_m + c_1) dt,
+        // B of stage 1
+        const int rows = scale_rows(p->d);
         std::vector<double> tab((size_t)rows * SC_COLS, 0.0);
         for (int l = 0; l < p->d.m && p->d.method == SPSTD_SYMPLECTIC; ++l)
             scale_row(p->d, p->c[l] * p->dt, -p->dd[l] * p->dt, &tab[(size_t)l * SC_COLS]);
         scale_row(p->d, 1.0, -1.0, &tab[(size_t)p->d.m * SC_COLS]);
+        if (p->d.method == SPSTD_SYMPLECTIC && p->d.m >= 2)
+            scale_row(p->d, (p->c[p->d.m - 1] + p->c[0]) * p->dt, -p->dd[0] * p->dt,
+                      &tab[(size_t)(p->d.m + 1) * SC_COLS]);
         std::vector<R> tr(tab.size());
         for (size_t i = 0; i < tab.size(); ++i) tr[i] = (R)tab[i];
         HIPCHK(hipMemcpyAsync(p->ws + p->L.scales, tr.data(), tr.size() * sizeof(R), hipMemcpyHostToDevice, p->st));

@@ -90,6 +90,17 @@ hipError_t launch_probe(const R* psiR, const R* psiI, const int64_t* idx,
                         int nprobes, double* out, int64_t* counter,
                         int64_t capacity, hipStream_t st);
 
+// Merged step boundary (the last A half of a step and the first A half of
+// the next as one): save[p] = psi[idx_p] as doubles; then the sample
+// out[slot][p] = (saveR_p + w (psiR[idx_p] - saveR_p), saveI_p), slot =
+// *counter, then (*counter)++.  Single thread block, nprobes 1..64.
+template <typename R>
+hipError_t launch_probe_save(const R* psi, const int64_t* idx, int nprobes, double* save, hipStream_t st);
+template <typename R>
+hipError_t launch_probe_merged(const R* psiR, const int64_t* idx, int nprobes, const double* saveR,
+                               const double* saveI, double w, double* out, int64_t* counter, int64_t capacity,
+                               hipStream_t st);
+
 // per-block FP64 partial sums of psiR^2 + psiI^2 (fixed order)
 template <typename R>
 hipError_t launch_norm_partials(const R* psiR, const R* psiI, int64_t n,

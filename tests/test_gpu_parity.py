@@ -259,3 +259,31 @@ def test_small_2d_plans_resident_vs_passes(n, prec):
     r2, i2, _ = q.get_state()
     assert np.array_equal(r2, a[0]) and np.array_equal(i2, a[1])
     assert np.array_equal(ser[s:], a[2][s:])
+
+
+@pytest.mark.parametrize("name", ["forest_ruth", "yoshida6"])
+@pytest.mark.parametrize("n", [(32, 16, 64), (64, 32), (256,)])
+@pytest.mark.parametrize("prec", [spstd.FP64, spstd.FP32])
+def test_merged_step_boundaries(name, n, prec):
+    # sets whose last stage has no B half run the A half ending a step and
+    # the one opening the next as one (coefficient c_m + c_1); the boundary
+    # probe samples are interpolated.  40 steps: two graph chunks of 16 and
+    # 8 eager steps; eager launches merge the same boundaries
+    steps = 40
+    w = case(n, seed=len(n) * 11 + 5, steps=steps, coeffs=W.COEFFS[name])
+    dt = oracle.stable_dt(*w.coeffs, w.V, w.n, w.dx)
+    base = spstd.NO_RESIDENT if len(n) == 1 else 0
+    g = gpu_run(w, dt, steps, precision=prec, flags=base)
+    ea = gpu_run(w, dt, steps, precision=prec, flags=base | spstd.EAGER)
+    assert np.array_equal(g[0], ea[0]) and np.array_equal(g[1], ea[1]) and np.array_equal(g[2], ea[2])
+    ro, io, so = oracle_run(w, dt, steps)
+    tol = 1e-12 if prec == spstd.FP64 else 2e-5
+    assert rel(np.concatenate(g[:2]), np.concatenate([ro, io])) <= tol
+    assert rel(g[2], so) <= tol
+    # split over two calls (other boundaries merged): the same run
+    p = spstd.plan_from_workload(w, precision=prec, dt=dt, nsteps_max=steps, flags=base)
+    p.run(13)
+    ser, _ = p.run(steps - 13)
+    r, i, _ = p.get_state()
+    assert rel(np.concatenate([r, i]), np.concatenate([ro, io])) <= tol
+    assert rel(ser, so) <= tol

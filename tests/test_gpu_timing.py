@@ -72,3 +72,18 @@ def test_rk4_pass_counts():
     assert t["y"][0] == t["z"][0] == t["x"][0] == 8 * steps
     assert t["xab"][0] == t["yba"][0] == 0
     assert all(t[k][1] > 0.0 for k in ("y", "z", "x"))
+
+
+def test_merged_boundaries_pass_counts():
+    # Yoshida-6 ends on an A-only stage: within a chunk of 16 steps the 15
+    # boundaries between steps each run one A half (y, z, x) instead of two
+    steps = 16
+    w = case((32, 16, 16), coeffs=W.YOSHIDA6)
+    p = spstd.plan_from_workload(w, nsteps_max=steps, flags=spstd.TIMING)
+    p.step(steps)
+    t = p.pass_times()
+    per_step = {"y": 1, "z": 15, "xab": 7, "x": 1, "yba": 7}
+    saved = {"y": 15, "z": 15, "x": 15, "xab": 0, "yba": 0}
+    for kind, count in per_step.items():
+        assert t[kind][0] == count * steps - saved[kind], (kind, t[kind])
+
