@@ -88,3 +88,13 @@ def test_infinite_well_levels_are_the_sine_ladder():
     for k, e in enumerate(E, start=1):
         want = modal.theta(c, d, 0.5 * (np.pi * k / L) ** 2 * dt) / dt
         assert abs(e / want - 1.0) < 5e-5
+
+
+@pytest.mark.parametrize("n,L,bc", [((32, 16, 16), (6.0, 5.0, 5.0), (D, P, N)), ((64, 32), (8.0, 6.0), (N, D))])
+def test_walled_yoshida6_merged_boundaries(n, L, bc):
+    # Yoshida-6 ends on an A-only stage: consecutive steps share their
+    # boundary A half (two graph chunks of 16 and 8 eager steps)
+    w = W.walled_box(seed=23, n=n, L=L, bc=bc, V0=3.0, coeffs=W.YOSHIDA6)
+    (r, i, s), (ro, io, so), _ = both(w, 40)
+    assert rel(np.concatenate([r, i]), np.concatenate([ro, io])) <= 1e-12
+    assert np.abs(s - so).max() <= 1e-12 * np.abs(w.psiR).max()
