@@ -6,8 +6,10 @@ Workload: the 3D isotropic harmonic oscillator on a 256^3 periodic grid over
 Yoshida sixth-order 8-stage symplectic set (15 non-zero substeps per step),
 dt = 0.5 x the stability limit, 3 probes.  One "step" is one full time step
 of the hot path (every directional pass of every stage plus the probe
-sample).  A stage update is one A plus one B substep at one grid point, so a
-step is 7.5 stage updates per point.
+sample); the set's last stage has no B half, so within each chunk of 16
+steps the A half ending one step and the A half opening the next run as one
+(exact: they see the same psi_I).  A stage update is one A plus one B
+substep at one grid point, so a step is 7.5 stage updates per point.
 
 The timed region runs with per-pass HIP events on the plan's stream; the
 dominant kernel's average duration gives the roofline entry.  The CPU oracle
@@ -348,7 +350,9 @@ def main():
                                "Yoshida-6 8-stage symplectic set, dt = 0.5 x stability limit, "
                                "3 probes",
                    "grid": [args.n] * 3, "stage_updates_per_step": r64["stage_updates_per_step"],
-                   "dt": r64["dt"], "execution": "eager launches with per-pass HIP events"},
+                   "dt": r64["dt"], "execution": "eager launches with per-pass HIP events",
+                   "step_boundaries": "A halves of consecutive steps applied as one within 16-step chunks "
+                                      "(the set's last stage has no B half)"},
         "roofline": r64["roofline"],
         "cpu_baseline": cpu,
         "kernels": r64["kernels"],
