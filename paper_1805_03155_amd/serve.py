@@ -124,9 +124,14 @@ class Server:
             return None
         n, prec = key
         stream = self.torch.cuda.Stream(device=self.device)
+        # 1D classes choose between the resident kernel and the pass kernels
+        # by timing both (up to 25% apart); for 3D classes only the block
+        # size is open (about 2%), and timing a full 128^3 class takes a
+        # second during which the loop does not tick
+        flags = spstd.AUTOTUNE if len(n) == 1 else 0
         b = spstd.Batch(n, self.coeffs, capacity=int(cap), nprobes=self.nprobes,
                         nsteps_max=self.max_steps, precision=prec, device=self.device,
-                        stream=stream, flags=spstd.AUTOTUNE)
+                        stream=stream, flags=flags)
         nbytes = b.ws.numel()
         c = _Class(key, b, stream, nbytes)
         self.classes[key] = c
