@@ -118,7 +118,18 @@ def run_precision(w, prec, steps, warmup):
     del q
     pcie = {"plan_setup_s": setup_s, "readback_s": readback_s,
             "value_including_transfers": su_per_step * steps / (el + setup_s + readback_s)}
-    return {"value": su_per_step * steps / el, "ms_per_step": el / steps * 1e3, "host_transfers": pcie,
+    # whole-step byte accounting: the passes' algorithmic bytes over the
+    # timed steps, and the per-axis 3D FFT schedule model (192 B per stage
+    # update in FP64, 96 B in FP32) at the measured rate
+    rate = su_per_step * steps / el
+    step_bytes = sum(v[0] * v[2] for v in kinds.values()) / steps
+    model_b = 192.0 if prec == "fp64" else 96.0
+    step_model = {"engine_bytes_per_stage_update": step_bytes / su_per_step,
+                  "engine_GBps_over_step": step_bytes / (el / steps) / 1e9,
+                  "engine_frac_over_step": step_bytes / (el / steps) / 1e9 / HBM_PEAK_GBS,
+                  "schedule_model_bytes_per_stage_update": model_b,
+                  "schedule_model_frac": model_b * rate / (HBM_PEAK_GBS * 1e9)}
+    return {"value": rate, "ms_per_step": el / steps * 1e3, "host_transfers": pcie, "bytes": step_model,
             "roofline": roof, "kernels": per_kernel, "dt": info.dt,
             "graph_mode": {"value": su_per_step * steps / (g1 - g0),
                            "ms_per_step": (g1 - g0) / steps * 1e3},
@@ -356,6 +367,7 @@ def main():
         "roofline": r64["roofline"],
         "cpu_baseline": cpu,
         "kernels": r64["kernels"],
+        "bytes": r64["bytes"],
         "graph_mode": r64["graph_mode"],
         "host_transfers": r64["host_transfers"],
         "batching": batch,
@@ -363,6 +375,7 @@ def main():
         "fp32": {"value": r32["value"], "ms_per_step": r32["ms_per_step"], "dtype": "f32",
                  "roofline": r32["roofline"], "kernels": r32["kernels"],
                  "graph_mode": r32["graph_mode"], "host_transfers": r32["host_transfers"],
+                 "bytes": r32["bytes"],
                  "speedup_vs_fp64": r32["value"] / r64["value"]},
     }
     print(json.dumps(line), flush=True)
