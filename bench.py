@@ -178,7 +178,7 @@ def serving_leg(count, rate, steps, seed=0, budget_gb=64):
     srv = serve.Server(hbm_budget=budget_gb << 30, chunk=512, max_slots=64,
                        max_steps=steps[1], keep_series=False)
     t0 = time.perf_counter()
-    srv.run(reqs)
+    srv.run(reqs, progress=lambda t, k, n: log(f"  serving: {k}/{n} finished at {t:.0f} s"))
     el = time.perf_counter() - t0
     out = serve.latency_summary(reqs, el, srv.stage_updates)
     out.update({"rate_per_s": rate, "steps_range": list(steps), "budget_GB": budget_gb,
@@ -186,9 +186,10 @@ def serving_leg(count, rate, steps, seed=0, budget_gb=64):
     return out
 
 
-def serving_sweep(count, rates, steps, budgets_gb=(64,), small_budget_gb=2, small_rate=30.0):
+def serving_sweep(count, rates, steps, budgets_gb=(64,), small_budget_gb=2, small_rate=30.0, small=True):
     """The serving workload at several offered rates (same seeded request
-    mix at each rate), plus one run whose HBM budget forces queueing."""
+    mix at each rate), plus (small) one run whose HBM budget forces
+    queueing."""
     out = []
     for rate in rates:
         log(f"serving sweep: {count} requests at {rate}/s")
@@ -196,6 +197,8 @@ def serving_sweep(count, rates, steps, budgets_gb=(64,), small_budget_gb=2, smal
         r["offered_per_s"] = rate
         out.append(r)
         log(f"  p50 {r['p50_s']:.2f} s, p99 {r['p99_s']:.2f} s, {r['completed_per_s']:.2f} done/s")
+    if not small:
+        return out
     log(f"serving sweep: {count} requests at {small_rate}/s under a {small_budget_gb} GB budget")
     r = serving_leg(count, small_rate, steps, budget_gb=small_budget_gb)
     r["offered_per_s"] = small_rate
@@ -304,6 +307,10 @@ def main():
     ap.add_argument("--study-steps", type=int, default=100000)
     ap.add_argument("--serve-sweep", action="store_true",
                     help="serving at offered rates 10..1000/s instead of the timing line")
+    ap.add_argument("--serve-rates", default="10,30,100,300,1000",
+                    help="offered rates of --serve-sweep (requests/s, comma-separated)")
+    ap.add_argument("--no-small-budget", action="store_true",
+                    help="--serve-sweep without the small-budget run")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: this engine has no multi-GPU path "
@@ -323,7 +330,8 @@ def main():
         print(json.dumps(precision_study(w, args.study, args.study_steps)), flush=True)
         return
     if args.serve_sweep:
-        sweep = serving_sweep(args.serve_requests, (10.0, 30.0, 100.0, 300.0, 1000.0), (2000, 20000))
+        rates = tuple(float(x) for x in args.serve_rates.split(","))
+        sweep = serving_sweep(args.serve_requests, rates, (2000, 20000), small=not args.no_small_budget)
         print(json.dumps({"serving_sweep": sweep}), flush=True)
         return
     res = {}

@@ -229,12 +229,18 @@ class Server:
     def busy(self):
         return bool(self.waiting) or any(c.slots for c in self.classes.values())
 
-    def run(self, requests, time_limit=None):
+    def run(self, requests, time_limit=None, progress=None, progress_every=20.0):
         """Serve requests whose ``arrival`` times are offsets on the server's
-        clock; returns them when all have finished (or at the time limit)."""
+        clock; returns them when all have finished (or at the time limit).
+        ``progress(now, finished, total)`` is called every ``progress_every``
+        seconds if given."""
         pending = deque(sorted(requests, key=lambda r: r.arrival))
         self.t0 = time.perf_counter()
+        next_report = progress_every
         while pending or self.busy():
+            if progress is not None and self.now() >= next_report:
+                progress(self.now(), len(self.finished), len(requests))
+                next_report += progress_every
             t = self.now()
             while pending and pending[0].arrival <= t:
                 self.submit(pending.popleft())
