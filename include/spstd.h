@@ -61,6 +61,10 @@ enum { SPSTD_LAP_SPECTRAL = 0, SPSTD_LAP_FD3 = 1 };  /* spatial second derivativ
                                                         where a resident kernel applies */
 #define SPSTD_AUTOTUNE 0x10u                         /* batch flags: time the candidate schedules
                                                         at creation and keep the faster */
+#define SPSTD_NO_MERGE 0x20u                         /* flags: keep every step boundary even where
+                                                        the last stage has no B half (then a run
+                                                        split over calls equals the unsplit run
+                                                        bitwise) */
 #define SPSTD_MAX_STAGES 16
 #define SPSTD_MAX_PROBES 64
 #define SPSTD_MAX_EIG 8
@@ -91,10 +95,15 @@ enum { SPSTD_LAP_SPECTRAL = 0, SPSTD_LAP_FD3 = 1 };  /* spatial second derivativ
  *                term removed, as Eq. (10) read literally (two first
  *                derivatives, real part kept after each inverse transform).
  *   nprobes      0..64 probe points; probe_idx (host) their linear indices.
- *   flags        SPSTD_ALLOW_UNSTABLE, SPSTD_EAGER, SPSTD_TIMING, SPSTD_NO_RESIDENT
- *                (OR-ed), or 0.  Periodic 1D symplectic plans with at most 8
- *                probes (and no SPSTD_TIMING) run each spstd_step call as one
- *                launch of a kernel that keeps the grid on chip.
+ *   flags        SPSTD_ALLOW_UNSTABLE, SPSTD_EAGER, SPSTD_TIMING, SPSTD_NO_RESIDENT,
+ *                SPSTD_NO_MERGE
+ *                (OR-ed), or 0.  Periodic spectral symplectic plans in 1D,
+ *                or in 2D with n_x, n_y in {16, 32, 64}, with at most 8
+ *                probes, no eigenstate sums and no SPSTD_TIMING run each
+ *                spstd_step call as one launch of a kernel that keeps the
+ *                grid on chip.  Where the last stage has no B half, the A
+ *                halves at the boundaries between the steps of one call run
+ *                as one (unless SPSTD_NO_MERGE).
  *   bc[3]        boundary per axis (Sec. 2.2, last paragraph):
  *                SPSTD_BC_PERIODIC (DFT; sample j at j * dx), or walls at
  *                x = 0 and x = L_d with samples at cell centres (j + 1/2) dx:

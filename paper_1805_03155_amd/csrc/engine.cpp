@@ -323,7 +323,9 @@ static hipError_t x_half(Plan* p, const R* src, R* dst, const ScaleRef& sc, int 
 // state) or the difference operator.
 static bool merges_steps(const Plan* p) {
     const spstd_desc& d = p->d;
-    if (d.method != SPSTD_SYMPLECTIC || d.laplacian != SPSTD_LAP_SPECTRAL || p->eig_on || d.m < 2) return false;
+    if (d.method != SPSTD_SYMPLECTIC || d.laplacian != SPSTD_LAP_SPECTRAL || p->eig_on || d.m < 2 ||
+        (d.flags & SPSTD_NO_MERGE))
+        return false;
     const double cl = p->c[d.m - 1], c1 = p->c[0];
     return p->dd[d.m - 1] == 0.0 && cl != 0.0 && c1 != 0.0 && cl + c1 != 0.0;
 }

@@ -287,3 +287,12 @@ def test_merged_step_boundaries(name, n, prec):
     r, i, _ = p.get_state()
     assert rel(np.concatenate([r, i]), np.concatenate([ro, io])) <= tol
     assert rel(ser, so) <= tol
+    # without merging, a split run equals the unsplit one bitwise
+    nm = base | spstd.NO_MERGE
+    u = gpu_run(w, dt, steps, precision=prec, flags=nm)
+    assert rel(np.concatenate(u[:2]), np.concatenate([ro, io])) <= tol
+    q = spstd.plan_from_workload(w, precision=prec, dt=dt, nsteps_max=steps, flags=nm)
+    q.run(13)
+    ser, _ = q.run(steps - 13)
+    r, i, _ = q.get_state()
+    assert np.array_equal(r, u[0]) and np.array_equal(i, u[1]) and np.array_equal(ser, u[2])
