@@ -98,3 +98,44 @@ def test_walled_yoshida6_merged_boundaries(n, L, bc):
     (r, i, s), (ro, io, so), _ = both(w, 40)
     assert rel(np.concatenate([r, i]), np.concatenate([ro, io])) <= 1e-12
     assert np.abs(s - so).max() <= 1e-12 * np.abs(w.psiR).max()
+
+
+@pytest.mark.parametrize("shape", [(16,), (16, 16)])
+def test_si_units_dirichlet_well_levels_at_bin_resolution(shape):
+    # the setting of the paper's well runs (Sec. 3.1-3.2) on a power-of-two
+    # grid: cells of 0.1 nm between Dirichlet walls, SI units (hbar, m_e),
+    # dt = (m*/4D hbar) dx^2, 1024 steps, a unit source off-centre with the
+    # probe on it.  Series and extracted levels against the oracle; in 1D the
+    # levels against the closed form hbar theta(x_k)/dt, x_k = (hbar/2m*)
+    # (k pi/L)^2 dt, within a small fraction of a frequency bin (in 2D the
+    # degenerate and nearly degenerate modes of the box share bins)
+    hb, me = 1.054571817e-34, 9.1093837015e-31
+    dx, nsteps = 1e-10, 1024
+    n = shape[0]
+    L = n * dx
+    dt = 0.25 / len(shape) * me / hb * dx ** 2
+    N = int(np.prod(shape))
+    src = 9 if len(shape) == 1 else 9 * n + 6
+    psi = np.zeros(N)
+    psi[src] = 1.0
+    w = W.Workload("si_well", shape, (dx,) * len(shape), (0.0,) * len(shape), np.zeros(N), psi,
+                   np.zeros(N), np.array([src], np.int64), nsteps, W.PAPER, hbar=hb, mass=me,
+                   bc=(D,) * len(shape))
+    p = spstd.plan_from_workload(w, dt=dt, nsteps_max=nsteps)
+    s, _ = p.run(nsteps)
+    r, i, _ = p.get_state()
+    ro, io, so, _ = oracle.run(w.psiR, w.psiI, w.V, w.n, w.dx, *w.coeffs, dt, nsteps, w.probes,
+                               hbar=hb, mass=me, bc=w.bc)
+    assert rel(np.concatenate([r, i]), np.concatenate([ro, io])) <= 1e-12
+    assert np.abs(s - so).max() <= 1e-12
+    E, _ = spstd.spectrum(s, dt, hbar=hb, nlevels=8)
+    Eo, _ = spectrum.extract(so, dt, hb, 8)
+    assert len(E) == len(Eo) >= 6
+    assert np.abs(E / Eo - 1.0).max() <= 1e-9
+    if len(shape) == 1:
+        c, d = W.PAPER
+        dw = 2 * np.pi / (nsteps * dt)
+        closed = np.array([modal.theta(c, d, hb / (2 * me) * (np.pi * k / L) ** 2 * dt) / dt
+                           for k in range(1, n + 1)])
+        for e in E:
+            assert np.abs(closed - e / hb).min() / dw < 0.06
