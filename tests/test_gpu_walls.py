@@ -24,13 +24,13 @@ def rel(a, b):
 
 
 def both(w, steps, precision=spstd.FP64, method=spstd.SYMPLECTIC, nyquist=spstd.NYQ_FULL, dt=None):
-    dt = dt or oracle.stable_dt(*w.coeffs, w.V, w.n, w.dx)
+    dt = dt or oracle.stable_dt(*w.coeffs, w.V, w.n, w.dx, w.hbar, w.mass)
     p = spstd.plan_from_workload(w, precision=precision, method=method, dt=dt, nsteps_max=steps,
                                  nyquist=nyquist)
     ser, _ = p.run(steps)
     r, i, _ = p.get_state()
     ro, io, so, _ = oracle.run(w.psiR, w.psiI, w.V, w.n, w.dx, *w.coeffs, dt, steps, w.probes,
-                               nyquist=nyquist, method=method, bc=w.bc)
+                               hbar=w.hbar, mass=w.mass, nyquist=nyquist, method=method, bc=w.bc)
     return (r, i, ser), (ro, io, so), p
 
 
