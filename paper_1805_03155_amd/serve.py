@@ -79,7 +79,7 @@ class Server:
 
     def __init__(self, hbm_budget, coeffs=W.PAPER, chunk=512, max_slots=64, max_steps=20000,
                  nprobes=1, device="cuda", keep_series=True, resident_chunk=2048,
-                 max_concurrent=8):
+                 max_concurrent=6):
         import torch
         self.torch = torch
         self.budget = int(hbm_budget)
