@@ -39,8 +39,11 @@ bool row_len_ok(int64_t n) { return n >= 16 && n <= 16384 && (n & (n - 1)) == 0;
 //   YZ_PPL_F64, YZ_MIN_WAVES, YZ_NT  y/z pass variants measured slower
 //                  (two pencils per FP64 lane group, a forced 4 waves per
 //                  SIMD, non-temporal loads and stores)
-//   X_RELOAD       x passes re-read their inputs in the epilogue instead of
-//                  keeping them in registers through the transforms
+//   X_RELOAD, X_RELOAD_FROM  x passes re-read their inputs in the epilogue
+//                  instead of keeping them in registers through the
+//                  transforms, for all lengths or from X_RELOAD_FROM points
+//                  (16384: FP32 batch of 33 such rows 196 -> 178 us per
+//                  step; 8192 slower, 84 -> 93 us)
 //   MIN_WAVES      minimum waves per SIMD requested for the pass kernels (2
 //                  keeps the FP64 x passes of 512..2048-point rows out of
 //                  accumulation registers, at one wave per SIMD otherwise)
@@ -90,6 +93,9 @@ bool row_len_ok(int64_t n) { return n >= 16 && n <= 16384 && (n & (n - 1)) == 0;
 #endif
 #ifndef SPSTD_SPLIT_XAB_F32
 #define SPSTD_SPLIT_XAB_F32 0
+#endif
+#ifndef SPSTD_X_RELOAD_FROM
+#define SPSTD_X_RELOAD_FROM 16384
 #endif
 #ifndef SPSTD_X_RELOAD
 #define SPSTD_X_RELOAD 0
@@ -229,6 +235,13 @@ __device__ __forceinline__ R load_v(const R* p) {
     if constexpr (tuning<R>::V_NT) return __builtin_nontemporal_load(p);
     else return *p;
 }
+
+// x passes re-read their inputs in the epilogue (instead of keeping them in
+// registers through the transforms) for every length with X_RELOAD, else
+// from X_RELOAD_FROM points: a 16384-point row runs 1024 lanes per block,
+// which caps a lane at 128 registers
+template <int N>
+constexpr bool x_reload() { return SPSTD_X_RELOAD || N >= SPSTD_X_RELOAD_FROM; }
 
 // Compiler-only memory barrier: values loaded before it are not reused
 // after it (the epilogues re-read their inputs rather than keep them live
@@ -645,23 +658,20 @@ __global__ __launch_bounds__((row_map<R, N, WPB>::THREADS)) SPSTD_WAVES_ATTR voi
     R* __restrict__ db = dst + b;
     const R* __restrict__ Vb = V + b;
     const int o0 = L.off, o1 = L.off + N;
+    constexpr bool RL = x_reload<N>();
     cpx<R> v[1][16];
-#if !SPSTD_X_RELOAD
-    R f0[16], f1[16];
-#endif
+    R f0[RL ? 1 : 16], f1[RL ? 1 : 16];
 #pragma unroll
     for (int e = 0; e < 16; ++e) {
         const R a = v0 ? sb[o0 + C::T * e] : (R)0;
         const R c = v1 ? sb[o1 + C::T * e] : (R)0;
         v[0][e] = cpx<R>{a, c};
-#if !SPSTD_X_RELOAD
-        f0[e] = a;
-        f1[e] = c;
-#endif
+        if constexpr (!RL) {
+            f0[e] = a;
+            f1[e] = c;
+        }
     }
-#if SPSTD_X_RELOAD
-    reload_fence();
-#endif
+    if constexpr (RL) reload_fence();
     R* l0 = lds + L.pin_block * M::SL;
     fft_pencils<R, N, false, C::WAVE, M::SPLIT, TU::PRODUCTS, 1, 1>(v, j, l0, M::SL, tw);
     apply_k2<R, N>(v[0], j, nyq_zero);
@@ -672,12 +682,14 @@ __global__ __launch_bounds__((row_map<R, N, WPB>::THREADS)) SPSTD_WAVES_ATTR voi
 #pragma unroll
     for (int e = 0; e < 16; ++e) {
         const int i0 = o0 + C::T * e, i1 = o1 + C::T * e;
-#if SPSTD_X_RELOAD
-        const R a = v0 ? sb[i0] : (R)0;
-        const R c = v1 ? sb[i1] : (R)0;
-#else
-        const R a = f0[e], c = f1[e];
-#endif
+        R a, c;
+        if constexpr (RL) {
+            a = v0 ? sb[i0] : (R)0;
+            c = v1 ? sb[i1] : (R)0;
+        } else {
+            a = f0[e];
+            c = f1[e];
+        }
         if (v0) db[i0] = db[i0] + k0 * v[0][e].x + p0 * load_v(Vb + i0) * a;
         if (v1) db[i1] = db[i1] + k1 * v[0][e].y + p1 * load_v(Vb + i1) * c;
         epi_fence(e);
@@ -710,21 +722,16 @@ __global__ __launch_bounds__((row_map<R, N, WPB>::THREADS)) __attribute__((amdgp
     R* __restrict__ Ib = psiI + b;
     const R* __restrict__ Vb = V + b;
     const int o0 = L.off, o1 = L.off + N;
+    constexpr bool RL = x_reload<N>();
     cpx<R> v[1][16];
-#if !SPSTD_X_RELOAD
-    cpx<R> f[16];   // psi_I on entry; later psi_I + vb * V * psi_R(new)
-#endif
+    cpx<R> f[RL ? 1 : 16];   // psi_I on entry; later psi_I + vb * V * psi_R(new)
 #pragma unroll
     for (int e = 0; e < 16; ++e) {
         v[0][e].x = v0 ? Ib[o0 + C::T * e] : (R)0;
         v[0][e].y = v1 ? Ib[o1 + C::T * e] : (R)0;
-#if !SPSTD_X_RELOAD
-        f[e] = v[0][e];
-#endif
+        if constexpr (!RL) f[e] = v[0][e];
     }
-#if SPSTD_X_RELOAD
-    reload_fence();
-#endif
+    if constexpr (RL) reload_fence();
     R* l0 = lds + L.pin_block * M::SL;
     // A half: psi_R += T_x^A psi_I + p_A V psi_I
     fft_pencils<R, N, false, C::WAVE, M::SPLIT, TU::PRODUCTS, 1, 1>(v, j, l0, M::SL, tw);
@@ -739,11 +746,8 @@ __global__ __launch_bounds__((row_map<R, N, WPB>::THREADS)) __attribute__((amdgp
     for (int e = 0; e < 16; ++e) {
         const int i0 = o0 + C::T * e, i1 = o1 + C::T * e;
         cpx<R> vv = {(R)0, (R)0}, g = {(R)0, (R)0}, fe;
-#if SPSTD_X_RELOAD
-        fe = cpx<R>{v0 ? Ib[i0] : (R)0, v1 ? Ib[i1] : (R)0};
-#else
-        fe = f[e];
-#endif
+        if constexpr (RL) fe = cpx<R>{v0 ? Ib[i0] : (R)0, v1 ? Ib[i1] : (R)0};
+        else fe = f[e];
         if (v0) { vv.x = load_v(Vb + i0); g.x = Rb[i0]; }
         if (v1) { vv.y = load_v(Vb + i1); g.y = Rb[i1]; }
         g.x = g.x + sa.x * v[0][e].x + va.x * vv.x * fe.x;
@@ -751,15 +755,13 @@ __global__ __launch_bounds__((row_map<R, N, WPB>::THREADS)) __attribute__((amdgp
         if (v0) Rb[i0] = g.x;
         if (v1) Rb[i1] = g.y;
         v[0][e] = g;
-#if !SPSTD_X_RELOAD
-        f[e].x = fe.x + vb.x * vv.x * g.x;
-        f[e].y = fe.y + vb.y * vv.y * g.y;
-#endif
+        if constexpr (!RL) {
+            f[e].x = fe.x + vb.x * vv.x * g.x;
+            f[e].y = fe.y + vb.y * vv.y * g.y;
+        }
         epi_fence(e);
     }
-#if SPSTD_X_RELOAD
-    reload_fence();
-#endif
+    if constexpr (RL) reload_fence();
     // B half: psi_I += T_x^B psi_R(new) + p_B V psi_R(new)
     fft_pencils<R, N, false, C::WAVE, M::SPLIT, TU::PRODUCTS, 1, 1>(v, j, l0, M::SL, tw);
     apply_k2<R, N>(v[0], j, nyq_zero);
@@ -768,14 +770,14 @@ __global__ __launch_bounds__((row_map<R, N, WPB>::THREADS)) __attribute__((amdgp
 #pragma unroll
     for (int e = 0; e < 16; ++e) {
         const int i0 = o0 + C::T * e, i1 = o1 + C::T * e;
-#if SPSTD_X_RELOAD
-        // psi_R here is the value this lane stored in the A epilogue
-        if (v0) Ib[i0] = Ib[i0] + vb.x * load_v(Vb + i0) * Rb[i0] + sb.x * v[0][e].x;
-        if (v1) Ib[i1] = Ib[i1] + vb.y * load_v(Vb + i1) * Rb[i1] + sb.y * v[0][e].y;
-#else
-        if (v0) Ib[i0] = f[e].x + sb.x * v[0][e].x;
-        if (v1) Ib[i1] = f[e].y + sb.y * v[0][e].y;
-#endif
+        if constexpr (RL) {
+            // psi_R here is the value this lane stored in the A epilogue
+            if (v0) Ib[i0] = Ib[i0] + vb.x * load_v(Vb + i0) * Rb[i0] + sb.x * v[0][e].x;
+            if (v1) Ib[i1] = Ib[i1] + vb.y * load_v(Vb + i1) * Rb[i1] + sb.y * v[0][e].y;
+        } else {
+            if (v0) Ib[i0] = f[e].x + sb.x * v[0][e].x;
+            if (v1) Ib[i1] = f[e].y + sb.y * v[0][e].y;
+        }
         epi_fence(e);
     }
 }
