@@ -145,8 +145,17 @@ def cpu_baseline(w, steps):
     oracle.run(w.psiR, w.psiI, w.V, w.n, w.dx, c, d, dt, steps, w.probes)
     el = time.perf_counter() - t0
     su = w.npoints * nsub / 2.0 * steps
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
     return {"value": su / el, "unit": "stage updates/s", "cores": oracle.num_threads(),
-            "kind": "oracle",
+            "cpu_model": model, "host_cpus": os.cpu_count(), "kind": "oracle",
             "sample": f"{steps} full time step(s) ({nsub} substeps each) of the 256^3 FP64 "
                       f"oracle run, {el:.1f} s wall"}
 
