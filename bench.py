@@ -156,8 +156,8 @@ def cpu_baseline(w, steps):
         pass
     return {"value": su / el, "unit": "stage updates/s", "cores": oracle.num_threads(),
             "cpu_model": model, "host_cpus": os.cpu_count(), "kind": "oracle",
-            "sample": f"{steps} full time step(s) ({nsub} substeps each) of the 256^3 FP64 "
-                      f"oracle run, {el:.1f} s wall"}
+            "sample": f"{steps} full time step(s) ({nsub} substeps each) of the "
+                      f"{'x'.join(str(k) for k in w.n)} FP64 oracle run, {el:.1f} s wall"}
 
 
 def batching_leg(count, steps, seed=0):
