@@ -169,6 +169,117 @@ def test_sharp_stability_edge_on_a_real_run():
         assert grows or amp < 3.0
 
 
+# ------------------------- T4: the spectral-radius bound that sets dt
+# The configs' "dt = 0.5 x stability limit" is 0.5 x_max / rho with rho the
+# bound of the spectrum of K (Eq. 24-30 read with V).  These tests tie the
+# oracle's bound to the spectrum of a dense K built from its definition
+# (the kinetic circulant of each axis, Kronecker-summed, plus diag(V/hbar)),
+# computed by a library eigensolver: no FFT and no copy of the formula.
+
+def _dense_K(n, dx, V=None, hbar=1.0, mass=1.0):
+    """Dense K of Eq. (16) on a periodic grid, row-major [z][y][x]."""
+    mats = [modal.kinetic_circulant(nn, dd, hbar, mass) for nn, dd in zip(n, dx)]
+    N = int(np.prod(n))
+    K = np.zeros((N, N))
+    for a, Ka in enumerate(mats):
+        # axis a is the a-th fastest index: I(slower axes) x Ka x I(faster axes)
+        slow = int(np.prod(n[a + 1:]))
+        fast = int(np.prod(n[:a]))
+        K += np.kron(np.eye(slow), np.kron(Ka, np.eye(fast)))
+    if V is not None:
+        K += np.diag(np.asarray(V, np.float64).ravel() / hbar)
+    return K
+
+
+def _spectral_radius(K):
+    w = np.linalg.eigvalsh(K)
+    return max(abs(w[0]), abs(w[-1]))
+
+
+@pytest.mark.parametrize("n,dx,hbar,mass", [
+    ((64,), (0.3,), 1.0, 1.0),
+    ((48,), (0.15,), 0.7, 1.9),
+    ((16, 8), (0.25, 0.4), 1.3, 0.6),
+    ((8, 4, 8), (0.5, 0.2, 0.35), 0.9, 2.2),
+])
+def test_rho_bound_is_the_top_of_the_free_spectrum(n, dx, hbar, mass):
+    # V = 0: the largest eigenvalue of K is the Nyquist mode of every axis,
+    # so the bound is attained exactly (hbar, m* and anisotropic spacing
+    # enter as the paper's (hbar/2m*) k^2 symbol does)
+    lam = _spectral_radius(_dense_K(n, dx, None, hbar, mass))
+    assert oracle.rho_bound(None, n, dx, hbar, mass) == pytest.approx(lam, rel=1e-12)
+
+
+@pytest.mark.parametrize("V0", [0.0, 3.5, 40.0])
+def test_rho_bound_with_a_constant_potential_is_exact(V0):
+    # a constant V shifts every eigenvalue by V0/hbar: the bound is exact
+    n, dx, hbar, mass = (8, 16), (0.3, 0.2), 0.8, 1.4
+    V = np.full(int(np.prod(n)), V0)
+    lam = _spectral_radius(_dense_K(n, dx, V, hbar, mass))
+    assert oracle.rho_bound(V, n, dx, hbar, mass) == pytest.approx(lam, rel=1e-12)
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_rho_bound_bounds_the_spectrum_with_signed_potentials(seed):
+    # any V (negative values included): the bound is at least the spectral
+    # radius, which is what stability needs (max |omega_j| dt < x_max)
+    rng = np.random.default_rng(seed)
+    n, dx = (12, 10), (0.4, 0.3)
+    V = rng.normal(0.0, 30.0, int(np.prod(n)))
+    lam = _spectral_radius(_dense_K(n, dx, V, 1.1, 0.9))
+    rb = oracle.rho_bound(V, n, dx, 1.1, 0.9)
+    assert lam <= rb * (1 + 1e-12)
+    # and not loose by more than the potential's own share
+    assert rb - lam <= np.abs(V).max() / 1.1 + 1e-9
+
+
+def test_rho_bound_of_the_configs_bounds_the_dense_spectrum_tightly():
+    # 1D finite well (256 points): 211.34 <= 212.13
+    w = W.finite_well_1d()
+    lam = _spectral_radius(_dense_K(w.n, w.dx, w.V))
+    rb = oracle.rho_bound(w.V, w.n, w.dx)
+    assert lam <= rb and lam / rb > 0.99
+    assert lam == pytest.approx(211.337, abs=5e-3)
+    # separable 3D oscillator: the top of K is three times the top of the
+    # 1D operator with V1 = x^2/2 (64 points on [-8, 8)): 302.67 <= 332.87
+    wl = W.harmonic_3d(seed=7, n=64, half_box=8.0, steps=1)
+    lam1 = _spectral_radius(modal.hamiltonian_1d(wl.meta["V1"], wl.dx[0]))
+    rb3 = oracle.rho_bound(wl.V, wl.n, wl.dx)
+    assert 3 * lam1 <= rb3 and 3 * lam1 / rb3 > 0.9
+    assert 3 * lam1 == pytest.approx(302.67, abs=1e-2)
+
+
+def test_stability_limit_is_the_dense_spectrum_edge():
+    # 1D finite well: a run at dt = f x_max / lambda_max(dense K) grows for
+    # f = 1.01 and stays bounded for f = 0.99 (Eq. 24-25 applied to the
+    # eigenvalues of K), so "the stability limit" is x_max / lambda_max and
+    # the oracle's dt = 0.5 x_max / rho_bound sits at or below half of it
+    w = W.finite_well_1d(steps=1)
+    c, d = w.coeffs
+    lam = _spectral_radius(_dense_K(w.n, w.dx, w.V))
+    K = _dense_K(w.n, w.dx, w.V)
+    phi_top = np.linalg.eigh(K)[1][:, -1]
+    f0 = w.psiR + 1e-3 * phi_top
+    for frac, grows in ((0.99, False), (1.01, True)):
+        dt = frac * oracle.xmax(c, d) / lam
+        r, i, _, _ = oracle.run(f0, np.zeros_like(f0), w.V, w.n, w.dx, c, d, dt, 3000)
+        amp = np.sqrt(np.sum(r * r + i * i) / np.sum(f0 * f0))
+        assert (not np.isfinite(amp) or amp > 10.0) == grows, (frac, amp)
+    assert oracle.stable_dt(c, d, w.V, w.n, w.dx) <= 0.5 * oracle.xmax(c, d) / lam
+
+
+def test_stable_dt_of_the_configs():
+    # the three configs' time steps, 0.5 x_max / rho, recomputed independently
+    # (mode-matrix root and grid bound in extended precision) when the
+    # workloads were specified
+    w = W.finite_well_1d(steps=1)
+    assert oracle.stable_dt(*w.coeffs, w.V, w.n, w.dx) == pytest.approx(0.0106540804, rel=1e-8)
+    h = W.harmonic_3d(seed=7, n=64, half_box=8.0, steps=1)
+    assert oracle.stable_dt(*h.coeffs, h.V, h.n, h.dx) == pytest.approx(0.006789561379, rel=1e-9)
+    b = W.harmonic_3d(seed=0, n=256, half_box=12.0, steps=1, coeffs=W.YOSHIDA6)
+    assert oracle.stable_dt(*b.coeffs, b.V, b.n, b.dx) == pytest.approx(5.969909204e-4, rel=1e-9)
+
+
 # ------------------------------------------ T3: per-mode closed form
 def test_plane_wave_follows_mode_matrix():
     n, dx = (8, 16, 8), (0.5, 0.25, 0.5)
