@@ -108,8 +108,11 @@ def run_precision(w, prec, steps, warmup):
                                     "share_of_pass_time": v[1] / sum(x[1] for x in kinds.values())}
                   for k, v in kinds.items()}
     # graph-replayed steps (the default execution mode) for reference
-    q = spstd.plan_from_workload(w, precision=code, nsteps_max=steps + warmup)
-    q.step(warmup)
+    # its warm-up covers at least one 16-step chunk, so that the chunk's graph
+    # is captured and instantiated before the timed region
+    gw = max(warmup, 32)
+    q = spstd.plan_from_workload(w, precision=code, nsteps_max=steps + gw)
+    q.step(gw)
     torch.cuda.synchronize()
     g0 = time.perf_counter()
     q.step(steps)
@@ -119,16 +122,21 @@ def run_precision(w, prec, steps, warmup):
     pcie = {"plan_setup_s": setup_s, "readback_s": readback_s,
             "value_including_transfers": su_per_step * steps / (el + setup_s + readback_s)}
     # whole-step byte accounting: the passes' algorithmic bytes over the
-    # timed steps, and the per-axis 3D FFT schedule model (192 B per stage
-    # update in FP64, 96 B in FP32) at the measured rate
+    # timed steps; the irreducible bytes of a stage update (read f, V, g and
+    # write g once per half-stage: 64 B FP64, 32 B FP32) at the measured
+    # rate; and the per-axis 3D FFT schedule model (192 B / 96 B), whose
+    # fraction only says how far the engine's schedule is from that one
     rate = su_per_step * steps / el
     step_bytes = sum(v[0] * v[2] for v in kinds.values()) / steps
     model_b = 192.0 if prec == "fp64" else 96.0
+    irred_b = 64.0 if prec == "fp64" else 32.0
     step_model = {"engine_bytes_per_stage_update": step_bytes / su_per_step,
                   "engine_GBps_over_step": step_bytes / (el / steps) / 1e9,
                   "engine_frac_over_step": step_bytes / (el / steps) / 1e9 / HBM_PEAK_GBS,
+                  "irreducible_bytes_per_stage_update": irred_b,
+                  "irreducible_frac": irred_b * rate / (HBM_PEAK_GBS * 1e9),
                   "schedule_model_bytes_per_stage_update": model_b,
-                  "schedule_model_frac": model_b * rate / (HBM_PEAK_GBS * 1e9)}
+                  "schedule_model_ratio_not_bandwidth": model_b * rate / (HBM_PEAK_GBS * 1e9)}
     return {"value": rate, "ms_per_step": el / steps * 1e3, "host_transfers": pcie, "bytes": step_model,
             "roofline": roof, "kernels": per_kernel, "dt": info.dt,
             "graph_mode": {"value": su_per_step * steps / (g1 - g0),
@@ -142,7 +150,7 @@ def cpu_baseline(w, steps):
     dt = oracle.stable_dt(c, d, w.V, w.n, w.dx)
     nsub = sum(1 for x in c if x != 0.0) + sum(1 for x in d if x != 0.0)
     t0 = time.perf_counter()
-    oracle.run(w.psiR, w.psiI, w.V, w.n, w.dx, c, d, dt, steps, w.probes)
+    ro, io, so, _ = oracle.run(w.psiR, w.psiI, w.V, w.n, w.dx, c, d, dt, steps, w.probes)
     el = time.perf_counter() - t0
     su = w.npoints * nsub / 2.0 * steps
     model = None
@@ -154,10 +162,51 @@ def cpu_baseline(w, steps):
                     break
     except OSError:
         pass
-    return {"value": su / el, "unit": "stage updates/s", "cores": oracle.num_threads(),
-            "cpu_model": model, "host_cpus": os.cpu_count(), "kind": "oracle",
-            "sample": f"{steps} full time step(s) ({nsub} substeps each) of the "
-                      f"{'x'.join(str(k) for k in w.n)} FP64 oracle run, {el:.1f} s wall"}
+    out = {"value": su / el, "unit": "stage updates/s", "cores": oracle.num_threads(),
+           "cpu_model": model, "host_cpus": os.cpu_count(), "kind": "oracle",
+           "sample": f"{steps} full time step(s) ({nsub} substeps each) of the "
+                     f"{'x'.join(str(k) for k in w.n)} FP64 oracle run, {el:.1f} s wall"}
+    return out, (dt, steps, ro, io, so)
+
+
+def accuracy_vs_oracle(w, ref):
+    """Error of each precision against the FP64 oracle: the state and probe
+    samples after the CPU baseline's steps of the bench workload (same dt),
+    and the levels of the 1D finite-well workload (20000 steps, paper set)
+    against the oracle's levels of the same run."""
+    import numpy as np
+    import oracle
+    from oracle import spectrum
+    from paper_1805_03155_amd import spstd
+    from paper_1805_03155_amd import workloads as W
+    dt, steps, ro, io, so = ref
+    b = np.concatenate([ro, io])
+    fw = W.finite_well_1d(seed=0)
+    c, d = fw.coeffs
+    fdt = oracle.stable_dt(c, d, fw.V, fw.n, fw.dx)
+    _, _, fso, _ = oracle.run(fw.psiR, fw.psiI, fw.V, fw.n, fw.dx, c, d, fdt, fw.steps, fw.probes)
+    E_or, _ = spectrum.extract(fso, fdt, 1.0, 4)
+    out = {"reference": "FP64 oracle",
+           "state": f"{'x'.join(str(k) for k in w.n)} bench workload after {steps} steps",
+           "levels": "1D finite well (256 points, 20000 steps, paper set), lowest 4 levels",
+           "oracle_levels": [float(e) for e in E_or]}
+    for name, code in (("fp64", spstd.FP64), ("fp32", spstd.FP32)):
+        p = spstd.plan_from_workload(w, precision=code, dt=dt, nsteps_max=steps)
+        ser, _ = p.run(steps)
+        r, i, _ = p.get_state()
+        del p
+        a = np.concatenate([r, i])
+        q = spstd.plan_from_workload(fw, precision=code, dt=fdt, nsteps_max=fw.steps)
+        fser, _ = q.run(fw.steps)
+        del q
+        E, _ = spstd.spectrum(fser, fdt, nlevels=4)
+        k = min(len(E), len(E_or))
+        out[name] = {"psi_rel_l2": float(np.linalg.norm(a - b) / np.linalg.norm(b)),
+                     "probe_rel_l2": float(np.linalg.norm(ser - so) / np.linalg.norm(so)),
+                     "level_rel_err": [float(abs(E[j] - E_or[j]) / abs(E_or[j])) for j in range(k)]}
+        log(f"accuracy {name}: psi rel-L2 {out[name]['psi_rel_l2']:.2e}, "
+            f"levels max rel err {max(out[name]['level_rel_err']):.2e}")
+    return out
 
 
 def batching_leg(count, steps, seed=0):
@@ -167,7 +216,7 @@ def batching_leg(count, steps, seed=0):
     from paper_1805_03155_amd import batching, spstd
     from paper_1805_03155_amd import workloads as W
     inst = W.batch_instances(count=count, seed=seed, steps=steps)
-    _, st = batching.run_instances(inst, steps, precision=spstd.FP32)
+    _, st = batching.run_instances(inst, steps, precision=spstd.FP32, warmup=32)
     # schedules the autotuner chose, counted over the shape groups
     picks = {}
     for sched, wpb in st["schedules"].values():
@@ -304,11 +353,12 @@ def main():
     ap.add_argument("--n", type=int, default=256, help="grid points per axis")
     ap.add_argument("--cpu-baseline", choices=["on", "off"], default="on")
     ap.add_argument("--cpu-steps", type=int, default=5)
-    ap.add_argument("--batch-steps", type=int, default=500,
+    ap.add_argument("--batch-steps", type=int, default=5000,
                     help="steps of the 512-instance batching leg (0: skip)")
-    ap.add_argument("--serve-requests", type=int, default=40,
-                    help="requests of the serving leg (0: skip)")
-    ap.add_argument("--serve-rate", type=float, default=10.0)
+    ap.add_argument("--serve-requests", type=int, default=200,
+                    help="requests per offered rate of the serving leg (0: skip)")
+    ap.add_argument("--serve-rate", default="5,30",
+                    help="offered rates of the serving leg (requests/s, comma-separated)")
     ap.add_argument("--pmc-sample", action="store_true",
                     help="short run for rocprofv3 counter passes (no timing output)")
     ap.add_argument("--study", choices=["precision", "rk4"],
@@ -353,13 +403,18 @@ def main():
         batch = batching_leg(512, args.batch_steps)
         log(f"batching: {batch['value']:.3e} stage updates/s")
     if args.serve_requests > 0:
-        log(f"serving leg: {args.serve_requests} requests at {args.serve_rate}/s")
-        serving = serving_leg(args.serve_requests, args.serve_rate, (2000, 20000))
-        log(f"serving: p50 {serving['p50_s']:.2f} s, p99 {serving['p99_s']:.2f} s")
-    cpu = None
+        serving = []
+        for rate in (float(x) for x in args.serve_rate.split(",")):
+            log(f"serving leg: {args.serve_requests} requests at {rate}/s")
+            r = serving_leg(args.serve_requests, rate, (2000, 20000))
+            log(f"serving: p50 {r['p50_s']:.2f} s, p99 {r['p99_s']:.2f} s, "
+                f"{r['completed_per_s']:.2f} completed/s")
+            serving.append(r)
+    cpu = accuracy = None
     if args.cpu_baseline == "on":
         log("timing the CPU oracle on a bounded sample")
-        cpu = cpu_baseline(w, args.cpu_steps)
+        cpu, ref = cpu_baseline(w, args.cpu_steps)
+        accuracy = accuracy_vs_oracle(w, ref)
     r64, r32 = res["fp64"], res["fp32"]
     line = {
         "metric": METRIC,
@@ -389,6 +444,7 @@ def main():
         "host_transfers": r64["host_transfers"],
         "batching": batch,
         "serving": serving,
+        "accuracy": accuracy,
         "fp32": {"value": r32["value"], "ms_per_step": r32["ms_per_step"], "dtype": "f32",
                  "roofline": r32["roofline"], "kernels": r32["kernels"],
                  "graph_mode": r32["graph_mode"], "host_transfers": r32["host_transfers"],

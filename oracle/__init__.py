@@ -74,6 +74,7 @@ def lib():
                              i64, i, pi64, pd, pd]
         L.or_run.restype = i
         L.or_num_threads.restype = i
+        L.or_set_threads.argtypes = [i]
         _lib = L
     return _lib
 
@@ -100,6 +101,11 @@ def _grid(n, dx):
 
 def num_threads() -> int:
     return lib().or_num_threads()
+
+
+def set_threads(n: int) -> None:
+    """Threads of the calling host thread's later oracle runs."""
+    lib().or_set_threads(int(n))
 
 
 def dft_naive(x, sign=-1):

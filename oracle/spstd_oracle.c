@@ -515,3 +515,14 @@ int or_num_threads(void)
     return 1;
 #endif
 }
+
+/* Threads of the calling host thread's later parallel regions (for several
+ * oracle runs side by side on host threads). */
+void or_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}

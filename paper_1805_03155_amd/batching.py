@@ -16,12 +16,14 @@ from . import spstd
 
 
 def run_instances(instances, steps, precision=spstd.FP32, coeffs=None, nprobes=1,
-                  device="cuda", dt=None):
-    """Advance every instance by `steps` steps; returns (results, stats).
+                  device="cuda", dt=None, warmup=0):
+    """Advance every instance by `warmup` untimed and then `steps` timed
+    steps; returns (results, stats).
 
-    results[i] = (probe series [(steps+1), nprobes, 2], dt); stats holds the
-    elapsed device time (wall clock around the stepping, inputs resident),
-    the stage updates done and the group layout."""
+    results[i] = (probe series [(warmup+steps+1), nprobes, 2], dt); stats
+    holds the elapsed device time of the timed steps (wall clock around the
+    stepping, inputs resident; warm-up steps capture the step graphs), the
+    stage updates done in them and the group layout."""
     import torch
     groups = defaultdict(list)
     for i, w in enumerate(instances):
@@ -31,7 +33,7 @@ def run_instances(instances, steps, precision=spstd.FP32, coeffs=None, nprobes=1
     batches, dts = {}, {}
     for shape, idx in groups.items():
         st = torch.cuda.Stream(device=device)
-        b = spstd.Batch(shape, coeffs, capacity=len(idx), nprobes=nprobes, nsteps_max=steps,
+        b = spstd.Batch(shape, coeffs, capacity=len(idx), nprobes=nprobes, nsteps_max=steps + warmup,
                         precision=precision, device=device, stream=st, flags=spstd.AUTOTUNE)
         for s, i in enumerate(idx):
             w = instances[i]
@@ -39,6 +41,9 @@ def run_instances(instances, steps, precision=spstd.FP32, coeffs=None, nprobes=1
                             dt=0.0 if dt is None else dt[i], cfl_fraction=w.cfl_fraction,
                             hbar=w.hbar, mass=w.mass)
         batches[shape] = (b, st, idx)
+    if warmup > 0:
+        for b, st, _ in batches.values():
+            b.step(warmup)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for b, st, _ in batches.values():
