@@ -34,7 +34,8 @@ os.environ.setdefault("GPU_MAX_HW_QUEUES", "16")
 
 METRIC = "grid-point stage updates/s (3D HO 256³, FP64 vs FP32); p50/p99 solve latency"
 HBM_PEAK_GBS = 8000.0
-KERNEL_SOURCES = ["paper_1805_03155_amd/csrc/kernels.hip", "paper_1805_03155_amd/csrc/fft_core.hpp"]
+KERNEL_SOURCES = ["paper_1805_03155_amd/csrc/kernels.hip", "paper_1805_03155_amd/csrc/passes.hpp",
+                  "paper_1805_03155_amd/csrc/fft_core.hpp"]
 KERNEL_NAMES = {"y": "k_axis_acc (y pass)", "z": "k_axis_acc (z pass)",
                 "yba": "k_axis_ba (y passes of a stage boundary, fused)",
                 "xab": "k_x_ab (fused A+B x pass)", "x": "k_x_acc (x half-stage)"}
@@ -212,7 +213,11 @@ def accuracy_vs_oracle(w, ref):
 def batching_leg(count, steps, seed=0):
     """The batching workload: `count` seeded 1D/2D instances of uneven sizes
     (1D 2^7..2^14, 2D 32^2..512^2, square or harmonic wells), FP32 fields
-    with FP64 probes, paper coefficient set; one batch per shape."""
+    with FP64 probes, paper coefficient set; one batch per shape; the 2D
+    shapes of 128^2..512^2 either stepped together as one group (one launch
+    per pass) or on their own streams, whichever a 64-step trial of each on
+    the loaded workload finds faster; the others by their resident
+    kernels."""
     from paper_1805_03155_amd import batching, spstd
     from paper_1805_03155_amd import workloads as W
     inst = W.batch_instances(count=count, seed=seed, steps=steps)
@@ -224,7 +229,9 @@ def batching_leg(count, steps, seed=0):
         picks[k] = picks.get(k, 0) + 1
     return {"value": st["stage_updates_per_s"], "unit": "stage updates/s", "instances": count,
             "steps": steps, "points": st["points"], "elapsed_s": st["elapsed_s"],
-            "shape_groups": len(st["groups"]), "schedules": picks, "dtype": "f32 fields, f64 probes"}
+            "shape_groups": len(st["groups"]), "workload_schedule": st["workload_schedule"],
+            "trials_us_per_step": st["trials"], "schedules_outside_the_group": picks,
+            "mixed_group": st["mixed_group"], "dtype": "f32 fields, f64 probes"}
 
 
 def serving_leg(count, rate, steps, seed=0, budget_gb=64):
@@ -265,9 +272,9 @@ def serving_sweep(count, rates, steps, budgets_gb=(64,), small_budget_gb=2, smal
 
 
 def pmc_sample(w, steps):
-    """Short run for hardware-counter passes: a plain device copy of a known
-    size (the calibration of FETCH_SIZE / WRITE_SIZE), then a few eager
-    steps of the hot path in each precision."""
+    """Short run for hardware-counter passes: a plain device copy and an
+    in-place add of known sizes (the calibration of FETCH_SIZE /
+    WRITE_SIZE), then a few eager steps of the hot path in each precision."""
     import torch
     from paper_1805_03155_amd import spstd
     nbytes = 256 << 20
@@ -275,6 +282,10 @@ def pmc_sample(w, steps):
     b = torch.empty_like(a)
     for _ in range(3):
         b.copy_(a)
+    torch.cuda.synchronize()
+    # a second streaming kernel of known bytes: b += a reads 2 and writes 1 array
+    for _ in range(3):
+        b.add_(a)
     torch.cuda.synchronize()
     del a, b
     for code in (spstd.FP64, spstd.FP32):

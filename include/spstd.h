@@ -311,6 +311,7 @@ spstd_status spstd_pass_times(spstd_plan_t plan, int64_t *launches, double *tota
 spstd_status spstd_destroy(spstd_plan_t plan);
 const char *spstd_strerror(spstd_status status);
 
+
 /* ------------------------------------------------------------------------
  * Batches: many independent instances of one grid shape advanced together
  * (each with its own spacing, hbar, m*, V, initial state, dt and probes; the
@@ -419,6 +420,68 @@ spstd_status spstd_batch_slot_info(spstd_batch_t batch, int slot, int *active, i
 
 spstd_status spstd_batch_destroy(spstd_batch_t batch);
 const char *spstd_batch_last_error(spstd_batch_t batch);
+
+/* ------------------------------------------------------------------------
+ * Groups: 2D batches of different shapes (the uneven instances of the
+ * batching form) advanced together.  Every pass of the stage sequence is
+ * one persistent launch over all members: it walks a device table of tiles
+ * (member, block of that member's own grid) and runs, per tile, the pass
+ * body for that member's shape, fields, twiddles and scales.  A group
+ * takes over its members: from its creation until its destruction the
+ * members' kernels, and their slot loads, reads and releases, run on the
+ * group's stream (so they order with the group's steps); step the members
+ * through the group only.
+ * ------------------------------------------------------------------------ */
+typedef struct spstd_batch_group_s *spstd_batch_group_t;
+
+/*
+ * Members: 1..64 distinct 2D batches whose axes have 128, 256 or 512
+ * points, with one precision, coefficient set, Nyquist convention and
+ * probe count.  Exact device workspace of a group (tile tables).  Pure host
+ * computation.  SPSTD_ERR_ARG for members that do not qualify.
+ */
+spstd_status spstd_batch_group_workspace_size(const spstd_batch_t *members, int nmembers, size_t *bytes);
+
+/*
+ * Create a group over the caller's device workspace (256-byte aligned).
+ * Schedules (candidates): k < n (n = 16 in FP32, 8 in FP64) the mixed-shape
+ * kernels with 2 << (k & 1) waves per block, the joint LDS exchange of the
+ * fused x pass for rows under 512 points if k & 2 (else split), one
+ * persistent block per compute unit if k & 4 (else a grid that fills the
+ * device), and two complex pencils per lane group in the y passes if k & 8
+ * (FP32); k = n the members' own pass kernels one member after another on
+ * the group's stream.  Sets whose stages do not all have both halves (a zero c_l or
+ * d_l) run k = n only.  flags: SPSTD_AUTOTUNE times every candidate (16
+ * warm-up and 32 timed steps, every slot stepping a zero state at a nominal
+ * instance's scales; the members must have no active slot) and keeps the
+ * fastest (within 3% of it, one block per compute unit, which leaves room
+ * for other streams' kernels); otherwise the built-in choice (4 waves per
+ * block, the exchange of the single-shape kernels, a filling grid, one
+ * pencil per lane group).  Synchronises the
+ * members' streams.  Errors: SPSTD_ERR_ARG, SPSTD_ERR_WORKSPACE,
+ * SPSTD_ERR_DEVICE.
+ */
+spstd_status spstd_batch_group_create(const spstd_batch_t *members, int nmembers, uint32_t flags,
+                                      void *d_workspace, size_t ws_bytes, void *stream,
+                                      spstd_batch_group_t *out);
+
+/* Enqueue nsteps steps of every active slot of every member (asynchronous);
+ * SPSTD_ERR_CAPACITY (nothing queued) if a slot would pass its nsteps_max. */
+spstd_status spstd_batch_group_step(spstd_batch_group_t group, int64_t nsteps);
+
+/* The schedule in use (*choice, as numbered for spstd_batch_group_create),
+ * the number of candidates and, after SPSTD_AUTOTUNE, the measured
+ * microseconds per step of each (0 where not measured); any may be NULL. */
+spstd_status spstd_batch_group_schedule(spstd_batch_group_t group, int *choice, int *ncandidates,
+                                        double *tuned_us);
+
+/* Use schedule `choice` from now on (synchronises the group's stream). */
+spstd_status spstd_batch_group_set_schedule(spstd_batch_group_t group, int choice);
+
+/* Release the group (the members keep their slots and return to their own
+ * streams; synchronises). */
+spstd_status spstd_batch_group_destroy(spstd_batch_group_t group);
+const char *spstd_batch_group_last_error(spstd_batch_group_t group);
 /* Text of the last error recorded on the plan (never NULL). */
 const char *spstd_last_error(spstd_plan_t plan);
 

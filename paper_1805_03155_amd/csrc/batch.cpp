@@ -26,7 +26,7 @@
 namespace spstd {
 
 struct BatchLayout {
-    size_t psiR, psiI, V, tw[3], scales, pidx, active, counter, probes, rinst, total;
+    size_t psiR, psiI, V, tw[3], scales, pidx, active, counter, fault, probes, rinst, total;
 };
 
 static const int kBatchGraphChunk = 16;
@@ -50,6 +50,8 @@ static BatchLayout batch_layout(const spstd_batch_desc* d) {
     L.pidx = off; off += align256(cap * np * sizeof(int64_t));
     L.active = off; off += align256(cap * sizeof(int));
     L.counter = off; off += align256(cap * sizeof(int64_t));
+    // set by a probe kernel that met a device-side probe index outside the grid
+    L.fault = off; off += 256;
     L.probes = off; off += align256(cap * (size_t)(d->nsteps_max + 1) * np * 2 * sizeof(double));
     L.rinst = off; off += align256(cap * sizeof(ResidentInst<double>));
     L.total = off;
@@ -172,7 +174,8 @@ static hipError_t batch_step_once(Batch* b) {
         e = launch_probe_batch<R>(pr, pi, b->npts, reinterpret_cast<const int64_t*>(b->ws + b->L.pidx),
                                   b->d.nprobes, reinterpret_cast<const int*>(b->ws + b->L.active),
                                   b->d.capacity, reinterpret_cast<double*>(b->ws + b->L.probes),
-                                  reinterpret_cast<int64_t*>(b->ws + b->L.counter), b->d.nsteps_max + 1, b->st);
+                                  reinterpret_cast<int64_t*>(b->ws + b->L.counter), b->d.nsteps_max + 1,
+                                  reinterpret_cast<int*>(b->ws + b->L.fault), b->st);
     return e;
 }
 
@@ -217,6 +220,7 @@ static spstd_status upload_rtab(Batch* b) {
         const size_t np = (size_t)(b->d.nprobes > 0 ? b->d.nprobes : 1);
         I.probes = reinterpret_cast<double*>(b->ws + b->L.probes) + (size_t)i * (b->d.nsteps_max + 1) * np * 2;
         I.counter = reinterpret_cast<int64_t*>(b->ws + b->L.counter) + i;
+        I.fault = reinterpret_cast<int*>(b->ws + b->L.fault);
         I.capacity = b->d.nsteps_max + 1;
         I.nprobes = b->d.nprobes;
         for (int q = 0; q < b->d.nprobes; ++q) I.probe_idx[q] = s.probe_idx[q];
@@ -323,20 +327,13 @@ static void drop_graph(Batch* b) {
     b->graph_ready = false;
 }
 
+// Trial state for timing schedules on an empty batch: every slot active,
+// stepping its (zero) state with the scales of a nominal instance (dx =
+// hbar = m* = 1, V = 0, dt = 0.5 x_max / rho) and sampling point 0; and
+// back to the empty batch (zero scales, counters and active flags; a zero
+// state stays zero).
 template <typename R>
-static spstd_status batch_autotune(Batch* b) {
-    const auto key = std::make_tuple(b->d.n[0], b->d.n[1], b->d.n[2], b->esz, b->d.capacity);
-    {
-        std::lock_guard<std::mutex> g(g_tune_mu);
-        auto it = g_tune.find(key);
-        if (it != g_tune.end()) {
-            b->resident = it->second.resident;
-            b->wpb = it->second.wpb;
-            for (int k = 0; k < 3; ++k) b->tuned_us[k] = it->second.us[k];
-            return SPSTD_OK;
-        }
-    }
-    // nominal instance: dx = hbar = m* = 1, V = 0, dt = 0.5 x_max / rho
+static spstd_status batch_trial_begin(Batch* b) {
     spstd_desc one{};
     one.ndim = b->d.ndim;
     for (int a = 0; a < 3; ++a) {
@@ -351,7 +348,6 @@ static spstd_status batch_autotune(Batch* b) {
     for (int i = 0; i < b->d.capacity; ++i)
         for (size_t k = 0; k < rows.size(); ++k) rr[(size_t)i * rows.size() + k] = (R)rows[k];
     std::vector<int> act(b->d.capacity, 1);
-    // every slot samples point 0 during the trial
     std::vector<int64_t> pz((size_t)b->d.capacity * (b->d.nprobes > 0 ? b->d.nprobes : 1), 0);
     BCHK(hipMemcpyAsync(b->ws + b->L.pidx, pz.data(), pz.size() * sizeof(int64_t), hipMemcpyHostToDevice, b->st));
     BCHK(hipMemcpyAsync(b->ws + b->L.scales, rr.data(), rr.size() * sizeof(R), hipMemcpyHostToDevice, b->st));
@@ -363,6 +359,41 @@ static spstd_status batch_autotune(Batch* b) {
         sl.hbar = sl.mass = 1.0;
         for (int a = 0; a < 3; ++a) sl.dx[a] = 1.0;
         for (int q = 0; q < b->d.nprobes; ++q) sl.probe_idx[q] = 0;
+    }
+    return SPSTD_OK;
+}
+
+template <typename R>
+static spstd_status batch_trial_end(Batch* b) {
+    const size_t nsc = (size_t)b->d.m * SC_COLS * (size_t)b->d.capacity;
+    std::vector<R> zr(nsc, (R)0);
+    std::vector<int> za(b->d.capacity, 0);
+    std::vector<int64_t> zc(b->d.capacity, 0);
+    BCHK(hipMemcpyAsync(b->ws + b->L.scales, zr.data(), zr.size() * sizeof(R), hipMemcpyHostToDevice, b->st));
+    BCHK(hipMemcpyAsync(b->ws + b->L.active, za.data(), za.size() * sizeof(int), hipMemcpyHostToDevice, b->st));
+    BCHK(hipMemcpyAsync(b->ws + b->L.counter, zc.data(), zc.size() * sizeof(int64_t), hipMemcpyHostToDevice, b->st));
+    BCHK(hipStreamSynchronize(b->st));
+    for (Slot& sl : b->slots) sl = Slot{};
+    b->rtab_dirty = true;
+    return SPSTD_OK;
+}
+
+template <typename R>
+static spstd_status batch_autotune(Batch* b) {
+    const auto key = std::make_tuple(b->d.n[0], b->d.n[1], b->d.n[2], b->esz, b->d.capacity);
+    {
+        std::lock_guard<std::mutex> g(g_tune_mu);
+        auto it = g_tune.find(key);
+        if (it != g_tune.end()) {
+            b->resident = it->second.resident;
+            b->wpb = it->second.wpb;
+            for (int k = 0; k < 3; ++k) b->tuned_us[k] = it->second.us[k];
+            return SPSTD_OK;
+        }
+    }
+    {
+        spstd_status s0 = batch_trial_begin<R>(b);
+        if (s0 != SPSTD_OK) return s0;
     }
     const int64_t trial = 2 * kBatchGraphChunk;
     double us[3] = {0.0, 0.0, 0.0};
@@ -386,17 +417,10 @@ static spstd_status batch_autotune(Batch* b) {
         s = time_steps<R>(b, kBatchGraphChunk, trial, &us[1 + k]);
     }
     drop_graph(b);
-    // back to an empty batch: zero scales, counters and active flags (the
-    // fields stayed zero: a zero state steps to zero)
-    std::vector<R> zr(rr.size(), (R)0);
-    std::vector<int> za(b->d.capacity, 0);
-    std::vector<int64_t> zc(b->d.capacity, 0);
-    BCHK(hipMemcpyAsync(b->ws + b->L.scales, zr.data(), zr.size() * sizeof(R), hipMemcpyHostToDevice, b->st));
-    BCHK(hipMemcpyAsync(b->ws + b->L.active, za.data(), za.size() * sizeof(int), hipMemcpyHostToDevice, b->st));
-    BCHK(hipMemcpyAsync(b->ws + b->L.counter, zc.data(), zc.size() * sizeof(int64_t), hipMemcpyHostToDevice, b->st));
-    BCHK(hipStreamSynchronize(b->st));
-    for (Slot& sl : b->slots) sl = Slot{};
-    b->rtab_dirty = true;
+    {
+        spstd_status s1 = batch_trial_end<R>(b);
+        if (s == SPSTD_OK) s = s1;
+    }
     if (s != SPSTD_OK) return s;
     b->wpb = (both && us[2] < us[1]) ? 4 : 2;
     const double pass_us = us[b->wpb == 4 ? 2 : 1];
@@ -498,6 +522,7 @@ spstd_status spstd_batch_create(const spstd_batch_desc* d, void* d_workspace, si
                                             hipMemcpyHostToDevice, b->st);
     if (e == hipSuccess) e = hipMemcpyAsync(b->ws + L.counter, cnt.data(), cnt.size() * sizeof(int64_t),
                                             hipMemcpyHostToDevice, b->st);
+    if (e == hipSuccess) e = launch_fill0<int>(1, reinterpret_cast<int*>(b->ws + L.fault), b->st);
     for (int a = 0; a < d->ndim && e == hipSuccess; ++a) {
         // FP64 in every precision: the kernels round each twiddle once
         std::vector<double> t = twiddles(d->n[a]);
@@ -597,7 +622,7 @@ spstd_status spstd_batch_load(spstd_batch_t b, int slot, const double* dx, doubl
                                            reinterpret_cast<const int*>(b->ws + b->L.active) + slot, 1,
                                            reinterpret_cast<double*>(b->ws + b->L.probes + poff),
                                            reinterpret_cast<int64_t*>(b->ws + b->L.counter) + slot,
-                                           b->d.nsteps_max + 1, b->st);
+                                           b->d.nsteps_max + 1, reinterpret_cast<int*>(b->ws + b->L.fault), b->st);
         else
             e = launch_probe_batch<float>(BF<float>(b, b->L.psiR) + (int64_t)slot * b->npts,
                                           BF<float>(b, b->L.psiI) + (int64_t)slot * b->npts, b->npts,
@@ -605,7 +630,7 @@ spstd_status spstd_batch_load(spstd_batch_t b, int slot, const double* dx, doubl
                                           reinterpret_cast<const int*>(b->ws + b->L.active) + slot, 1,
                                           reinterpret_cast<double*>(b->ws + b->L.probes + poff),
                                           reinterpret_cast<int64_t*>(b->ws + b->L.counter) + slot,
-                                          b->d.nsteps_max + 1, b->st);
+                                          b->d.nsteps_max + 1, reinterpret_cast<int*>(b->ws + b->L.fault), b->st);
     } else if (e == hipSuccess) {
         int64_t one64 = 1;
         e = hipMemcpyAsync(b->ws + b->L.counter + (size_t)slot * sizeof(int64_t), &one64, sizeof(one64),
@@ -642,6 +667,13 @@ spstd_status spstd_batch_read(spstd_batch_t b, int slot, double* probes_out, dou
     const Slot& s = b->slots[slot];
     hipError_t e = hipStreamSynchronize(b->st);
     const size_t np = (size_t)b->d.nprobes;
+    int fault = 0;
+    if (e == hipSuccess && np > 0)
+        e = hipMemcpy(&fault, b->ws + b->L.fault, sizeof(int), hipMemcpyDeviceToHost);
+    if (e == hipSuccess && fault) {
+        b->err = "a probe index in device memory lies outside the grid (samples skipped)";
+        return SPSTD_ERR_DEVICE;
+    }
     if (e == hipSuccess && probes_out && np > 0) {
         const size_t poff = (size_t)slot * (b->d.nsteps_max + 1) * np * 2 * sizeof(double);
         e = hipMemcpy(probes_out, b->ws + b->L.probes + poff, (size_t)(s.steps + 1) * np * 2 * sizeof(double),
@@ -710,5 +742,438 @@ spstd_status spstd_batch_destroy(spstd_batch_t b) {
 }
 
 const char* spstd_batch_last_error(spstd_batch_t b) { return b ? b->err.c_str() : "null batch"; }
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Groups: 2D batches of different shapes stepped together, one launch per
+// pass of the stage sequence for all of them (the mixed-shape kernels), or
+// their own pass kernels one member after another on one stream.
+// ---------------------------------------------------------------------------
+namespace spstd {
+
+static const int kMixMaxVariants = 16;
+
+// Candidate k of the mixed kernels: waves per block 2 or 4 (bit 0), joint
+// LDS exchange of the fused x pass for rows under 512 points (bit 1), one
+// persistent block per compute unit instead of a grid that fills the device
+// (bit 2), two complex pencils per lane group in the y passes (bit 3; FP32
+// only).
+static MixVariant mix_variant(int k) { return MixVariant{(k & 1) ? 4 : 2, (k >> 1) & 1, 1 + ((k >> 3) & 1)}; }
+static bool mix_one_per_cu(int k) { return (k >> 2) & 1; }
+
+struct Group {
+    std::vector<Batch*> members;
+    std::vector<hipStream_t> member_streams;   // the members' own streams, restored on destroy
+    size_t esz = 8;
+    int m = 0;
+    bool mixable = false;   // every stage has both halves: the mixed kernels apply
+    int nvar = 0;           // mixed-kernel candidates
+    int choice = 0;         // candidate in use: < nvar a mixed variant, nvar the members' own kernels
+    double tuned_us[kMixMaxVariants + 1] = {0.0};
+    int cus = 256;          // compute units of the device
+    char* ws = nullptr;
+    hipStream_t st = nullptr;
+    size_t mem_off = 0, tile_off = 0, slot_off = 0, total = 0;
+    int64_t x_off[kMixMaxVariants] = {0}, x_n[kMixMaxVariants] = {0};
+    int64_t y_off[kMixMaxVariants] = {0}, y_n[kMixMaxVariants] = {0};
+    int nslots = 0;
+    hipGraphExec_t graph;
+    bool graph_ready = false;
+    std::string err;
+};
+
+#define GCHK(x)                                                      \
+    do {                                                             \
+        hipError_t e_ = (x);                                         \
+        if (e_ != hipSuccess) {                                      \
+            g->err = std::string(#x) + ": " + hipGetErrorString(e_); \
+            return SPSTD_ERR_DEVICE;                                 \
+        }                                                            \
+    } while (0)
+
+// Members must be 2D pass-kernel batches of row and column lengths 128,
+// 256 or 512 that share precision, coefficient set, Nyquist convention and
+// probe count.
+static spstd_status group_check(const spstd_batch_t* mem, int n, std::string* why) {
+    if (!mem || n < 1 || n > 64) { *why = "1..64 members"; return SPSTD_ERR_ARG; }
+    const Batch* b0 = mem[0];
+    for (int i = 0; i < n; ++i) {
+        const Batch* b = mem[i];
+        if (!b) { *why = "null member"; return SPSTD_ERR_ARG; }
+        if (b->d.ndim != 2 || !mix_len_ok(b->d.n[0]) || !mix_len_ok(b->d.n[1]) || b->resident) {
+            *why = "members are 2D batches of 128, 256 or 512 points per axis";
+            return SPSTD_ERR_ARG;
+        }
+        if (b->esz != b0->esz || b->d.m != b0->d.m || b->d.nyquist != b0->d.nyquist ||
+            b->d.nprobes != b0->d.nprobes) {
+            *why = "members differ in precision, stage count, Nyquist convention or probes";
+            return SPSTD_ERR_ARG;
+        }
+        for (int l = 0; l < b->d.m; ++l)
+            if (b->c[l] != b0->c[l] || b->dd[l] != b0->dd[l]) { *why = "members differ in coefficients"; return SPSTD_ERR_ARG; }
+        for (int j = 0; j < i; ++j)
+            if (mem[j] == b) { *why = "a member appears twice"; return SPSTD_ERR_ARG; }
+    }
+    return SPSTD_OK;
+}
+
+// Workspace pieces: the member table, the tile tables of every candidate
+// (x tiles, then y tiles), the (member, slot) table of the probe kernel.
+static void group_layout(Group* g) {
+    const int nm = (int)g->members.size();
+    size_t off = 0;
+    g->mem_off = off;
+    off += align256((size_t)nm * sizeof(MixMember<double>));
+    g->tile_off = off;
+    int64_t t = 0;
+    for (int k = 0; k < g->nvar; ++k) {
+        const MixVariant v = mix_variant(k);
+        g->x_off[k] = t;
+        g->x_n[k] = 0;
+        for (Batch* b : g->members) g->x_n[k] += mix_blocks(0, (int)b->d.n[0], (int)b->d.n[1], b->d.capacity, (int)g->esz, v);
+        t += g->x_n[k];
+        g->y_off[k] = t;
+        g->y_n[k] = 0;
+        for (Batch* b : g->members) g->y_n[k] += mix_blocks(1, (int)b->d.n[0], (int)b->d.n[1], b->d.capacity, (int)g->esz, v);
+        t += g->y_n[k];
+    }
+    off += align256((size_t)t * sizeof(MixTile));
+    g->slot_off = off;
+    g->nslots = 0;
+    for (Batch* b : g->members) g->nslots += b->d.capacity;
+    off += align256((size_t)(g->nslots > 0 ? g->nslots : 1) * sizeof(MixTile));
+    g->total = off;
+}
+
+template <typename R>
+static spstd_status group_upload(Group* g) {
+    std::vector<MixMember<R>> mt;
+    for (Batch* b : g->members) {
+        MixMember<R> M{};
+        M.nx = (int)b->d.n[0];
+        M.ny = (int)b->d.n[1];
+        M.psiR = BF<R>(b, b->L.psiR);
+        M.psiI = BF<R>(b, b->L.psiI);
+        M.V = BF<R>(b, b->L.V);
+        M.twx = b->ws + b->L.tw[0];
+        M.twy = b->ws + b->L.tw[1];
+        M.scales = b->ws + b->L.scales;
+        M.rg = RowGeom{b->d.n[1] * b->d.capacity, b->d.n[1]};
+        M.gy = axis_geom_of_n(2, b->d.n, 1, b->d.capacity);
+        M.npts = b->npts;
+        M.pidx = reinterpret_cast<const int64_t*>(b->ws + b->L.pidx);
+        M.active = reinterpret_cast<const int*>(b->ws + b->L.active);
+        M.probes = reinterpret_cast<double*>(b->ws + b->L.probes);
+        M.counter = reinterpret_cast<int64_t*>(b->ws + b->L.counter);
+        M.samples = b->d.nsteps_max + 1;
+        M.fault = reinterpret_cast<int*>(b->ws + b->L.fault);
+        mt.push_back(M);
+    }
+    GCHK(hipMemcpyAsync(g->ws + g->mem_off, mt.data(), mt.size() * sizeof(MixMember<R>), hipMemcpyHostToDevice, g->st));
+    std::vector<MixTile> tiles;
+    for (int k = 0; k < g->nvar; ++k) {
+        const MixVariant v = mix_variant(k);
+        for (int kind = 0; kind < 2; ++kind)
+            for (int i = 0; i < (int)g->members.size(); ++i) {
+                const Batch* b = g->members[i];
+                const int64_t nb = mix_blocks(kind, (int)b->d.n[0], (int)b->d.n[1], b->d.capacity, (int)g->esz, v);
+                for (int64_t q = 0; q < nb; ++q) tiles.push_back(MixTile{i, (int)q});
+            }
+    }
+    if (!tiles.empty())
+        GCHK(hipMemcpyAsync(g->ws + g->tile_off, tiles.data(), tiles.size() * sizeof(MixTile), hipMemcpyHostToDevice,
+                            g->st));
+    std::vector<MixTile> slots;
+    for (int i = 0; i < (int)g->members.size(); ++i)
+        for (int s = 0; s < g->members[i]->d.capacity; ++s) slots.push_back(MixTile{i, s});
+    if (!slots.empty())
+        GCHK(hipMemcpyAsync(g->ws + g->slot_off, slots.data(), slots.size() * sizeof(MixTile), hipMemcpyHostToDevice,
+                            g->st));
+    GCHK(hipStreamSynchronize(g->st));
+    return SPSTD_OK;
+}
+
+// Blocks of a persistent launch: one per compute unit (the passes are
+// bound by memory bandwidth, and the rest of the device stays free for
+// other streams' kernels), or enough to fill the device a few times over.
+static int group_grid(int64_t ntiles, int wpb, bool one_per_cu, int cus) {
+    const int64_t cap = one_per_cu ? cus : 8192 / wpb;
+    return (int)(ntiles < cap ? ntiles : cap);
+}
+
+// One step of every member: the stage sequence of batch_step_once (the y
+// sweep owed by a B half fused with the next A half's), each pass one
+// launch over all members; then the probe samples.
+template <typename R>
+static hipError_t group_step_once(Group* g) {
+    if (g->choice >= g->nvar) {
+        for (Batch* b : g->members) {
+            const hipError_t e = batch_step_once<R>(b);
+            if (e != hipSuccess) return e;
+        }
+        return hipSuccess;
+    }
+    const int k = g->choice;
+    const MixVariant v = mix_variant(k);
+    const MixMember<R>* mem = reinterpret_cast<const MixMember<R>*>(g->ws + g->mem_off);
+    const MixTile* tiles = reinterpret_cast<const MixTile*>(g->ws + g->tile_off);
+    const MixTile* tx = tiles + g->x_off[k];
+    const MixTile* ty = tiles + g->y_off[k];
+    const int nx = (int)g->x_n[k], ny = (int)g->y_n[k];
+    const int gx = group_grid(nx, v.wpb, mix_one_per_cu(k), g->cus), gy = group_grid(ny, v.wpb, mix_one_per_cu(k), g->cus);
+    const int nyq = g->members[0]->d.nyquist;
+    hipError_t e = hipSuccess;
+    int owed = -1;
+    for (int l = 0; l < g->m && e == hipSuccess; ++l) {
+        if (owed >= 0) e = launch_mix_axis_ba<R>(mem, ty, ny, gy, g->m, owed, l, nyq, v, g->st);
+        else e = launch_mix_axis_acc<R>(mem, ty, ny, gy, g->m, l, 0, nyq, v, g->st);
+        if (e == hipSuccess) e = launch_mix_x_ab<R>(mem, tx, nx, gx, g->m, l, nyq, v, g->st);
+        owed = l;
+    }
+    if (e == hipSuccess && owed >= 0) e = launch_mix_axis_acc<R>(mem, ty, ny, gy, g->m, owed, 1, nyq, v, g->st);
+    if (e == hipSuccess && g->members[0]->d.nprobes > 0)
+        e = launch_mix_probe<R>(mem, reinterpret_cast<const MixTile*>(g->ws + g->slot_off), g->nslots,
+                                g->members[0]->d.nprobes, g->st);
+    return e;
+}
+
+static void group_drop_graph(Group* g) {
+    if (g->graph_ready) (void)hipGraphExecDestroy(g->graph);
+    g->graph_ready = false;
+}
+
+template <typename R>
+static spstd_status group_build_graph(Group* g) {
+    hipStream_t cap;
+    GCHK(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+    hipStream_t user = g->st;
+    g->st = cap;
+    for (Batch* b : g->members) b->st = cap;
+    hipGraph_t gr = nullptr;
+    hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        hipError_t e2 = hipSuccess;
+        for (int s = 0; s < kBatchGraphChunk && e2 == hipSuccess; ++s) e2 = group_step_once<R>(g);
+        e = hipStreamEndCapture(cap, &gr);
+        if (e == hipSuccess) e = e2;
+    }
+    g->st = user;
+    for (Batch* b : g->members) b->st = user;
+    if (e == hipSuccess) e = hipGraphInstantiate(&g->graph, gr, nullptr, nullptr, 0);
+    if (gr) (void)hipGraphDestroy(gr);
+    (void)hipStreamDestroy(cap);
+    if (e != hipSuccess) {
+        g->err = std::string("graph capture: ") + hipGetErrorString(e);
+        return SPSTD_ERR_DEVICE;
+    }
+    g->graph_ready = true;
+    return SPSTD_OK;
+}
+
+template <typename R>
+static spstd_status group_step_t(Group* g, int64_t n) {
+    int64_t left = n;
+    if (n >= kBatchGraphChunk) {
+        if (!g->graph_ready) {
+            spstd_status s = group_build_graph<R>(g);
+            if (s != SPSTD_OK) return s;
+        }
+        for (; left >= kBatchGraphChunk; left -= kBatchGraphChunk) GCHK(hipGraphLaunch(g->graph, g->st));
+    }
+    for (; left > 0; --left) GCHK(group_step_once<R>(g));
+    return SPSTD_OK;
+}
+
+template <typename R>
+static spstd_status group_time(Group* g, double* us) {
+    spstd_status s = group_step_t<R>(g, kBatchGraphChunk);
+    if (s != SPSTD_OK) return s;
+    hipEvent_t e0, e1;
+    GCHK(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return SPSTD_ERR_DEVICE;
+    }
+    const int64_t trial = 2 * kBatchGraphChunk;
+    hipError_t e = hipEventRecord(e0, g->st);
+    if (e == hipSuccess) s = group_step_t<R>(g, trial);
+    if (e == hipSuccess && s == SPSTD_OK) e = hipEventRecord(e1, g->st);
+    if (e == hipSuccess && s == SPSTD_OK) e = hipEventSynchronize(e1);
+    float ms = 0.0f;
+    if (e == hipSuccess && s == SPSTD_OK) e = hipEventElapsedTime(&ms, e0, e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (e != hipSuccess) {
+        g->err = hipGetErrorString(e);
+        return SPSTD_ERR_DEVICE;
+    }
+    *us = s == SPSTD_OK ? 1e3 * ms / (double)trial : 0.0;
+    return s;
+}
+
+// Time every candidate on the empty members (each slot stepping a zero
+// state at a nominal instance's scales) and keep the fastest.
+template <typename R>
+static spstd_status group_autotune(Group* g) {
+    spstd_status s = SPSTD_OK;
+    for (Batch* b : g->members) {
+        if (s == SPSTD_OK) s = batch_trial_begin<R>(b);
+        b->rtab_dirty = true;
+    }
+    const int first = g->mixable ? 0 : g->nvar;
+    for (int k = first; k <= g->nvar && s == SPSTD_OK; ++k) {
+        group_drop_graph(g);
+        for (Batch* b : g->members) drop_graph(b);
+        g->choice = k;
+        s = group_time<R>(g, &g->tuned_us[k]);
+    }
+    group_drop_graph(g);
+    for (Batch* b : g->members) {
+        drop_graph(b);
+        const spstd_status s1 = batch_trial_end<R>(b);
+        if (s == SPSTD_OK) s = s1;
+    }
+    if (s != SPSTD_OK) return s;
+    // the fastest; within 3% of it, one block per compute unit (it leaves
+    // the rest of the device to other streams' kernels)
+    int best = g->nvar;
+    for (int k = first; k < g->nvar; ++k)
+        if (g->tuned_us[k] < g->tuned_us[best]) best = k;
+    for (int k = first; k < g->nvar; ++k)
+        if (mix_one_per_cu(k) && !mix_one_per_cu(best) && g->tuned_us[k] <= 1.03 * g->tuned_us[best]) best = k;
+    g->choice = best;
+    return SPSTD_OK;
+}
+
+}  // namespace spstd
+
+struct spstd_batch_group_s : Group {};
+
+extern "C" {
+
+spstd_status spstd_batch_group_workspace_size(const spstd_batch_t* members, int nmembers, size_t* bytes) {
+    std::string why;
+    spstd_status s = group_check(members, nmembers, &why);
+    if (s != SPSTD_OK) return s;
+    if (!bytes) return SPSTD_ERR_ARG;
+    Group g;
+    g.esz = members[0]->esz;
+    g.nvar = g.esz == 4 ? 16 : 8;
+    for (int i = 0; i < nmembers; ++i) g.members.push_back(members[i]);
+    group_layout(&g);
+    *bytes = g.total;
+    return SPSTD_OK;
+}
+
+spstd_status spstd_batch_group_create(const spstd_batch_t* members, int nmembers, uint32_t flags, void* d_workspace,
+                                      size_t ws_bytes, void* stream, spstd_batch_group_t* out) {
+    if (!out) return SPSTD_ERR_ARG;
+    *out = nullptr;
+    std::string why;
+    spstd_status s = group_check(members, nmembers, &why);
+    if (s != SPSTD_OK) return s;
+    if ((flags & SPSTD_AUTOTUNE))
+        for (int i = 0; i < nmembers; ++i)
+            for (const Slot& sl : members[i]->slots)
+                if (sl.active) return SPSTD_ERR_ARG;   // tuning steps every slot: members must be empty
+    spstd_batch_group_s* g = new (std::nothrow) spstd_batch_group_s();
+    if (!g) return SPSTD_ERR_DEVICE;
+    g->esz = members[0]->esz;
+    g->m = members[0]->d.m;
+    g->nvar = g->esz == 4 ? 16 : 8;
+    {
+        int dev = 0, cus = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
+            g->cus = cus;
+    }
+    g->mixable = true;
+    for (int l = 0; l < g->m; ++l)
+        if (members[0]->c[l] == 0.0 || members[0]->dd[l] == 0.0) g->mixable = false;
+    for (int i = 0; i < nmembers; ++i) g->members.push_back(members[i]);
+    group_layout(g);
+    if (!d_workspace || ws_bytes < g->total || ((uintptr_t)d_workspace & 255)) {
+        delete g;
+        return SPSTD_ERR_WORKSPACE;
+    }
+    g->ws = (char*)d_workspace;
+    g->st = (hipStream_t)stream;
+    // the members' work runs on the group's stream from now on, so that
+    // their slot loads, reads and releases order with the group's steps
+    for (Batch* b : g->members) {
+        if (hipStreamSynchronize(b->st) != hipSuccess) {
+            delete g;
+            return SPSTD_ERR_DEVICE;
+        }
+        g->member_streams.push_back(b->st);
+        drop_graph(b);
+    }
+    for (Batch* b : g->members) b->st = g->st;
+    // built-in choice: 4 waves per block, the fused x pass's exchange as
+    // the single-shape kernels take it (joint in FP32, split in FP64), one
+    // pencil per lane group in the y passes; the members' own kernels where
+    // a stage has only one half
+    g->choice = g->mixable ? (1 | (g->esz == 4 ? 2 : 0)) : g->nvar;
+    s = g->esz == 8 ? group_upload<double>(g) : group_upload<float>(g);
+    if (s == SPSTD_OK && (flags & SPSTD_AUTOTUNE))
+        s = g->esz == 8 ? group_autotune<double>(g) : group_autotune<float>(g);
+    if (s != SPSTD_OK) {
+        for (size_t i = 0; i < g->members.size(); ++i) g->members[i]->st = g->member_streams[i];
+        group_drop_graph(g);
+        delete g;
+        return s;
+    }
+    *out = g;
+    return SPSTD_OK;
+}
+
+spstd_status spstd_batch_group_step(spstd_batch_group_t g, int64_t nsteps) {
+    if (!g || nsteps < 0) return SPSTD_ERR_ARG;
+    for (Batch* b : g->members)
+        for (const Slot& sl : b->slots)
+            if (sl.active && sl.steps + nsteps > b->d.nsteps_max) {
+                g->err = "probe buffer capacity exceeded";
+                return SPSTD_ERR_CAPACITY;
+            }
+    spstd_status s = g->esz == 8 ? group_step_t<double>(g, nsteps) : group_step_t<float>(g, nsteps);
+    if (s != SPSTD_OK) return s;
+    for (Batch* b : g->members)
+        for (Slot& sl : b->slots)
+            if (sl.active) sl.steps += nsteps;
+    return SPSTD_OK;
+}
+
+spstd_status spstd_batch_group_schedule(spstd_batch_group_t g, int* choice, int* ncandidates, double* tuned_us) {
+    if (!g) return SPSTD_ERR_ARG;
+    if (choice) *choice = g->choice;
+    if (ncandidates) *ncandidates = g->nvar + 1;
+    if (tuned_us)
+        for (int k = 0; k <= g->nvar; ++k) tuned_us[k] = g->tuned_us[k];
+    return SPSTD_OK;
+}
+
+spstd_status spstd_batch_group_set_schedule(spstd_batch_group_t g, int choice) {
+    if (!g || choice < 0 || choice > g->nvar || (choice < g->nvar && !g->mixable)) return SPSTD_ERR_ARG;
+    if (hipStreamSynchronize(g->st) != hipSuccess) return SPSTD_ERR_DEVICE;
+    group_drop_graph(g);
+    for (Batch* b : g->members) drop_graph(b);
+    g->choice = choice;
+    return SPSTD_OK;
+}
+
+spstd_status spstd_batch_group_destroy(spstd_batch_group_t g) {
+    if (!g) return SPSTD_ERR_ARG;
+    (void)hipStreamSynchronize(g->st);
+    group_drop_graph(g);
+    for (size_t i = 0; i < g->members.size(); ++i) {
+        drop_graph(g->members[i]);
+        g->members[i]->st = g->member_streams[i];
+    }
+    delete g;
+    return SPSTD_OK;
+}
+
+const char* spstd_batch_group_last_error(spstd_batch_group_t g) { return g ? g->err.c_str() : "null group"; }
 
 }  // extern "C"

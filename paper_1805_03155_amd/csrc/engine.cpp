@@ -35,14 +35,9 @@ struct Layout {
 
 static const int kNormBlocks = 256;
 
-#ifndef SPSTD_FIELD_PAD
-#define SPSTD_FIELD_PAD 0
-#endif
-
-// Axis whose passes are fused at stage boundaries in 3D grids (1: y, 2: z).
-#ifndef SPSTD_FUSE_AXIS
-#define SPSTD_FUSE_AXIS 1
-#endif
+// Axis whose passes are fused at stage boundaries (y; fusing z instead
+// measured equal at 256^3).
+static const int kFuseAxis = 1;
 static const int kGraphChunk = 16;
 
 struct Plan {
@@ -54,6 +49,10 @@ struct Plan {
     size_t esz;
     char* ws;
     Layout L;
+    // device fields psi_R, psi_I, V and the FP64 probe buffer: pieces of the
+    // workspace, or arrays the caller owns
+    char *fR, *fI, *fV;
+    double* prb;
     hipStream_t st;
     hipGraphExec_t graph;
     bool graph_ready;
@@ -135,8 +134,11 @@ static spstd_status validate(const spstd_desc* d, std::string* why) {
             const int64_t nt = wall ? 2 * d->n[a] : d->n[a];
             bool ok = (a == 0) ? row_len_ok(nt) : axis_len_ok(nt);
             if (wall && d->n[a] < 16) ok = false;
+            // a walled axis of at most 32 cells of any count
+            if (wall && wall_dft_len_ok(d->n[a])) ok = true;
             if (!ok) {
-                *why = "axis length must be a power of two (x: 16..16384, y/z: 16..1024; walled: half that)";
+                *why = "axis length must be a power of two (x: 16..16384, y/z: 16..1024; walled: half "
+                       "that, or any 2..32 cells)";
                 return SPSTD_ERR_ARG;
             }
             if (!(d->dx[a] > 0.0) || !std::isfinite(d->dx[a])) { *why = "dx must be positive"; return SPSTD_ERR_ARG; }
@@ -184,18 +186,19 @@ static spstd_status edge_of(const spstd_desc* d, double* x) {
     return xmax_symplectic(d->m, d->c, d->d, x) ? SPSTD_OK : SPSTD_ERR_ARG;
 }
 
-static Layout layout_of(const spstd_desc* d, int64_t nsteps_max) {
+// Workspace pieces of a plan.  external: the fields and the probe buffer
+// are device arrays the caller owns and take no room.
+static Layout layout_of(const spstd_desc* d, int64_t nsteps_max, bool external = false) {
     Layout L{};
     const int64_t N = d->n[0] * d->n[1] * d->n[2];
     const size_t esz = d->precision == SPSTD_FP64 ? 8 : 4;
-    const size_t fb = align256((size_t)N * esz);
+    const size_t fb = external ? 0 : align256((size_t)N * esz);
     size_t off = 0;
-    // SPSTD_FIELD_PAD bytes between the fields shift their relative
-    // placement across memory channels (the fields of a power-of-two grid are
-    // otherwise a power of two apart); measured at 256^3: 4 KB and 52 KB
-    // neutral, 1 MB and more slower, so 0
-    L.psiR = off; off += fb + SPSTD_FIELD_PAD;
-    L.psiI = off; off += fb + SPSTD_FIELD_PAD;
+    // the fields sit back to back (padding between them, to shift their
+    // placement across memory channels, measured neutral at 4 KB and 52 KB
+    // and slower from 1 MB at 256^3)
+    L.psiR = off; off += fb;
+    L.psiI = off; off += fb;
     L.V = off; off += fb;
     for (int k = 0; k < 6; ++k) {
         L.rk[k] = off;
@@ -208,7 +211,9 @@ static Layout layout_of(const spstd_desc* d, int64_t nsteps_max) {
     }
     L.pidx = off; off += align256(sizeof(int64_t) * (size_t)(d->nprobes > 0 ? d->nprobes : 1));
     L.probes = off;
-    off += align256(sizeof(double) * 2 * (size_t)(d->nprobes > 0 ? d->nprobes : 1) * (size_t)(nsteps_max + 1));
+    if (!external)
+        off += align256(sizeof(double) * 2 * (size_t)(d->nprobes > 0 ? d->nprobes : 1) * (size_t)(nsteps_max + 1));
+    // the device step counter (int64), then the probe-index fault flag (int)
     L.counter = off; off += 256;
     // probe values saved around a merged step boundary: psi_R before, psi_I
     L.psave = off; off += align256(sizeof(double) * 2 * SPSTD_MAX_PROBES);
@@ -226,6 +231,15 @@ static Layout layout_of(const spstd_desc* d, int64_t nsteps_max) {
 
 template <typename R>
 static R* F(Plan* p, size_t off) { return reinterpret_cast<R*>(p->ws + off); }
+template <typename R>
+static R* FR(Plan* p) { return reinterpret_cast<R*>(p->fR); }
+template <typename R>
+static R* FI(Plan* p) { return reinterpret_cast<R*>(p->fI); }
+template <typename R>
+static R* FV(Plan* p) { return reinterpret_cast<R*>(p->fV); }
+
+// Set by a probe kernel that met a device-side probe index outside the grid.
+static int* fault_flag(Plan* p) { return reinterpret_cast<int*>(p->ws + p->L.counter + sizeof(int64_t)); }
 
 #define HIPCHK(x)                                                   \
     do {                                                            \
@@ -237,19 +251,19 @@ static R* F(Plan* p, size_t off) { return reinterpret_cast<R*>(p->ws + off); }
     } while (0)
 
 template <typename R>
-static spstd_status upload(Plan* p, size_t off, const double* src) {
+static spstd_status upload(Plan* p, char* dst, const double* src) {
     const int64_t N = p->N;
     if (sizeof(R) == 8) {
-        if (src) HIPCHK(hipMemcpyAsync(p->ws + off, src, N * 8, hipMemcpyHostToDevice, p->st));
-        else HIPCHK(launch_fill0<R>(N, F<R>(p, off), p->st));
+        if (src) HIPCHK(hipMemcpyAsync(dst, src, N * 8, hipMemcpyHostToDevice, p->st));
+        else HIPCHK(launch_fill0<R>(N, reinterpret_cast<R*>(dst), p->st));
     } else {
         if (src) {
             std::vector<float> tmp(N);
             for (int64_t i = 0; i < N; ++i) tmp[i] = (float)src[i];
-            HIPCHK(hipMemcpyAsync(p->ws + off, tmp.data(), N * 4, hipMemcpyHostToDevice, p->st));
+            HIPCHK(hipMemcpyAsync(dst, tmp.data(), N * 4, hipMemcpyHostToDevice, p->st));
             HIPCHK(hipStreamSynchronize(p->st));   // tmp goes out of scope
         } else {
-            HIPCHK(launch_fill0<R>(N, F<R>(p, off), p->st));
+            HIPCHK(launch_fill0<R>(N, reinterpret_cast<R*>(dst), p->st));
         }
     }
     return SPSTD_OK;
@@ -296,7 +310,7 @@ static hipError_t yz_passes(Plan* p, const R* src, R* dst, const ScaleRef& sc, i
 template <typename R>
 static hipError_t fd_half(Plan* p, const R* src, R* dst, const ScaleRef& sc, int ab) {
     PassTimer tm(p, SPSTD_PASS_X);
-    return launch_fd_acc<R>(src, dst, F<R>(p, p->L.V), p->d.n, sc, ab ? SC_KXB : SC_KXA, ab ? SC_PB : SC_PA,
+    return launch_fd_acc<R>(src, dst, FV<R>(p), p->d.n, sc, ab ? SC_KXB : SC_KXA, ab ? SC_PB : SC_PA,
                             p->st);
 }
 
@@ -304,7 +318,7 @@ static hipError_t fd_half(Plan* p, const R* src, R* dst, const ScaleRef& sc, int
 // half-stage.
 template <typename R>
 static hipError_t x_half(Plan* p, const R* src, R* dst, const ScaleRef& sc, int kcol, int pcol) {
-    const R* V = F<R>(p, p->L.V);
+    const R* V = FV<R>(p);
     const void* twx = p->ws + p->L.tw[0];
     if (walled(p, 0))
         return launch_wall_acc<R>(p->d.n[0], 1, p->d.bc[0], src, dst, V, twx, lines_of(p, 0), p->N, sc, kcol,
@@ -335,11 +349,12 @@ template <typename R>
 static hipError_t step_end(Plan* p) {
     hipError_t e = hipSuccess;
     if (p->d.nprobes > 0)
-        e = launch_probe<R>(F<R>(p, p->L.psiR), F<R>(p, p->L.psiI), reinterpret_cast<const int64_t*>(p->ws + p->L.pidx),
-                            p->d.nprobes, reinterpret_cast<double*>(p->ws + p->L.probes),
-                            reinterpret_cast<int64_t*>(p->ws + p->L.counter), p->nsteps_max + 1, p->st);
+        e = launch_probe<R>(FR<R>(p), FI<R>(p), reinterpret_cast<const int64_t*>(p->ws + p->L.pidx),
+                            p->d.nprobes, p->N, p->prb,
+                            reinterpret_cast<int64_t*>(p->ws + p->L.counter), p->nsteps_max + 1, fault_flag(p),
+                            p->st);
     if (e == hipSuccess && p->eig_on) {
-        e = launch_eig_acc<R>(F<R>(p, p->L.psiR), F<R>(p, p->L.psiI), p->N, p->eig, p->st);
+        e = launch_eig_acc<R>(FR<R>(p), FI<R>(p), p->N, p->eig, p->st);
         if (e == hipSuccess) e = launch_count_tick(reinterpret_cast<int64_t*>(p->ws + p->L.ecount), p->st);
     }
     ev_break(p);
@@ -350,9 +365,9 @@ static hipError_t step_end(Plan* p) {
 // consecutive steps share their boundary A half (merges_steps).
 template <typename R>
 static hipError_t enqueue_symplectic_steps(Plan* p, int64_t k, bool merge) {
-    R* pr = F<R>(p, p->L.psiR);
-    R* pi = F<R>(p, p->L.psiI);
-    const R* V = F<R>(p, p->L.V);
+    R* pr = FR<R>(p);
+    R* pi = FI<R>(p);
+    const R* V = FV<R>(p);
     const RowGeom rg{p->N / p->d.n[0], p->N / p->d.n[0]};
     const int64_t nx = p->d.n[0];
     const void* twx = p->ws + p->L.tw[0];
@@ -360,12 +375,12 @@ static hipError_t enqueue_symplectic_steps(Plan* p, int64_t k, bool merge) {
     const int64_t* pidx = reinterpret_cast<const int64_t*>(p->ws + p->L.pidx);
     double* save = reinterpret_cast<double*>(p->ws + p->L.psave);
     hipError_t e = hipSuccess;
-    // The B half ends with the pass along axis fa (y, or z with
-    // SPSTD_FUSE_AXIS=2) and the A half starts with it, so the pass owed by
+    // The B half ends with the pass along axis fa (y) and the A half starts
+    // with it, so the pass owed by
     // the B half of one stage and the first pass of the next A half are one
     // sweep of those pencils (launch_axis_ba).  Steps end with the owed pass
     // on its own: the probes sample the completed step.
-    const int fa = p->d.ndim == 3 ? SPSTD_FUSE_AXIS : 1, oa = 3 - fa;
+    const int fa = kFuseAxis, oa = 3 - fa;
     const bool fuse = p->d.ndim >= 2 && !walled(p, fa);
     int owed = -1;   // scale row whose B half still owes its pass along fa
     auto owed_pass = [&](int row) -> hipError_t {
@@ -386,7 +401,7 @@ static hipError_t enqueue_symplectic_steps(Plan* p, int64_t k, bool merge) {
         }
         if (smp) {
             // psi_R before the merged A half (B passes leave it alone)
-            r = launch_probe_save<R>(pr, pidx, p->d.nprobes, save, p->st);
+            r = launch_probe_save<R>(pr, pidx, p->d.nprobes, p->N, save, fault_flag(p), p->st);
             ev_break(p);
             if (r != hipSuccess) return r;
         }
@@ -409,7 +424,7 @@ static hipError_t enqueue_symplectic_steps(Plan* p, int64_t k, bool merge) {
         if (r != hipSuccess) return r;
         if (smp) {
             // psi_I of the boundary state: every B pass before it is done
-            r = launch_probe_save<R>(pi, pidx, p->d.nprobes, save + SPSTD_MAX_PROBES, p->st);
+            r = launch_probe_save<R>(pi, pidx, p->d.nprobes, p->N, save + SPSTD_MAX_PROBES, fault_flag(p), p->st);
             ev_break(p);
             if (r != hipSuccess) return r;
         }
@@ -429,9 +444,10 @@ static hipError_t enqueue_symplectic_steps(Plan* p, int64_t k, bool merge) {
         if (r != hipSuccess) return r;
         if (smp) {
             const double w = p->c[m - 1] / (p->c[m - 1] + p->c[0]);
-            r = launch_probe_merged<R>(pr, pidx, p->d.nprobes, save, save + SPSTD_MAX_PROBES, w,
-                                       reinterpret_cast<double*>(p->ws + p->L.probes),
-                                       reinterpret_cast<int64_t*>(p->ws + p->L.counter), p->nsteps_max + 1, p->st);
+            r = launch_probe_merged<R>(pr, pidx, p->d.nprobes, p->N, save, save + SPSTD_MAX_PROBES, w,
+                                       p->prb,
+                                       reinterpret_cast<int64_t*>(p->ws + p->L.counter), p->nsteps_max + 1,
+                                       fault_flag(p), p->st);
             ev_break(p);
             if (r != hipSuccess) return r;
         }
@@ -482,8 +498,8 @@ static hipError_t apply_K(Plan* p, const R* src, R* kout, double coef) {
 
 template <typename R>
 static hipError_t enqueue_rk4_step(Plan* p) {
-    R* pr = F<R>(p, p->L.psiR);
-    R* pi = F<R>(p, p->L.psiI);
+    R* pr = FR<R>(p);
+    R* pi = FI<R>(p);
     R* kR = F<R>(p, p->L.rk[0]);
     R* kI = F<R>(p, p->L.rk[1]);
     R* yR = F<R>(p, p->L.rk[2]);
@@ -528,11 +544,12 @@ static bool uses_resident(const Plan* p) {
 template <typename R>
 static spstd_status upload_resident_inst(Plan* p) {
     ResidentInst<R> I{};
-    I.V = F<R>(p, p->L.V);
-    I.psiR = F<R>(p, p->L.psiR);
-    I.psiI = F<R>(p, p->L.psiI);
-    I.probes = reinterpret_cast<double*>(p->ws + p->L.probes);
+    I.V = FV<R>(p);
+    I.psiR = FR<R>(p);
+    I.psiI = FI<R>(p);
+    I.probes = p->prb;
     I.counter = reinterpret_cast<int64_t*>(p->ws + p->L.counter);
+    I.fault = fault_flag(p);
     I.capacity = p->nsteps_max + 1;
     I.nprobes = p->d.nprobes;
     for (int q = 0; q < p->d.nprobes; ++q) I.probe_idx[q] = p->probe_idx[q];
@@ -626,7 +643,7 @@ static spstd_status enqueue_steps(Plan* p, int64_t n) {
 
 template <typename R>
 static spstd_status compute_norm(Plan* p, double* out) {
-    HIPCHK(launch_norm_partials<R>(F<R>(p, p->L.psiR), F<R>(p, p->L.psiI), p->N,
+    HIPCHK(launch_norm_partials<R>(FR<R>(p), FI<R>(p), p->N,
                                    reinterpret_cast<double*>(p->ws + p->L.partials), kNormBlocks, p->st));
     double part[kNormBlocks];
     HIPCHK(hipMemcpyAsync(part, p->ws + p->L.partials, sizeof(part), hipMemcpyDeviceToHost, p->st));
@@ -644,10 +661,10 @@ static spstd_status compute_energy(Plan* p, double* out) {
     double* part = reinterpret_cast<double*>(p->ws + p->L.partials) + kNormBlocks;
     int nb[3] = {0, 0, 0};
     for (int a = 0; a < p->d.ndim; ++a)
-        HIPCHK(launch_energy_axis<R>(p->d.n[a], a == 0, p->d.bc[a], F<R>(p, p->L.psiR), F<R>(p, p->L.psiI),
+        HIPCHK(launch_energy_axis<R>(p->d.n[a], a == 0, p->d.bc[a], FR<R>(p), FI<R>(p),
                                      p->ws + p->L.tw[a], lines_of(p, a), p->d.nyquist == SPSTD_NYQ_ZERO,
                                      part + a * kNormBlocks, kNormBlocks, &nb[a], p->st));
-    HIPCHK(launch_energy_pot<R>(F<R>(p, p->L.psiR), F<R>(p, p->L.psiI), F<R>(p, p->L.V), p->N,
+    HIPCHK(launch_energy_pot<R>(FR<R>(p), FI<R>(p), FV<R>(p), p->N,
                                 part + 3 * kNormBlocks, part + 4 * kNormBlocks, kNormBlocks, p->st));
     std::vector<double> h((size_t)5 * kNormBlocks);
     HIPCHK(hipMemcpyAsync(h.data(), part, h.size() * sizeof(double), hipMemcpyDeviceToHost, p->st));
@@ -674,12 +691,11 @@ static spstd_status compute_energy(Plan* p, double* out) {
     return SPSTD_OK;
 }
 
+// Twiddle and scale tables, probe indices, the zeroed step counter and
+// fault flag, probe sample 0 of the current fields, and the resident
+// kernel's instance table.
 template <typename R>
-static spstd_status plan_init(Plan* p, const double* V, const double* psiR0, const double* psiI0) {
-    spstd_status s;
-    if ((s = upload<R>(p, p->L.psiR, psiR0)) != SPSTD_OK) return s;
-    if ((s = upload<R>(p, p->L.psiI, psiI0)) != SPSTD_OK) return s;
-    if ((s = upload<R>(p, p->L.V, V)) != SPSTD_OK) return s;
+static spstd_status init_tables(Plan* p) {
     for (int a = 0; a < p->d.ndim; ++a) {
         // FP64 in every precision: the kernels round each twiddle once
         std::vector<double> t = twiddles(transform_len(p->d, a));
@@ -711,18 +727,29 @@ static spstd_status plan_init(Plan* p, const double* V, const double* psiR0, con
     if (p->d.nprobes > 0)
         HIPCHK(hipMemcpyAsync(p->ws + p->L.pidx, p->probe_idx, sizeof(int64_t) * p->d.nprobes,
                               hipMemcpyHostToDevice, p->st));
-    int64_t zero = 0;
-    HIPCHK(hipMemcpyAsync(p->ws + p->L.counter, &zero, sizeof(zero), hipMemcpyHostToDevice, p->st));
+    // step counter and fault flag start at zero (a fill kernel, not a memset)
+    HIPCHK(launch_fill0<int64_t>(2, reinterpret_cast<int64_t*>(p->ws + p->L.counter), p->st));
     if (p->d.nprobes > 0)
-        HIPCHK(launch_probe<R>(F<R>(p, p->L.psiR), F<R>(p, p->L.psiI),
-                               reinterpret_cast<const int64_t*>(p->ws + p->L.pidx), p->d.nprobes,
-                               reinterpret_cast<double*>(p->ws + p->L.probes),
-                               reinterpret_cast<int64_t*>(p->ws + p->L.counter), p->nsteps_max + 1, p->st));
+        HIPCHK(launch_probe<R>(FR<R>(p), FI<R>(p),
+                               reinterpret_cast<const int64_t*>(p->ws + p->L.pidx), p->d.nprobes, p->N,
+                               p->prb,
+                               reinterpret_cast<int64_t*>(p->ws + p->L.counter), p->nsteps_max + 1, fault_flag(p),
+                               p->st));
     HIPCHK(hipStreamSynchronize(p->st));
     if (uses_resident(p)) {
         spstd_status s2 = upload_resident_inst<R>(p);
         if (s2 != SPSTD_OK) return s2;
     }
+    return SPSTD_OK;
+}
+
+template <typename R>
+static spstd_status plan_init(Plan* p, const double* V, const double* psiR0, const double* psiI0) {
+    spstd_status s;
+    if ((s = upload<R>(p, p->fR, psiR0)) != SPSTD_OK) return s;
+    if ((s = upload<R>(p, p->fI, psiI0)) != SPSTD_OK) return s;
+    if ((s = upload<R>(p, p->fV, V)) != SPSTD_OK) return s;
+    if ((s = init_tables<R>(p)) != SPSTD_OK) return s;
     return compute_norm<R>(p, &p->norm0);
 }
 
@@ -731,10 +758,10 @@ static spstd_status get_state_t(Plan* p, double* psiR, double* psiI) {
     const int64_t N = p->N;
     std::vector<R> tmp(N);
     double* outs[2] = {psiR, psiI};
-    size_t offs[2] = {p->L.psiR, p->L.psiI};
+    const char* srcs[2] = {p->fR, p->fI};
     for (int k = 0; k < 2; ++k) {
         if (!outs[k]) continue;
-        HIPCHK(hipMemcpyAsync(tmp.data(), p->ws + offs[k], N * sizeof(R), hipMemcpyDeviceToHost, p->st));
+        HIPCHK(hipMemcpyAsync(tmp.data(), srcs[k], N * sizeof(R), hipMemcpyDeviceToHost, p->st));
         HIPCHK(hipStreamSynchronize(p->st));
         for (int64_t i = 0; i < N; ++i) outs[k][i] = (double)tmp[i];
     }
@@ -822,6 +849,10 @@ spstd_status spstd_plan(const spstd_desc* desc, const double* V, const double* p
     p->esz = desc->precision == SPSTD_FP64 ? 8 : 4;
     p->ws = (char*)d_workspace;
     p->L = L;
+    p->fR = p->ws + L.psiR;
+    p->fI = p->ws + L.psiI;
+    p->fV = p->ws + L.V;
+    p->prb = reinterpret_cast<double*>(p->ws + L.probes);
     p->st = (hipStream_t)stream;
     p->graph_ready = false;
     p->cellvol = 1.0;
@@ -853,12 +884,20 @@ spstd_status spstd_run(spstd_plan_t p, int64_t nsteps, double* probe_out, spstd_
     if (s != SPSTD_OK) return s;
     s = (p->esz == 8) ? compute_norm<double>(p, &p->norm) : compute_norm<float>(p, &p->norm);
     if (s != SPSTD_OK) return s;
-    if (probe_out && p->d.nprobes > 0) {
-        const size_t bytes = sizeof(double) * 2 * p->d.nprobes * (size_t)(p->steps_done + 1);
-        hipError_t e = hipMemcpyAsync(probe_out, p->ws + p->L.probes, bytes, hipMemcpyDeviceToHost, p->st);
+    if (p->d.nprobes > 0) {
+        int fault = 0;
+        hipError_t e = hipMemcpyAsync(&fault, fault_flag(p), sizeof(int), hipMemcpyDeviceToHost, p->st);
+        if (e == hipSuccess && probe_out) {
+            const size_t bytes = sizeof(double) * 2 * p->d.nprobes * (size_t)(p->steps_done + 1);
+            e = hipMemcpyAsync(probe_out, p->prb, bytes, hipMemcpyDeviceToHost, p->st);
+        }
         if (e == hipSuccess) e = hipStreamSynchronize(p->st);
         if (e != hipSuccess) {
             p->err = hipGetErrorString(e);
+            return SPSTD_ERR_DEVICE;
+        }
+        if (fault) {
+            p->err = "a probe index in device memory lies outside the grid (samples skipped)";
             return SPSTD_ERR_DEVICE;
         }
     }
@@ -939,10 +978,10 @@ spstd_status spstd_plan_info(spstd_plan_t p, spstd_stats* st) {
 
 spstd_status spstd_device_fields(spstd_plan_t p, void** psiR, void** psiI, void** V, double** probes) {
     if (!p) return SPSTD_ERR_ARG;
-    if (psiR) *psiR = p->ws + p->L.psiR;
-    if (psiI) *psiI = p->ws + p->L.psiI;
-    if (V) *V = p->ws + p->L.V;
-    if (probes) *probes = reinterpret_cast<double*>(p->ws + p->L.probes);
+    if (psiR) *psiR = p->fR;
+    if (psiI) *psiI = p->fI;
+    if (V) *V = p->fV;
+    if (probes) *probes = p->prb;
     return SPSTD_OK;
 }
 
@@ -957,23 +996,25 @@ spstd_status spstd_set_state(spstd_plan_t p, const double* psiR, const double* p
     if (!p || !psiR || step < 0 || step > p->nsteps_max) return SPSTD_ERR_ARG;
     for (int64_t i = 0; i < p->N; ++i)
         if (!std::isfinite(psiR[i]) || (psiI && !std::isfinite(psiI[i]))) return SPSTD_ERR_ARG;
-    spstd_status s = (p->esz == 8) ? upload<double>(p, p->L.psiR, psiR) : upload<float>(p, p->L.psiR, psiR);
+    spstd_status s = (p->esz == 8) ? upload<double>(p, p->fR, psiR) : upload<float>(p, p->fR, psiR);
     if (s == SPSTD_OK)
-        s = (p->esz == 8) ? upload<double>(p, p->L.psiI, psiI) : upload<float>(p, p->L.psiI, psiI);
+        s = (p->esz == 8) ? upload<double>(p, p->fI, psiI) : upload<float>(p, p->fI, psiI);
     if (s != SPSTD_OK) return s;
     // the next sample goes to slot step + 1; slot `step` holds this state
     int64_t next = step;
     hipError_t e = hipMemcpyAsync(p->ws + p->L.counter, &next, sizeof(next), hipMemcpyHostToDevice, p->st);
     if (e == hipSuccess && p->d.nprobes > 0) {
         e = (p->esz == 8)
-                ? launch_probe<double>(F<double>(p, p->L.psiR), F<double>(p, p->L.psiI),
-                                       reinterpret_cast<const int64_t*>(p->ws + p->L.pidx), p->d.nprobes,
-                                       reinterpret_cast<double*>(p->ws + p->L.probes),
-                                       reinterpret_cast<int64_t*>(p->ws + p->L.counter), p->nsteps_max + 1, p->st)
-                : launch_probe<float>(F<float>(p, p->L.psiR), F<float>(p, p->L.psiI),
-                                      reinterpret_cast<const int64_t*>(p->ws + p->L.pidx), p->d.nprobes,
-                                      reinterpret_cast<double*>(p->ws + p->L.probes),
-                                      reinterpret_cast<int64_t*>(p->ws + p->L.counter), p->nsteps_max + 1, p->st);
+                ? launch_probe<double>(FR<double>(p), FI<double>(p),
+                                       reinterpret_cast<const int64_t*>(p->ws + p->L.pidx), p->d.nprobes, p->N,
+                                       p->prb,
+                                       reinterpret_cast<int64_t*>(p->ws + p->L.counter), p->nsteps_max + 1,
+                                       fault_flag(p), p->st)
+                : launch_probe<float>(FR<float>(p), FI<float>(p),
+                                      reinterpret_cast<const int64_t*>(p->ws + p->L.pidx), p->d.nprobes, p->N,
+                                      p->prb,
+                                      reinterpret_cast<int64_t*>(p->ws + p->L.counter), p->nsteps_max + 1,
+                                      fault_flag(p), p->st);
     }
     if (e == hipSuccess) e = hipStreamSynchronize(p->st);
     if (e != hipSuccess) {
@@ -1037,3 +1078,4 @@ const char* spstd_strerror(spstd_status s) {
 const char* spstd_last_error(spstd_plan_t p) { return p ? p->err.c_str() : "null plan"; }
 
 }  // extern "C"
+

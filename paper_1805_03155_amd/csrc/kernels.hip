@@ -1,800 +1,39 @@
-// SPSTD device kernels for gfx950 (MI355X).
-//
-// The kinetic part of K (Eq. 16) is a sum over axes, so the paper's update
-// (Eq. 18) applies one 1D spectral second derivative per axis (as Eq. 11-12
-// write it).  Each kernel here is one such directional pass over the whole
-// field: it loads pencils along its axis, runs the forward FFT, multiplies by
-// the real, even symbol coef*(hbar/2m*)*k^2/N, runs the inverse FFT, and adds
-// the result into the destination field.  Because the symbol is real and
-// even, the operator maps real fields to real fields, so two real pencils are
-// carried as one complex pencil (real and imaginary parts) at no extra cost.
-//
-// Passes of one stage l (Eq. 17-18, A(c_l) before B(d_l)):
-//   y: psi_R += c_l dt T_y psi_I          z: psi_R += c_l dt T_z psi_I
-//   x: psi_R += c_l dt (T_x psi_I + V psi_I / hbar), then on the same rows
-//      psi_I -= d_l dt (T_x psi_R + V psi_R / hbar)       (fused A and B)
-//   y: psi_I -= d_l dt T_y psi_R          z: psi_I -= d_l dt T_z psi_R
-#include <type_traits>
-
-#include "fft_core.hpp"
-#include "kernels.hpp"
+// SPSTD device kernels for gfx950 (MI355X): launchers of the directional
+// passes (passes.hpp), the small kernels (probes, norms, energy, walls,
+// the difference operator, eigenstate sums) and their launchers.
+#include "passes.hpp"
 
 namespace spstd {
 
 bool axis_len_ok(int64_t n) { return n >= 16 && n <= 1024 && (n & (n - 1)) == 0; }
 bool row_len_ok(int64_t n) { return n >= 16 && n <= 16384 && (n & (n - 1)) == 0; }
+// Walled axes whose mirrored line of 2n points is not one the FFT passes
+// take (a power of two of at least 32): the direct Fourier sum, n <= 32.
+bool wall_dft_len_ok(int64_t n) { return n >= 2 && n <= 32 && n != 16 && n != 32; }
 
-// Build-time tuning switches (defaults are the measured choices):
-//   TW_PRODUCTS_*  twiddles of a pass from two table reads and FP64 products
-//                  instead of one table read per twiddle (FP32 256^3 graph
-//                  step 1.58 -> 1.44 ms, FP32 512^2 batch 428 -> 319 us)
-//   SPLIT_*        real-then-imaginary LDS exchange (half the LDS per wave);
-//                  the fused FP32 x pass takes the joint exchange below
-//                  SPLIT_XAB_F32_FROM points per row, the other FP32 passes
-//                  gain occupancy from the split one
-//   WPB, WPB_F64_256  waves per block of the pass kernels (wpb_of)
-//   BA_RELOAD_*    the stage-boundary y sweep re-reads psi_R for its second
-//                  epilogue instead of keeping it in registers (measured
-//                  slower: 106 -> 121 us FP64, 65 -> 68 us FP32 at 256^3)
-//   YZ_PPL_F64, YZ_MIN_WAVES, YZ_NT  y/z pass variants measured slower
-//                  (two pencils per FP64 lane group, a forced 4 waves per
-//                  SIMD, non-temporal loads and stores)
-//   X_RELOAD, X_RELOAD_FROM  x passes re-read their inputs in the epilogue
-//                  instead of keeping them in registers through the
-//                  transforms, for all lengths or from X_RELOAD_FROM points
-//                  (16384: FP32 batch of 33 such rows 196 -> 178 us per
-//                  step; 8192 slower, 84 -> 93 us)
-//   MIN_WAVES      minimum waves per SIMD requested for the pass kernels (2
-//                  keeps the FP64 x passes of 512..2048-point rows out of
-//                  accumulation registers, at one wave per SIMD otherwise)
-//   YZ_PPL_F32     complex pencils per lane group in FP32 y/z passes
-//   EPI_CHUNK      epilogue elements scheduled together (caps the loads in
-//                  flight, and with them the registers)
-//   YZ_ACC_WAVES_*, YZ_BA_WAVES_F32, X_AB_WAVES_F32  minimum waves per SIMD of
-//                  the 256-point passes (yz_acc_waves and its kin).  Taken:
-//                  4 for the FP32 y/z pass.  Measured slower: 4 for the FP64
-//                  y/z pass (spills; z 70.5 -> 103 us), 3 or 4 for the FP32
-//                  boundary sweep (spills), 4 for the FP32 fused x pass
-//                  (54.7 -> 55.4 us); fewer FP64 y/z blocks per CU (4 or 2,
-//                  by unused dynamic LDS) slower too (z 70.5 -> 75.9, 99 us)
-//   BA_PPL_F32, BA_PPL_F32_LONG  complex pencils per lane group in the FP32
-//                  stage-boundary sweep up to 256 and from 512 points: one
-//                  (142 registers, three waves per SIMD) against two (248,
-//                  two waves) at 256: 256^3 sweep 59.1 -> 55.0 us; two at
-//                  512 (a 512^2 batch of 49: 316 against 352 us per step).
-//                  Reading psi_I together with psi_R at the start instead
-//                  of after the first transform pair was slower in both
-//                  precisions (FP32 58.9, with psi_R re-read and four waves
-//                  62.2; FP64 98.2 -> 124.4 us with psi_R re-read)
-//   YZ_EPI_BATCH_* y/z pass epilogues read YZ_CHUNK elements of the
-//                  accumulated field before writing any of them (element by
-//                  element, each read waits for the previous write: the
-//                  compiler cannot prove that the elements of one pencil are
-//                  distinct).  FP32 256^3: z 41.8 -> 41.3 us, boundary sweep
-//                  59.5 -> 58.1 us; FP64 slower (z 71.0 -> 73.3 us, sweep
-//                  98.6 -> 102.4 us); 8 or 16 reads at once slower in both
-//   EPI_FENCE      keep epilogue loads from being hoisted into the inverse
-//                  transform
-//   YZ_ORDER       0: consecutive blocks take neighbouring x column groups of
-//                  one (z or y) plane; 1: consecutive blocks take the same
-//                  column groups of neighbouring planes (spreads the
-//                  concurrently running blocks over more memory channels)
-#ifndef SPSTD_TW_PRODUCTS_F64
-#define SPSTD_TW_PRODUCTS_F64 1
-#endif
-#ifndef SPSTD_TW_PRODUCTS_F32
-#define SPSTD_TW_PRODUCTS_F32 1
-#endif
-#ifndef SPSTD_SPLIT_F64
-#define SPSTD_SPLIT_F64 1
-#endif
-#ifndef SPSTD_SPLIT_F32
-#define SPSTD_SPLIT_F32 1
-#endif
-#ifndef SPSTD_SPLIT_XAB_F32
-#define SPSTD_SPLIT_XAB_F32 0
-#endif
-#ifndef SPSTD_X_RELOAD_FROM
-#define SPSTD_X_RELOAD_FROM 16384
-#endif
-#ifndef SPSTD_X_RELOAD
-#define SPSTD_X_RELOAD 0
-#endif
-#ifndef SPSTD_MIN_WAVES
-#define SPSTD_MIN_WAVES 2
-#endif
-#ifndef SPSTD_YZ_PPL_F32
-#define SPSTD_YZ_PPL_F32 2
-#endif
-#ifndef SPSTD_YZ_PPL_F64
-#define SPSTD_YZ_PPL_F64 1
-#endif
-#ifndef SPSTD_YZ_MIN_WAVES
-#define SPSTD_YZ_MIN_WAVES 0
-#endif
-#ifndef SPSTD_YZ_NT
-#define SPSTD_YZ_NT 0
-#endif
-#ifndef SPSTD_BA_RELOAD_F64
-#define SPSTD_BA_RELOAD_F64 0
-#endif
-#ifndef SPSTD_BA_RELOAD_F32
-#define SPSTD_BA_RELOAD_F32 0
-#endif
-#ifndef SPSTD_V_NT_F64
-#define SPSTD_V_NT_F64 1
-#endif
-#ifndef SPSTD_V_NT_F32
-#define SPSTD_V_NT_F32 0
-#endif
-#ifndef SPSTD_WPB
-#define SPSTD_WPB 4
-#endif
-#ifndef SPSTD_WPB_F64_256
-#define SPSTD_WPB_F64_256 2
-#endif
-#ifndef SPSTD_SPLIT_XAB_F32_FROM
-#define SPSTD_SPLIT_XAB_F32_FROM 512
-#endif
-#ifndef SPSTD_EPI_CHUNK
-#define SPSTD_EPI_CHUNK 4
-#endif
-#ifndef SPSTD_YZ_ACC_WAVES_F32
-#define SPSTD_YZ_ACC_WAVES_F32 4
-#endif
-#ifndef SPSTD_YZ_ACC_WAVES_F64
-#define SPSTD_YZ_ACC_WAVES_F64 0
-#endif
-#ifndef SPSTD_YZ_BA_WAVES_F32
-#define SPSTD_YZ_BA_WAVES_F32 0
-#endif
-#ifndef SPSTD_X_AB_WAVES_F32
-#define SPSTD_X_AB_WAVES_F32 0
-#endif
-#ifndef SPSTD_BA_PPL_F32
-#define SPSTD_BA_PPL_F32 1
-#endif
-#ifndef SPSTD_BA_PPL_F32_LONG
-#define SPSTD_BA_PPL_F32_LONG 2
-#endif
-#ifndef SPSTD_YZ_EPI_BATCH_F64
-#define SPSTD_YZ_EPI_BATCH_F64 0
-#endif
-#ifndef SPSTD_YZ_EPI_BATCH_F32
-#define SPSTD_YZ_EPI_BATCH_F32 1
-#endif
-#ifndef SPSTD_YZ_CHUNK
-#define SPSTD_YZ_CHUNK 4
-#endif
-#ifndef SPSTD_EPI_FENCE
-#define SPSTD_EPI_FENCE 1
-#endif
-#ifndef SPSTD_YZ_ORDER
-#define SPSTD_YZ_ORDER 1
-#endif
-
-#if SPSTD_MIN_WAVES > 0
-#define SPSTD_WAVES_ATTR __attribute__((amdgpu_waves_per_eu(SPSTD_MIN_WAVES)))
-#else
-#define SPSTD_WAVES_ATTR
-#endif
-
-template <typename R>
-struct tuning;
-template <>
-struct tuning<double> {
-    static constexpr bool PRODUCTS = SPSTD_TW_PRODUCTS_F64;
-    static constexpr bool SPLIT = SPSTD_SPLIT_F64;
-    static constexpr bool SPLIT_XAB = SPSTD_SPLIT_F64;
-    static constexpr int YZ_PPL = SPSTD_YZ_PPL_F64;
-    static constexpr bool BA_RELOAD = SPSTD_BA_RELOAD_F64;
-    static constexpr bool V_NT = SPSTD_V_NT_F64;
-    static constexpr bool EPI_BATCH = SPSTD_YZ_EPI_BATCH_F64;
-    static constexpr int BA_PPL = 1;
-};
-template <>
-struct tuning<float> {
-    static constexpr bool PRODUCTS = SPSTD_TW_PRODUCTS_F32;
-    static constexpr bool SPLIT = SPSTD_SPLIT_F32;
-    static constexpr bool SPLIT_XAB = SPSTD_SPLIT_XAB_F32;
-    static constexpr int YZ_PPL = SPSTD_YZ_PPL_F32;
-    static constexpr bool BA_RELOAD = SPSTD_BA_RELOAD_F32;
-    static constexpr bool V_NT = SPSTD_V_NT_F32;
-    static constexpr bool EPI_BATCH = SPSTD_YZ_EPI_BATCH_F32;
-    static constexpr int BA_PPL = SPSTD_BA_PPL_F32;
-};
-
-// Minimum waves per SIMD requested for the 256-point pass kernels (a value
-// of 0 leaves the general setting).  A 256^3 FP32 y/z pass is 16 waves per
-// CU: at 137 registers three waves per SIMD fit, which leaves a second round
-// a third full; capped at 128 registers all 16 run at once (z 41.4 -> 35.6
-// us).
-template <typename R, int N>
-constexpr int yz_acc_waves() {
-    const int k = N != 256 ? 0 : sizeof(R) == 4 ? SPSTD_YZ_ACC_WAVES_F32 : SPSTD_YZ_ACC_WAVES_F64;
-    return k > 0 ? k : SPSTD_YZ_MIN_WAVES > 0 ? SPSTD_YZ_MIN_WAVES : SPSTD_MIN_WAVES > 0 ? SPSTD_MIN_WAVES : 1;
-}
-template <typename R, int N>
-constexpr int yz_ba_waves() {
-    const int k = N != 256 ? 0 : sizeof(R) == 4 ? SPSTD_YZ_BA_WAVES_F32 : 0;
-    return k > 0 ? k : SPSTD_YZ_MIN_WAVES > 0 ? SPSTD_YZ_MIN_WAVES : SPSTD_MIN_WAVES > 0 ? SPSTD_MIN_WAVES : 1;
-}
-template <typename R, int N>
-constexpr int x_ab_waves() {
-    const int k = N != 256 ? 0 : sizeof(R) == 4 ? SPSTD_X_AB_WAVES_F32 : 0;
-    return k > 0 ? k : SPSTD_MIN_WAVES > 0 ? SPSTD_MIN_WAVES : 1;
-}
-
-// The potential is read once per x pass.  In FP64 the three fields of a
-// 256^3 grid (403 MB) exceed the 256 MB last-level cache, and reading V
-// without keeping it there leaves the cache to psi_R and psi_I, which the
-// next pass reads (the z pass after the fused x pass: 86 -> 71 us); in FP32
-// the fields fit and V is better cached (non-temporal V: x pass 63 -> 80 us).
-template <typename R>
-__device__ __forceinline__ R load_v(const R* p) {
-    if constexpr (tuning<R>::V_NT) return __builtin_nontemporal_load(p);
-    else return *p;
-}
-
-// x passes re-read their inputs in the epilogue (instead of keeping them in
-// registers through the transforms) for every length with X_RELOAD, else
-// from X_RELOAD_FROM points: a 16384-point row runs 1024 lanes per block,
-// which caps a lane at 128 registers
-template <int N>
-constexpr bool x_reload() { return SPSTD_X_RELOAD || N >= SPSTD_X_RELOAD_FROM; }
-
-// Compiler-only memory barrier: values loaded before it are not reused
-// after it (the epilogues re-read their inputs rather than keep them live
-// in registers through the transforms).
-__device__ __forceinline__ void reload_fence() { asm volatile("" ::: "memory"); }
-
-// Start of an epilogue: its loads stay below the inverse transform.
-__device__ __forceinline__ void epi_begin() {
-    if constexpr (SPSTD_EPI_FENCE) asm volatile("" ::: "memory");
-}
-
-// Scheduling fence after every EPI_CHUNK-th epilogue element.
-__device__ __forceinline__ void epi_fence(int e) {
-    if constexpr (SPSTD_EPI_CHUNK < 16) {
-        if ((e + 1) % SPSTD_EPI_CHUNK == 0) __builtin_amdgcn_sched_barrier(0);
-    }
-}
-
-// Multiply bins kk = j + T*e by ks^2 (ks the signed bin index); under the
-// ZERO convention the Nyquist bin kk = N/2 is removed.  The instance's
-// scale is applied after the inverse transform.
-template <typename R, int N>
-__device__ __forceinline__ void apply_k2(cpx<R> (&v)[16], int j, int nyq_zero) {
-    constexpr int T = N / 16;
-#pragma unroll
-    for (int e = 0; e < 16; ++e) {
-        const int kk = j + T * e;
-        const int ks = (kk <= N / 2) ? kk : kk - N;
-        R s = (R)(ks * ks);
-        if (nyq_zero && kk == N / 2) s = (R)0;
-        v[e].x *= s;
-        v[e].y *= s;
-    }
-}
-
-template <typename R>
-__device__ __forceinline__ R scale_of(const ScaleRef& sc, int64_t inst, int col) {
-    return reinterpret_cast<const R*>(sc.tab)[(inst * sc.m + sc.l) * SC_COLS + col];
-}
-
-// Lanes per pencil T = N/16; lane groups per wave for N <= 1024.
-template <int N>
-struct pencil_cfg {
-    static constexpr int T = N / 16;
-    static constexpr bool WAVE = T <= 64;
-    static constexpr int PPW = WAVE ? 64 / T : 1;
-};
-
-// Vector of 2*P reals: P complex pencils of a lane group.
-template <typename R, int P>
-struct vec_of;
-template <>
-struct vec_of<double, 1> { using type = double2; };
-template <>
-struct vec_of<float, 1> { using type = float2; };
-template <>
-struct vec_of<double, 2> { using type = double4; };
-template <>
-struct vec_of<float, 2> { using type = float4; };
-
-// Streaming variant: the passes touch each element once, so the loads and
-// stores may bypass cache retention (SPSTD_YZ_NT).
-template <typename R, int P>
-using ext_vec = R __attribute__((ext_vector_type(2 * P)));
-
-template <typename R, int P>
-__device__ __forceinline__ void load_group(const R* src, cpx<R> (&v)[P][16], int e) {
-    if constexpr (SPSTD_YZ_NT) {
-        const ext_vec<R, P> a = __builtin_nontemporal_load(reinterpret_cast<const ext_vec<R, P>*>(src));
-#pragma unroll
-        for (int q = 0; q < P; ++q) v[q][e] = cpx<R>{a[2 * q], a[2 * q + 1]};
-        return;
-    }
-    using V = typename vec_of<R, P>::type;
-    const V a = *reinterpret_cast<const V*>(src);
-    if constexpr (P == 1) {
-        v[0][e] = cpx<R>{a.x, a.y};
-    } else {
-        v[0][e] = cpx<R>{a.x, a.y};
-        v[1][e] = cpx<R>{a.z, a.w};
-    }
-}
-
-template <typename R, int P>
-__device__ __forceinline__ void add_group(R* dst, const cpx<R> (&v)[P][16], int e) {
-    if constexpr (SPSTD_YZ_NT) {
-        ext_vec<R, P>* q = reinterpret_cast<ext_vec<R, P>*>(dst);
-        ext_vec<R, P> a = __builtin_nontemporal_load(q);
-#pragma unroll
-        for (int k = 0; k < P; ++k) {
-            a[2 * k] += v[k][e].x;
-            a[2 * k + 1] += v[k][e].y;
-        }
-        __builtin_nontemporal_store(a, q);
-        return;
-    }
-    using V = typename vec_of<R, P>::type;
-    V* q = reinterpret_cast<V*>(dst);
-    V a = *q;
-    if constexpr (P == 1) {
-        a.x += v[0][e].x; a.y += v[0][e].y;
-    } else {
-        a.x += v[0][e].x; a.y += v[0][e].y;
-        a.z += v[1][e].x; a.w += v[1][e].y;
-    }
-    *q = a;
-}
-
-// a += s * (the P complex values of element e), as one vector of 2P reals
-template <typename R, int P>
-__device__ __forceinline__ void add_vec(typename vec_of<R, P>::type& a, const cpx<R> (&v)[P][16], int e, R s) {
-    if constexpr (P == 1) {
-        a.x += s * v[0][e].x; a.y += s * v[0][e].y;
-    } else {
-        a.x += s * v[0][e].x; a.y += s * v[0][e].y;
-        a.z += s * v[1][e].x; a.w += s * v[1][e].y;
-    }
-}
-
-// ---------------------------------------------------------------------------
-// y / z pass: dst += T_axis src.  A lane group carries P complex pencils
-// (2P neighbouring x columns, one vector load per element).  Lane l of a
-// wave: group g = l % PPW (the fast index, so neighbouring lanes read
-// neighbouring columns), position j = l / PPW.
-// ---------------------------------------------------------------------------
-template <typename R, int N, int WPB, int P>
-__global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(yz_acc_waves<R, N>()))) void k_axis_acc(
-    const R* __restrict__ src, R* __restrict__ dst, const cpx<double>* __restrict__ tw, AxisGeom g,
-    ScaleRef sc, int col, int nyq_zero) {
-    using C = pencil_cfg<N>;
-    using TU = tuning<R>;
-    static_assert(C::WAVE, "y/z pencils must fit in one wavefront");
-    constexpr int LS = lds_size<N>::value;
-    constexpr int SL = (TU::SPLIT ? 1 : 2) * LS;
-    __shared__ R lds[N == 16 ? 1 : WPB * C::PPW * P * SL];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int p = lane % C::PPW, j = lane / C::PPW;
-    const int64_t groups_x = g.half_x / P;
-    const int64_t ngroups = groups_x * g.n_outer;
-    constexpr int GPB = WPB * C::PPW;                 // lane groups per block
-    int64_t group;
-    if (SPSTD_YZ_ORDER == 1 && groups_x % GPB == 0) {
-        // block b: plane b mod n_outer, column block b / n_outer
-        const int64_t b = blockIdx.x;
-        group = ((b % g.n_outer) * (groups_x / GPB) + b / g.n_outer) * GPB + wave * C::PPW + p;
-    } else {
-        group = ((int64_t)blockIdx.x * WPB + wave) * C::PPW + p;
-    }
-    const bool valid = group < ngroups;
-    const int64_t gx = valid ? group % groups_x : 0, outer = valid ? group / groups_x : 0;
-    const int64_t inst = outer / g.n_in;
-    const int64_t base = inst * g.stride_hi + (outer - inst * g.n_in) * g.stride_lo + 2 * P * gx;
-    const R scale = scale_of<R>(sc, inst, col);
-    // a free batch slot has zero scales: a wave with nothing to update leaves
-    // (its LDS barriers are wave-local)
-    if (__all(!valid || scale == (R)0)) return;
-
-    cpx<R> v[P][16];
-#pragma unroll
-    for (int e = 0; e < 16; ++e) {
-        if (valid) {
-            load_group<R, P>(src + base + (int64_t)(j + C::T * e) * g.stride, v, e);
-        } else {
-#pragma unroll
-            for (int q = 0; q < P; ++q) v[q][e] = cpx<R>{(R)0, (R)0};
-        }
-    }
-    R* l0 = lds + (wave * C::PPW + p) * P * SL;
-    fft_pencils<R, N, false, true, TU::SPLIT, TU::PRODUCTS, P, C::PPW>(v, j, l0, SL, tw);
-#pragma unroll
-    for (int q = 0; q < P; ++q) apply_k2<R, N>(v[q], j, nyq_zero);
-    fft_pencils<R, N, true, true, TU::SPLIT, TU::PRODUCTS, P, C::PPW>(v, j, l0, SL, tw);
-    epi_begin();
-    if (valid) {
-#pragma unroll
-        for (int q = 0; q < P; ++q) {
-#pragma unroll
-            for (int e = 0; e < 16; ++e) {
-                v[q][e].x *= scale;
-                v[q][e].y *= scale;
-            }
-        }
-        if constexpr (TU::EPI_BATCH && !SPSTD_YZ_NT) {
-            using V = typename vec_of<R, P>::type;
-            constexpr int CH = SPSTD_YZ_CHUNK;
-#pragma unroll
-            for (int e0 = 0; e0 < 16; e0 += CH) {
-                V a[CH];
-#pragma unroll
-                for (int k = 0; k < CH; ++k)
-                    a[k] = *reinterpret_cast<const V*>(dst + base + (int64_t)(j + C::T * (e0 + k)) * g.stride);
-#pragma unroll
-                for (int k = 0; k < CH; ++k) {
-                    add_vec<R, P>(a[k], v, e0 + k, (R)1);
-                    *reinterpret_cast<V*>(dst + base + (int64_t)(j + C::T * (e0 + k)) * g.stride) = a[k];
-                }
-                __builtin_amdgcn_sched_barrier(0);
-            }
-        } else {
-#pragma unroll
-            for (int e = 0; e < 16; ++e) {
-                add_group<R, P>(dst + base + (int64_t)(j + C::T * e) * g.stride, v, e);
-                epi_fence(e);
-            }
-        }
-    }
-}
-
-// ---------------------------------------------------------------------------
-// y pass at a stage boundary: the B half of stage l and the A half of stage
-// l + 1 along the same pencils in one sweep,
-//   psi_I += sB T_y psi_R,  then  psi_R += sA T_y psi_I(new).
-// With the B half ordered x, z, y and the A half y, z, x, the y pencil of
-// psi_I holds its x and z contributions of stage l when its y contribution
-// is added, so the pencil is complete in registers when the A half of stage
-// l + 1 transforms it.  Reads psi_R, psi_I; writes both (32 B per point in
-// FP64 against 48 B for the two passes it replaces).
-// ---------------------------------------------------------------------------
-template <typename R, int N, int WPB, int P>
-__global__ __launch_bounds__(64 * WPB) __attribute__((amdgpu_waves_per_eu(yz_ba_waves<R, N>()))) void k_axis_ba(
-    R* __restrict__ psiR, R* __restrict__ psiI, const cpx<double>* __restrict__ tw, AxisGeom g,
-    ScaleRef scB, ScaleRef scA, int colB, int colA, int nyq_zero) {
-    using C = pencil_cfg<N>;
-    using TU = tuning<R>;
-    using V = typename vec_of<R, P>::type;
-    static_assert(C::WAVE, "y/z pencils must fit in one wavefront");
-    constexpr int LS = lds_size<N>::value;
-    constexpr int SL = (TU::SPLIT ? 1 : 2) * LS;
-    __shared__ R lds[N == 16 ? 1 : WPB * C::PPW * P * SL];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int p = lane % C::PPW, j = lane / C::PPW;
-    const int64_t groups_x = g.half_x / P;
-    const int64_t ngroups = groups_x * g.n_outer;
-    constexpr int GPB = WPB * C::PPW;
-    int64_t group;
-    if (SPSTD_YZ_ORDER == 1 && groups_x % GPB == 0) {
-        const int64_t b = blockIdx.x;
-        group = ((b % g.n_outer) * (groups_x / GPB) + b / g.n_outer) * GPB + wave * C::PPW + p;
-    } else {
-        group = ((int64_t)blockIdx.x * WPB + wave) * C::PPW + p;
-    }
-    const bool valid = group < ngroups;
-    const int64_t gx = valid ? group % groups_x : 0, outer = valid ? group / groups_x : 0;
-    const int64_t inst = outer / g.n_in;
-    const int64_t base = inst * g.stride_hi + (outer - inst * g.n_in) * g.stride_lo + 2 * P * gx;
-    const R sB = scale_of<R>(scB, inst, colB), sA = scale_of<R>(scA, inst, colA);
-    if (__all(!valid || (sB == (R)0 && sA == (R)0))) return;
-
-    constexpr bool RL = TU::BA_RELOAD;
-    cpx<R> v[P][16], f[P][RL ? 1 : 16];
-#pragma unroll
-    for (int e = 0; e < 16; ++e) {
-        if (valid) {
-            load_group<R, P>(psiR + base + (int64_t)(j + C::T * e) * g.stride, v, e);
-        } else {
-#pragma unroll
-            for (int q = 0; q < P; ++q) v[q][e] = cpx<R>{(R)0, (R)0};
-        }
-        if constexpr (!RL) {
-#pragma unroll
-            for (int q = 0; q < P; ++q) f[q][e] = v[q][e];
-        }
-    }
-    if constexpr (RL) reload_fence();
-    R* l0 = lds + (wave * C::PPW + p) * P * SL;
-    // B half of stage l: psi_I += sB T psi_R
-    fft_pencils<R, N, false, true, TU::SPLIT, TU::PRODUCTS, P, C::PPW>(v, j, l0, SL, tw);
-#pragma unroll
-    for (int q = 0; q < P; ++q) apply_k2<R, N>(v[q], j, nyq_zero);
-    fft_pencils<R, N, true, true, TU::SPLIT, TU::PRODUCTS, P, C::PPW>(v, j, l0, SL, tw);
-    epi_begin();
-    if constexpr (TU::EPI_BATCH) {
-        constexpr int CH = SPSTD_YZ_CHUNK;
-#pragma unroll
-        for (int e0 = 0; e0 < 16; e0 += CH) {
-            V a[CH];
-#pragma unroll
-            for (int k = 0; k < CH; ++k) {
-                a[k] = V{};
-                if (valid) a[k] = *reinterpret_cast<const V*>(psiI + base + (int64_t)(j + C::T * (e0 + k)) * g.stride);
-            }
-#pragma unroll
-            for (int k = 0; k < CH; ++k) {
-                add_vec<R, P>(a[k], v, e0 + k, sB);
-                v[0][e0 + k] = cpx<R>{a[k].x, a[k].y};
-                if constexpr (P == 2) v[1][e0 + k] = cpx<R>{a[k].z, a[k].w};
-                if (valid) *reinterpret_cast<V*>(psiI + base + (int64_t)(j + C::T * (e0 + k)) * g.stride) = a[k];
-            }
-            __builtin_amdgcn_sched_barrier(0);
-        }
-    } else {
-#pragma unroll
-        for (int e = 0; e < 16; ++e) {
-            V a{};
-            V* q = reinterpret_cast<V*>(psiI + base + (int64_t)(j + C::T * e) * g.stride);
-            if (valid) a = *q;
-            if constexpr (P == 1) {
-                a.x += sB * v[0][e].x; a.y += sB * v[0][e].y;
-                v[0][e] = cpx<R>{a.x, a.y};
-            } else {
-                a.x += sB * v[0][e].x; a.y += sB * v[0][e].y;
-                a.z += sB * v[1][e].x; a.w += sB * v[1][e].y;
-                v[0][e] = cpx<R>{a.x, a.y};
-                v[1][e] = cpx<R>{a.z, a.w};
-            }
-            if (valid) *q = a;
-            epi_fence(e);
-        }
-    }
-    // A half of stage l + 1: psi_R += sA T psi_I(new)
-    fft_pencils<R, N, false, true, TU::SPLIT, TU::PRODUCTS, P, C::PPW>(v, j, l0, SL, tw);
-#pragma unroll
-    for (int q = 0; q < P; ++q) apply_k2<R, N>(v[q], j, nyq_zero);
-    fft_pencils<R, N, true, true, TU::SPLIT, TU::PRODUCTS, P, C::PPW>(v, j, l0, SL, tw);
-    epi_begin();
-    if (valid) {
-#pragma unroll
-        for (int e = 0; e < 16; ++e) {
-            V* q = reinterpret_cast<V*>(psiR + base + (int64_t)(j + C::T * e) * g.stride);
-            V a;
-            if constexpr (RL) {
-                a = *q;   // psi_R as loaded at the start (unchanged in memory)
-                if constexpr (P == 1) {
-                    a.x += sA * v[0][e].x; a.y += sA * v[0][e].y;
-                } else {
-                    a.x += sA * v[0][e].x; a.y += sA * v[0][e].y;
-                    a.z += sA * v[1][e].x; a.w += sA * v[1][e].y;
-                }
-            } else if constexpr (P == 1) {
-                a.x = f[0][e].x + sA * v[0][e].x; a.y = f[0][e].y + sA * v[0][e].y;
-            } else {
-                a.x = f[0][e].x + sA * v[0][e].x; a.y = f[0][e].y + sA * v[0][e].y;
-                a.z = f[1][e].x + sA * v[1][e].x; a.w = f[1][e].y + sA * v[1][e].y;
-            }
-            *q = a;
-            epi_fence(e);
-        }
-    }
-}
-
-// ---------------------------------------------------------------------------
-// x pass helpers: lane l -> position j = l % T, pencil-in-wave p = l / T
-// (neighbouring lanes read neighbouring x), or one pencil per block for
-// N > 1024.
-// ---------------------------------------------------------------------------
-template <typename R, int N, int WPB, bool SPLIT_PREF = tuning<R>::SPLIT>
-struct row_map {
-    using C = pencil_cfg<N>;
-    static constexpr int PPB = C::WAVE ? WPB * C::PPW : 1;   // pencils per block
-    static constexpr int THREADS = C::WAVE ? 64 * WPB : C::T;
-    static constexpr int LS = lds_size<N>::value;
-    // large pencils always exchange re and im in turn to stay within LDS
-    static constexpr bool SPLIT = C::WAVE ? SPLIT_PREF : true;
-    static constexpr int SL = (SPLIT ? 1 : 2) * LS;
-    // a 16-point pencil is one radix-16 pass in registers: no LDS at all
-    static constexpr int LDS_REALS = N == 16 ? 1 : PPB * SL;
-};
-
-// Row pair of this lane: rows 2q and 2q + 1 with q = block_pair0 + pin_block.
-// Fields are addressed as (block-uniform pointer) + (32-bit lane offset) +
-// (compile-time element offset), so one VGPR holds a lane's address.
-template <typename R, int N, int WPB>
-struct row_lane {
-    int j;            // position in the pencil
-    int pin_block;    // pencil index within the block
-    int64_t q;        // global pencil (row pair) index
-    int64_t row0;     // first row of the block (uniform)
-    int off;          // lane offset of row 2q, element j, from row0
-};
-
-template <typename R, int N, int WPB>
-__device__ __forceinline__ row_lane<R, N, WPB> row_coords() {
-    using C = pencil_cfg<N>;
-    row_lane<R, N, WPB> L;
-    if constexpr (C::WAVE) {
-        const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-        L.j = lane % C::T;
-        L.pin_block = wave * C::PPW + lane / C::T;
-    } else {
-        L.j = threadIdx.x;
-        L.pin_block = 0;
-    }
-    L.q = (int64_t)blockIdx.x * row_map<R, N, WPB>::PPB + L.pin_block;
-    L.row0 = (int64_t)blockIdx.x * row_map<R, N, WPB>::PPB * 2;
-    L.off = 2 * L.pin_block * N + L.j;
-    return L;
-}
-
-// FULL: every row pair of every block exists (no per-lane guards, so the
-// epilogue's loads can be batched); otherwise rows past nrows are skipped.
-template <typename R, int N, int WPB, bool FULL>
-__global__ __launch_bounds__((row_map<R, N, WPB>::THREADS)) SPSTD_WAVES_ATTR void k_x_acc(
-    const R* __restrict__ src, R* __restrict__ dst, const R* __restrict__ V,
-    const cpx<double>* __restrict__ tw, RowGeom rg, ScaleRef sc, int kcol, int pcol, int nyq_zero) {
-    using C = pencil_cfg<N>;
-    using M = row_map<R, N, WPB>;
-    using TU = tuning<R>;
-    __shared__ R lds[M::LDS_REALS];
-    const row_lane<R, N, WPB> L = row_coords<R, N, WPB>();
-    const int j = L.j;
-    const int64_t nrows = rg.nrows;
-    const bool v0 = FULL || 2 * L.q < nrows, v1 = FULL || 2 * L.q + 1 < nrows;
-    const int64_t inst0 = v0 ? (2 * L.q) / rg.rows_per_inst : 0;
-    const int64_t inst1 = v1 ? (2 * L.q + 1) / rg.rows_per_inst : inst0;
-    {
-        // rows of free batch slots (zero scales) need no work; the test is
-        // uniform over the wave, or over the workgroup for one-pencil blocks
-        const bool idle = scale_of<R>(sc, inst0, kcol) == (R)0 && scale_of<R>(sc, inst1, kcol) == (R)0 &&
-                          scale_of<R>(sc, inst0, pcol) == (R)0 && scale_of<R>(sc, inst1, pcol) == (R)0;
-        if (__all(idle)) return;
-    }
-    const int64_t b = L.row0 * N;
-    const R* __restrict__ sb = src + b;
-    R* __restrict__ db = dst + b;
-    const R* __restrict__ Vb = V + b;
-    const int o0 = L.off, o1 = L.off + N;
-    constexpr bool RL = x_reload<N>();
-    cpx<R> v[1][16];
-    R f0[RL ? 1 : 16], f1[RL ? 1 : 16];
-#pragma unroll
-    for (int e = 0; e < 16; ++e) {
-        const R a = v0 ? sb[o0 + C::T * e] : (R)0;
-        const R c = v1 ? sb[o1 + C::T * e] : (R)0;
-        v[0][e] = cpx<R>{a, c};
-        if constexpr (!RL) {
-            f0[e] = a;
-            f1[e] = c;
-        }
-    }
-    if constexpr (RL) reload_fence();
-    R* l0 = lds + L.pin_block * M::SL;
-    fft_pencils<R, N, false, C::WAVE, M::SPLIT, TU::PRODUCTS, 1, 1>(v, j, l0, M::SL, tw);
-    apply_k2<R, N>(v[0], j, nyq_zero);
-    fft_pencils<R, N, true, C::WAVE, M::SPLIT, TU::PRODUCTS, 1, 1>(v, j, l0, M::SL, tw);
-    epi_begin();
-    const R k0 = scale_of<R>(sc, inst0, kcol), p0 = scale_of<R>(sc, inst0, pcol);
-    const R k1 = scale_of<R>(sc, inst1, kcol), p1 = scale_of<R>(sc, inst1, pcol);
-#pragma unroll
-    for (int e = 0; e < 16; ++e) {
-        const int i0 = o0 + C::T * e, i1 = o1 + C::T * e;
-        R a, c;
-        if constexpr (RL) {
-            a = v0 ? sb[i0] : (R)0;
-            c = v1 ? sb[i1] : (R)0;
-        } else {
-            a = f0[e];
-            c = f1[e];
-        }
-        if (v0) db[i0] = db[i0] + k0 * v[0][e].x + p0 * load_v(Vb + i0) * a;
-        if (v1) db[i1] = db[i1] + k1 * v[0][e].y + p1 * load_v(Vb + i1) * c;
-        epi_fence(e);
-    }
-}
-
-template <typename R, int N, int WPB, bool FULL>
-__global__ __launch_bounds__((row_map<R, N, WPB>::THREADS)) __attribute__((amdgpu_waves_per_eu(x_ab_waves<R, N>()))) void k_x_ab(
-    R* __restrict__ psiR, R* __restrict__ psiI, const R* __restrict__ V,
-    const cpx<double>* __restrict__ tw, RowGeom rg, ScaleRef sc, int nyq_zero) {
-    using C = pencil_cfg<N>;
-    // FP32: the joint exchange up to 256-point rows, the split one beyond
-    // (512^2 batch 463 -> 428 us per step; 256^3 x pass 63 -> 75 us split)
-    using M = row_map<R, N, WPB, (sizeof(R) == 4 ? (N >= SPSTD_SPLIT_XAB_F32_FROM) : tuning<R>::SPLIT_XAB)>;
-    using TU = tuning<R>;
-    __shared__ R lds[M::LDS_REALS];
-    const row_lane<R, N, WPB> L = row_coords<R, N, WPB>();
-    const int j = L.j;
-    const int64_t nrows = rg.nrows;
-    const bool v0 = FULL || 2 * L.q < nrows, v1 = FULL || 2 * L.q + 1 < nrows;
-    const int64_t inst0 = v0 ? (2 * L.q) / rg.rows_per_inst : 0;
-    const int64_t inst1 = v1 ? (2 * L.q + 1) / rg.rows_per_inst : inst0;
-    {
-        const bool idle = scale_of<R>(sc, inst0, SC_KXA) == (R)0 && scale_of<R>(sc, inst1, SC_KXA) == (R)0 &&
-                          scale_of<R>(sc, inst0, SC_KXB) == (R)0 && scale_of<R>(sc, inst1, SC_KXB) == (R)0;
-        if (__all(idle)) return;
-    }
-    const int64_t b = L.row0 * N;
-    R* __restrict__ Rb = psiR + b;
-    R* __restrict__ Ib = psiI + b;
-    const R* __restrict__ Vb = V + b;
-    const int o0 = L.off, o1 = L.off + N;
-    constexpr bool RL = x_reload<N>();
-    cpx<R> v[1][16];
-    cpx<R> f[RL ? 1 : 16];   // psi_I on entry; later psi_I + vb * V * psi_R(new)
-#pragma unroll
-    for (int e = 0; e < 16; ++e) {
-        v[0][e].x = v0 ? Ib[o0 + C::T * e] : (R)0;
-        v[0][e].y = v1 ? Ib[o1 + C::T * e] : (R)0;
-        if constexpr (!RL) f[e] = v[0][e];
-    }
-    if constexpr (RL) reload_fence();
-    R* l0 = lds + L.pin_block * M::SL;
-    // A half: psi_R += T_x^A psi_I + p_A V psi_I
-    fft_pencils<R, N, false, C::WAVE, M::SPLIT, TU::PRODUCTS, 1, 1>(v, j, l0, M::SL, tw);
-    apply_k2<R, N>(v[0], j, nyq_zero);
-    fft_pencils<R, N, true, C::WAVE, M::SPLIT, TU::PRODUCTS, 1, 1>(v, j, l0, M::SL, tw);
-    epi_begin();
-    const cpx<R> sa = {scale_of<R>(sc, inst0, SC_KXA), scale_of<R>(sc, inst1, SC_KXA)};
-    const cpx<R> va = {scale_of<R>(sc, inst0, SC_PA), scale_of<R>(sc, inst1, SC_PA)};
-    const cpx<R> sb = {scale_of<R>(sc, inst0, SC_KXB), scale_of<R>(sc, inst1, SC_KXB)};
-    const cpx<R> vb = {scale_of<R>(sc, inst0, SC_PB), scale_of<R>(sc, inst1, SC_PB)};
-#pragma unroll
-    for (int e = 0; e < 16; ++e) {
-        const int i0 = o0 + C::T * e, i1 = o1 + C::T * e;
-        cpx<R> vv = {(R)0, (R)0}, g = {(R)0, (R)0}, fe;
-        if constexpr (RL) fe = cpx<R>{v0 ? Ib[i0] : (R)0, v1 ? Ib[i1] : (R)0};
-        else fe = f[e];
-        if (v0) { vv.x = load_v(Vb + i0); g.x = Rb[i0]; }
-        if (v1) { vv.y = load_v(Vb + i1); g.y = Rb[i1]; }
-        g.x = g.x + sa.x * v[0][e].x + va.x * vv.x * fe.x;
-        g.y = g.y + sa.y * v[0][e].y + va.y * vv.y * fe.y;
-        if (v0) Rb[i0] = g.x;
-        if (v1) Rb[i1] = g.y;
-        v[0][e] = g;
-        if constexpr (!RL) {
-            f[e].x = fe.x + vb.x * vv.x * g.x;
-            f[e].y = fe.y + vb.y * vv.y * g.y;
-        }
-        epi_fence(e);
-    }
-    if constexpr (RL) reload_fence();
-    // B half: psi_I += T_x^B psi_R(new) + p_B V psi_R(new)
-    fft_pencils<R, N, false, C::WAVE, M::SPLIT, TU::PRODUCTS, 1, 1>(v, j, l0, M::SL, tw);
-    apply_k2<R, N>(v[0], j, nyq_zero);
-    fft_pencils<R, N, true, C::WAVE, M::SPLIT, TU::PRODUCTS, 1, 1>(v, j, l0, M::SL, tw);
-    epi_begin();
-#pragma unroll
-    for (int e = 0; e < 16; ++e) {
-        const int i0 = o0 + C::T * e, i1 = o1 + C::T * e;
-        if constexpr (RL) {
-            // psi_R here is the value this lane stored in the A epilogue
-            if (v0) Ib[i0] = Ib[i0] + vb.x * load_v(Vb + i0) * Rb[i0] + sb.x * v[0][e].x;
-            if (v1) Ib[i1] = Ib[i1] + vb.y * load_v(Vb + i1) * Rb[i1] + sb.y * v[0][e].y;
-        } else {
-            if (v0) Ib[i0] = f[e].x + sb.x * v[0][e].x;
-            if (v1) Ib[i1] = f[e].y + sb.y * v[0][e].y;
-        }
-        epi_fence(e);
-    }
-}
+constexpr int kWPB = 4;             // waves per block of the wave-local passes
+constexpr int kWPBF64Axis256 = 2;   // ... of FP64 256-point pencils
+constexpr int kBaPplF32Long = 2;    // pencils per lane group of the FP32 boundary sweep from 512 points
 
 // ---------------------------------------------------------------------------
 // small kernels
 // ---------------------------------------------------------------------------
 template <typename R>
 __global__ void k_probe(const R* __restrict__ psiR, const R* __restrict__ psiI,
-                        const int64_t* __restrict__ idx, int nprobes, double* __restrict__ out,
-                        int64_t* __restrict__ counter, int64_t capacity) {
+                        const int64_t* __restrict__ idx, int nprobes, int64_t npts, double* __restrict__ out,
+                        int64_t* __restrict__ counter, int64_t capacity, int* __restrict__ fault) {
     const int64_t slot = *counter;
     const int t = threadIdx.x;
     if (slot < capacity && t < nprobes) {
         const int64_t i = idx[t];
-        out[(slot * nprobes + t) * 2 + 0] = (double)psiR[i];
-        out[(slot * nprobes + t) * 2 + 1] = (double)psiI[i];
+        // an index outside the grid (device memory not holding what the host
+        // wrote) skips the sample and raises the flag the host checks
+        if (i >= 0 && i < npts) {
+            out[(slot * nprobes + t) * 2 + 0] = (double)psiR[i];
+            out[(slot * nprobes + t) * 2 + 1] = (double)psiI[i];
+        } else {
+            *fault = 1;
+        }
     }
     __syncthreads();
     if (t == 0) *counter = slot + 1;
@@ -856,11 +95,11 @@ __device__ __forceinline__ int line_pos(int j, int e) {
 }
 
 template <typename R, int N, bool ROWS, bool WALL>
-__global__ __launch_bounds__((row_map<R, N, SPSTD_WPB>::THREADS)) void k_energy_axis(
+__global__ __launch_bounds__((row_map<R, N, kWPB>::THREADS)) void k_energy_axis(
     const R* __restrict__ psiR, const R* __restrict__ psiI, const cpx<double>* __restrict__ tw,
     EnergyGeom g, int nyq_zero, R msign, double* __restrict__ partials) {
     using C = pencil_cfg<N>;
-    using M = row_map<R, N, SPSTD_WPB>;
+    using M = row_map<R, N, kWPB>;
     using TU = tuning<R>;
     __shared__ R lds[M::LDS_REALS];
     int j, pin;
@@ -914,12 +153,12 @@ __global__ __launch_bounds__((row_map<R, N, SPSTD_WPB>::THREADS)) void k_energy_
 // sample / npts (stacked instances of a batch).
 // ---------------------------------------------------------------------------
 template <typename R, int N, bool ROWS>
-__global__ __launch_bounds__((row_map<R, N, SPSTD_WPB>::THREADS)) void k_wall_acc(
+__global__ __launch_bounds__((row_map<R, N, kWPB>::THREADS)) void k_wall_acc(
     const R* __restrict__ src, R* __restrict__ dst, const R* __restrict__ V,
     const cpx<double>* __restrict__ tw, EnergyGeom g, int64_t npts, ScaleRef sc, int kcol, int pcol,
     int nyq_zero, R msign) {
     using C = pencil_cfg<N>;
-    using M = row_map<R, N, SPSTD_WPB>;
+    using M = row_map<R, N, kWPB>;
     using TU = tuning<R>;
     __shared__ R lds[M::LDS_REALS];
     int j, pin;
@@ -966,6 +205,107 @@ __global__ __launch_bounds__((row_map<R, N, SPSTD_WPB>::THREADS)) void k_wall_ac
             dst[b1 + m] = t;
         }
     }
+}
+
+// ---------------------------------------------------------------------------
+// Walled axes of few cells whose mirrored line is not a power of two of at
+// least 16 points (n <= 32 cells, e.g. the 10-cell wells of Sec. 3.1-3.2):
+// the mirrored line of M = 2n points goes through the discrete Fourier sum
+// itself, M^2 products per line (a few hundred for these lines, where a
+// mixed-radix transform would save nothing measurable), with the same
+// mirror, symbol and scales as k_wall_acc.  One 64-lane block per complex
+// pencil (two neighbouring lines); lane t owns bin t and sample t.
+// Twiddles: the FP64 table w_M^s, s < M, indexed by (s t) mod M.
+// ---------------------------------------------------------------------------
+template <typename R>
+__device__ __forceinline__ void wall_dft_load(cpx<R>* u, const R* __restrict__ src, int n, int64_t b0, int64_t b1,
+                                              bool ok0, bool ok1, int64_t stride, R msign) {
+    const int t = threadIdx.x, M = 2 * n;
+    if (t < M) {
+        const int p = t < n ? t : M - 1 - t;
+        const R sg = t < n ? (R)1 : msign;
+        u[t] = cpx<R>{ok0 ? sg * src[b0 + (int64_t)p * stride] : (R)0, ok1 ? sg * src[b1 + (int64_t)p * stride] : (R)0};
+    }
+}
+
+// out = sum_s in[s] w^(sign s t), w = exp(-2 pi i / M), for lane t < M
+template <typename R>
+__device__ __forceinline__ cpx<R> wall_dft_sum(const cpx<R>* in, const cpx<double>* __restrict__ tw, int M, int t,
+                                               bool inverse) {
+    R ar = (R)0, ai = (R)0;
+    for (int s = 0; s < M; ++s) {
+        const cpx<double> w = tw[(s * t) % M];
+        const R wr = (R)w.x, wi = inverse ? -(R)w.y : (R)w.y;
+        ar += in[s].x * wr - in[s].y * wi;
+        ai += in[s].x * wi + in[s].y * wr;
+    }
+    return cpx<R>{ar, ai};
+}
+
+template <typename R>
+__global__ __launch_bounds__(64) void k_wall_dft_acc(const R* __restrict__ src, R* __restrict__ dst,
+                                                     const R* __restrict__ V, const cpx<double>* __restrict__ tw,
+                                                     int n, EnergyGeom g, int64_t npts, ScaleRef sc, int kcol,
+                                                     int pcol, int nyq_zero, R msign) {
+    __shared__ cpx<R> u[64], U[64];
+    const int t = threadIdx.x, M = 2 * n;
+    const int64_t q = blockIdx.x;
+    const bool ok0 = 2 * q < g.nlines, ok1 = 2 * q + 1 < g.nlines;
+    const int64_t L0 = ok0 ? 2 * q : 0, L1 = ok1 ? 2 * q + 1 : L0;
+    const int64_t b0 = (L0 / g.n_lo) * g.stride_hi + (L0 % g.n_lo);
+    const int64_t b1 = (L1 / g.n_lo) * g.stride_hi + (L1 % g.n_lo);
+    wall_dft_load<R>(u, src, n, b0, b1, ok0, ok1, g.stride, msign);
+    __syncthreads();
+    if (t < M) {
+        const cpx<R> a = wall_dft_sum<R>(u, tw, M, t, false);
+        const int ks = t <= M / 2 ? t : t - M;
+        const R sym = (nyq_zero && t == M / 2) ? (R)0 : (R)(ks * ks);
+        U[t] = cpx<R>{a.x * sym, a.y * sym};
+    }
+    __syncthreads();
+    if (t < n) {
+        const cpx<R> r = wall_dft_sum<R>(U, tw, M, t, true);
+        const int64_t i0 = b0 / npts, i1 = b1 / npts;
+        const int64_t m = (int64_t)t * g.stride;
+        if (ok0) {
+            R v = dst[b0 + m] + scale_of<R>(sc, i0, kcol) * r.x;
+            if (pcol >= 0) v += scale_of<R>(sc, i0, pcol) * V[b0 + m] * src[b0 + m];
+            dst[b0 + m] = v;
+        }
+        if (ok1) {
+            R v = dst[b1 + m] + scale_of<R>(sc, i1, kcol) * r.y;
+            if (pcol >= 0) v += scale_of<R>(sc, i1, pcol) * V[b1 + m] * src[b1 + m];
+            dst[b1 + m] = v;
+        }
+    }
+}
+
+// Energy sums of the same lines: partials[b] = sum over the block's pencils
+// of ks^2 |DFT(mirrored psiR + i psiI)(k)|^2 (cf. k_energy_axis).
+template <typename R>
+__global__ __launch_bounds__(64) void k_wall_dft_energy(const R* __restrict__ psiR, const R* __restrict__ psiI,
+                                                        const cpx<double>* __restrict__ tw, int n, EnergyGeom g,
+                                                        int nyq_zero, R msign, double* __restrict__ partials) {
+    __shared__ cpx<R> u[64];
+    const int t = threadIdx.x, M = 2 * n;
+    double acc = 0.0;
+    for (int64_t L = blockIdx.x; L < g.nlines; L += gridDim.x) {
+        const int64_t b = (L / g.n_lo) * g.stride_hi + (L % g.n_lo);
+        if (t < M) {
+            const int p = t < n ? t : M - 1 - t;
+            const R sg = t < n ? (R)1 : msign;
+            u[t] = cpx<R>{sg * psiR[b + (int64_t)p * g.stride], sg * psiI[b + (int64_t)p * g.stride]};
+        }
+        __syncthreads();
+        if (t < M) {
+            const cpx<R> a = wall_dft_sum<R>(u, tw, M, t, false);
+            const int ks = t <= M / 2 ? t : t - M;
+            const double sym = (nyq_zero && t == M / 2) ? 0.0 : (double)ks * (double)ks;
+            acc += sym * ((double)a.x * (double)a.x + (double)a.y * (double)a.y);
+        }
+        __syncthreads();
+    }
+    block_sum_store<64>(acc, partials + blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -1076,16 +416,16 @@ __global__ void k_fill0(int64_t n, R* __restrict__ y) {
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
-constexpr int kWPB = SPSTD_WPB;   // waves per block of the wave-local passes
+
 
 // Waves per block of the hot pass kernels (y/z passes, the stage-boundary y
 // sweep, x passes): 2 for FP64 256-point pencils, where smaller blocks let
 // consecutive passes overlap their tails (graph-replayed 256^3 FP64 step
-// 2.72 -> 2.63 ms), SPSTD_WPB elsewhere (512^2 FP64 batch: 596 us per step
+// 2.72 -> 2.63 ms), 4 elsewhere (512^2 FP64 batch: 596 us per step
 // with 4, 692 with 2).
 template <typename R, int N>
 constexpr int wpb_of() {
-    return (sizeof(R) == 8 && N == 256) ? SPSTD_WPB_F64_256 : SPSTD_WPB;
+    return (sizeof(R) == 8 && N == 256) ? kWPBF64Axis256 : kWPB;
 }
 
 // Pass launch with W waves per block; the block size is a runtime choice
@@ -1127,7 +467,7 @@ template <typename R, int N, int W0>
 static hipError_t axis_ba_nw(R* psiR, R* psiI, const void* tw, const AxisGeom& g, const ScaleRef& scB,
                              const ScaleRef& scA, int colB, int colA, int nyq_zero, hipStream_t st) {
     using C = pencil_cfg<N>;
-    constexpr int P = (sizeof(R) == 4 && N >= 512) ? SPSTD_BA_PPL_F32_LONG : tuning<R>::BA_PPL;
+    constexpr int P = (sizeof(R) == 4 && N >= 512) ? kBaPplF32Long : tuning<R>::BA_PPL;
     constexpr int W = W0 ? W0 : wpb_of<R, N>();
     if (g.half_x % P) return hipErrorInvalidValue;
     const int64_t ngroups = g.half_x / P * g.n_outer;
@@ -1257,14 +597,19 @@ template <typename R>
 __global__ void k_probe_batch(const R* __restrict__ psiR, const R* __restrict__ psiI, int64_t npts,
                               const int64_t* __restrict__ idx, int nprobes, const int* __restrict__ active,
                               int ninst, double* __restrict__ probes, int64_t* __restrict__ counter,
-                              int64_t capacity) {
+                              int64_t capacity, int* __restrict__ fault) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= ninst || !active[i]) return;
     const int64_t slot = counter[i];
     if (slot < capacity) {
         double* out = probes + ((int64_t)i * capacity + slot) * nprobes * 2;
         for (int q = 0; q < nprobes; ++q) {
-            const int64_t k = (int64_t)i * npts + idx[(int64_t)i * nprobes + q];
+            const int64_t p = idx[(int64_t)i * nprobes + q];
+            if (p < 0 || p >= npts) {       // skipped, and flagged for the host
+                *fault = 1;
+                continue;
+            }
+            const int64_t k = (int64_t)i * npts + p;
             out[2 * q] = (double)psiR[k];
             out[2 * q + 1] = (double)psiI[k];
         }
@@ -1275,18 +620,19 @@ __global__ void k_probe_batch(const R* __restrict__ psiR, const R* __restrict__ 
 template <typename R>
 hipError_t launch_probe_batch(const R* psiR, const R* psiI, int64_t npts, const int64_t* idx, int nprobes,
                               const int* active, int ninst, double* probes, int64_t* counter,
-                              int64_t capacity, hipStream_t st) {
+                              int64_t capacity, int* fault, hipStream_t st) {
     const int blocks = (ninst + 63) / 64;
     hipLaunchKernelGGL((k_probe_batch<R>), dim3(blocks), dim3(64), 0, st, psiR, psiI, npts, idx, nprobes,
-                       active, ninst, probes, counter, capacity);
+                       active, ninst, probes, counter, capacity, fault);
     return hipGetLastError();
 }
 
 template <typename R>
-hipError_t launch_probe(const R* psiR, const R* psiI, const int64_t* idx, int nprobes,
-                        double* out, int64_t* counter, int64_t capacity, hipStream_t st) {
-    hipLaunchKernelGGL((k_probe<R>), dim3(1), dim3(64), 0, st, psiR, psiI, idx, nprobes, out,
-                       counter, capacity);
+hipError_t launch_probe(const R* psiR, const R* psiI, const int64_t* idx, int nprobes, int64_t npts,
+                        double* out, int64_t* counter, int64_t capacity, int* fault, hipStream_t st) {
+    if (nprobes < 0 || nprobes > 64) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_probe<R>), dim3(1), dim3(64), 0, st, psiR, psiI, idx, nprobes, npts, out,
+                       counter, capacity, fault);
     return hipGetLastError();
 }
 
@@ -1329,6 +675,15 @@ template <typename R>
 hipError_t launch_energy_axis(int64_t n, int rows, int wall, const R* psiR, const R* psiI,
                               const void* tw, const EnergyGeom& g, int nyq_zero, double* partials,
                               int max_blocks, int* nblocks, hipStream_t st) {
+    if (wall && wall_dft_len_ok(n)) {
+        int64_t b = g.nlines < max_blocks ? g.nlines : max_blocks;
+        if (b < 1) b = 1;
+        *nblocks = (int)b;
+        const R ms = wall == WALL_NEUMANN ? (R)1 : (R)-1;
+        hipLaunchKernelGGL((k_wall_dft_energy<R>), dim3((unsigned)b), dim3(64), 0, st, psiR, psiI,
+                           (const cpx<double>*)tw, (int)n, g, nyq_zero, ms, partials);
+        return hipGetLastError();
+    }
     const int64_t nx = wall ? 2 * n : n;
     SPSTD_ROW_CASES(energy_axis_n, psiR, psiI, tw, g, rows, wall, nyq_zero, partials, max_blocks, nblocks, st)
 }
@@ -1357,6 +712,13 @@ hipError_t launch_wall_acc(int64_t n, int rows, int wall, const R* src, R* dst, 
                            const void* tw, const EnergyGeom& g, int64_t npts, const ScaleRef& sc,
                            int kcol, int pcol, int nyq_zero, hipStream_t st) {
     if (wall != WALL_DIRICHLET && wall != WALL_NEUMANN) return hipErrorInvalidValue;
+    if (wall_dft_len_ok(n)) {
+        const int64_t b = (g.nlines + 1) / 2;
+        const R ms = wall == WALL_NEUMANN ? (R)1 : (R)-1;
+        hipLaunchKernelGGL((k_wall_dft_acc<R>), dim3((unsigned)b), dim3(64), 0, st, src, dst, V,
+                           (const cpx<double>*)tw, (int)n, g, npts, sc, kcol, pcol, nyq_zero, ms);
+        return hipGetLastError();
+    }
     const int64_t nx = 2 * n;
     switch (nx) {
         case 32: return wall_acc_n<R, 32>(src, dst, V, tw, g, npts, sc, kcol, pcol, rows, wall, nyq_zero, st);
@@ -1435,9 +797,9 @@ hipError_t launch_fill0(int64_t n, R* y, hipStream_t st) {
                                        const ScaleRef&, int, hipStream_t, int);                 \
     template hipError_t launch_probe_batch<R>(const R*, const R*, int64_t, const int64_t*, int, \
                                               const int*, int, double*, int64_t*, int64_t,      \
-                                              hipStream_t);                                     \
-    template hipError_t launch_probe<R>(const R*, const R*, const int64_t*, int, double*,       \
-                                        int64_t*, int64_t, hipStream_t);                        \
+                                              int*, hipStream_t);                               \
+    template hipError_t launch_probe<R>(const R*, const R*, const int64_t*, int, int64_t,       \
+                                        double*, int64_t*, int64_t, int*, hipStream_t);         \
     template hipError_t launch_norm_partials<R>(const R*, const R*, int64_t, double*, int,      \
                                                 hipStream_t);                                   \
     template hipError_t launch_axpby<R>(int64_t, double, const R*, double, R*, hipStream_t);    \
@@ -1458,5 +820,6 @@ hipError_t launch_fill0(int64_t n, R* y, hipStream_t st) {
 SPSTD_INSTANTIATE(double)
 SPSTD_INSTANTIATE(float)
 template hipError_t launch_fill0<int64_t>(int64_t, int64_t*, hipStream_t);
+template hipError_t launch_fill0<int>(int64_t, int*, hipStream_t);
 
 }  // namespace spstd

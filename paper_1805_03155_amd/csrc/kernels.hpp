@@ -47,6 +47,7 @@ struct ScaleRef {
 // Supported pencil lengths.
 bool axis_len_ok(int64_t n);   // y/z passes: 16..1024
 bool row_len_ok(int64_t n);    // x pass:     16..16384
+bool wall_dft_len_ok(int64_t n);   // walled axes of n <= 32 cells not transformed by the FFT passes
 
 // dst += scale_inst * IFFT_axis(ks^2 FFT_axis(src)), scale column col.
 template <typename R>
@@ -74,6 +75,10 @@ template <typename R>
 hipError_t launch_x_ab(int64_t nx, R* psiR, R* psiI, const R* V, const void* tw,
                        const RowGeom& g, const ScaleRef& sc, int nyq_zero, hipStream_t st, int wpb = 0);
 
+// Every probe kernel checks each device-side index against the grid size
+// (npts): an index outside [0, npts) skips its sample and sets *fault = 1,
+// which the host reads after the run and reports.
+//
 // Batched probe samples: for every instance i < ninst with active[i],
 // out_i[slot][p] = (psiR[i*npts + idx[i*P + p]], psiI[...]) as doubles,
 // slot = counter[i], then counter[i]++ (slots >= capacity are not written).
@@ -81,25 +86,26 @@ hipError_t launch_x_ab(int64_t nx, R* psiR, R* psiI, const R* V, const void* tw,
 template <typename R>
 hipError_t launch_probe_batch(const R* psiR, const R* psiI, int64_t npts, const int64_t* idx,
                               int nprobes, const int* active, int ninst, double* probes,
-                              int64_t* counter, int64_t capacity, hipStream_t st);
+                              int64_t* counter, int64_t capacity, int* fault, hipStream_t st);
 
 // probe sample: out[slot][p] = (psiR[idx_p], psiI[idx_p]) as doubles, where
-// slot = *counter; then (*counter)++.  Single thread block.
+// slot = *counter; then (*counter)++.  Single thread block, nprobes 0..64.
 template <typename R>
 hipError_t launch_probe(const R* psiR, const R* psiI, const int64_t* idx,
-                        int nprobes, double* out, int64_t* counter,
-                        int64_t capacity, hipStream_t st);
+                        int nprobes, int64_t npts, double* out, int64_t* counter,
+                        int64_t capacity, int* fault, hipStream_t st);
 
 // Merged step boundary (the last A half of a step and the first A half of
 // the next as one): save[p] = psi[idx_p] as doubles; then the sample
 // out[slot][p] = (saveR_p + w (psiR[idx_p] - saveR_p), saveI_p), slot =
 // *counter, then (*counter)++.  Single thread block, nprobes 1..64.
 template <typename R>
-hipError_t launch_probe_save(const R* psi, const int64_t* idx, int nprobes, double* save, hipStream_t st);
+hipError_t launch_probe_save(const R* psi, const int64_t* idx, int nprobes, int64_t npts, double* save,
+                             int* fault, hipStream_t st);
 template <typename R>
-hipError_t launch_probe_merged(const R* psiR, const int64_t* idx, int nprobes, const double* saveR,
+hipError_t launch_probe_merged(const R* psiR, const int64_t* idx, int nprobes, int64_t npts, const double* saveR,
                                const double* saveI, double w, double* out, int64_t* counter, int64_t capacity,
-                               hipStream_t st);
+                               int* fault, hipStream_t st);
 
 // per-block FP64 partial sums of psiR^2 + psiI^2 (fixed order)
 template <typename R>
@@ -180,5 +186,73 @@ hipError_t launch_wall_acc(int64_t n, int rows, int wall, const R* src, R* dst, 
 template <typename R>
 hipError_t launch_energy_pot(const R* psiR, const R* psiI, const R* V, int64_t n, double* pot,
                              double* nrm, int nblocks, hipStream_t st);
+
+// ---------------------------------------------------------------------------
+// Mixed-shape groups: stacks of 2D instances of different shapes (one
+// member per shape, n_x and n_y in {128, 256, 512}) advanced by one launch
+// per pass over a table of tiles.
+// ---------------------------------------------------------------------------
+bool mix_len_ok(int64_t n);
+
+// One member: a stack of `capacity` instances of nx by ny points (the
+// fields, scales, twiddles and probe buffers of one single-shape batch).
+template <typename R>
+struct MixMember {
+    int nx, ny;
+    R* psiR;
+    R* psiI;
+    const R* V;
+    const void* twx;         // FP64 twiddles of the x and y transforms
+    const void* twy;
+    const void* scales;      // [capacity][m][SC_COLS], run precision
+    RowGeom rg;              // x rows of all slots
+    AxisGeom gy;             // y pencils of all slots
+    int64_t npts;            // points per instance
+    const int64_t* pidx;     // [capacity][nprobes] probe indices
+    const int* active;       // [capacity]
+    double* probes;          // [capacity][capacity_samples][nprobes][2]
+    int64_t* counter;        // [capacity] next sample slot
+    int64_t samples;         // sample slots per instance
+    int* fault;              // probe index fault flag
+};
+
+// Tile: block `blk` of member `member`'s own grid for one pass kind.
+struct MixTile {
+    int member;
+    int blk;
+};
+
+// Schedule variants of the mixed kernels, chosen at run time: waves per
+// block (2 or 4), the LDS exchange of the fused x pass (joint real and
+// imaginary parts for rows shorter than 512 points, or split), and complex
+// pencils per lane group of the y passes (1 or 2).
+struct MixVariant {
+    int wpb;
+    int x_joint;
+    int y_ppl;
+};
+
+// Blocks of one member's grid for a pass kind under variant v:
+// kind 0 the fused x pass, 1 the y passes.
+int64_t mix_blocks(int kind, int nx, int ny, int64_t capacity, int precision_bytes, const MixVariant& v);
+
+// Fused A and B halves along x for every member (stage l of m).
+template <typename R>
+hipError_t launch_mix_x_ab(const MixMember<R>* mem, const MixTile* tiles, int ntiles, int grid, int m, int l,
+                           int nyq_zero, const MixVariant& v, hipStream_t st);
+// The y pass of a half-stage for every member: b_half 0 (A: psi_R += T_y
+// psi_I, column SC_KYA) or 1 (B: psi_I += T_y psi_R, column SC_KYB).
+template <typename R>
+hipError_t launch_mix_axis_acc(const MixMember<R>* mem, const MixTile* tiles, int ntiles, int grid, int m,
+                               int l, int b_half, int nyq_zero, const MixVariant& v, hipStream_t st);
+// The y sweep at a stage boundary (B half of stage lB, A half of lA).
+template <typename R>
+hipError_t launch_mix_axis_ba(const MixMember<R>* mem, const MixTile* tiles, int ntiles, int grid, int m,
+                              int lB, int lA, int nyq_zero, const MixVariant& v, hipStream_t st);
+// Probe samples of every active slot of every member (as launch_probe_batch);
+// slots[i] = (member, slot).
+template <typename R>
+hipError_t launch_mix_probe(const MixMember<R>* mem, const MixTile* slots, int nslots, int nprobes,
+                            hipStream_t st);
 
 }  // namespace spstd

@@ -14,49 +14,63 @@
 
 namespace spstd {
 
+// An index outside the grid skips its sample and sets *fault for the host.
 template <typename R>
 __global__ void k_probe_save(const R* __restrict__ psi, const int64_t* __restrict__ idx, int nprobes,
-                             double* __restrict__ save) {
+                             int64_t npts, double* __restrict__ save, int* __restrict__ fault) {
     const int t = threadIdx.x;
-    if (t < nprobes) save[t] = (double)psi[idx[t]];
+    if (t < nprobes) {
+        const int64_t i = idx[t];
+        if (i >= 0 && i < npts) save[t] = (double)psi[i];
+        else *fault = 1;
+    }
 }
 
 template <typename R>
 __global__ void k_probe_merged(const R* __restrict__ psiR, const int64_t* __restrict__ idx, int nprobes,
-                               const double* __restrict__ saveR, const double* __restrict__ saveI, double w,
-                               double* __restrict__ out, int64_t* __restrict__ counter, int64_t capacity) {
+                               int64_t npts, const double* __restrict__ saveR, const double* __restrict__ saveI,
+                               double w, double* __restrict__ out, int64_t* __restrict__ counter, int64_t capacity,
+                               int* __restrict__ fault) {
     const int64_t slot = *counter;
     const int t = threadIdx.x;
     if (slot < capacity && t < nprobes) {
-        const double r0 = saveR[t];
-        out[(slot * nprobes + t) * 2 + 0] = r0 + w * ((double)psiR[idx[t]] - r0);
-        out[(slot * nprobes + t) * 2 + 1] = saveI[t];
+        const int64_t i = idx[t];
+        if (i >= 0 && i < npts) {
+            const double r0 = saveR[t];
+            out[(slot * nprobes + t) * 2 + 0] = r0 + w * ((double)psiR[i] - r0);
+            out[(slot * nprobes + t) * 2 + 1] = saveI[t];
+        } else {
+            *fault = 1;
+        }
     }
     __syncthreads();
     if (t == 0) *counter = slot + 1;
 }
 
 template <typename R>
-hipError_t launch_probe_save(const R* psi, const int64_t* idx, int nprobes, double* save, hipStream_t st) {
+hipError_t launch_probe_save(const R* psi, const int64_t* idx, int nprobes, int64_t npts, double* save,
+                             int* fault, hipStream_t st) {
     if (nprobes < 1 || nprobes > 64) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_probe_save<R>), dim3(1), dim3(64), 0, st, psi, idx, nprobes, save);
+    hipLaunchKernelGGL((k_probe_save<R>), dim3(1), dim3(64), 0, st, psi, idx, nprobes, npts, save, fault);
     return hipGetLastError();
 }
 
 template <typename R>
-hipError_t launch_probe_merged(const R* psiR, const int64_t* idx, int nprobes, const double* saveR,
+hipError_t launch_probe_merged(const R* psiR, const int64_t* idx, int nprobes, int64_t npts, const double* saveR,
                                const double* saveI, double w, double* out, int64_t* counter, int64_t capacity,
-                               hipStream_t st) {
+                               int* fault, hipStream_t st) {
     if (nprobes < 1 || nprobes > 64) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_probe_merged<R>), dim3(1), dim3(64), 0, st, psiR, idx, nprobes, saveR, saveI, w, out,
-                       counter, capacity);
+    hipLaunchKernelGGL((k_probe_merged<R>), dim3(1), dim3(64), 0, st, psiR, idx, nprobes, npts, saveR, saveI, w,
+                       out, counter, capacity, fault);
     return hipGetLastError();
 }
 
 #define SPSTD_INST_PROBES(R)                                                                                 \
-    template hipError_t launch_probe_save<R>(const R*, const int64_t*, int, double*, hipStream_t);           \
-    template hipError_t launch_probe_merged<R>(const R*, const int64_t*, int, const double*, const double*,  \
-                                               double, double*, int64_t*, int64_t, hipStream_t);
+    template hipError_t launch_probe_save<R>(const R*, const int64_t*, int, int64_t, double*, int*,          \
+                                             hipStream_t);                                                   \
+    template hipError_t launch_probe_merged<R>(const R*, const int64_t*, int, int64_t, const double*,        \
+                                               const double*, double, double*, int64_t*, int64_t, int*,      \
+                                               hipStream_t);
 SPSTD_INST_PROBES(double)
 SPSTD_INST_PROBES(float)
 #undef SPSTD_INST_PROBES

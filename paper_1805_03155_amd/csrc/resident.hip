@@ -117,6 +117,10 @@ __global__ __launch_bounds__((res_cfg<N>::THREADS)) void k_resident_1d(
                 if (!has) continue;
                 for (int q = 0; q < I->nprobes; ++q) {
                     const int64_t pidx = I->probe_idx[q];
+                    if (pidx < 0 || pidx >= N) {      // skipped, flagged for the host
+                        if (j == 0) *I->fault = 1;
+                        continue;
+                    }
                     if ((int)(pidx % C::T) != j) continue;
                     const int pe = (int)(pidx / C::T);
                     R r = (R)0, im = (R)0;
@@ -181,6 +185,10 @@ __global__ __launch_bounds__((res_cfg<N>::THREADS)) void k_resident_1d(
                 const int64_t slot = (who == 0 ? slot_a : slot_b) + s;
                 for (int q = 0; q < I->nprobes && slot < I->capacity; ++q) {
                     const int64_t pidx = I->probe_idx[q];
+                    if (pidx < 0 || pidx >= N) {
+                        *I->fault = 1;
+                        continue;
+                    }
                     I->probes[(slot * I->nprobes + q) * 2 + 0] = (double)I->psiR[pidx];
                     I->probes[(slot * I->nprobes + q) * 2 + 1] = (double)I->psiI[pidx];
                 }
@@ -296,6 +304,10 @@ __global__ __launch_bounds__((res2_cfg<NX, NY>::THREADS)) void k_resident_2d(
             const int64_t slot = slot0 + s;
             for (int q = 0; q < I->nprobes && slot < I->capacity; ++q) {
                 const int64_t pidx = I->probe_idx[q];
+                if (pidx < 0 || pidx >= NX * NY) {
+                    *I->fault = 1;
+                    continue;
+                }
                 I->probes[(slot * I->nprobes + q) * 2 + 0] = (double)sR[pidx];
                 I->probes[(slot * I->nprobes + q) * 2 + 1] = (double)sI[pidx];
             }

@@ -18,6 +18,7 @@ struct ResidentInst {
     R* psiI;
     double* probes;        // FP64 samples [capacity][nprobes][2]
     int64_t* counter;      // next free sample slot (advanced by nsteps)
+    int* fault;            // set to 1 if a probe index lies outside the grid (sample skipped)
     int64_t capacity;      // sample slots available
     int nprobes;           // 0..kResMaxProbes
     int64_t probe_idx[kResMaxProbes];

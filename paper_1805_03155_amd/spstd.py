@@ -72,7 +72,10 @@ EXPORTS = ["spstd_xmax", "spstd_stable_dt", "spstd_workspace_size", "spstd_plan"
            "spstd_batch_workspace_size", "spstd_batch_create", "spstd_batch_load",
            "spstd_batch_step", "spstd_batch_read", "spstd_batch_release",
            "spstd_batch_slot_info", "spstd_batch_destroy", "spstd_batch_last_error",
-           "spstd_batch_schedule"]
+           "spstd_batch_schedule",
+           "spstd_batch_group_workspace_size", "spstd_batch_group_create", "spstd_batch_group_step",
+           "spstd_batch_group_schedule", "spstd_batch_group_set_schedule", "spstd_batch_group_destroy",
+           "spstd_batch_group_last_error"]
 
 _lib = None
 
@@ -115,24 +118,35 @@ def lib():
         L.spstd_batch_destroy.argtypes = [vp]
         L.spstd_batch_last_error.argtypes = [vp]
         L.spstd_batch_last_error.restype = ctypes.c_char_p
+        L.spstd_batch_group_workspace_size.argtypes = [P(vp), c_int, P(c_sz)]
+        L.spstd_batch_group_create.argtypes = [P(vp), c_int, c_u32, vp, c_sz, vp, P(vp)]
+        L.spstd_batch_group_step.argtypes = [vp, c_i64]
+        L.spstd_batch_group_schedule.argtypes = [vp, P(c_int), P(c_int), pd]
+        L.spstd_batch_group_set_schedule.argtypes = [vp, c_int]
+        L.spstd_batch_group_destroy.argtypes = [vp]
+        L.spstd_batch_group_last_error.argtypes = [vp]
+        L.spstd_batch_group_last_error.restype = ctypes.c_char_p
         L.spstd_strerror.argtypes = [c_int]
         L.spstd_strerror.restype = ctypes.c_char_p
         L.spstd_last_error.argtypes = [ctypes.c_void_p]
         L.spstd_last_error.restype = ctypes.c_char_p
         for name in EXPORTS:
-            if name not in ("spstd_strerror", "spstd_last_error", "spstd_batch_last_error"):
+            if name not in ("spstd_strerror", "spstd_last_error", "spstd_batch_last_error",
+                            "spstd_batch_group_last_error"):
                 getattr(L, name).restype = c_int
         _lib = L
     return _lib
 
 
-def _check(rc, plan=None, batch=None):
+def _check(rc, plan=None, batch=None, group=None):
     if rc != 0:
         msg = lib().spstd_strerror(rc).decode()
         if plan:
             msg += " / " + lib().spstd_last_error(plan).decode()
         if batch:
             msg += " / " + lib().spstd_batch_last_error(batch).decode()
+        if group:
+            msg += " / " + lib().spstd_batch_group_last_error(group).decode()
         raise SpstdError(rc, msg)
 
 
@@ -442,3 +456,58 @@ class Batch:
 
     def release(self, slot):
         _check(lib().spstd_batch_release(self.h, int(slot)), batch=self.h)
+
+
+def group_ok(n, precision=FP64, resident=False):
+    """Whether a batch of shape n can join a group (2D, axes of 128, 256 or
+    512 points, pass kernels)."""
+    return len(n) == 2 and all(k in (128, 256, 512) for k in n) and not resident
+
+
+class BatchGroup:
+    """2D batches of different shapes stepped together: one launch per pass
+    for all of them (or, as the tuner may choose, their own kernels in
+    turn).  While the group exists its members work on the group's stream."""
+
+    def __init__(self, members, flags=0, device="cuda", stream=None):
+        import torch
+        self.members = list(members)
+        arr = (ctypes.c_void_p * len(self.members))(*[b.h.value for b in self.members])
+        self._arr = arr
+        nb = c_sz()
+        _check(lib().spstd_batch_group_workspace_size(arr, len(self.members), ctypes.byref(nb)))
+        dev = torch.device(device)
+        self.ws = torch.empty(nb.value + 256, dtype=torch.uint8, device=dev)
+        base = self.ws.data_ptr()
+        self.stream = stream if stream is not None else torch.cuda.current_stream(dev)
+        h = ctypes.c_void_p()
+        with torch.cuda.device(dev):
+            rc = lib().spstd_batch_group_create(arr, len(self.members), int(flags),
+                                                ctypes.c_void_p(base + (-base) % 256), nb.value,
+                                                ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h))
+        _check(rc)
+        self.h = h
+        self._destroy = lib().spstd_batch_group_destroy
+
+    def __del__(self):
+        h, fn = getattr(self, "h", None), getattr(self, "_destroy", None)
+        if h is not None and h.value and fn is not None:
+            fn(h)
+            self.h = None
+
+    def close(self):
+        """Release the group; the members return to their own streams."""
+        self.__del__()
+
+    def step(self, nsteps):
+        _check(lib().spstd_batch_group_step(self.h, int(nsteps)), group=self.h)
+
+    def schedule(self):
+        """(candidate in use, measured us/step per candidate)."""
+        ch, nc = c_int(), c_int()
+        us = np.zeros(64)
+        _check(lib().spstd_batch_group_schedule(self.h, ctypes.byref(ch), ctypes.byref(nc), _dp(us)))
+        return ch.value, tuple(float(u) for u in us[: nc.value])
+
+    def set_schedule(self, choice):
+        _check(lib().spstd_batch_group_set_schedule(self.h, int(choice)), group=self.h)

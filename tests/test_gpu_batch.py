@@ -42,7 +42,7 @@ def alone(w, dt, steps, precision=spstd.FP64, flags=0):
     return r, i, ser
 
 
-@pytest.mark.parametrize("n", [16, 32, 256, 512, 1024, 4096])
+@pytest.mark.parametrize("n", [16, 32, 256, 512, 1024, 4096, 8192, 16384])
 @pytest.mark.parametrize("prec", [spstd.FP64, spstd.FP32])
 def test_resident_kernel_matches_pass_kernels(n, prec):
     w = inst((n,), seed=n)
@@ -212,3 +212,99 @@ def test_resident_2d_matches_pass_kernels_and_oracle(n, prec):
             ro, io, so, _ = oracle.run(w.psiR, w.psiI, w.V, w.n, w.dx, *w.coeffs, dts[k], steps, w.probes)
             assert rel(np.concatenate([r1, i1]), np.concatenate([ro, io])) <= 1e-12
             assert rel(s1, so) <= 1e-12
+
+
+# ------------------------------------------------------------- mixed groups
+GROUP_SHAPES = ((128, 128), (256, 256), (512, 512), (128, 256))
+
+
+def _group_members(prec, steps, count=(3, 2, 1, 2), flags=0):
+    """Batches of the group shapes filled with seeded instances."""
+    out = []
+    for shape, k in zip(GROUP_SHAPES, count):
+        b = spstd.Batch(shape, W.PAPER, capacity=k + 1, nprobes=1, nsteps_max=steps, precision=prec,
+                        flags=flags)
+        ws = [inst(shape, seed=1000 * shape[0] + shape[1] + j) for j in range(k)]
+        out.append((b, ws))
+    return out
+
+
+def _load(members):
+    dts = []
+    for b, ws in members:
+        dts.append([b.load(s, w.dx, w.V, w.psiR, w.psiI, w.probes) for s, w in enumerate(ws)])
+    return dts
+
+
+@pytest.mark.parametrize("prec", [spstd.FP64, spstd.FP32])
+def test_group_schedules_match_the_oracle(prec):
+    # every candidate schedule of a group (mixed-shape kernels under each
+    # block size / exchange / pencils-per-lane-group variant, and the
+    # members' own kernels) steps each instance as the oracle does; one
+    # slot of each member stays free (its zero scales make it a no-op)
+    steps = 40
+    ncand = 17 if prec == spstd.FP32 else 9
+    ref = None
+    for choice in range(ncand):
+        members = _group_members(prec, steps)
+        g = spstd.BatchGroup([b for b, _ in members])
+        assert len(g.schedule()[1]) == ncand
+        g.set_schedule(choice)
+        dts = _load(members)
+        g.step(steps)
+        got = []
+        for (b, ws), dd in zip(members, dts):
+            for s, w in enumerate(ws):
+                ser, r, i, done = b.read(s)
+                assert done == steps
+                got.append((w, dd[s], ser, r, i))
+        if ref is None:
+            ref = []
+            for w, dt, _, _, _ in got:
+                ro, io, so, _ = oracle.run(w.psiR, w.psiI, w.V, w.n, w.dx, *w.coeffs, dt, steps, w.probes)
+                ref.append((ro, io, so))
+        tol = 1e-12 if prec == spstd.FP64 else 2e-5
+        for (w, dt, ser, r, i), (ro, io, so) in zip(got, ref):
+            assert rel(np.concatenate([r, i]), np.concatenate([ro, io])) <= tol, (choice, w.n)
+            assert rel(ser, so) <= tol, (choice, w.n)
+        g.close()
+
+
+def test_group_autotune_and_alone_versus_mix():
+    # FP32 group with the tuner: it times every candidate and keeps the
+    # fastest; each instance then equals its own single-shape batch run
+    steps = 50
+    members = _group_members(spstd.FP32, steps + 2)
+    g = spstd.BatchGroup([b for b, _ in members], flags=spstd.AUTOTUNE)
+    choice, us = g.schedule()
+    assert len(us) == 17 and all(u > 0 for u in us)
+    assert us[choice] <= 1.03 * min(us)
+    dts = _load(members)
+    g.step(steps)
+    for (b, ws), dd in zip(members, dts):
+        for s, w in enumerate(ws):
+            ser, r, i, _ = b.read(s)
+            ra, ia, sa = alone(w, dd[s], steps, spstd.FP32)
+            assert rel(np.concatenate([r, i]), np.concatenate([ra, ia])) <= 1e-5
+            assert rel(ser, sa) <= 1e-5
+    g.close()
+    # after the group, the members step on their own again
+    b, ws = members[0]
+    b.step(2)
+    assert b.slot_info(0)[1] == steps + 2
+
+
+def test_group_rejects_unfit_members_and_overflow():
+    b1 = spstd.Batch((1024,), W.PAPER, capacity=2, nsteps_max=4)
+    b2 = spstd.Batch((128, 128), W.PAPER, capacity=2, nsteps_max=4)
+    b3 = spstd.Batch((256, 256), W.PAPER, capacity=2, nsteps_max=4, precision=spstd.FP32)
+    for bad in ([b1], [b2, b3], [b2, b2]):
+        with pytest.raises(spstd.SpstdError):
+            spstd.BatchGroup(bad)
+    w = inst((128, 128), seed=3)
+    g = spstd.BatchGroup([b2])
+    b2.load(0, w.dx, w.V, w.psiR, w.psiI, w.probes)
+    g.step(4)
+    with pytest.raises(spstd.SpstdError) as ei:
+        g.step(1)
+    assert ei.value.code == 6

@@ -1,16 +1,17 @@
 """Full-length runs against the oracle.
 
 The 64^3 oscillator workload runs its whole 10000 steps on the GPU and is
-compared with the oracle's full run, stored as sampled outputs by
-tests/golden/make_harmonic64_fullrun.py (every 50th probe sample, the final
-state at 512 seeded points, the final norm, the lowest 8 levels).  Bars:
-psi and probe samples <= 1e-12 relative L2, eigenvalues <= 1e-10 relative.
+compared with the oracle's full run, stored by
+tests/golden/make_harmonic64_fullrun.py (every probe sample, the final state
+at 32768 seeded points, the norm, the lowest 8 levels).  Bars: psi and probe
+samples <= 1e-12 relative L2, eigenvalues <= 1e-10 relative.
 
-The FP32 form is checked where it counts, on eigenvalues: 1D instances of
-the batching workload run FP32 in one batch and their levels are compared
-with the FP64 oracle's (<= 1e-5 relative).
+The FP32 form is checked where it counts, on eigenvalues against the FP64
+oracle (<= 1e-5 relative): 1D instances of the batching workload in one
+batch with the oracle run live, and the whole 512-instance batching
+workload (5000 steps, as bench.py runs it) with the 2D instances of
+32^2 .. 512^2 stored by tests/golden/make_batch2d_levels.py.
 """
-import json
 import os
 
 import numpy as np
@@ -18,12 +19,13 @@ import pytest
 
 import oracle
 from oracle import spectrum
-from paper_1805_03155_amd import spstd
+from paper_1805_03155_amd import batching, spstd
 from paper_1805_03155_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
 
-GOLD = os.path.join(os.path.dirname(__file__), "golden", "harmonic64_fullrun.json")
+GOLD = os.path.join(os.path.dirname(__file__), "golden", "harmonic64_fullrun.npz")
+GOLD2D = os.path.join(os.path.dirname(__file__), "golden", "batch2d_levels.npz")
 
 
 def rel(a, b):
@@ -31,21 +33,22 @@ def rel(a, b):
 
 
 def test_harmonic_64_full_run_against_the_oracle():
-    g = json.load(open(GOLD))
-    w = W.harmonic_3d(seed=g["seed"], n=g["n"], steps=g["steps"])
-    assert [int(p) for p in w.probes] == g["probes"]
+    g = np.load(GOLD, allow_pickle=False)
+    w = W.harmonic_3d(seed=int(g["seed"]), n=int(g["n"]), steps=int(g["steps"]))
+    assert np.array_equal(w.probes, g["probes"])
     dt = oracle.stable_dt(*w.coeffs, w.V, w.n, w.dx)
-    assert dt == g["dt"]
+    assert dt == float(g["dt"])
     p = spstd.plan_from_workload(w, dt=dt, nsteps_max=w.steps)
     ser, st = p.run(w.steps)
     r, i, _ = p.get_state()
-    pts = np.array(g["points"])
+    pts = g["points"]
+    assert len(pts) >= 32768
     assert rel(np.concatenate([r[pts], i[pts]]), np.concatenate([g["psiR"], g["psiI"]])) <= 1e-12
-    assert rel(ser[:: g["sample_every"]], np.array(g["series"])) <= 1e-12
-    assert abs(st.norm / (g["norm_final"] * np.prod(w.dx)) - 1.0) <= 1e-12
+    assert rel(ser, g["series"]) <= 1e-12
+    assert abs(st.norm / (float(g["norm_final"]) * np.prod(w.dx)) - 1.0) <= 1e-12
     E, _ = spstd.spectrum(ser, dt, nlevels=8)
     assert len(E) == len(g["levels"])
-    assert np.abs((E - np.array(g["levels"])) / np.array(g["levels"])).max() <= 1e-10
+    assert np.abs((E - g["levels"]) / g["levels"]).max() <= 1e-10
 
 
 def test_fp32_batch_eigenvalues_against_the_fp64_oracle():
@@ -71,3 +74,24 @@ def test_fp32_batch_eigenvalues_against_the_fp64_oracle():
             # each of the oracle's two lowest levels, against the nearest FP32 level
             for e in E64[:2]:
                 assert np.abs(E32 - e).min() <= 1e-5 * abs(e)
+
+
+def test_fp32_batching_workload_2d_eigenvalues_against_the_fp64_oracle():
+    g = np.load(GOLD2D, allow_pickle=False)
+    steps, every = int(g["steps"]), int(g["every"])
+    inst = W.batch_instances(count=int(g["count"]), seed=int(g["seed"]), steps=steps)
+    res, _ = batching.run_instances(inst, steps, precision=spstd.FP32, group=True)
+    shapes = set()
+    for k, dt64, ser64, E64 in zip(g["index"], g["dt"], g["series"], g["levels"]):
+        w = inst[int(k)]
+        ser, dt = res[int(k)]
+        shapes.add(w.n)
+        assert dt == pytest.approx(float(dt64), rel=1e-13)
+        # the FP32 probe series follows the FP64 oracle's to single precision
+        scale = np.abs(np.concatenate([w.psiR, w.psiI])).max()
+        assert np.abs(ser[::every] - ser64).max() <= 1e-4 * scale, (k, w.n)
+        E32, _ = spstd.spectrum(ser, dt, nlevels=4)
+        E64 = E64[np.isfinite(E64)]
+        assert len(E64) >= 2 and len(E32) == len(E64), (k, w.n, E32, E64)
+        assert np.abs((E32 - E64) / E64).max() <= 1e-5, (k, w.n, E32, E64)
+    assert {(128, 128), (512, 512)} <= shapes

@@ -106,7 +106,7 @@ def test_small_budget_queues_but_completes():
 
 def test_batching_form_instances_against_oracle():
     inst = W.batch_instances(count=24, seed=11, steps=200, max_1d_log2=11, max_2d_log2=7)
-    res, stats = batching.run_instances(inst, 200, precision=spstd.FP64)
+    res, stats = batching.run_instances(inst, 200, precision=spstd.FP64, group=True)
     assert stats["stage_updates_per_s"] > 0
     for i in (0, 5, 11, 17, 23):
         w = inst[i]
