@@ -42,7 +42,8 @@ typedef enum spstd_status {
     SPSTD_ERR_WORKSPACE = 3,  /* workspace missing, too small or misaligned */
     SPSTD_ERR_DEVICE = 4,     /* a HIP runtime call failed */
     SPSTD_ERR_NONFINITE = 5,  /* the state holds NaN or Inf after a run */
-    SPSTD_ERR_CAPACITY = 6    /* more steps than the probe buffer holds */
+    SPSTD_ERR_CAPACITY = 6,   /* more steps than the probe buffer holds */
+    SPSTD_ERR_SCRATCH = 7     /* spstd_run_noalloc: working memory beyond its fixed scratch */
 } spstd_status;
 
 enum { SPSTD_FP64 = 0, SPSTD_FP32 = 1 };            /* storage and arithmetic of fields */
@@ -311,6 +312,39 @@ spstd_status spstd_pass_times(spstd_plan_t plan, int64_t *launches, double *tota
 spstd_status spstd_destroy(spstd_plan_t plan);
 const char *spstd_strerror(spstd_status status);
 
+/*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the work
+ * of spstd_plan + spstd_run on fields the caller already holds on the
+ * device, with every other piece of working memory (twiddle and scale
+ * tables, probe indices, the step counter, merged-boundary samples, the
+ * resident kernels' instance table) in one fixed static device array of the
+ * library, SPSTD_NOALLOC_SCRATCH_BYTES per GPU, held until the process
+ * ends.  No hipMalloc, hipFree or other device allocation is made.
+ *   desc    as for spstd_plan, with method SPSTD_SYMPLECTIC, neig = 0, an
+ *           explicit dt > 0 (V is not read on the host, so dt is neither
+ *           derived nor checked against the stability edge; use
+ *           spstd_stable_dt beforehand) and no SPSTD_TIMING; kernels launch
+ *           one by one (no graph is captured).
+ *   V       device, N values in desc->precision, read only.
+ *   psiR, psiI  device, N values each in desc->precision: the initial state
+ *           on entry, the state after nsteps steps on return.
+ *   probes  device, (nsteps + 1) * nprobes * 2 doubles written as
+ *           spstd_run's series (sample 0 = the initial state); may be NULL
+ *           when nprobes = 0.
+ *   The three fields are 256-byte aligned; all memory is on the current
+ *   device; stream is a hipStream_t (NULL: null stream).  Synchronises the
+ *   stream before returning.
+ * The scratch array is shared by every call on a GPU and keeps the last
+ * call's contents (each call re-initialises what it reads): calls that
+ * overlap on one GPU (from several host threads or streams) race.
+ * Errors: SPSTD_ERR_ARG (bad descriptor or pointers), SPSTD_ERR_SCRATCH (the
+ * grid's tables exceed the scratch: x transforms of up to 16384 points fit),
+ * SPSTD_ERR_DEVICE (HIP error, or a probe index found outside the grid).
+ */
+#define SPSTD_NOALLOC_SCRATCH_BYTES (384u * 1024u)
+spstd_status spstd_run_noalloc(const spstd_desc *desc, const void *V, void *psiR, void *psiI,
+                               int64_t nsteps, double *probes, void *stream);
 
 /* ------------------------------------------------------------------------
  * Batches: many independent instances of one grid shape advanced together

@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <array>
+#include <mutex>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -50,7 +51,7 @@ struct Plan {
     char* ws;
     Layout L;
     // device fields psi_R, psi_I, V and the FP64 probe buffer: pieces of the
-    // workspace, or arrays the caller owns
+    // workspace, or the caller's own arrays (spstd_run_noalloc)
     char *fR, *fI, *fV;
     double* prb;
     hipStream_t st;
@@ -187,7 +188,7 @@ static spstd_status edge_of(const spstd_desc* d, double* x) {
 }
 
 // Workspace pieces of a plan.  external: the fields and the probe buffer
-// are device arrays the caller owns and take no room.
+// are the caller's own device arrays (spstd_run_noalloc) and take no room.
 static Layout layout_of(const spstd_desc* d, int64_t nsteps_max, bool external = false) {
     Layout L{};
     const int64_t N = d->n[0] * d->n[1] * d->n[2];
@@ -1071,6 +1072,7 @@ const char* spstd_strerror(spstd_status s) {
         case SPSTD_ERR_DEVICE: return "HIP runtime error";
         case SPSTD_ERR_NONFINITE: return "state is not finite";
         case SPSTD_ERR_CAPACITY: return "probe buffer capacity exceeded";
+        case SPSTD_ERR_SCRATCH: return "working memory exceeds the fixed no-allocation scratch";
     }
     return "unknown status";
 }
@@ -1079,3 +1081,93 @@ const char* spstd_last_error(spstd_plan_t p) { return p ? p->err.c_str() : "null
 
 }  // extern "C"
 
+// ---------------------------------------------------------------------------
+// Run without allocation
+// ---------------------------------------------------------------------------
+// Working memory of spstd_run_noalloc: one file-scope device array, one copy
+// per GPU, held until the process ends.  In host code its name stands for a
+// host-side shadow, not a device address: the device address is looked up
+// once per device (with that device current) and only that pointer is
+// handed to kernels and copies.
+static __device__ __align__(256) char scratch[SPSTD_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch[kMaxDevices] = {};
+}  // namespace
+
+// Device address of the current device's scratch array.
+static hipError_t scratch_of_current_device(char** out) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        void* ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!ptr) return hipErrorInvalidSymbol;
+        g_scratch[dev] = ptr;
+    }
+    *out = static_cast<char*>(g_scratch[dev]);
+    return hipSuccess;
+}
+
+extern "C" spstd_status spstd_run_noalloc(const spstd_desc* desc, const void* V, void* psiR, void* psiI,
+                                          int64_t nsteps, double* probes, void* stream) {
+    std::string why;
+    spstd_status s = validate(desc, &why);
+    if (s != SPSTD_OK) return s;
+    if (desc->method != SPSTD_SYMPLECTIC || desc->neig != 0 || !(desc->dt > 0.0) ||
+        (desc->flags & SPSTD_TIMING))
+        return SPSTD_ERR_ARG;
+    if (!V || !psiR || !psiI || nsteps < 0 || (desc->nprobes > 0 && !probes)) return SPSTD_ERR_ARG;
+    const size_t esz = desc->precision == SPSTD_FP64 ? 8 : 4;
+    if (((uintptr_t)V | (uintptr_t)psiR | (uintptr_t)psiI) & 255) return SPSTD_ERR_ARG;
+    const Layout L = layout_of(desc, nsteps, true);
+    if (L.total > SPSTD_NOALLOC_SCRATCH_BYTES) return SPSTD_ERR_SCRATCH;
+    double x;
+    if ((s = edge_of(desc, &x)) != SPSTD_OK) return s;
+    char* ws = nullptr;
+    if (scratch_of_current_device(&ws) != hipSuccess) return SPSTD_ERR_DEVICE;
+
+    Plan p{};
+    p.d = *desc;
+    for (int l = 0; l < desc->m; ++l) {
+        p.c[l] = desc->c[l];
+        p.dd[l] = desc->d[l];
+    }
+    p.d.c = p.c;
+    p.d.d = p.dd;
+    for (int q = 0; q < desc->nprobes; ++q) p.probe_idx[q] = desc->probe_idx[q];
+    p.d.probe_idx = p.probe_idx;
+    // launches one by one: no graph is captured or instantiated
+    p.d.flags |= SPSTD_EAGER;
+    p.dt = desc->dt;
+    p.xmax = x;
+    p.rho = 0.0;
+    p.N = desc->n[0] * desc->n[1] * desc->n[2];
+    p.nsteps_max = nsteps;
+    p.steps_done = 0;
+    p.esz = esz;
+    p.ws = ws;
+    p.L = L;
+    p.fR = static_cast<char*>(psiR);
+    p.fI = static_cast<char*>(psiI);
+    p.fV = const_cast<char*>(static_cast<const char*>(V));   // read only
+    p.prb = probes;
+    p.st = (hipStream_t)stream;
+    p.graph_ready = false;
+    p.cellvol = 1.0;
+    Plan* pp = &p;
+    s = esz == 8 ? init_tables<double>(pp) : init_tables<float>(pp);
+    if (s == SPSTD_OK) s = esz == 8 ? enqueue_steps<double>(pp, nsteps) : enqueue_steps<float>(pp, nsteps);
+    if (s != SPSTD_OK) return s;
+    int fault = 0;
+    hipError_t e = hipMemcpyAsync(&fault, fault_flag(pp), sizeof(int), hipMemcpyDeviceToHost, p.st);
+    if (e == hipSuccess) e = hipStreamSynchronize(p.st);
+    if (e != hipSuccess || fault) return SPSTD_ERR_DEVICE;
+    return SPSTD_OK;
+}

@@ -30,7 +30,7 @@ MAX_PROBES = 64
 
 STATUS = {0: "SPSTD_OK", 1: "SPSTD_ERR_ARG", 2: "SPSTD_ERR_UNSTABLE",
           3: "SPSTD_ERR_WORKSPACE", 4: "SPSTD_ERR_DEVICE", 5: "SPSTD_ERR_NONFINITE",
-          6: "SPSTD_ERR_CAPACITY"}
+          6: "SPSTD_ERR_CAPACITY", 7: "SPSTD_ERR_SCRATCH"}
 
 
 class SpstdError(RuntimeError):
@@ -72,7 +72,7 @@ EXPORTS = ["spstd_xmax", "spstd_stable_dt", "spstd_workspace_size", "spstd_plan"
            "spstd_batch_workspace_size", "spstd_batch_create", "spstd_batch_load",
            "spstd_batch_step", "spstd_batch_read", "spstd_batch_release",
            "spstd_batch_slot_info", "spstd_batch_destroy", "spstd_batch_last_error",
-           "spstd_batch_schedule",
+           "spstd_batch_schedule", "spstd_run_noalloc",
            "spstd_batch_group_workspace_size", "spstd_batch_group_create", "spstd_batch_group_step",
            "spstd_batch_group_schedule", "spstd_batch_group_set_schedule", "spstd_batch_group_destroy",
            "spstd_batch_group_last_error"]
@@ -107,6 +107,7 @@ def lib():
         L.spstd_eig_read.argtypes = [ctypes.c_void_p, c_int, pd, pd]
         L.spstd_destroy.argtypes = [ctypes.c_void_p]
         vp = ctypes.c_void_p
+        L.spstd_run_noalloc.argtypes = [P(Desc), vp, vp, vp, c_i64, vp, vp]
         L.spstd_batch_workspace_size.argtypes = [P(BatchDesc), P(c_sz)]
         L.spstd_batch_create.argtypes = [P(BatchDesc), vp, c_sz, vp, P(vp)]
         L.spstd_batch_load.argtypes = [vp, c_int, pd, c_d, c_d, c_d, c_d, pd, pd, pd, pi64, pd]
@@ -338,6 +339,24 @@ class Plan:
             off = x.value - base
             out.append(self.ws[off: off + es * self.npoints].view(dt))
         return tuple(out)
+
+
+def run_noalloc(desc, V, psiR, psiI, nsteps, probes=None, stream=None):
+    """spstd_run_noalloc: advance the device tensors psiR, psiI (in place)
+    by nsteps steps with V, writing the probe series into the device tensor
+    probes ([(nsteps+1), nprobes, 2] float64); no device memory is
+    allocated.  desc needs an explicit dt."""
+    import torch
+    for t in (V, psiR, psiI):
+        assert t.is_contiguous() and t.device.type == "cuda"
+    st = stream if stream is not None else torch.cuda.current_stream(psiR.device)
+    with torch.cuda.device(psiR.device):
+        rc = lib().spstd_run_noalloc(ctypes.byref(desc), ctypes.c_void_p(V.data_ptr()),
+                                     ctypes.c_void_p(psiR.data_ptr()), ctypes.c_void_p(psiI.data_ptr()),
+                                     int(nsteps),
+                                     ctypes.c_void_p(probes.data_ptr() if probes is not None else 0),
+                                     ctypes.c_void_p(st.cuda_stream))
+    _check(rc)
 
 
 def plan_from_workload(w, precision=FP64, method=SYMPLECTIC, dt=0.0, nsteps_max=None,
