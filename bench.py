@@ -35,7 +35,8 @@ os.environ.setdefault("GPU_MAX_HW_QUEUES", "16")
 METRIC = "grid-point stage updates/s (3D HO 256³, FP64 vs FP32); p50/p99 solve latency"
 HBM_PEAK_GBS = 8000.0
 KERNEL_SOURCES = ["paper_1805_03155_amd/csrc/kernels.hip", "paper_1805_03155_amd/csrc/passes.hpp",
-                  "paper_1805_03155_amd/csrc/fft_core.hpp"]
+                  "paper_1805_03155_amd/csrc/body_axis_acc.inc", "paper_1805_03155_amd/csrc/body_axis_ba.inc",
+                  "paper_1805_03155_amd/csrc/body_x_ab.inc", "paper_1805_03155_amd/csrc/fft_core.hpp"]
 KERNEL_NAMES = {"y": "k_axis_acc (y pass)", "z": "k_axis_acc (z pass)",
                 "yba": "k_axis_ba (y passes of a stage boundary, fused)",
                 "xab": "k_x_ab (fused A+B x pass)", "x": "k_x_acc (x half-stage)"}
