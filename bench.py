@@ -121,6 +121,16 @@ def run_precision(w, prec, steps, warmup):
     torch.cuda.synchronize()
     g1 = time.perf_counter()
     del q
+    # the same graph-replayed steps with every step boundary kept (no merged
+    # A halves): the rate the stage sequence gives without the merge
+    u = spstd.plan_from_workload(w, precision=code, nsteps_max=steps + gw, flags=spstd.NO_MERGE)
+    u.step(gw)
+    torch.cuda.synchronize()
+    u0 = time.perf_counter()
+    u.step(steps)
+    torch.cuda.synchronize()
+    u1 = time.perf_counter()
+    del u
     pcie = {"plan_setup_s": setup_s, "readback_s": readback_s,
             "value_including_transfers": su_per_step * steps / (el + setup_s + readback_s)}
     # whole-step byte accounting: the passes' algorithmic bytes over the
@@ -142,7 +152,9 @@ def run_precision(w, prec, steps, warmup):
     return {"value": rate, "ms_per_step": el / steps * 1e3, "host_transfers": pcie, "bytes": step_model,
             "roofline": roof, "kernels": per_kernel, "dt": info.dt,
             "graph_mode": {"value": su_per_step * steps / (g1 - g0),
-                           "ms_per_step": (g1 - g0) / steps * 1e3},
+                           "ms_per_step": (g1 - g0) / steps * 1e3,
+                           "without_merged_boundaries": {"value": su_per_step * steps / (u1 - u0),
+                                                         "ms_per_step": (u1 - u0) / steps * 1e3}},
             "stage_updates_per_step": su_per_step}
 
 

@@ -62,10 +62,11 @@ enum { SPSTD_LAP_SPECTRAL = 0, SPSTD_LAP_FD3 = 1 };  /* spatial second derivativ
                                                         where a resident kernel applies */
 #define SPSTD_AUTOTUNE 0x10u                         /* batch flags: time the candidate schedules
                                                         at creation and keep the faster */
-#define SPSTD_NO_MERGE 0x20u                         /* flags: keep every step boundary even where
-                                                        the last stage has no B half (then a run
-                                                        split over calls equals the unsplit run
-                                                        bitwise) */
+#define SPSTD_NO_MERGE 0x20u                         /* flags: keep every step boundary whole:
+                                                        neither merged (last stage without a B
+                                                        half; then a run split over calls equals
+                                                        the unsplit run bitwise) nor chained
+                                                        (last stage with one) */
 #define SPSTD_MAX_STAGES 16
 #define SPSTD_MAX_PROBES 64
 #define SPSTD_MAX_EIG 8
@@ -104,7 +105,10 @@ enum { SPSTD_LAP_SPECTRAL = 0, SPSTD_LAP_FD3 = 1 };  /* spatial second derivativ
  *                spstd_step call as one launch of a kernel that keeps the
  *                grid on chip.  Where the last stage has no B half, the A
  *                halves at the boundaries between the steps of one call run
- *                as one (unless SPSTD_NO_MERGE).
+ *                as one; where it has one, the y pass that ends a step and
+ *                the one that opens the next run as one sweep (both unless
+ *                SPSTD_NO_MERGE; the probe samples are those of the whole
+ *                boundaries).
  *   bc[3]        boundary per axis (Sec. 2.2, last paragraph):
  *                SPSTD_BC_PERIODIC (DFT; sample j at j * dx), or walls at
  *                x = 0 and x = L_d with samples at cell centres (j + 1/2) dx:

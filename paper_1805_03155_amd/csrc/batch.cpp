@@ -125,7 +125,24 @@ static hipError_t batch_axis(Batch* b, int a, const R* src, R* dst, const ScaleR
 }
 
 template <typename R>
-static hipError_t batch_step_once(Batch* b) {
+static hipError_t batch_probe(Batch* b, int part) {
+    if (b->d.nprobes == 0) return hipSuccess;
+    return launch_probe_batch<R>(BF<R>(b, b->L.psiR), BF<R>(b, b->L.psiI), b->npts,
+                                 reinterpret_cast<const int64_t*>(b->ws + b->L.pidx), b->d.nprobes,
+                                 reinterpret_cast<const int*>(b->ws + b->L.active), b->d.capacity,
+                                 reinterpret_cast<double*>(b->ws + b->L.probes),
+                                 reinterpret_cast<int64_t*>(b->ws + b->L.counter), b->d.nsteps_max + 1,
+                                 reinterpret_cast<int*>(b->ws + b->L.fault), b->st, part);
+}
+
+// One step and its probe samples.  *owed: on entry, the stage whose B half
+// still owes its y pass from the previous step (-1: none); chain: leave the
+// last B half's y pass owed to the next step, whose first y sweep then does
+// it fused with its own.  A chained boundary writes the psi_R half of its
+// sample at once (the owed pass changes psi_I alone) and the psi_I half
+// after that sweep (A halves leave psi_I alone).
+template <typename R>
+static hipError_t batch_step_once(Batch* b, int* owed_io, bool chain) {
     R* pr = BF<R>(b, b->L.psiR);
     R* pi = BF<R>(b, b->L.psiI);
     const R* V = BF<R>(b, b->L.V);
@@ -136,7 +153,9 @@ static hipError_t batch_step_once(Batch* b) {
     hipError_t e = hipSuccess;
     // A half y, z, x; B half x, z, y: the B half's y pass and the next A
     // half's y pass are one sweep (as in the single-plan engine)
-    int owed = -1;
+    int owed = *owed_io;
+    const bool pending = owed >= 0;
+    *owed_io = -1;
     for (int l = 0; l < b->d.m && e == hipSuccess; ++l) {
         const bool a = b->c[l] != 0.0, bb = b->dd[l] != 0.0;
         const ScaleRef sc{b->ws + b->L.scales, b->d.m, l};
@@ -154,6 +173,7 @@ static hipError_t batch_step_once(Batch* b) {
                 if (a && e == hipSuccess) e = batch_axis<R>(b, 1, pi, pr, sc, SC_KYA);
             }
             owed = -1;
+            if (l == 0 && pending && e == hipSuccess) e = batch_probe<R>(b, PROBE_I);
             if (a && e == hipSuccess && b->d.ndim == 3) e = batch_axis<R>(b, 2, pi, pr, sc, SC_KZA);
         }
         if (e != hipSuccess) break;
@@ -166,16 +186,24 @@ static hipError_t batch_step_once(Batch* b) {
             owed = l;
         }
     }
-    if (e == hipSuccess && owed >= 0) {
+    if (e != hipSuccess) return e;
+    if (chain && owed >= 0) {
+        *owed_io = owed;
+        return batch_probe<R>(b, PROBE_R);
+    }
+    if (owed >= 0) {
         const ScaleRef so{b->ws + b->L.scales, b->d.m, owed};
         e = batch_axis<R>(b, 1, pr, pi, so, SC_KYB);
     }
-    if (e == hipSuccess && b->d.nprobes > 0)
-        e = launch_probe_batch<R>(pr, pi, b->npts, reinterpret_cast<const int64_t*>(b->ws + b->L.pidx),
-                                  b->d.nprobes, reinterpret_cast<const int*>(b->ws + b->L.active),
-                                  b->d.capacity, reinterpret_cast<double*>(b->ws + b->L.probes),
-                                  reinterpret_cast<int64_t*>(b->ws + b->L.counter), b->d.nsteps_max + 1,
-                                  reinterpret_cast<int*>(b->ws + b->L.fault), b->st);
+    return e == hipSuccess ? batch_probe<R>(b, PROBE_FULL) : e;
+}
+
+// n steps, chained: every boundary between them but the last is fused.
+template <typename R>
+static hipError_t batch_steps(Batch* b, int64_t n) {
+    int owed = -1;
+    hipError_t e = hipSuccess;
+    for (int64_t s = 0; s < n && e == hipSuccess; ++s) e = batch_step_once<R>(b, &owed, s + 1 < n);
     return e;
 }
 
@@ -188,8 +216,7 @@ static spstd_status batch_build_graph(Batch* b) {
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
-        hipError_t e2 = hipSuccess;
-        for (int s = 0; s < kBatchGraphChunk && e2 == hipSuccess; ++s) e2 = batch_step_once<R>(b);
+        const hipError_t e2 = batch_steps<R>(b, kBatchGraphChunk);
         e = hipStreamEndCapture(cap, &g);
         if (e == hipSuccess) e = e2;
     }
@@ -277,7 +304,7 @@ static spstd_status batch_step_t(Batch* b, int64_t n) {
         }
         for (; left >= kBatchGraphChunk; left -= kBatchGraphChunk) BCHK(hipGraphLaunch(b->graph, b->st));
     }
-    for (; left > 0; --left) BCHK(batch_step_once<R>(b));
+    if (left > 0) BCHK(batch_steps<R>(b, left));
     return SPSTD_OK;
 }
 
@@ -903,15 +930,20 @@ static int group_grid(int64_t ntiles, int wpb, bool one_per_cu, int cus) {
 }
 
 // One step of every member: the stage sequence of batch_step_once (the y
-// sweep owed by a B half fused with the next A half's), each pass one
-// launch over all members; then the probe samples.
+// sweep owed by a B half fused with the next A half's, *owed and chain as
+// there), each pass one launch over all members; then the probe samples.
 template <typename R>
-static hipError_t group_step_once(Group* g) {
+static hipError_t group_step_once(Group* g, int* owed_io, bool chain) {
     if (g->choice >= g->nvar) {
+        // the members share one coefficient set: their owed stages agree
+        int next = -1;
         for (Batch* b : g->members) {
-            const hipError_t e = batch_step_once<R>(b);
+            int o = *owed_io;
+            const hipError_t e = batch_step_once<R>(b, &o, chain);
             if (e != hipSuccess) return e;
+            next = o;
         }
+        *owed_io = next;
         return hipSuccess;
     }
     const int k = g->choice;
@@ -923,18 +955,33 @@ static hipError_t group_step_once(Group* g) {
     const int nx = (int)g->x_n[k], ny = (int)g->y_n[k];
     const int gx = group_grid(nx, v.wpb, mix_one_per_cu(k), g->cus), gy = group_grid(ny, v.wpb, mix_one_per_cu(k), g->cus);
     const int nyq = g->members[0]->d.nyquist;
+    const int nprobes = g->members[0]->d.nprobes;
+    const MixTile* slots = reinterpret_cast<const MixTile*>(g->ws + g->slot_off);
     hipError_t e = hipSuccess;
-    int owed = -1;
+    int owed = *owed_io;
+    const bool pending = owed >= 0;
+    *owed_io = -1;
     for (int l = 0; l < g->m && e == hipSuccess; ++l) {
         if (owed >= 0) e = launch_mix_axis_ba<R>(mem, ty, ny, gy, g->m, owed, l, nyq, v, g->st);
         else e = launch_mix_axis_acc<R>(mem, ty, ny, gy, g->m, l, 0, nyq, v, g->st);
+        if (l == 0 && pending && e == hipSuccess) e = launch_mix_probe<R>(mem, slots, g->nslots, nprobes, g->st, PROBE_I);
         if (e == hipSuccess) e = launch_mix_x_ab<R>(mem, tx, nx, gx, g->m, l, nyq, v, g->st);
         owed = l;
     }
-    if (e == hipSuccess && owed >= 0) e = launch_mix_axis_acc<R>(mem, ty, ny, gy, g->m, owed, 1, nyq, v, g->st);
-    if (e == hipSuccess && g->members[0]->d.nprobes > 0)
-        e = launch_mix_probe<R>(mem, reinterpret_cast<const MixTile*>(g->ws + g->slot_off), g->nslots,
-                                g->members[0]->d.nprobes, g->st);
+    if (e != hipSuccess) return e;
+    if (chain) {
+        *owed_io = owed;
+        return launch_mix_probe<R>(mem, slots, g->nslots, nprobes, g->st, PROBE_R);
+    }
+    e = launch_mix_axis_acc<R>(mem, ty, ny, gy, g->m, owed, 1, nyq, v, g->st);
+    return e == hipSuccess ? launch_mix_probe<R>(mem, slots, g->nslots, nprobes, g->st, PROBE_FULL) : e;
+}
+
+template <typename R>
+static hipError_t group_steps(Group* g, int64_t n) {
+    int owed = -1;
+    hipError_t e = hipSuccess;
+    for (int64_t s = 0; s < n && e == hipSuccess; ++s) e = group_step_once<R>(g, &owed, s + 1 < n);
     return e;
 }
 
@@ -953,8 +1000,7 @@ static spstd_status group_build_graph(Group* g) {
     hipGraph_t gr = nullptr;
     hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
-        hipError_t e2 = hipSuccess;
-        for (int s = 0; s < kBatchGraphChunk && e2 == hipSuccess; ++s) e2 = group_step_once<R>(g);
+        const hipError_t e2 = group_steps<R>(g, kBatchGraphChunk);
         e = hipStreamEndCapture(cap, &gr);
         if (e == hipSuccess) e = e2;
     }
@@ -981,7 +1027,7 @@ static spstd_status group_step_t(Group* g, int64_t n) {
         }
         for (; left >= kBatchGraphChunk; left -= kBatchGraphChunk) GCHK(hipGraphLaunch(g->graph, g->st));
     }
-    for (; left > 0; --left) GCHK(group_step_once<R>(g));
+    if (left > 0) GCHK(group_steps<R>(g, left));
     return SPSTD_OK;
 }
 

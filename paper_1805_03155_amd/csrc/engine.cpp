@@ -336,6 +336,23 @@ static hipError_t x_half(Plan* p, const R* src, R* dst, const ScaleRef& sc, int 
 // formed; its probe samples are interpolated from psi_R around the merged
 // half (probes.hip).  Not with eigenstate sums (they need every step's
 // state) or the difference operator.
+// When the last stage has a B half, a step ends with the B half's own pass
+// along the fused axis; between consecutive steps of one enqueue that pass
+// and the first A half's pass along the same axis run as one sweep
+// (launch_axis_ba), exactly as at the stage boundaries inside a step.  The
+// step's end state is then never complete in memory at once: its probe
+// samples take psi_R before the sweep (it leaves psi_R of the step alone
+// until the A half adds to it) and psi_I after it (the A half leaves psi_I
+// alone until the x pass).  Not with eigenstate sums, the difference
+// operator, a walled fused axis or SPSTD_NO_MERGE.
+static bool chains_steps(const Plan* p) {
+    const spstd_desc& d = p->d;
+    if (d.method != SPSTD_SYMPLECTIC || d.laplacian != SPSTD_LAP_SPECTRAL || p->eig_on || d.ndim < 2 ||
+        d.bc[kFuseAxis] != SPSTD_BC_PERIODIC || (d.flags & SPSTD_NO_MERGE))
+        return false;
+    return p->dd[d.m - 1] != 0.0 && p->c[0] != 0.0;
+}
+
 static bool merges_steps(const Plan* p) {
     const spstd_desc& d = p->d;
     if (d.method != SPSTD_SYMPLECTIC || d.laplacian != SPSTD_LAP_SPECTRAL || p->eig_on || d.m < 2 ||
@@ -389,9 +406,10 @@ static hipError_t enqueue_symplectic_steps(Plan* p, int64_t k, bool merge) {
         return axis_pass<R>(p, fa, pr, pi, so, SC_KXB + fa);
     };
     // one stage: A half (a) with row's A columns, B half (b) with its B
-    // columns; boundary: a merged step boundary, whose probe samples are
-    // taken around it
-    auto stage = [&](int row, bool a, bool b, bool boundary) -> hipError_t {
+    // columns; boundary: a merged or chained step boundary, whose probe
+    // samples are taken around it: psi_R interpolated with weight w between
+    // its values before and after the stage's A half, psi_I before the x pass
+    auto stage = [&](int row, bool a, bool b, bool boundary, double w) -> hipError_t {
         const ScaleRef sc{p->ws + p->L.scales, rows, row};
         const bool smp = boundary && p->d.nprobes > 0;
         hipError_t r = hipSuccess;
@@ -444,7 +462,6 @@ static hipError_t enqueue_symplectic_steps(Plan* p, int64_t k, bool merge) {
         }
         if (r != hipSuccess) return r;
         if (smp) {
-            const double w = p->c[m - 1] / (p->c[m - 1] + p->c[0]);
             r = launch_probe_merged<R>(pr, pidx, p->d.nprobes, p->N, save, save + SPSTD_MAX_PROBES, w,
                                        p->prb,
                                        reinterpret_cast<int64_t*>(p->ws + p->L.counter), p->nsteps_max + 1,
@@ -462,17 +479,20 @@ static hipError_t enqueue_symplectic_steps(Plan* p, int64_t k, bool merge) {
         }
         return r;
     };
+    const bool chain = !merge && fuse && chains_steps(p);
+    const double w_merge = merge ? p->c[m - 1] / (p->c[m - 1] + p->c[0]) : 0.0;
     for (int64_t s = 0; s < k && e == hipSuccess; ++s) {
         const bool head = merge && s > 0;        // stage 1's A half ran at the boundary before
         const bool tail = merge && s + 1 < k;    // the last A half runs merged with the next
+        const bool chained = chain && s > 0;     // the previous step's owed pass runs fused with stage 1's
         ev_break(p);
         for (int l = head ? 1 : 0; l < m && e == hipSuccess; ++l) {
             if (l == m - 1 && tail)
-                e = stage(m + 1, true, p->dd[0] != 0.0, true);
+                e = stage(m + 1, true, p->dd[0] != 0.0, true, w_merge);
             else
-                e = stage(l, p->c[l] != 0.0, p->dd[l] != 0.0, false);
+                e = stage(l, p->c[l] != 0.0, p->dd[l] != 0.0, l == 0 && chained, 0.0);
         }
-        if (e != hipSuccess || tail) continue;
+        if (e != hipSuccess || tail || (chain && s + 1 < k)) continue;
         if (owed >= 0) {
             e = owed_pass(owed);
             owed = -1;

@@ -597,7 +597,7 @@ template <typename R>
 __global__ void k_probe_batch(const R* __restrict__ psiR, const R* __restrict__ psiI, int64_t npts,
                               const int64_t* __restrict__ idx, int nprobes, const int* __restrict__ active,
                               int ninst, double* __restrict__ probes, int64_t* __restrict__ counter,
-                              int64_t capacity, int* __restrict__ fault) {
+                              int64_t capacity, int* __restrict__ fault, int part) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= ninst || !active[i]) return;
     const int64_t slot = counter[i];
@@ -610,20 +610,21 @@ __global__ void k_probe_batch(const R* __restrict__ psiR, const R* __restrict__ 
                 continue;
             }
             const int64_t k = (int64_t)i * npts + p;
-            out[2 * q] = (double)psiR[k];
-            out[2 * q + 1] = (double)psiI[k];
+            if (part & PROBE_R) out[2 * q] = (double)psiR[k];
+            if (part & PROBE_I) out[2 * q + 1] = (double)psiI[k];
         }
     }
-    counter[i] = slot + 1;
+    if (part & PROBE_I) counter[i] = slot + 1;
 }
 
 template <typename R>
 hipError_t launch_probe_batch(const R* psiR, const R* psiI, int64_t npts, const int64_t* idx, int nprobes,
                               const int* active, int ninst, double* probes, int64_t* counter,
-                              int64_t capacity, int* fault, hipStream_t st) {
+                              int64_t capacity, int* fault, hipStream_t st, int part) {
+    if (part < PROBE_R || part > PROBE_FULL) return hipErrorInvalidValue;
     const int blocks = (ninst + 63) / 64;
     hipLaunchKernelGGL((k_probe_batch<R>), dim3(blocks), dim3(64), 0, st, psiR, psiI, npts, idx, nprobes,
-                       active, ninst, probes, counter, capacity, fault);
+                       active, ninst, probes, counter, capacity, fault, part);
     return hipGetLastError();
 }
 
@@ -797,7 +798,7 @@ hipError_t launch_fill0(int64_t n, R* y, hipStream_t st) {
                                        const ScaleRef&, int, hipStream_t, int);                 \
     template hipError_t launch_probe_batch<R>(const R*, const R*, int64_t, const int64_t*, int, \
                                               const int*, int, double*, int64_t*, int64_t,      \
-                                              int*, hipStream_t);                               \
+                                              int*, hipStream_t, int);                          \
     template hipError_t launch_probe<R>(const R*, const R*, const int64_t*, int, int64_t,       \
                                         double*, int64_t*, int64_t, int*, hipStream_t);         \
     template hipError_t launch_norm_partials<R>(const R*, const R*, int64_t, double*, int,      \

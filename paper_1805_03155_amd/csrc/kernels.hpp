@@ -83,10 +83,18 @@ hipError_t launch_x_ab(int64_t nx, R* psiR, R* psiI, const R* V, const void* tw,
 // out_i[slot][p] = (psiR[i*npts + idx[i*P + p]], psiI[...]) as doubles,
 // slot = counter[i], then counter[i]++ (slots >= capacity are not written).
 // out_i = probes + i * capacity * P * 2.
+//
+// part: the whole sample (PROBE_FULL), or one half of it: PROBE_R writes
+// the psi_R values and keeps the counter, PROBE_I writes the psi_I values
+// and advances it.  The halves serve a step boundary whose last pass runs
+// fused with the next step's first: psi_R is final before that sweep,
+// psi_I after it.
+enum ProbePart { PROBE_R = 1, PROBE_I = 2, PROBE_FULL = 3 };
 template <typename R>
 hipError_t launch_probe_batch(const R* psiR, const R* psiI, int64_t npts, const int64_t* idx,
                               int nprobes, const int* active, int ninst, double* probes,
-                              int64_t* counter, int64_t capacity, int* fault, hipStream_t st);
+                              int64_t* counter, int64_t capacity, int* fault, hipStream_t st,
+                              int part = PROBE_FULL);
 
 // probe sample: out[slot][p] = (psiR[idx_p], psiI[idx_p]) as doubles, where
 // slot = *counter; then (*counter)++.  Single thread block, nprobes 0..64.
@@ -249,10 +257,10 @@ hipError_t launch_mix_axis_acc(const MixMember<R>* mem, const MixTile* tiles, in
 template <typename R>
 hipError_t launch_mix_axis_ba(const MixMember<R>* mem, const MixTile* tiles, int ntiles, int grid, int m,
                               int lB, int lA, int nyq_zero, const MixVariant& v, hipStream_t st);
-// Probe samples of every active slot of every member (as launch_probe_batch);
-// slots[i] = (member, slot).
+// Probe samples of every active slot of every member (as launch_probe_batch,
+// with its parts); slots[i] = (member, slot).
 template <typename R>
 hipError_t launch_mix_probe(const MixMember<R>* mem, const MixTile* slots, int nslots, int nprobes,
-                            hipStream_t st);
+                            hipStream_t st, int part = PROBE_FULL);
 
 }  // namespace spstd

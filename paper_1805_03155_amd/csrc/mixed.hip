@@ -100,7 +100,7 @@ __global__ __launch_bounds__(64 * W) SPSTD_WAVES_ATTR void k_mix_axis_ba(const M
 
 template <typename R>
 __global__ void k_mix_probe(const MixMember<R>* __restrict__ mem, const MixTile* __restrict__ slots, int nslots,
-                            int nprobes) {
+                            int nprobes, int part) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= nslots) return;
     const MixTile ms = slots[i];
@@ -117,11 +117,11 @@ __global__ void k_mix_probe(const MixMember<R>* __restrict__ mem, const MixTile*
                 continue;
             }
             const int64_t k = (int64_t)s * M.npts + p;
-            out[2 * q] = (double)M.psiR[k];
-            out[2 * q + 1] = (double)M.psiI[k];
+            if (part & PROBE_R) out[2 * q] = (double)M.psiR[k];
+            if (part & PROBE_I) out[2 * q + 1] = (double)M.psiI[k];
         }
     }
-    M.counter[s] = slot + 1;
+    if (part & PROBE_I) M.counter[s] = slot + 1;
 }
 
 // ---------------------------------------------------------------------------
@@ -201,10 +201,11 @@ hipError_t launch_mix_axis_ba(const MixMember<R>* mem, const MixTile* tiles, int
 
 template <typename R>
 hipError_t launch_mix_probe(const MixMember<R>* mem, const MixTile* slots, int nslots, int nprobes,
-                            hipStream_t st) {
+                            hipStream_t st, int part) {
+    if (part < PROBE_R || part > PROBE_FULL) return hipErrorInvalidValue;
     if (nslots <= 0 || nprobes <= 0) return hipSuccess;
     hipLaunchKernelGGL((k_mix_probe<R>), dim3((unsigned)((nslots + 63) / 64)), dim3(64), 0, st, mem, slots, nslots,
-                       nprobes);
+                       nprobes, part);
     return hipGetLastError();
 }
 
@@ -215,7 +216,7 @@ hipError_t launch_mix_probe(const MixMember<R>* mem, const MixTile* slots, int n
                                                int, int, const MixVariant&, hipStream_t);                  \
     template hipError_t launch_mix_axis_ba<R>(const MixMember<R>*, const MixTile*, int, int, int, int,     \
                                               int, int, const MixVariant&, hipStream_t);                   \
-    template hipError_t launch_mix_probe<R>(const MixMember<R>*, const MixTile*, int, int, hipStream_t);
+    template hipError_t launch_mix_probe<R>(const MixMember<R>*, const MixTile*, int, int, hipStream_t, int);
 SPSTD_INST_MIX(double)
 SPSTD_INST_MIX(float)
 #undef SPSTD_INST_MIX

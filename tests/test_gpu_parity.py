@@ -261,14 +261,17 @@ def test_small_2d_plans_resident_vs_passes(n, prec):
     assert np.array_equal(ser[s:], a[2][s:])
 
 
-@pytest.mark.parametrize("name", ["forest_ruth", "yoshida6"])
+@pytest.mark.parametrize("name", ["forest_ruth", "yoshida6", "paper", "leapfrog"])
 @pytest.mark.parametrize("n", [(32, 16, 64), (64, 32), (256,)])
 @pytest.mark.parametrize("prec", [spstd.FP64, spstd.FP32])
 def test_merged_step_boundaries(name, n, prec):
     # sets whose last stage has no B half run the A half ending a step and
     # the one opening the next as one (coefficient c_m + c_1); the boundary
-    # probe samples are interpolated.  40 steps: two graph chunks of 16 and
-    # 8 eager steps; eager launches merge the same boundaries
+    # probe samples are interpolated.  Sets whose last stage has a B half
+    # (paper, leapfrog) chain instead: the step's last y pass runs fused with
+    # the next step's first, the samples taken around that sweep.  40 steps:
+    # two graph chunks of 16 and 8 eager steps; eager launches merge or
+    # chain the same boundaries
     steps = 40
     w = case(n, seed=len(n) * 11 + 5, steps=steps, coeffs=W.COEFFS[name])
     dt = oracle.stable_dt(*w.coeffs, w.V, w.n, w.dx)

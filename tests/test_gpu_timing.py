@@ -29,18 +29,24 @@ def case(n, seed=5, coeffs=W.PAPER):
 # passes per step for the three-stage paper set (every c_l and d_l nonzero):
 # stage 1 opens with a plain y pass, stages 2 and 3 with the fused boundary
 # sweep, every stage has one fused x pass and two z passes, and the step
-# ends with the y pass its last B half owes
+# ends with the y pass its last B half owes.  Within one call the boundaries
+# between steps chain: each of the steps - 1 boundaries runs one fused sweep
+# in place of the owed y pass and the next opening y pass (not with
+# SPSTD_NO_MERGE)
 @pytest.mark.parametrize("n,per_step", [((32, 16, 64), {"y": 2, "z": 6, "xab": 3, "x": 0, "yba": 2}),
                                         ((64, 32), {"y": 2, "z": 0, "xab": 3, "x": 0, "yba": 2}),
                                         ((256,), {"y": 0, "z": 0, "xab": 3, "x": 0, "yba": 0})])
 @pytest.mark.parametrize("precision", [spstd.FP64, spstd.FP32])
-def test_pass_counts_durations_and_state(n, per_step, precision):
+@pytest.mark.parametrize("chained", [True, False])
+def test_pass_counts_durations_and_state(n, per_step, precision, chained):
     steps = 10
     w = case(n)
-    p = spstd.plan_from_workload(w, precision=precision, nsteps_max=2 * steps + 2, flags=spstd.TIMING)
+    extra = 0 if chained else spstd.NO_MERGE
+    p = spstd.plan_from_workload(w, precision=precision, nsteps_max=2 * steps + 2, flags=spstd.TIMING | extra)
     # the same pass kernels, replayed from graphs (1D plans would otherwise
-    # take the resident kernel)
-    q = spstd.plan_from_workload(w, precision=precision, nsteps_max=2 * steps + 2, flags=spstd.NO_RESIDENT)
+    # take the resident kernel), with the same calls
+    q = spstd.plan_from_workload(w, precision=precision, nsteps_max=2 * steps + 2,
+                                 flags=spstd.NO_RESIDENT | extra)
     p.step(2)
     p.pass_times()                                  # discard the first steps
     torch.cuda.synchronize()
@@ -49,14 +55,19 @@ def test_pass_counts_durations_and_state(n, per_step, precision):
     torch.cuda.synchronize()
     wall_ms = (time.perf_counter() - t0) * 1e3
     t = p.pass_times()
-    for kind, count in per_step.items():
-        assert t[kind][0] == count * steps, (kind, t[kind])
+    want = {k: v * steps for k, v in per_step.items()}
+    if chained and len(n) >= 2:
+        want["y"] -= 2 * (steps - 1)
+        want["yba"] += steps - 1
+    for kind, count in want.items():
+        assert t[kind][0] == count, (kind, t[kind], count)
         if count:
             assert t[kind][1] > 0.0
     assert sum(v[1] for v in t.values()) <= wall_ms
     # nothing left over: a second call reports no launches
     assert all(v[0] == 0 for v in p.pass_times().values())
-    q.step(2 + steps)
+    q.step(2)
+    q.step(steps)
     r, i, _ = p.get_state()
     rq, iq, _ = q.get_state()
     assert np.array_equal(r, rq) and np.array_equal(i, iq)
