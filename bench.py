@@ -28,9 +28,12 @@ import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
-# the serving leg runs one stream per request class; give HIP enough hardware
-# queues that classes do not wait behind each other (set before HIP starts)
-os.environ.setdefault("GPU_MAX_HW_QUEUES", "16")
+# the serving and batching legs run one stream per request class or shape;
+# with fewer hardware queues than streams, streams share in-order queues and
+# a long chunk on one holds back the others' launches and copies.  Raised to
+# 16 (not lowered) before HIP starts.
+if int(os.environ.get("GPU_MAX_HW_QUEUES", "0") or 0) < 16:
+    os.environ["GPU_MAX_HW_QUEUES"] = "16"
 
 METRIC = "grid-point stage updates/s (3D HO 256³, FP64 vs FP32); p50/p99 solve latency"
 HBM_PEAK_GBS = 8000.0
@@ -253,8 +256,7 @@ def serving_leg(count, rate, steps, seed=0, budget_gb=64):
     with continuous batching under an HBM budget."""
     from paper_1805_03155_amd import serve
     reqs = serve.request_mix(count, rate, seed=seed, steps=steps)
-    srv = serve.Server(hbm_budget=budget_gb << 30, chunk=512, max_slots=64,
-                       max_steps=steps[1], keep_series=False)
+    srv = serve.Server(hbm_budget=budget_gb << 30, max_slots=64, max_steps=steps[1], keep_series=False)
     t0 = time.perf_counter()
     srv.run(reqs, progress=lambda t, k, n: log(f"  serving: {k}/{n} finished at {t:.0f} s"))
     el = time.perf_counter() - t0

@@ -695,27 +695,34 @@ spstd_status spstd_batch_read(spstd_batch_t b, int slot, double* probes_out, dou
     hipError_t e = hipStreamSynchronize(b->st);
     const size_t np = (size_t)b->d.nprobes;
     int fault = 0;
+    // copies on the batch's own stream: a caller stepping other batches on
+    // other streams is not made to wait for them
     if (e == hipSuccess && np > 0)
-        e = hipMemcpy(&fault, b->ws + b->L.fault, sizeof(int), hipMemcpyDeviceToHost);
+        e = hipMemcpyAsync(&fault, b->ws + b->L.fault, sizeof(int), hipMemcpyDeviceToHost, b->st);
+    if (e == hipSuccess && np > 0) e = hipStreamSynchronize(b->st);
     if (e == hipSuccess && fault) {
         b->err = "a probe index in device memory lies outside the grid (samples skipped)";
         return SPSTD_ERR_DEVICE;
     }
     if (e == hipSuccess && probes_out && np > 0) {
         const size_t poff = (size_t)slot * (b->d.nsteps_max + 1) * np * 2 * sizeof(double);
-        e = hipMemcpy(probes_out, b->ws + b->L.probes + poff, (size_t)(s.steps + 1) * np * 2 * sizeof(double),
-                      hipMemcpyDeviceToHost);
+        e = hipMemcpyAsync(probes_out, b->ws + b->L.probes + poff, (size_t)(s.steps + 1) * np * 2 * sizeof(double),
+                           hipMemcpyDeviceToHost, b->st);
+        if (e == hipSuccess) e = hipStreamSynchronize(b->st);
     }
     double* outs[2] = {psiR, psiI};
     const size_t offs[2] = {b->L.psiR, b->L.psiI};
     for (int k = 0; k < 2 && e == hipSuccess; ++k) {
         if (!outs[k]) continue;
         if (b->esz == 8) {
-            e = hipMemcpy(outs[k], b->ws + offs[k] + (size_t)slot * b->npts * 8, b->npts * 8, hipMemcpyDeviceToHost);
+            e = hipMemcpyAsync(outs[k], b->ws + offs[k] + (size_t)slot * b->npts * 8, b->npts * 8,
+                               hipMemcpyDeviceToHost, b->st);
+            if (e == hipSuccess) e = hipStreamSynchronize(b->st);
         } else {
             std::vector<float> tmp(b->npts);
-            e = hipMemcpy(tmp.data(), b->ws + offs[k] + (size_t)slot * b->npts * 4, b->npts * 4,
-                          hipMemcpyDeviceToHost);
+            e = hipMemcpyAsync(tmp.data(), b->ws + offs[k] + (size_t)slot * b->npts * 4, b->npts * 4,
+                               hipMemcpyDeviceToHost, b->st);
+            if (e == hipSuccess) e = hipStreamSynchronize(b->st);
             for (int64_t i = 0; i < b->npts && e == hipSuccess; ++i) outs[k][i] = tmp[i];
         }
     }

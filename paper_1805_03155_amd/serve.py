@@ -2,33 +2,37 @@
 
 Requests of one grid shape and precision form a class; each class owns one
 batch (``spstd.Batch``) whose slots hold the wavefunctions of its admitted
-requests on the device for their whole run.  A tick of the loop
+requests on the device for their whole run, one stream and one worker
+thread.  A worker repeatedly
 
-1. admits waiting requests (first come, first served) into free slots of
-   their class, creating the class's batch on first use when its workspace
-   fits the HBM budget;
-2. advances every class that has active slots and no chunk in flight by K
-   steps, K = min(chunk, the smallest remaining step count among its active
-   slots), each class on its own stream so that classes run concurrently on
-   the device and all requests of a class share every launch;
-3. polls each class's last chunk (a HIP event, no device-wide wait); when it
-   has completed, finishes the requests whose step count is reached: reads
-   their probe series, extracts eigenvalues with ``spstd.spectrum`` and
-   frees their slots.  Classes advance independently: a slow class never
-   holds back a fast one.
+1. admits the class's routed requests into free slots, first come first
+   served (loading a slot synchronises the class's own stream only);
+2. advances the batch by K steps and waits for them on its stream:
+   K = min(the smallest remaining step count among its active slots, the
+   steps that fill the chunk's time budget at the class's measured step
+   time, the chunk cap), so that every request of the class shares every
+   launch and a chunk never holds an arrival back for long;
+3. finishes the requests whose step count is reached: reads their probe
+   series, extracts eigenvalues with ``spstd.spectrum`` and frees their
+   slots.
 
-Requests that arrive while others are running are admitted at the next
-tick as slots and budget allow.  Latency is measured from arrival to the
-result; throughput is counted in grid-point stage updates.
+The library calls and the stream waits release the interpreter lock, so
+the classes advance independently: a copy, a long chunk or the host's
+spectrum in one class never holds back another.  The dispatcher (the
+caller's thread) routes arrivals to their classes, opens a class when its
+workspace fits the HBM budget, and closes idle classes while requests wait
+for budget.  Latency is measured from arrival to the result; throughput is
+counted in grid-point stage updates.
 
-The loop itself is host orchestration (Python); every step of the solver
-runs in the library's kernels.
+Host code only orchestrates; every step of the solver runs in the
+library's kernels.
 """
 from __future__ import annotations
 
+import threading
 import time
 from collections import deque
-from dataclasses import dataclass, field
+from dataclasses import dataclass
 
 import numpy as np
 
@@ -60,198 +64,275 @@ class Request:
         return None if self.done is None else self.done - self.arrival
 
 
-@dataclass
 class _Class:
-    key: tuple
-    batch: spstd.Batch
-    stream: object
-    bytes: int
-    slots: dict = field(default_factory=dict)   # slot -> Request
-    idle_ticks: int = 0
-    event: object = None                        # completion of the chunk in flight
+    """One class: its routed requests, its slots and its worker's state."""
 
-    def free_slots(self):
-        return [s for s in range(self.batch.capacity) if s not in self.slots]
+    def __init__(self, key, capacity, nbytes):
+        self.key = key
+        self.capacity = capacity
+        self.bytes = nbytes
+        self.queue = deque()        # routed to the class, not yet admitted (server lock)
+        self.slots = {}             # slot -> Request (worker only)
+        self.step_s = None          # measured seconds per step
+        self.idle_since = None      # server clock time the class became empty
+        self.closing = False
+        self.finished = False       # the worker has exited and freed the batch
+        self.error = None
+        self.thread = None
 
 
 class Server:
-    """Continuous-batching eigenvalue server on one GPU."""
+    """Continuous-batching eigenvalue server on one GPU.
 
-    def __init__(self, hbm_budget, coeffs=W.PAPER, chunk=512, max_slots=64, max_steps=20000,
-                 nprobes=1, device="cuda", keep_series=True, resident_chunk=2048,
-                 max_concurrent=6):
-        import torch
-        self.torch = torch
+    chunk: the most steps per launch chunk; chunk_ms: the chunk's time
+    budget at the class's measured step time; max_slots: slots per class
+    (fewer when the HBM budget is short); max_steps: the longest request
+    (it sizes the probe buffers); max_concurrent: classes stepping at once
+    (None: all).  batch_factory(key, capacity, stream) and stream_factory()
+    replace the device batch and stream (host tests of the scheduling)."""
+
+    def __init__(self, hbm_budget, coeffs=W.PAPER, chunk=4096, chunk_ms=25.0, max_slots=64,
+                 max_steps=20000, nprobes=1, device="cuda", keep_series=True, max_concurrent=None,
+                 idle_close_s=0.05, batch_factory=None, stream_factory=None, workspace_bytes=None):
         self.budget = int(hbm_budget)
         self.coeffs = coeffs
         self.chunk = int(chunk)
-        # 1D classes run a whole chunk in one launch; longer chunks cost them
-        # nothing, shorter ones bound how long an arrival waits for a slot
-        self.resident_chunk = int(resident_chunk)
-        # classes stepping at once: small latency-bound classes slow each
-        # other down when too many share the device, so the classes holding
-        # the oldest requests go first
-        self.max_concurrent = int(max_concurrent)
+        self.chunk_s = float(chunk_ms) * 1e-3
         self.max_slots = int(max_slots)
         self.max_steps = int(max_steps)
         self.nprobes = int(nprobes)
         self.device = device
         self.keep_series = keep_series
+        self.idle_close_s = float(idle_close_s)
+        self._gate = threading.BoundedSemaphore(max_concurrent) if max_concurrent else None
+        self._batch_factory = batch_factory or self._device_batch
+        self._stream_factory = stream_factory or self._device_stream
+        self._workspace_bytes = workspace_bytes or self._device_workspace_bytes
+        self.subs = sum(1 for x in coeffs[0] if x) + sum(1 for x in coeffs[1] if x)
         self.classes = {}
-        self.waiting = deque()
+        self.blocked = deque()      # requests whose class cannot open yet (budget)
         self.finished = []
         self.used = 0
-        self.stage_updates = 0.0
         self.peak_used = 0
+        self.stage_updates = 0.0
+        self.cv = threading.Condition()
+        self.stopping = False
         self.t0 = time.perf_counter()
 
     def now(self):
         return time.perf_counter() - self.t0
 
-    # -- admission ---------------------------------------------------------
-    def _slot_bytes(self, key):
-        n, prec = key
-        d1 = spstd.make_batch_desc(n, self.coeffs, 1, self.nprobes, self.max_steps, prec)
-        d2 = spstd.make_batch_desc(n, self.coeffs, 2, self.nprobes, self.max_steps, prec)
-        b1, b2 = spstd.batch_workspace_size(d1), spstd.batch_workspace_size(d2)
-        return b2 - b1, b1 - (b2 - b1)
+    # -- device hooks --------------------------------------------------------
+    def _device_stream(self):
+        import torch
+        return torch.cuda.Stream(device=self.device)
 
+    def _device_batch(self, key, capacity, stream):
+        n, prec = key
+        # 1D classes choose between the resident kernel and the pass kernels
+        # by timing both (up to 25% apart); for 3D classes only the block
+        # size is open (about 2%), and timing a full 128^3 class takes a second
+        flags = spstd.AUTOTUNE if len(n) == 1 else 0
+        return spstd.Batch(n, self.coeffs, capacity=capacity, nprobes=self.nprobes,
+                           nsteps_max=self.max_steps, precision=prec, device=self.device,
+                           stream=stream, flags=flags)
+
+    def _device_workspace_bytes(self, key, capacity):
+        n, prec = key
+        d = spstd.make_batch_desc(n, self.coeffs, capacity, self.nprobes, self.max_steps, prec)
+        return spstd.batch_workspace_size(d) + 256       # Batch aligns its base to 256 bytes
+
+    # -- dispatcher: routing, budget -----------------------------------------
     def _open_class(self, key):
-        per, base = self._slot_bytes(key)
-        room = self.budget - self.used - base - 256
+        """Open a class with as many slots (up to max_slots) as the budget
+        leaves room for; None if not even one fits."""
+        one, two = self._workspace_bytes(key, 1), self._workspace_bytes(key, 2)
+        per, base = two - one, one - (two - one)
+        room = self.budget - self.used - base
         cap = min(self.max_slots, room // per) if per > 0 else 0
         if cap < 1:
             return None
-        n, prec = key
-        stream = self.torch.cuda.Stream(device=self.device)
-        # 1D classes choose between the resident kernel and the pass kernels
-        # by timing both (up to 25% apart); for 3D classes only the block
-        # size is open (about 2%), and timing a full 128^3 class takes a
-        # second during which the loop does not tick
-        flags = spstd.AUTOTUNE if len(n) == 1 else 0
-        b = spstd.Batch(n, self.coeffs, capacity=int(cap), nprobes=self.nprobes,
-                        nsteps_max=self.max_steps, precision=prec, device=self.device,
-                        stream=stream, flags=flags)
-        nbytes = b.ws.numel()
-        c = _Class(key, b, stream, nbytes)
+        nbytes = self._workspace_bytes(key, int(cap))
+        c = _Class(key, int(cap), nbytes)
         self.classes[key] = c
         self.used += nbytes
         self.peak_used = max(self.peak_used, self.used)
+        c.thread = threading.Thread(target=self._worker, args=(c,), daemon=True)
+        c.thread.start()
         return c
 
-    def _close_idle_classes(self):
-        """Free the batches of classes that are empty while requests wait
-        for budget."""
-        if not self.waiting:
-            return
-        for key in list(self.classes):
-            c = self.classes[key]
-            if not c.slots and c.idle_ticks > 0 and c.event is None:
-                self.used -= c.bytes
-                del self.classes[key]
+    def _reap(self):
+        """Drop classes whose workers have exited, returning their budget."""
+        for key in [k for k, c in self.classes.items() if c.finished]:
+            c = self.classes.pop(key)
+            c.thread.join()
+            self.used -= c.bytes
+            if c.error is not None:
+                raise c.error
+
+    def _route(self):
+        """Move blocked requests into their classes in arrival order,
+        opening classes as the budget allows; a request that cannot be
+        placed holds back every later one (no overtaking, so no class
+        starves).  While requests wait, close classes that have been empty
+        for idle_close_s."""
+        with self.cv:
+            self._reap()
+            still = deque()
+            while self.blocked:
+                r = self.blocked.popleft()
+                c = None
+                if not still:
+                    c = self.classes.get(r.key)
+                    if c is None:
+                        c = self._open_class(r.key)
+                    elif c.closing:
+                        c = None
+                if c is None:
+                    still.append(r)
+                    continue
+                c.queue.append(r)
+            self.blocked = still
+            if self.blocked:
+                t = self.now()
+                for c in self.classes.values():
+                    if (not c.closing and not c.queue and not c.slots and c.idle_since is not None
+                            and t - c.idle_since >= self.idle_close_s):
+                        c.closing = True
+            self.cv.notify_all()
 
     def submit(self, req: Request):
         if req.steps > self.max_steps:
             raise ValueError("request has more steps than the server's probe buffers hold")
-        self.waiting.append(req)
+        with self.cv:
+            self.blocked.append(req)
 
-    def _admit(self):
-        still = deque()
-        while self.waiting:
-            r = self.waiting.popleft()
-            c = self.classes.get(r.key) or self._open_class(r.key)
-            free = c.free_slots() if (c is not None and c.event is None) else []
-            if not free:
-                still.append(r)
-                continue
-            s = free[0]
+    # -- worker: one class ----------------------------------------------------
+    def _admit(self, c, batch):
+        with self.cv:
+            free = [s for s in range(c.capacity) if s not in c.slots]
+            take = []
+            while c.queue and free:
+                take.append((free.pop(0), c.queue.popleft()))
+        for s, r in take:
             w = r.work
-            r.dt = c.batch.load(s, w.dx, w.V, w.psiR, w.psiI, w.probes[: self.nprobes],
-                                cfl_fraction=w.cfl_fraction, hbar=w.hbar, mass=w.mass)
+            r.dt = batch.load(s, w.dx, w.V, w.psiR, w.psiI, w.probes[: self.nprobes],
+                              cfl_fraction=w.cfl_fraction, hbar=w.hbar, mass=w.mass)
             c.slots[s] = r
             r.admitted = self.now()
             r.status = "running"
-        self.waiting = still
 
-    # -- one tick ------------------------------------------------------------
-    def _harvest(self, c):
-        done = []
+    def _chunk_steps(self, c, batch):
+        left = min(r.steps - batch.slot_info(s)[1] for s, r in c.slots.items())
+        if c.step_s is None:
+            k = 16                          # first chunk: measures the step time
+        else:
+            k = int(self.chunk_s / max(c.step_s, 1e-7))
+        return max(1, min(k, left, self.chunk))
+
+    def _harvest(self, c, batch):
         for s, r in list(c.slots.items()):
-            if c.batch.slot_info(s)[1] >= r.steps:
-                ser, _, _, _ = c.batch.read(s, state=False)
-                E, _ = spstd.spectrum(ser, r.dt, hbar=r.work.hbar, nlevels=r.nlevels)
-                r.E = E
-                if self.keep_series:
-                    r.series = ser
-                c.batch.release(s)
-                del c.slots[s]
-                r.done = self.now()
-                r.status = "done"
-                done.append(r)
-        return done
-
-    def tick(self):
-        """One pass over the classes; returns the requests finished in it."""
-        done = []
-        # classes whose chunk has completed: finish their requests
-        for c in self.classes.values():
-            if c.event is not None and c.event.query():
-                c.event = None
-                done.extend(self._harvest(c))
-        self._close_idle_classes()
-        # admission only into classes with nothing in flight (loading a slot
-        # synchronises the class's stream)
-        if self.waiting:
-            self._admit()
-        subs = sum(1 for x in self.coeffs[0] if x) + sum(1 for x in self.coeffs[1] if x)
-        running = sum(1 for c in self.classes.values() if c.event is not None)
-        ready = []
-        for c in self.classes.values():
-            if c.event is not None:
+            if batch.slot_info(s)[1] < r.steps:
                 continue
-            if not c.slots:
-                c.idle_ticks += 1
-                continue
-            c.idle_ticks = 0
-            ready.append(c)
-        ready.sort(key=lambda c: min(r.arrival for r in c.slots.values()))
-        for c in ready[: max(0, self.max_concurrent - running)]:
-            left = min(r.steps - c.batch.slot_info(s)[1] for s, r in c.slots.items())
-            cap = self.resident_chunk if len(c.key[0]) == 1 else self.chunk
-            k = max(1, min(cap, left))
-            c.batch.step(k)
-            c.event = self.torch.cuda.Event()
-            c.event.record(c.stream)
-            self.stage_updates += len(c.slots) * c.batch.npoints * k * subs / 2.0
-        self.finished.extend(done)
-        return done
+            ser, _, _, _ = batch.read(s, state=False)
+            E, _ = spstd.spectrum(ser, r.dt, hbar=r.work.hbar, nlevels=r.nlevels)
+            r.E = E
+            if self.keep_series:
+                r.series = ser
+            batch.release(s)
+            del c.slots[s]
+            r.done = self.now()
+            r.status = "done"
+            with self.cv:
+                self.finished.append(r)
+                self.cv.notify_all()
 
-    def busy(self):
-        return bool(self.waiting) or any(c.slots for c in self.classes.values())
+    def _worker(self, c):
+        batch = None
+        try:
+            stream = self._stream_factory()
+            batch = self._batch_factory(c.key, c.capacity, stream)
+            while True:
+                with self.cv:
+                    while not c.queue and not c.slots and not (c.closing or self.stopping):
+                        if c.idle_since is None:
+                            c.idle_since = self.now()
+                        self.cv.wait(timeout=0.05)
+                    if self.stopping or (not c.queue and not c.slots):
+                        break                       # stopped, or closing with nothing left
+                    c.idle_since = None
+                self._admit(c, batch)
+                k = self._chunk_steps(c, batch)
+                if self._gate:
+                    self._gate.acquire()
+                try:
+                    t0 = time.perf_counter()
+                    batch.step(k)
+                    stream.synchronize()
+                    el = time.perf_counter() - t0
+                finally:
+                    if self._gate:
+                        self._gate.release()
+                c.step_s = el / k if c.step_s is None else 0.5 * c.step_s + 0.5 * el / k
+                with self.cv:
+                    self.stage_updates += len(c.slots) * batch.npoints * k * self.subs / 2.0
+                self._harvest(c, batch)
+        except BaseException as e:          # reported by the dispatcher
+            c.error = e
+        finally:
+            del batch
+            with self.cv:
+                c.finished = True
+                self.cv.notify_all()
 
+    # -- the loop ---------------------------------------------------------------
     def run(self, requests, time_limit=None, progress=None, progress_every=20.0):
         """Serve requests whose ``arrival`` times are offsets on the server's
-        clock; returns them when all have finished (or at the time limit).
+        clock; returns them when all have finished (or at the time limit:
+        the workers stop after their current chunk).
         ``progress(now, finished, total)`` is called every ``progress_every``
         seconds if given."""
+        if self._batch_factory == self._device_batch:
+            spstd.lib()                     # loaded once, before the workers start
         pending = deque(sorted(requests, key=lambda r: r.arrival))
+        total = len(pending)
+        start_done = len(self.finished)
         self.t0 = time.perf_counter()
+        self.stopping = False
         next_report = progress_every
-        while pending or self.busy():
-            if progress is not None and self.now() >= next_report:
-                progress(self.now(), len(self.finished), len(requests))
-                next_report += progress_every
-            t = self.now()
-            while pending and pending[0].arrival <= t:
-                self.submit(pending.popleft())
-            if not self.busy():
-                time.sleep(max(0.0, min(0.01, pending[0].arrival - t)))
-                continue
-            if not self.tick():
-                time.sleep(2e-4)        # nothing finished: let the device work
-            if time_limit is not None and self.now() > time_limit:
-                break
+        try:
+            while True:
+                t = self.now()
+                while pending and pending[0].arrival <= t:
+                    self.submit(pending.popleft())
+                self._route()
+                with self.cv:
+                    if len(self.finished) - start_done >= total:
+                        break
+                    wait = 0.005
+                    if pending:
+                        wait = min(wait, max(0.0, pending[0].arrival - self.now()))
+                    self.cv.wait(timeout=wait)
+                if progress is not None and self.now() >= next_report:
+                    progress(self.now(), len(self.finished) - start_done, total)
+                    next_report += progress_every
+                if time_limit is not None and self.now() > time_limit:
+                    break
+        finally:
+            with self.cv:
+                self.stopping = True
+                for c in self.classes.values():
+                    c.closing = True
+                self.cv.notify_all()
+            for c in list(self.classes.values()):
+                c.thread.join()
+            with self.cv:
+                self._reap()
         return requests
+
+    def busy(self):
+        with self.cv:
+            return bool(self.blocked) or any(c.slots or c.queue for c in self.classes.values())
 
 
 def latency_summary(reqs, elapsed, stage_updates):
