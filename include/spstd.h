@@ -370,11 +370,12 @@ typedef struct spstd_batch_s *spstd_batch_t;
  *   nprobes       probe points per slot, 0..8.
  *   nsteps_max    probe samples kept per slot after sample 0.
  *   flags         SPSTD_ALLOW_UNSTABLE, SPSTD_NO_RESIDENT, SPSTD_AUTOTUNE.
- *                 A 1D batch of up to 16384 points, or a 2D batch of n_x,
- *                 n_y in {16, 32, 64}, has two schedules: the resident
- *                 kernel (whole step chunks in one launch; a 2D instance
- *                 lives in one workgroup's LDS) or the pass kernels
- *                 replayed as step graphs.  The pass kernels
+ *                 A 1D batch of up to 16384 points, a 2D batch of n_x,
+ *                 n_y in {16, 32, 64}, or a 16^3 batch has two schedules:
+ *                 the resident kernel (whole step chunks in one launch; a
+ *                 2D instance lives in one workgroup's LDS, a 3D instance
+ *                 is stepped by one workgroup in its own arrays) or the
+ *                 pass kernels replayed as step graphs.  The pass kernels
  *                 run 2 or 4 waves per block.  SPSTD_AUTOTUNE runs every
  *                 candidate (resident where it applies; passes at 2 and at
  *                 4 waves per block) for a few steps on the empty batch at

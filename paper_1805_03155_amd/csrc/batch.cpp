@@ -4,8 +4,8 @@
 // every directional pass of a stage is one launch over all slots; each slot
 // has its own row of the scale table (its dt, spacing, m* and hbar), its own
 // probe points, probe buffer and step counter.  Free slots hold zero fields
-// and zero scales, so they stay zero.  Short 1D batches and 2D batches of
-// up to 64 x 64 points run a resident kernel (one launch per
+// and zero scales, so they stay zero.  Short 1D batches, 2D batches of up
+// to 64 x 64 points and 16^3 batches run a resident kernel (one launch per
 // spstd_batch_step call for every active slot).
 #include <hip/hip_runtime.h>
 
@@ -252,8 +252,8 @@ static spstd_status upload_rtab(Batch* b) {
         I.nprobes = b->d.nprobes;
         for (int q = 0; q < b->d.nprobes; ++q) I.probe_idx[q] = s.probe_idx[q];
         // kinetic scale per axis: (hbar/2m*) (2 pi/L)^2 / N for the bare k^2
-        double kin[2] = {0.0, 0.0};
-        for (int ax = 0; ax < b->d.ndim && ax < 2; ++ax) {
+        double kin[3] = {0.0, 0.0, 0.0};
+        for (int ax = 0; ax < b->d.ndim; ++ax) {
             const double k1 = k1base / ((double)b->d.n[ax] * s.dx[ax]);
             kin[ax] = s.hbar / (2.0 * s.mass) * k1 * k1 / (double)b->d.n[ax];
         }
@@ -263,6 +263,8 @@ static spstd_status upload_rtab(Batch* b) {
             I.kin[2 * l + 1] = (R)(bb * kin[0]);
             I.kin_y[2 * l] = (R)(a * kin[1]);
             I.kin_y[2 * l + 1] = (R)(bb * kin[1]);
+            I.kin_z[2 * l] = (R)(a * kin[2]);
+            I.kin_z[2 * l + 1] = (R)(bb * kin[2]);
             I.pot[2 * l] = (R)(a / s.hbar);
             I.pot[2 * l + 1] = (R)(bb / s.hbar);
         }
@@ -290,9 +292,13 @@ static spstd_status batch_step_t(Batch* b, int64_t n) {
             if (b->d.ndim == 1)
                 BCHK(launch_resident_1d<R>(b->d.n[0], tab, b->nres, b->d.m, n, b->d.nyquist, b->ws + b->L.tw[0],
                                            b->st));
-            else
+            else if (b->d.ndim == 2)
                 BCHK(launch_resident_2d<R>(b->d.n[0], b->d.n[1], tab, b->nres, b->d.m, n, b->d.nyquist,
                                            b->ws + b->L.tw[0], b->ws + b->L.tw[1], b->st));
+            else
+                BCHK(launch_resident_3d<R>(b->d.n[0], b->d.n[1], b->d.n[2], tab, b->nres, b->d.m, n,
+                                           b->d.nyquist, b->ws + b->L.tw[0], b->ws + b->L.tw[1],
+                                           b->ws + b->L.tw[2], b->st));
         }
         return SPSTD_OK;
     }
@@ -521,7 +527,8 @@ spstd_status spstd_batch_create(const spstd_batch_desc* d, void* d_workspace, si
     b->L = L;
     b->st = (hipStream_t)stream;
     b->slots.resize(d->capacity);
-    b->resident = ((d->ndim == 1 && resident_len_ok(d->n[0])) || (d->ndim == 2 && resident2d_ok(d->n[0], d->n[1]))) &&
+    b->resident = ((d->ndim == 1 && resident_len_ok(d->n[0])) || (d->ndim == 2 && resident2d_ok(d->n[0], d->n[1])) ||
+                   (d->ndim == 3 && resident3d_ok(d->n[0], d->n[1], d->n[2]))) &&
                   !(d->flags & SPSTD_NO_RESIDENT);
     b->wpb = d->waves_per_block;
     // zero fields and scales, twiddles, probe slots inactive

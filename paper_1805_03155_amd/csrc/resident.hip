@@ -322,6 +322,155 @@ __global__ __launch_bounds__((res2_cfg<NX, NY>::THREADS)) void k_resident_2d(
     if (t == 0) *I->counter = slot0 + nsteps;
 }
 
+// ---------------------------------------------------------------------------
+// Resident 3D kernel: one workgroup per instance of NX x NY x NZ points, a
+// whole step chunk per launch (16^3 grids; at 32^3 one workgroup per
+// instance is latency-bound: 611 against 126 us per step of the pass
+// kernels, while at 16^3 it takes 67 against 120 us in FP64).  The
+// fields are too large for LDS and stay in the instance's own arrays; only
+// this workgroup touches them, so they stay in its cache.  A substep is
+// three phases
+//   g += kin_x T_x f + pot V f,   g += kin_y T_y f,   g += kin_z T_z f
+// (A: f = psi_I, g = psi_R; B: f = psi_R, g = psi_I, kin and pot from
+// -d_l dt), separated by workgroup barriers.  f is not written within a
+// substep and every element of g is written by one lane per phase.  A lane
+// group of N/16 lanes holds two neighbouring pencils as one complex pencil
+// (rows 2q, 2q+1 along x; columns 2q, 2q+1 along y and z), with the pencil
+// index fastest over the lanes, so that the transform's last pass runs on
+// lane swaps and the kernel needs no LDS.  After every step thread 0
+// records the probe samples (FP64).
+// ---------------------------------------------------------------------------
+template <typename R, int NX, int NY, int NZ>
+struct res3_cfg {
+    static constexpr int NPT = NX * NY * NZ;
+    static constexpr int LANES = NPT / 32;                 // lanes one phase needs (any axis)
+    // at most 8 waves: the transforms need more than the 128 registers a
+    // lane has with 16 waves per CU
+    static constexpr int THREADS = LANES > 512 ? 512 : LANES;
+};
+
+bool resident3d_ok(int64_t nx, int64_t ny, int64_t nz) { return nx == 16 && ny == 16 && nz == 16; }
+
+template <typename R, int N, int AX, int NX, int NY, int NZ>
+__device__ __forceinline__ void res3_phase(const R* __restrict__ f, R* __restrict__ g, const R* __restrict__ V,
+                                           R kin, R pot, int nyq_zero, const cpx<double>* __restrict__ tw) {
+    using C = res3_cfg<R, NX, NY, NZ>;
+    constexpr int T = N / 16, PPW = 64 / T;
+    constexpr int PAIRS = C::NPT / (2 * N);
+    constexpr int GROUPS = C::THREADS / T;
+    static_assert(N == 16 || tail_swaps<N, PPW>::OK, "the last pass must run on lane swaps");
+    static_assert(PAIRS % GROUPS == 0, "whole waves per phase");
+    constexpr int STRIDE = AX == 0 ? 1 : AX == 1 ? NX : NX * NY;   // between a pencil's points
+    constexpr int OFF = AX == 0 ? NX : 1;                           // to the pencil's partner
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int p = lane % PPW, j = lane / PPW;
+#pragma unroll 1
+    for (int q0 = 0; q0 < PAIRS; q0 += GROUPS) {
+        const int q = q0 + wave * PPW + p;
+        int base;
+        if constexpr (AX == 0) {
+            base = 2 * q * NX;
+        } else if constexpr (AX == 1) {
+            base = (q / (NX / 2)) * NX * NY + 2 * (q % (NX / 2));
+        } else {
+            base = (q / (NX / 2)) * NX + 2 * (q % (NX / 2));
+        }
+        cpx<R> v[1][16];
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+            const int i = base + (j + T * e) * STRIDE;
+            const R a = f[i], b = f[i + OFF];
+            v[0][e] = cpx<R>{a, b};
+            if constexpr (AX == 0) {
+                // the potential term now, so that f need not stay in
+                // registers through the transforms
+                g[i] += pot * V[i] * a;
+                g[i + OFF] += pot * V[i + OFF] * b;
+            }
+            // a few elements' loads in flight at a time (registers)
+            if ((e + 1) % 4 == 0) __builtin_amdgcn_sched_barrier(0);
+        }
+        fft_pencils<R, N, false, true, true, true, 1, PPW>(v, j, nullptr, 0, tw);
+        k2_symbol<R, N>(v[0], j, nyq_zero);
+        fft_pencils<R, N, true, true, true, true, 1, PPW>(v, j, nullptr, 0, tw);
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+            const int i = base + (j + T * e) * STRIDE;
+            g[i] += kin * v[0][e].x;
+            g[i + OFF] += kin * v[0][e].y;
+            if ((e + 1) % 4 == 0) __builtin_amdgcn_sched_barrier(0);
+        }
+    }
+}
+
+template <typename R, int NX, int NY, int NZ>
+__global__ __launch_bounds__((res3_cfg<R, NX, NY, NZ>::THREADS)) void k_resident_3d(
+    const ResidentInst<R>* __restrict__ inst, int ninst, int m, int64_t nsteps, int nyq_zero,
+    const cpx<double>* __restrict__ twx, const cpx<double>* __restrict__ twy, const cpx<double>* __restrict__ twz) {
+    using C = res3_cfg<R, NX, NY, NZ>;
+    if ((int)blockIdx.x >= ninst) return;   // uniform over the workgroup
+    const ResidentInst<R>* I = inst + blockIdx.x;
+    R* const pR = I->psiR;
+    R* const pI = I->psiI;
+    const R* __restrict__ V = I->V;
+    const int64_t slot0 = *I->counter;
+    for (int64_t s = 0; s < nsteps; ++s) {
+        for (int l = 0; l < m; ++l) {
+            for (int half = 0; half < 2; ++half) {
+                const R kx = I->kin[2 * l + half], ky = I->kin_y[2 * l + half], kz = I->kin_z[2 * l + half];
+                const R pt = I->pot[2 * l + half];
+                if (kx == (R)0 && ky == (R)0 && kz == (R)0 && pt == (R)0) continue;   // uniform
+                const R* f = half == 0 ? pI : pR;
+                R* g = half == 0 ? pR : pI;
+                res3_phase<R, NX, 0, NX, NY, NZ>(f, g, V, kx, pt, nyq_zero, twx);
+                __syncthreads();
+                res3_phase<R, NY, 1, NX, NY, NZ>(f, g, V, ky, (R)0, nyq_zero, twy);
+                __syncthreads();
+                res3_phase<R, NZ, 2, NX, NY, NZ>(f, g, V, kz, (R)0, nyq_zero, twz);
+                __syncthreads();
+            }
+        }
+        if (threadIdx.x == 0) {
+            const int64_t slot = slot0 + s;
+            for (int q = 0; q < I->nprobes && slot < I->capacity; ++q) {
+                const int64_t pidx = I->probe_idx[q];
+                if (pidx < 0 || pidx >= C::NPT) {
+                    *I->fault = 1;
+                    continue;
+                }
+                I->probes[(slot * I->nprobes + q) * 2 + 0] = (double)pR[pidx];
+                I->probes[(slot * I->nprobes + q) * 2 + 1] = (double)pI[pidx];
+            }
+        }
+        // the next step writes the fields thread 0 has just sampled
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *I->counter = slot0 + nsteps;
+}
+
+template <typename R, int NX, int NY, int NZ>
+static hipError_t res3_n(const ResidentInst<R>* inst, int ninst, int m, int64_t nsteps, int nyq_zero,
+                         const void* twx, const void* twy, const void* twz, hipStream_t st) {
+    hipLaunchKernelGGL((k_resident_3d<R, NX, NY, NZ>), dim3(ninst), dim3(res3_cfg<R, NX, NY, NZ>::THREADS), 0, st,
+                       inst, ninst, m, nsteps, nyq_zero, (const cpx<double>*)twx, (const cpx<double>*)twy,
+                       (const cpx<double>*)twz);
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_resident_3d(int64_t nx, int64_t ny, int64_t nz, const ResidentInst<R>* inst, int ninst, int m,
+                              int64_t nsteps, int nyq_zero, const void* twx, const void* twy, const void* twz,
+                              hipStream_t st) {
+    if (ninst < 1 || m < 1 || m > kResMaxSubsteps / 2 || nsteps < 0) return hipErrorInvalidValue;
+    if (!resident3d_ok(nx, ny, nz)) return hipErrorInvalidValue;
+    return res3_n<R, 16, 16, 16>(inst, ninst, m, nsteps, nyq_zero, twx, twy, twz, st);
+}
+
+template hipError_t launch_resident_3d<double>(int64_t, int64_t, int64_t, const ResidentInst<double>*, int, int,
+                                               int64_t, int, const void*, const void*, const void*, hipStream_t);
+template hipError_t launch_resident_3d<float>(int64_t, int64_t, int64_t, const ResidentInst<float>*, int, int,
+                                              int64_t, int, const void*, const void*, const void*, hipStream_t);
+
 bool resident_len_ok(int64_t n) { return n >= 16 && (n & (n - 1)) == 0 && n <= 16384; }
 
 bool resident2d_ok(int64_t nx, int64_t ny) {

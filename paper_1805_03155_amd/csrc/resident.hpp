@@ -24,12 +24,16 @@ struct ResidentInst {
     int64_t probe_idx[kResMaxProbes];
     R kin[kResMaxSubsteps];   // substep 2l (A) and 2l+1 (B): coef dt (hbar/2m*) (2 pi/L)^2 / N
     R pot[kResMaxSubsteps];   // substep 2l (A) and 2l+1 (B): coef dt / hbar
-    R kin_y[kResMaxSubsteps]; // 2D instances: kin of the y axis (L_y, N_y); kin is then the x axis's
+    R kin_y[kResMaxSubsteps]; // 2D and 3D instances: kin of the y axis (L_y, N_y); kin is then the x axis's
+    R kin_z[kResMaxSubsteps]; // 3D instances: kin of the z axis
 };
 
 bool resident_len_ok(int64_t n);
 // 2D grids the resident kernel holds whole in LDS: n_x, n_y in {16, 32, 64}.
 bool resident2d_ok(int64_t nx, int64_t ny);
+// 3D grids the resident 3D kernel steps (fields in global memory, one
+// workgroup per instance): 16^3.
+bool resident3d_ok(int64_t nx, int64_t ny, int64_t nz);
 
 // Advance every instance of the table (all of length n) by nsteps steps of
 // m stages.  tw: twiddle table w_n^t, t < n, in the run precision.
@@ -43,5 +47,12 @@ hipError_t launch_resident_1d(int64_t n, const ResidentInst<R>* inst, int ninst,
 template <typename R>
 hipError_t launch_resident_2d(int64_t nx, int64_t ny, const ResidentInst<R>* inst, int ninst, int m,
                               int64_t nsteps, int nyq_zero, const void* twx, const void* twy, hipStream_t st);
+
+// The same for 3D instances of nx by ny by nz points (x fastest), one
+// workgroup per instance, fields in the instances' own arrays.
+template <typename R>
+hipError_t launch_resident_3d(int64_t nx, int64_t ny, int64_t nz, const ResidentInst<R>* inst, int ninst, int m,
+                              int64_t nsteps, int nyq_zero, const void* twx, const void* twy, const void* twz,
+                              hipStream_t st);
 
 }  // namespace spstd

@@ -32,7 +32,9 @@ def resident_ok(n):
     """Shapes a batch can run with a resident kernel."""
     if len(n) == 1:
         return 16 <= n[0] <= 16384
-    return len(n) == 2 and n[0] in (16, 32, 64) and n[1] in (16, 32, 64)
+    if len(n) == 2:
+        return n[0] in (16, 32, 64) and n[1] in (16, 32, 64)
+    return len(n) == 3 and all(k == 16 for k in n)
 
 
 def alone(w, dt, steps, precision=spstd.FP64, flags=0):
@@ -308,3 +310,45 @@ def test_group_rejects_unfit_members_and_overflow():
     with pytest.raises(spstd.SpstdError) as ei:
         g.step(1)
     assert ei.value.code == 6
+
+
+@pytest.mark.parametrize("prec", [spstd.FP64, spstd.FP32])
+def test_resident_3d_matches_pass_kernels_and_oracle(prec):
+    # small 3D instances stepped by one workgroup each (fields in their own
+    # arrays) against the pass-kernel schedule of the same batch, and (FP64)
+    # against the oracle; a run split over two calls is the same arithmetic
+    n, steps = (16, 16, 16), 30
+    ws = [inst(n, seed=900 + k, nprobes=2) for k in range(3)]
+    res = spstd.Batch(n, W.PAPER, capacity=3, nprobes=2, nsteps_max=steps, precision=prec)
+    split = spstd.Batch(n, W.PAPER, capacity=3, nprobes=2, nsteps_max=steps, precision=prec)
+    pas = spstd.Batch(n, W.PAPER, capacity=3, nprobes=2, nsteps_max=steps, precision=prec,
+                      flags=spstd.NO_RESIDENT)
+    assert res.schedule()[0] == "resident" and pas.schedule()[0] == "passes"
+    dts = []
+    for k, w in enumerate(ws):
+        dt = 0.9 * oracle.stable_dt(*w.coeffs, w.V, w.n, w.dx)
+        dts.append(dt)
+        for b in (res, split, pas):
+            b.load(k, w.dx, w.V, w.psiR, w.psiI, w.probes, dt=dt)
+    res.release(1)              # a free slot between active ones
+    split.release(1)
+    pas.release(1)
+    res.step(steps)
+    split.step(7)
+    split.step(steps - 7)
+    pas.step(steps)
+    tol = 1e-13 if prec == spstd.FP64 else 2e-5
+    for k in (0, 2):
+        w = ws[k]
+        s1, r1, i1, c1 = res.read(k)
+        s2, r2, i2, c2 = pas.read(k)
+        s3, r3, i3, c3 = split.read(k)
+        assert c1 == c2 == c3 == steps
+        assert np.array_equal(r1, r3) and np.array_equal(i1, i3) and np.array_equal(s1, s3)
+        assert rel(np.concatenate([r1, i1]), np.concatenate([r2, i2])) < tol
+        assert rel(s1, s2) < tol
+        if prec == spstd.FP64:
+            ro, io, so, _ = oracle.run(w.psiR, w.psiI, w.V, w.n, w.dx, *w.coeffs, dts[k], steps, w.probes)
+            assert rel(np.concatenate([r1, i1]), np.concatenate([ro, io])) <= 1e-12
+            assert rel(s1, so) <= 1e-12
+    assert res.slot_info(1)[0] is False
