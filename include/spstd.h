@@ -486,17 +486,17 @@ spstd_status spstd_batch_group_workspace_size(const spstd_batch_t *members, int 
  * Schedules (candidates): k < n (n = 16 in FP32, 8 in FP64) the mixed-shape
  * kernels with 2 << (k & 1) waves per block, the joint LDS exchange of the
  * fused x pass for rows under 512 points if k & 2 (else split), one
- * persistent block per compute unit if k & 4 (else a grid that fills the
- * device), and two complex pencils per lane group in the y passes if k & 8
- * (FP32); k = n the members' own pass kernels one member after another on
- * the group's stream.  Sets whose stages do not all have both halves (a zero c_l or
+ * persistent block per compute unit striding over the tiles if k & 4 (else
+ * one block per tile), and two complex pencils per lane group in the y
+ * passes if k & 8 (FP32); k = n the members' own pass kernels one member
+ * after another on the group's stream.  Sets whose stages do not all have both halves (a zero c_l or
  * d_l) run k = n only.  flags: SPSTD_AUTOTUNE times every candidate (16
  * warm-up and 32 timed steps, every slot stepping a zero state at a nominal
  * instance's scales; the members must have no active slot) and keeps the
  * fastest (within 3% of it, one block per compute unit, which leaves room
  * for other streams' kernels); otherwise the built-in choice (4 waves per
- * block, the exchange of the single-shape kernels, a filling grid, one
- * pencil per lane group).  Synchronises the
+ * block, the exchange of the single-shape kernels, one block per tile, two
+ * pencils per lane group in FP32 and one in FP64).  Synchronises the
  * members' streams.  Errors: SPSTD_ERR_ARG, SPSTD_ERR_WORKSPACE,
  * SPSTD_ERR_DEVICE.
  */

@@ -244,6 +244,8 @@ struct MixVariant {
 // kind 0 the fused x pass, 1 the y passes.
 int64_t mix_blocks(int kind, int nx, int ny, int64_t capacity, int precision_bytes, const MixVariant& v);
 
+// The launchers below run the tile-per-block kernels when grid >= ntiles,
+// else the persistent kernels on `grid` blocks.
 // Fused A and B halves along x for every member (stage l of m).
 template <typename R>
 hipError_t launch_mix_x_ab(const MixMember<R>* mem, const MixTile* tiles, int ntiles, int grid, int m, int l,

@@ -98,6 +98,102 @@ __global__ __launch_bounds__(64 * W) SPSTD_WAVES_ATTR void k_mix_axis_ba(const M
     }
 }
 
+// Tile-per-block forms of the three kernels (grid = number of tiles): the
+// same pass bodies, expanded inline for each length.  Expanded this way
+// the compiler keeps each length's registers close to its single-shape
+// kernel's (FP32 boundary sweep: 168 registers, three waves per SIMD,
+// against 256 for the persistent form, whose bodies are device functions
+// inside the tile loop).  The persistent forms serve the one-block-per-CU
+// schedules.
+template <typename R, int P>
+constexpr int mix_tile_y_waves() {
+    return (sizeof(R) == 4 && P == 1) ? 3 : kMinWaves;
+}
+
+#define SPSTD_MIX_TILE_HEAD                                                 \
+    const MixTile T = tiles[blockIdx.x];                                    \
+    const int mb = __builtin_amdgcn_readfirstlane(T.member);                \
+    const int64_t blk = __builtin_amdgcn_readfirstlane(T.blk);              \
+    const MixMember<R> M = mem[mb];                                         \
+    R* const lds = lds_block;
+
+template <typename R, int W, bool J>
+__global__ __launch_bounds__(64 * W) SPSTD_WAVES_ATTR void k_mix_x_ab_tile(const MixMember<R>* __restrict__ mem,
+                                                                           const MixTile* __restrict__ tiles,
+                                                                           int m, int l, int nyq_zero) {
+    __shared__ R lds_block[mix_x_lds<R, W, J>()];
+    SPSTD_MIX_TILE_HEAD
+    const ScaleRef sc{M.scales, m, l};
+    const cpx<double>* __restrict__ tw = (const cpx<double>*)M.twx;
+    const RowGeom rg = M.rg;
+    R* __restrict__ psiR = M.psiR;
+    R* __restrict__ psiI = M.psiI;
+    const R* __restrict__ V = M.V;
+    constexpr bool FULL = true, JOINT = J;
+    constexpr int WPB = W;
+    if (M.nx == 128) {
+        constexpr int N = 128;
+#include "body_x_ab.inc"
+    } else if (M.nx == 256) {
+        constexpr int N = 256;
+#include "body_x_ab.inc"
+    } else if (M.nx == 512) {
+        constexpr int N = 512;
+#include "body_x_ab.inc"
+    }
+}
+
+template <typename R, int W, int P>
+__global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(mix_tile_y_waves<R, P>()))) void
+k_mix_axis_acc_tile(const MixMember<R>* __restrict__ mem, const MixTile* __restrict__ tiles, int m, int l,
+                    int b_half, int nyq_zero) {
+    __shared__ R lds_block[mix_y_lds<R, W, P>()];
+    SPSTD_MIX_TILE_HEAD
+    const int col = b_half ? SC_KYB : SC_KYA;
+    const ScaleRef sc{M.scales, m, l};
+    const cpx<double>* __restrict__ tw = (const cpx<double>*)M.twy;
+    const AxisGeom g = M.gy;
+    const R* __restrict__ src = b_half ? M.psiR : M.psiI;
+    R* __restrict__ dst = b_half ? M.psiI : M.psiR;
+    constexpr int WPB = W;
+    if (M.ny == 128) {
+        constexpr int N = 128;
+#include "body_axis_acc.inc"
+    } else if (M.ny == 256) {
+        constexpr int N = 256;
+#include "body_axis_acc.inc"
+    } else if (M.ny == 512) {
+        constexpr int N = 512;
+#include "body_axis_acc.inc"
+    }
+}
+
+template <typename R, int W, int P>
+__global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(mix_tile_y_waves<R, P>()))) void
+k_mix_axis_ba_tile(const MixMember<R>* __restrict__ mem, const MixTile* __restrict__ tiles, int m, int lB, int lA,
+                   int nyq_zero) {
+    __shared__ R lds_block[mix_y_lds<R, W, P>()];
+    SPSTD_MIX_TILE_HEAD
+    const ScaleRef scB{M.scales, m, lB}, scA{M.scales, m, lA};
+    const int colB = SC_KYB, colA = SC_KYA;
+    const cpx<double>* __restrict__ tw = (const cpx<double>*)M.twy;
+    const AxisGeom g = M.gy;
+    R* __restrict__ psiR = M.psiR;
+    R* __restrict__ psiI = M.psiI;
+    constexpr int WPB = W;
+    if (M.ny == 128) {
+        constexpr int N = 128;
+#include "body_axis_ba.inc"
+    } else if (M.ny == 256) {
+        constexpr int N = 256;
+#include "body_axis_ba.inc"
+    } else if (M.ny == 512) {
+        constexpr int N = 512;
+#include "body_axis_ba.inc"
+    }
+}
+#undef SPSTD_MIX_TILE_HEAD
+
 template <typename R>
 __global__ void k_mix_probe(const MixMember<R>* __restrict__ mem, const MixTile* __restrict__ slots, int nslots,
                             int nprobes, int part) {
@@ -167,8 +263,12 @@ hipError_t launch_mix_x_ab(const MixMember<R>* mem, const MixTile* tiles, int nt
     return with_variant_x(v, [&](auto w, auto j) {
         constexpr int W = decltype(w)::value;
         constexpr bool J = decltype(j)::value;
-        hipLaunchKernelGGL((k_mix_x_ab<R, W, J>), dim3((unsigned)grid), dim3(64 * W), 0, st, mem, tiles, ntiles, m,
-                           l, nyq_zero);
+        if (grid >= ntiles)
+            hipLaunchKernelGGL((k_mix_x_ab_tile<R, W, J>), dim3((unsigned)ntiles), dim3(64 * W), 0, st, mem, tiles,
+                               m, l, nyq_zero);
+        else
+            hipLaunchKernelGGL((k_mix_x_ab<R, W, J>), dim3((unsigned)grid), dim3(64 * W), 0, st, mem, tiles, ntiles,
+                               m, l, nyq_zero);
         return hipGetLastError();
     });
 }
@@ -180,8 +280,12 @@ hipError_t launch_mix_axis_acc(const MixMember<R>* mem, const MixTile* tiles, in
     return with_variant_y(v, [&](auto w, auto p) {
         constexpr int W = decltype(w)::value;
         constexpr int P = decltype(p)::value;
-        hipLaunchKernelGGL((k_mix_axis_acc<R, W, P>), dim3((unsigned)grid), dim3(64 * W), 0, st, mem, tiles,
-                           ntiles, m, l, b_half, nyq_zero);
+        if (grid >= ntiles)
+            hipLaunchKernelGGL((k_mix_axis_acc_tile<R, W, P>), dim3((unsigned)ntiles), dim3(64 * W), 0, st, mem,
+                               tiles, m, l, b_half, nyq_zero);
+        else
+            hipLaunchKernelGGL((k_mix_axis_acc<R, W, P>), dim3((unsigned)grid), dim3(64 * W), 0, st, mem, tiles,
+                               ntiles, m, l, b_half, nyq_zero);
         return hipGetLastError();
     });
 }
@@ -193,8 +297,12 @@ hipError_t launch_mix_axis_ba(const MixMember<R>* mem, const MixTile* tiles, int
     return with_variant_y(v, [&](auto w, auto p) {
         constexpr int W = decltype(w)::value;
         constexpr int P = decltype(p)::value;
-        hipLaunchKernelGGL((k_mix_axis_ba<R, W, P>), dim3((unsigned)grid), dim3(64 * W), 0, st, mem, tiles,
-                           ntiles, m, lB, lA, nyq_zero);
+        if (grid >= ntiles)
+            hipLaunchKernelGGL((k_mix_axis_ba_tile<R, W, P>), dim3((unsigned)ntiles), dim3(64 * W), 0, st, mem,
+                               tiles, m, lB, lA, nyq_zero);
+        else
+            hipLaunchKernelGGL((k_mix_axis_ba<R, W, P>), dim3((unsigned)grid), dim3(64 * W), 0, st, mem, tiles,
+                               ntiles, m, lB, lA, nyq_zero);
         return hipGetLastError();
     });
 }
