@@ -67,6 +67,11 @@ enum { SPSTD_LAP_SPECTRAL = 0, SPSTD_LAP_FD3 = 1 };  /* spatial second derivativ
                                                         half; then a run split over calls equals
                                                         the unsplit run bitwise) nor chained
                                                         (last stage with one) */
+#define SPSTD_NO_PLANES 0x40u                        /* batch flags: 3D batches whose x and z
+                                                        axes have 16, 32 or 64 points run the z
+                                                        and x passes of a stage as separate
+                                                        launches instead of one fused launch
+                                                        per x-z plane */
 #define SPSTD_MAX_STAGES 16
 #define SPSTD_MAX_PROBES 64
 #define SPSTD_MAX_EIG 8

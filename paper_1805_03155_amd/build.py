@@ -14,7 +14,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libspstd.so")
-SOURCES = ["kernels.hip", "mixed.hip", "resident.hip", "probes.hip", "engine.cpp", "batch.cpp", "spectrum.cpp"]
+SOURCES = ["kernels.hip", "mixed.hip", "resident.hip", "probes.hip", "planes.hip", "engine.cpp", "batch.cpp",
+           "spectrum.cpp"]
 ARCH = os.environ.get("SPSTD_OFFLOAD_ARCH", "gfx950")
 
 # Packed FP32 instructions are kept out of the generated code.

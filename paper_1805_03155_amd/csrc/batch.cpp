@@ -76,6 +76,7 @@ struct Batch {
     hipStream_t st;
     std::vector<Slot> slots;
     bool resident;
+    bool planes = false;        // 3D: the z and x passes of a stage as one launch per x-z plane
     bool rtab_dirty = true;
     int nres = 0;               // active slots in the resident table
     hipGraphExec_t graph;
@@ -174,6 +175,14 @@ static hipError_t batch_step_once(Batch* b, int* owed_io, bool chain) {
             }
             owed = -1;
             if (l == 0 && pending && e == hipSuccess) e = batch_probe<R>(b, PROBE_I);
+            if (b->planes) {
+                // z(A), x(A), x(B), z(B) in one launch per x-z plane
+                if (e == hipSuccess)
+                    e = launch_plane_zxz<R>(b->d.n[0], b->d.n[1], b->d.n[2], b->d.capacity, pr, pi, V, sc, a, bb,
+                                            b->d.nyquist, twx, b->ws + b->L.tw[2], b->st);
+                if (e == hipSuccess && bb) owed = l;
+                continue;
+            }
             if (a && e == hipSuccess && b->d.ndim == 3) e = batch_axis<R>(b, 2, pi, pr, sc, SC_KZA);
         }
         if (e != hipSuccess) break;
@@ -531,6 +540,7 @@ spstd_status spstd_batch_create(const spstd_batch_desc* d, void* d_workspace, si
                    (d->ndim == 3 && resident3d_ok(d->n[0], d->n[1], d->n[2]))) &&
                   !(d->flags & SPSTD_NO_RESIDENT);
     b->wpb = d->waves_per_block;
+    b->planes = d->ndim == 3 && plane_ok(d->n[0], d->n[2]) && !(d->flags & SPSTD_NO_PLANES);
     // zero fields and scales, twiddles, probe slots inactive
     hipError_t e = hipSuccess;
     const size_t fb = (size_t)d->capacity * b->npts;

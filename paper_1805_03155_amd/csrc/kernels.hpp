@@ -69,6 +69,19 @@ hipError_t launch_x_acc(int64_t nx, const R* src, R* dst, const R* V,
                         const void* tw, const RowGeom& g, const ScaleRef& sc,
                         int kcol, int pcol, int nyq_zero, hipStream_t st, int wpb = 0);
 
+// 3D grids whose x-z planes the fused plane kernel holds in LDS: n_x, n_z
+// in {16, 32, 64}.
+bool plane_ok(int64_t nx, int64_t nz);
+// The z and x terms of stage sc.l on every x-z plane of ninst stacked
+// instances (nx by ny by nz, x fastest), one workgroup per plane:
+// do_a: psi_R += T_z psi_I (SC_KZA), then += T_x psi_I + p_A V psi_I
+// (SC_KXA, SC_PA); do_b: then psi_I += T_x psi_R + p_B V psi_R (SC_KXB,
+// SC_PB), += T_z psi_R (SC_KZB).  Slots with zero scales are left alone.
+template <typename R>
+hipError_t launch_plane_zxz(int64_t nx, int64_t ny, int64_t nz, int64_t ninst, R* psiR, R* psiI, const R* V,
+                            const ScaleRef& sc, int do_a, int do_b, int nyq_zero, const void* twx, const void* twz,
+                            hipStream_t st);
+
 // Fused A and B halves along x (columns SC_KXA, SC_PA, SC_KXB, SC_PB):
 //   psi_R += T_x^A psi_I + p_A V psi_I;  then  psi_I += T_x^B psi_R + p_B V psi_R
 template <typename R>

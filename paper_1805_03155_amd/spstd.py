@@ -24,7 +24,8 @@ EAGER = 0x2          # no step-chunk graphs
 TIMING = 0x4         # pass kernels bracketed by HIP events (pass_times)
 NO_RESIDENT = 0x8    # 1D and small 2D plans/batches use the pass kernels, not a resident kernel
 AUTOTUNE = 0x10      # batches: time the candidate schedules at creation, keep the fastest
-NO_MERGE = 0x20      # plans: no merged A halves at step boundaries (bitwise split runs)
+NO_MERGE = 0x20      # plans: step boundaries kept whole (neither merged nor chained)
+NO_PLANES = 0x40     # 3D batches: separate z and x passes instead of one launch per x-z plane
 PASS_KINDS = ("y", "z", "xab", "x", "yba")
 MAX_PROBES = 64
 

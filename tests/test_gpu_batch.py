@@ -352,3 +352,46 @@ def test_resident_3d_matches_pass_kernels_and_oracle(prec):
             assert rel(np.concatenate([r1, i1]), np.concatenate([ro, io])) <= 1e-12
             assert rel(s1, so) <= 1e-12
     assert res.slot_info(1)[0] is False
+
+
+@pytest.mark.parametrize("n", [(32, 32, 32), (64, 16, 32), (16, 64, 64), (32, 128, 16)])
+@pytest.mark.parametrize("prec", [spstd.FP64, spstd.FP32])
+@pytest.mark.parametrize("name", ["paper", "yoshida6"])
+def test_fused_planes_match_separate_passes_and_oracle(n, prec, name):
+    # 3D batches with x and z of 16 to 64 points run z(A), x(A+B), z(B) of a
+    # stage as one launch per x-z plane; the same batch with separate passes
+    # (SPSTD_NO_PLANES) and the oracle agree.  Yoshida-6's last stage has no
+    # B half (a plane launch with the A part alone).  40 steps: two graph
+    # chunks and 8 eager steps; a free slot between active ones stays zero.
+    steps = 40
+    coeffs = W.COEFFS[name]
+    ws = []
+    for k in range(3):
+        w = inst(n, seed=1300 + k, nprobes=2)
+        w.coeffs = coeffs
+        ws.append(w)
+    fused = spstd.Batch(n, coeffs, capacity=3, nprobes=2, nsteps_max=steps, precision=prec)
+    sep = spstd.Batch(n, coeffs, capacity=3, nprobes=2, nsteps_max=steps, precision=prec, flags=spstd.NO_PLANES)
+    dts = []
+    for k, w in enumerate(ws):
+        dt = 0.9 * oracle.stable_dt(*coeffs, w.V, w.n, w.dx)
+        dts.append(dt)
+        if k == 1:
+            continue
+        for b in (fused, sep):
+            b.load(k, w.dx, w.V, w.psiR, w.psiI, w.probes, dt=dt)
+    fused.step(steps)
+    sep.step(steps)
+    tol = 1e-13 if prec == spstd.FP64 else 2e-5
+    for k in (0, 2):
+        w = ws[k]
+        s1, r1, i1, c1 = fused.read(k)
+        s2, r2, i2, c2 = sep.read(k)
+        assert c1 == c2 == steps
+        assert rel(np.concatenate([r1, i1]), np.concatenate([r2, i2])) < tol
+        assert rel(s1, s2) < tol
+        if prec == spstd.FP64:
+            ro, io, so, _ = oracle.run(w.psiR, w.psiI, w.V, w.n, w.dx, *coeffs, dts[k], steps, w.probes)
+            assert rel(np.concatenate([r1, i1]), np.concatenate([ro, io])) <= 1e-12
+            assert rel(s1, so) <= 1e-12
+    assert fused.slot_info(1)[0] is False
