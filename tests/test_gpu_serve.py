@@ -57,7 +57,7 @@ def check_oracle(reqs, coeffs=W.PAPER):
     it match the oracle's extraction of the oracle's series.  The oracle
     runs of the requests go side by side on host threads (its calls release
     the interpreter lock), each with its share of the host's cores."""
-    # 8 runs at a time on at most 16 host cores (the GPU box's share)
+    # 8 runs at a time on at most 16 host cores
     workers = 8
     threads = max(1, min(16, os.cpu_count() or 8) // workers)
     with ThreadPoolExecutor(max_workers=workers) as ex:
