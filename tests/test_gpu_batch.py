@@ -395,3 +395,24 @@ def test_fused_planes_match_separate_passes_and_oracle(n, prec, name):
             assert rel(np.concatenate([r1, i1]), np.concatenate([ro, io])) <= 1e-12
             assert rel(s1, so) <= 1e-12
     assert fused.slot_info(1)[0] is False
+
+
+@pytest.mark.parametrize("n,flags", [((32, 16, 64), 0), ((32, 16, 64), spstd.NO_PLANES), ((16, 16, 16), 0),
+                                     ((64, 32), 0), ((64, 32), spstd.NO_RESIDENT), ((1024,), 0),
+                                     ((1024,), spstd.NO_RESIDENT)])
+def test_zero_nyquist_batches_against_oracle(n, flags):
+    # the ZERO convention (the Nyquist bin removed) in every batch schedule:
+    # fused x-z planes and separate passes (3D), the resident kernels and the
+    # pass kernels (16^3, 2D and 1D)
+    steps = 20
+    w = inst(n, seed=1500 + len(n), nprobes=2)
+    b = spstd.Batch(n, W.PAPER, capacity=2, nprobes=2, nsteps_max=steps, nyquist=spstd.NYQ_ZERO, flags=flags)
+    dt = 0.9 * oracle.stable_dt(*w.coeffs, w.V, w.n, w.dx)
+    b.load(1, w.dx, w.V, w.psiR, w.psiI, w.probes, dt=dt)
+    b.step(steps)
+    ser, r, i, k = b.read(1)
+    assert k == steps
+    ro, io, so, _ = oracle.run(w.psiR, w.psiI, w.V, w.n, w.dx, *w.coeffs, dt, steps, w.probes,
+                               nyquist=oracle.NYQ_ZERO)
+    assert rel(np.concatenate([r, i]), np.concatenate([ro, io])) <= 1e-12
+    assert rel(ser, so) <= 1e-12
