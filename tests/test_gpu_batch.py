@@ -416,3 +416,53 @@ def test_zero_nyquist_batches_against_oracle(n, flags):
                                nyquist=oracle.NYQ_ZERO)
     assert rel(np.concatenate([r, i]), np.concatenate([ro, io])) <= 1e-12
     assert rel(ser, so) <= 1e-12
+
+
+@pytest.mark.parametrize("n", [(64, 32), (32, 16, 32), (32, 16, 128)])
+@pytest.mark.parametrize("prec", [spstd.FP64, spstd.FP32])
+def test_chained_boundaries_over_uneven_calls(n, prec):
+    # the paper set's step boundaries chain inside every call (graph chunks
+    # of 16 and eager remainders); calls of 1, 5, 16, 17 and 3 steps give
+    # the oracle's run and its probe series, every sample in place
+    sizes = (1, 5, 16, 17, 3)
+    steps = sum(sizes)
+    w = inst(n, seed=1700 + len(n), nprobes=3)
+    b = spstd.Batch(n, W.PAPER, capacity=2, nprobes=3, nsteps_max=steps, precision=prec,
+                    flags=spstd.NO_RESIDENT)
+    dt = 0.9 * oracle.stable_dt(*w.coeffs, w.V, w.n, w.dx)
+    b.load(0, w.dx, w.V, w.psiR, w.psiI, w.probes, dt=dt)
+    for k in sizes:
+        b.step(k)
+    ser, r, i, done = b.read(0)
+    assert done == steps and ser.shape == (steps + 1, 3, 2)
+    ro, io, so, _ = oracle.run(w.psiR, w.psiI, w.V, w.n, w.dx, *w.coeffs, dt, steps, w.probes)
+    tol = 1e-12 if prec == spstd.FP64 else 2e-5
+    assert rel(np.concatenate([r, i]), np.concatenate([ro, io])) <= tol
+    assert rel(ser, so) <= tol
+    # every sample individually (a sample written in two halves, one half
+    # missing, would show as a zero or stale entry)
+    scale = np.abs(so).max()
+    assert np.abs(ser - so).max() <= (1e-11 if prec == spstd.FP64 else 1e-4) * scale
+
+
+@pytest.mark.parametrize("choice", ["built-in", "members"])
+def test_group_chained_over_uneven_calls(choice):
+    # a group steps its members with chained step boundaries inside each
+    # call; calls of 1, 5, 16, 17 and 3 steps match the oracle (FP64)
+    sizes = (1, 5, 16, 17, 3)
+    steps = sum(sizes)
+    members = _group_members(spstd.FP64, steps)
+    g = spstd.BatchGroup([b for b, _ in members])
+    if choice == "members":
+        g.set_schedule(len(g.schedule()[1]) - 1)
+    dts = _load(members)
+    for k in sizes:
+        g.step(k)
+    for (b, ws), dd in zip(members, dts):
+        for s, w in enumerate(ws):
+            ser, r, i, done = b.read(s)
+            assert done == steps
+            ro, io, so, _ = oracle.run(w.psiR, w.psiI, w.V, w.n, w.dx, *w.coeffs, dd[s], steps, w.probes)
+            assert rel(np.concatenate([r, i]), np.concatenate([ro, io])) <= 1e-12, w.n
+            assert rel(ser, so) <= 1e-12, w.n
+    g.close()

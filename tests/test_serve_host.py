@@ -120,3 +120,34 @@ def test_requests_wait_for_budget_and_an_idle_class_closes():
     # first come, first served across classes: b (blocked behind a) starts
     # after a is done, c (a's class, arriving later) after b's class closed
     assert b.admitted >= a.done and c.admitted >= b.done
+
+
+class FailingBatch(FakeBatch):
+    def step(self, k):
+        raise RuntimeError("device step failed")
+
+
+def test_a_worker_error_reaches_the_caller():
+    log = []
+    reqs = _requests([(0.0, (64,), 100), (0.0, (8, 8, 8), 100)])
+    srv = serve.Server(hbm_budget=1 << 20, max_steps=5000,
+                       batch_factory=lambda key, cap, st: (FailingBatch if key[0] == (8, 8, 8) else FakeBatch)(
+                           key, cap, 1e-5, log),
+                       stream_factory=FakeStream, workspace_bytes=lambda key, cap: 1000 + 100 * cap)
+    try:
+        srv.run(reqs)
+    except RuntimeError as e:
+        assert "device step failed" in str(e)
+    else:
+        raise AssertionError("the worker's error was not raised")
+    assert all(not c.thread.is_alive() for c in srv.classes.values())
+
+
+def test_time_limit_stops_the_workers():
+    log = []
+    reqs = _requests([(0.0, (4, 4, 4), 4000)])               # 4000 x 1 ms: 4 s
+    srv = _server(budget=1 << 20, step_s={(4, 4, 4): 1e-3}, log=log)
+    t0 = time.perf_counter()
+    srv.run(reqs, time_limit=0.3)
+    assert time.perf_counter() - t0 < 2.0
+    assert reqs[0].status == "running" and reqs[0].done is None
