@@ -466,3 +466,25 @@ def test_group_chained_over_uneven_calls(choice):
             assert rel(np.concatenate([r, i]), np.concatenate([ro, io])) <= 1e-12, w.n
             assert rel(ser, so) <= 1e-12, w.n
     g.close()
+
+
+@pytest.mark.parametrize("n,flags", [((64, 32), spstd.NO_RESIDENT), ((32, 16, 32), 0), ((32, 16, 32), spstd.NO_PLANES),
+                                     ((16, 16, 16), 0), ((32, 32), 0), ((256, 128), 0)])
+@pytest.mark.parametrize("prec", [spstd.FP64, spstd.FP32])
+def test_batch_invariance_is_bitwise(n, flags, prec):
+    # the 2D and 3D kernels touch one instance's data per pencil and row
+    # (pencil pairs never straddle two slots), so an instance run alone in
+    # its batch and the same instance among others give identical bits
+    steps = 20
+    ws = [inst(n, seed=1900 + k, nprobes=2) for k in range(4)]
+    dts = [0.9 * oracle.stable_dt(*w.coeffs, w.V, w.n, w.dx) for w in ws]
+    mix = spstd.Batch(n, W.PAPER, capacity=4, nprobes=2, nsteps_max=steps, precision=prec, flags=flags)
+    one = spstd.Batch(n, W.PAPER, capacity=4, nprobes=2, nsteps_max=steps, precision=prec, flags=flags)
+    for k, w in enumerate(ws):
+        mix.load(k, w.dx, w.V, w.psiR, w.psiI, w.probes, dt=dts[k])
+    w = ws[2]
+    one.load(2, w.dx, w.V, w.psiR, w.psiI, w.probes, dt=dts[2])
+    mix.step(steps)
+    one.step(steps)
+    a, b = mix.read(2), one.read(2)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]) and np.array_equal(a[2], b[2])
