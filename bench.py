@@ -250,6 +250,19 @@ def batching_leg(count, steps, seed=0):
             "mixed_group": st["mixed_group"], "dtype": "f32 fields, f64 probes"}
 
 
+def pmc_batch(count=512, steps=48, seed=0):
+    """Short run of the batching workload for hardware-counter passes: the
+    same 512 seeded instances, FP32, the 2D shapes of 128^2..512^2 as one
+    group with its built-in schedule, 48 steps (resident launches of whole
+    chunks, the group's kernels and the long-row pass kernels)."""
+    from paper_1805_03155_amd import batching, spstd
+    from paper_1805_03155_amd import workloads as W
+    inst = W.batch_instances(count=count, seed=seed, steps=steps)
+    _, st = batching.run_instances(inst, steps, precision=spstd.FP32, group=True)
+    print(json.dumps({"pmc_batch": True, "instances": count, "steps": steps,
+                      "stage_updates": st["stage_updates"]}), flush=True)
+
+
 def serving_leg(count, rate, steps, seed=0, budget_gb=64):
     """Poisson arrivals of eigenvalue-solve requests (1D 1024..16384 points
     or 3D 32^3..128^3, 80/20; FP32 or FP64; square or harmonic wells), served
@@ -387,6 +400,8 @@ def main():
                     help="offered rates of the serving leg (requests/s, comma-separated)")
     ap.add_argument("--pmc-sample", action="store_true",
                     help="short run for rocprofv3 counter passes (no timing output)")
+    ap.add_argument("--pmc-batch", action="store_true",
+                    help="short run of the batching workload for rocprofv3 counter passes")
     ap.add_argument("--study", choices=["precision", "rk4"],
                     help="long-run accuracy study instead of the timing line")
     ap.add_argument("--study-steps", type=int, default=100000)
@@ -410,6 +425,9 @@ def main():
                       coeffs=W.YOSHIDA6, nprobes=3)
     if args.pmc_sample:
         pmc_sample(w, 2)
+        return
+    if args.pmc_batch:
+        pmc_batch()
         return
     if args.study:
         print(json.dumps(precision_study(w, args.study, args.study_steps)), flush=True)

@@ -221,9 +221,41 @@ __device__ __forceinline__ void add_vec(typename vec_of<R, P>::type& a, const cp
 // neighbouring columns), position j = l / PPW.
 // ---------------------------------------------------------------------------
 // LDS of a y/z pass block: per lane group P pencils of SL reals.
+// LDS pencil strides.  The LDS serves 128 bytes per cycle (32 FP32 or 16
+// FP64 lanes over 32 four-byte banks); the pencils whose lanes share a
+// cycle must start on different banks, or each exchange takes two to four
+// times its cycles.  A pencil's region is therefore made an odd multiple of
+// the words one pencil contributes to a cycle: 32/PPW words where the
+// pencil index is fastest over the lanes (y and z passes), T words per
+// FP32 lane and 2T per FP64 lane where the position is (x passes).  A
+// stride that is a multiple of 32 words put all four pencils of a
+// 256-point FP64 y/z wave on one bank (z pass 69.8 -> 67.4 us, boundary
+// sweep 96.7 -> 91.9 us once padded).
+constexpr int odd_multiple_at_least(int base, int words_per_elem, int unit_words) {
+    if (unit_words <= 0 || unit_words >= 32) return base;
+    int s = base;
+    while ((s * words_per_elem) % unit_words != 0 || ((s * words_per_elem) / unit_words) % 2 == 0) ++s;
+    return s;
+}
+
+// Elements between the lane groups of a y/z wave (pencil index fastest):
+// P pencils of sl elements each per lane group.
+template <typename R, int N, int P>
+constexpr int yz_pencil_stride(int sl) {
+    constexpr int ppw = pencil_cfg<N>::PPW;
+    constexpr int ew = (int)(sizeof(R) / 4);
+    constexpr int unit = ppw < 2 ? 0 : 32 / ppw;   // words of one pencil in an LDS cycle
+    // (an odd multiple is reachable only if P words per element divide it)
+    if (unit == 0 || unit % (P * ew) != 0) return sl;
+    // the lane-group stride P * sl must be an odd multiple of unit words
+    int s = sl;
+    while (((P * s * ew) % unit) != 0 || (((P * s * ew) / unit) % 2) == 0) ++s;
+    return s;
+}
+
 template <typename R, int N, int WPB, int P>
 struct yz_lds {
-    static constexpr int SL = (tuning<R>::SPLIT ? 1 : 2) * lds_size<N>::value;
+    static constexpr int SL = yz_pencil_stride<R, N, P>((tuning<R>::SPLIT ? 1 : 2) * lds_size<N>::value);
     static constexpr int REALS = N == 16 ? 1 : WPB * pencil_cfg<N>::PPW * P * SL;
 };
 
@@ -291,7 +323,8 @@ struct row_map {
     static constexpr int LS = lds_size<N>::value;
     // large pencils always exchange re and im in turn to stay within LDS
     static constexpr bool SPLIT = C::WAVE ? SPLIT_PREF : true;
-    static constexpr int SL = (SPLIT ? 1 : 2) * LS;
+    static constexpr int SL =
+        odd_multiple_at_least((SPLIT ? 1 : 2) * LS, (int)(sizeof(R) / 4), C::T * (int)(sizeof(R) / 4));
     // a 16-point pencil is one radix-16 pass in registers: no LDS at all
     static constexpr int LDS_REALS = N == 16 ? 1 : PPB * SL;
 };
