@@ -145,8 +145,20 @@ struct fft_shape<1> {
 };
 
 // LDS index padding: one spare slot every 16 keeps the radix-16 scatter
-// (stride-16 writes) off a single bank.
-__device__ __forceinline__ int lpad(int i) { return i + (i >> 4); }
+// (stride-16 writes) off a single bank.  Where one pencil fills an LDS
+// cycle (512- and 1024-point pencils with the position fastest over the
+// lanes, JS = 1: 32 lanes on one pencil) the gather reads 32 consecutive
+// positions, which one slot every 16 wraps onto the first bank again; one
+// slot every 32 keeps both the scatter and the gather conflict-free there.
+// (With the pencil index fastest, two 512-point pencils share a cycle and
+// one slot every 16 is the conflict-free choice.)  lds_size is the larger
+// of the two footprints.
+template <int N, int JS>
+struct lds_pad_shift {
+    static constexpr int value = (JS == 1 && (N == 512 || N == 1024)) ? 5 : 4;
+};
+template <int N, int JS>
+__device__ __forceinline__ int lpad(int i) { return i + (i >> lds_pad_shift<N, JS>::value); }
 template <int N>
 struct lds_size {
     static constexpr int value = N + N / 16;
@@ -339,7 +351,7 @@ __device__ __forceinline__ void fft_pencils(cpx<R> (&v)[P][16], int j, R* lds, i
                     R* lim = lre + LS;
 #pragma unroll
                     for (int r = 0; r < 16; ++r) {
-                        const int q = lpad(base + r * Ns);
+                        const int q = lpad<N, JS>(base + r * Ns);
                         lre[q] = v[p][r].x;
                         lim[q] = v[p][r].y;
                     }
@@ -351,7 +363,7 @@ __device__ __forceinline__ void fft_pencils(cpx<R> (&v)[P][16], int j, R* lds, i
                     R* lim = lre + LS;
 #pragma unroll
                     for (int e = 0; e < 16; ++e) {
-                        const int q = lpad(j + T * e);
+                        const int q = lpad<N, JS>(j + T * e);
                         v[p][e].x = lre[q];
                         v[p][e].y = lim[q];
                     }
@@ -361,7 +373,7 @@ __device__ __forceinline__ void fft_pencils(cpx<R> (&v)[P][16], int j, R* lds, i
                 for (int p = 0; p < P; ++p) {
                     R* lre = lds + p * lds_stride;
 #pragma unroll
-                    for (int r = 0; r < 16; ++r) lre[lpad(base + r * Ns)] = v[p][r].x;
+                    for (int r = 0; r < 16; ++r) lre[lpad<N, JS>(base + r * Ns)] = v[p][r].x;
                 }
                 lds_sync<WAVE>();
 #pragma unroll
@@ -369,7 +381,7 @@ __device__ __forceinline__ void fft_pencils(cpx<R> (&v)[P][16], int j, R* lds, i
                     R* lre = lds + p * lds_stride;
                     R keep[16];
 #pragma unroll
-                    for (int e = 0; e < 16; ++e) keep[e] = lre[lpad(j + T * e)];
+                    for (int e = 0; e < 16; ++e) keep[e] = lre[lpad<N, JS>(j + T * e)];
 #pragma unroll
                     for (int e = 0; e < 16; ++e) v[p][e].x = keep[e];
                 }
@@ -379,14 +391,14 @@ __device__ __forceinline__ void fft_pencils(cpx<R> (&v)[P][16], int j, R* lds, i
                 for (int p = 0; p < P; ++p) {
                     R* lre = lds + p * lds_stride;
 #pragma unroll
-                    for (int r = 0; r < 16; ++r) lre[lpad(base + r * Ns)] = v[p][r].y;
+                    for (int r = 0; r < 16; ++r) lre[lpad<N, JS>(base + r * Ns)] = v[p][r].y;
                 }
                 lds_sync<WAVE>();
 #pragma unroll
                 for (int p = 0; p < P; ++p) {
                     R* lre = lds + p * lds_stride;
 #pragma unroll
-                    for (int e = 0; e < 16; ++e) v[p][e].y = lre[lpad(j + T * e)];
+                    for (int e = 0; e < 16; ++e) v[p][e].y = lre[lpad<N, JS>(j + T * e)];
                 }
             }
         }
