@@ -13,7 +13,6 @@ bool wall_dft_len_ok(int64_t n) { return n >= 2 && n <= 32 && n != 16 && n != 32
 
 constexpr int kWPB = 4;             // waves per block of the wave-local passes
 constexpr int kWPBF64Axis256 = 2;   // ... of FP64 256-point pencils
-constexpr int kBaPplF32Long = 2;    // pencils per lane group of the FP32 boundary sweep from 512 points
 
 // ---------------------------------------------------------------------------
 // small kernels
@@ -467,7 +466,7 @@ template <typename R, int N, int W0>
 static hipError_t axis_ba_nw(R* psiR, R* psiI, const void* tw, const AxisGeom& g, const ScaleRef& scB,
                              const ScaleRef& scA, int colB, int colA, int nyq_zero, hipStream_t st) {
     using C = pencil_cfg<N>;
-    constexpr int P = (sizeof(R) == 4 && N >= 512) ? kBaPplF32Long : tuning<R>::BA_PPL;
+    constexpr int P = tuning<R>::BA_PPL;
     constexpr int W = W0 ? W0 : wpb_of<R, N>();
     if (g.half_x % P) return hipErrorInvalidValue;
     const int64_t ngroups = g.half_x / P * g.n_outer;

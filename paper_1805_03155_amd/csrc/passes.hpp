@@ -81,7 +81,10 @@ struct tuning<float> {
     static constexpr int YZ_PPL = 2;
     static constexpr bool V_NT = false;
     static constexpr bool EPI_BATCH = true;
-    static constexpr int BA_PPL = 1;
+    // two pencils per lane group in the boundary sweep too (256^3: 53.7 ->
+    // 51.2 us once the LDS strides were free of bank conflicts; slower
+    // before, 53.8 -> 56.9 us, when its exchanges conflicted four ways)
+    static constexpr int BA_PPL = 2;
 };
 
 // Minimum waves per SIMD requested for the 256-point pass kernels (a value
