@@ -12,7 +12,7 @@ bool row_len_ok(int64_t n) { return n >= 16 && n <= 16384 && (n & (n - 1)) == 0;
 bool wall_dft_len_ok(int64_t n) { return n >= 2 && n <= 32 && n != 16 && n != 32; }
 
 constexpr int kWPB = 4;             // waves per block of the wave-local passes
-constexpr int kWPBF64Axis256 = 2;   // ... of FP64 256-point pencils
+constexpr int kWPBF64Row256 = 2;    // ... of the FP64 256-point x passes
 
 // ---------------------------------------------------------------------------
 // small kernels
@@ -417,14 +417,19 @@ __global__ void k_fill0(int64_t n, R* __restrict__ y) {
 // ---------------------------------------------------------------------------
 
 
-// Waves per block of the hot pass kernels (y/z passes, the stage-boundary y
-// sweep, x passes): 2 for FP64 256-point pencils, where smaller blocks let
-// consecutive passes overlap their tails (graph-replayed 256^3 FP64 step
-// 2.72 -> 2.63 ms), 4 elsewhere (512^2 FP64 batch: 596 us per step
-// with 4, 692 with 2).
+// Waves per block of the hot pass kernels: 4, except 2 for the FP64
+// 256-point x passes (graph-replayed 256^3 FP64 step 2.33 -> 2.29 ms with
+// the y/z passes and boundary sweeps at 4 and the x passes at 2; with all
+// of them at 2, before the LDS strides were free of bank conflicts, 2 had
+// been the faster choice for the y/z passes too: 2.72 -> 2.63 ms; 512^2
+// FP64 batch: 596 us per step with 4, 692 with 2).
 template <typename R, int N>
 constexpr int wpb_of() {
-    return (sizeof(R) == 8 && N == 256) ? kWPBF64Axis256 : kWPB;
+    return kWPB;
+}
+template <typename R, int N>
+constexpr int wpb_row_of() {
+    return (sizeof(R) == 8 && N == 256) ? kWPBF64Row256 : kWPB;
 }
 
 // Pass launch with W waves per block; the block size is a runtime choice
@@ -518,7 +523,7 @@ hipError_t launch_axis_acc(int64_t n, const R* src, R* dst, const void* tw, cons
 template <typename R, int N, int W0>
 static hipError_t x_acc_nw(const R* src, R* dst, const R* V, const void* tw, const RowGeom& g,
                            const ScaleRef& sc, int kcol, int pcol, int nyq_zero, hipStream_t st) {
-    constexpr int W = W0 ? W0 : wpb_of<R, N>();
+    constexpr int W = W0 ? W0 : wpb_row_of<R, N>();
     using M = row_map<R, N, W>;
     const int64_t npen = (g.nrows + 1) / 2;
     const int64_t blocks = (npen + M::PPB - 1) / M::PPB;
@@ -542,7 +547,7 @@ static hipError_t x_acc_n(const R* src, R* dst, const R* V, const void* tw, cons
 template <typename R, int N, int W0>
 static hipError_t x_ab_nw(R* psiR, R* psiI, const R* V, const void* tw, const RowGeom& g,
                           const ScaleRef& sc, int nyq_zero, hipStream_t st) {
-    constexpr int W = W0 ? W0 : wpb_of<R, N>();
+    constexpr int W = W0 ? W0 : wpb_row_of<R, N>();
     using M = row_map<R, N, W>;
     const int64_t npen = (g.nrows + 1) / 2;
     const int64_t blocks = (npen + M::PPB - 1) / M::PPB;
