@@ -12,7 +12,7 @@ bool row_len_ok(int64_t n) { return n >= 16 && n <= 16384 && (n & (n - 1)) == 0;
 bool wall_dft_len_ok(int64_t n) { return n >= 2 && n <= 32 && n != 16 && n != 32; }
 
 constexpr int kWPB = 4;             // waves per block of the wave-local passes
-constexpr int kWPBF64Row256 = 2;    // ... of the FP64 256-point x passes
+constexpr int kWPBF64Fused256 = 2;  // ... of the FP64 256-point fused kernels (boundary sweep, x passes)
 
 // ---------------------------------------------------------------------------
 // small kernels
@@ -418,18 +418,18 @@ __global__ void k_fill0(int64_t n, R* __restrict__ y) {
 
 
 // Waves per block of the hot pass kernels: 4, except 2 for the FP64
-// 256-point x passes (graph-replayed 256^3 FP64 step 2.33 -> 2.29 ms with
-// the y/z passes and boundary sweeps at 4 and the x passes at 2; with all
-// of them at 2, before the LDS strides were free of bank conflicts, 2 had
-// been the faster choice for the y/z passes too: 2.72 -> 2.63 ms; 512^2
+// 256-point fused kernels, the boundary sweep and the x passes (256^3 FP64,
+// one box: boundary sweep 95.3 us at 4, 91.9 at 2; y/z passes 67.2 at 2,
+// 64.5 at 4 once the LDS strides were free of bank conflicts, while with
+// conflicting exchanges 2 had been the faster choice there too; 512^2
 // FP64 batch: 596 us per step with 4, 692 with 2).
 template <typename R, int N>
 constexpr int wpb_of() {
     return kWPB;
 }
 template <typename R, int N>
-constexpr int wpb_row_of() {
-    return (sizeof(R) == 8 && N == 256) ? kWPBF64Row256 : kWPB;
+constexpr int wpb_fused_of() {
+    return (sizeof(R) == 8 && N == 256) ? kWPBF64Fused256 : kWPB;
 }
 
 // Pass launch with W waves per block; the block size is a runtime choice
@@ -472,7 +472,7 @@ static hipError_t axis_ba_nw(R* psiR, R* psiI, const void* tw, const AxisGeom& g
                              const ScaleRef& scA, int colB, int colA, int nyq_zero, hipStream_t st) {
     using C = pencil_cfg<N>;
     constexpr int P = tuning<R>::BA_PPL;
-    constexpr int W = W0 ? W0 : wpb_of<R, N>();
+    constexpr int W = W0 ? W0 : wpb_fused_of<R, N>();
     if (g.half_x % P) return hipErrorInvalidValue;
     const int64_t ngroups = g.half_x / P * g.n_outer;
     const int64_t waves = (ngroups + C::PPW - 1) / C::PPW;
@@ -523,7 +523,7 @@ hipError_t launch_axis_acc(int64_t n, const R* src, R* dst, const void* tw, cons
 template <typename R, int N, int W0>
 static hipError_t x_acc_nw(const R* src, R* dst, const R* V, const void* tw, const RowGeom& g,
                            const ScaleRef& sc, int kcol, int pcol, int nyq_zero, hipStream_t st) {
-    constexpr int W = W0 ? W0 : wpb_row_of<R, N>();
+    constexpr int W = W0 ? W0 : wpb_fused_of<R, N>();
     using M = row_map<R, N, W>;
     const int64_t npen = (g.nrows + 1) / 2;
     const int64_t blocks = (npen + M::PPB - 1) / M::PPB;
@@ -547,7 +547,7 @@ static hipError_t x_acc_n(const R* src, R* dst, const R* V, const void* tw, cons
 template <typename R, int N, int W0>
 static hipError_t x_ab_nw(R* psiR, R* psiI, const R* V, const void* tw, const RowGeom& g,
                           const ScaleRef& sc, int nyq_zero, hipStream_t st) {
-    constexpr int W = W0 ? W0 : wpb_row_of<R, N>();
+    constexpr int W = W0 ? W0 : wpb_fused_of<R, N>();
     using M = row_map<R, N, W>;
     const int64_t npen = (g.nrows + 1) / 2;
     const int64_t blocks = (npen + M::PPB - 1) / M::PPB;
