@@ -263,6 +263,48 @@ def pmc_batch(count=512, steps=48, seed=0):
                       "stage_updates": st["stage_updates"]}), flush=True)
 
 
+def class_step_times(steps=1000, warmup=64, seed=5):
+    """Per-step time of serving classes alone: one batch of 1 or 8 seeded
+    requests of one shape and precision (the server's flags: 1D classes
+    autotuned, 3D classes with the fused x-z planes and, for comparison,
+    with the separate passes), `warmup` untimed steps (graph capture), then
+    `steps` timed steps on the batch's stream."""
+    import torch
+    from paper_1805_03155_amd import serve, spstd
+    from paper_1805_03155_amd import workloads as W
+    out = []
+    cases = [((n,), 0) for n in (1024, 16384)]
+    cases += [((n, n, n), f) for n in (32, 64, 128) for f in (0, spstd.NO_PLANES)]
+    for shape, extra in cases:
+        for prec in (spstd.FP64, spstd.FP32):
+            for k in (1, 8):
+                if len(shape) == 3 and shape[0] == 128 and extra:
+                    continue                 # 128^3 has no plane form
+                reqs = serve.request_mix(k, 1.0, seed=seed, p1d=1.0 if len(shape) == 1 else 0.0,
+                                         sizes_1d=(shape[0],), sizes_3d=((shape[0], 1.0),))
+                st = torch.cuda.Stream()
+                flags = (spstd.AUTOTUNE if len(shape) == 1 else 0) | extra
+                b = spstd.Batch(shape, W.PAPER, capacity=k, nprobes=1, nsteps_max=steps + warmup,
+                                precision=prec, stream=st, flags=flags)
+                for s, r in enumerate(reqs):
+                    w = r.work
+                    b.load(s, w.dx, w.V, w.psiR, w.psiI, w.probes[:1], cfl_fraction=w.cfl_fraction,
+                           hbar=w.hbar, mass=w.mass)
+                b.step(warmup)
+                st.synchronize()
+                t0 = time.perf_counter()
+                b.step(steps)
+                st.synchronize()
+                us = 1e6 * (time.perf_counter() - t0) / steps
+                rec = {"shape": list(shape), "precision": "fp64" if prec == spstd.FP64 else "fp32",
+                       "slots": k, "form": ("separate passes" if extra else "planes") if len(shape) == 3
+                       else b.schedule()[0], "us_per_step": us}
+                log(f"class {rec}")
+                out.append(rec)
+                del b
+    return out
+
+
 def serving_leg(count, rate, steps, seed=0, budget_gb=64):
     """Poisson arrivals of eigenvalue-solve requests (1D 1024..16384 points
     or 3D 32^3..128^3, 80/20; FP32 or FP64; square or harmonic wells), served
@@ -409,6 +451,8 @@ def main():
                     help="serving at offered rates 10..1000/s instead of the timing line")
     ap.add_argument("--serve-rates", default="10,30,100,300,1000",
                     help="offered rates of --serve-sweep (requests/s, comma-separated)")
+    ap.add_argument("--class-steps", type=int, default=0,
+                    help="per-step time of serving classes alone over this many steps, instead of the timing line")
     ap.add_argument("--no-small-budget", action="store_true",
                     help="--serve-sweep without the small-budget run")
     args = ap.parse_args()
@@ -431,6 +475,9 @@ def main():
         return
     if args.study:
         print(json.dumps(precision_study(w, args.study, args.study_steps)), flush=True)
+        return
+    if args.class_steps > 0:
+        print(json.dumps({"class_step_times": class_step_times(args.class_steps)}), flush=True)
         return
     if args.serve_sweep:
         rates = tuple(float(x) for x in args.serve_rates.split(","))
