@@ -72,6 +72,10 @@ enum { SPSTD_LAP_SPECTRAL = 0, SPSTD_LAP_FD3 = 1 };  /* spatial second derivativ
                                                         and x passes of a stage as separate
                                                         launches instead of one fused launch
                                                         per x-z plane */
+#define SPSTD_NO_FOURSTEP 0x80u                      /* batch flags: 1D batches of 8192- or
+                                                        16384-point rows run each x pass as one
+                                                        workgroup per pair of rows instead of
+                                                        the four-step launches over many */
 #define SPSTD_MAX_STAGES 16
 #define SPSTD_MAX_PROBES 64
 #define SPSTD_MAX_EIG 8

@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libspstd.so")
-SOURCES = ["kernels.hip", "mixed.hip", "resident.hip", "probes.hip", "planes.hip", "engine.cpp", "batch.cpp",
+SOURCES = ["kernels.hip", "mixed.hip", "resident.hip", "probes.hip", "planes.hip", "fourstep.hip", "engine.cpp", "batch.cpp",
            "spectrum.cpp"]
 ARCH = os.environ.get("SPSTD_OFFLOAD_ARCH", "gfx950")
 

@@ -26,7 +26,9 @@
 namespace spstd {
 
 struct BatchLayout {
-    size_t psiR, psiI, V, tw[3], scales, pidx, active, counter, fault, probes, rinst, total;
+    size_t psiR, psiI, V, tw[3], scales, pidx, active, counter, fault, probes, rinst;
+    size_t twsub, fs;   // four-step x passes of long 1D rows: 128- and n/128-entry tables, scratch
+    size_t total;
 };
 
 static const int kBatchGraphChunk = 16;
@@ -54,6 +56,10 @@ static BatchLayout batch_layout(const spstd_batch_desc* d) {
     L.fault = off; off += 256;
     L.probes = off; off += align256(cap * (size_t)(d->nsteps_max + 1) * np * 2 * sizeof(double));
     L.rinst = off; off += align256(cap * sizeof(ResidentInst<double>));
+    if (d->ndim == 1 && fourstep_ok(d->n[0])) {
+        L.twsub = off; off += align256((size_t)(128 + d->n[0] / 128) * 2 * sizeof(double));
+        L.fs = off; off += align256(fourstep_scratch_bytes(d->n[0], d->capacity, esz));
+    }
     L.total = off;
     return L;
 }
@@ -77,6 +83,7 @@ struct Batch {
     std::vector<Slot> slots;
     bool resident;
     bool planes = false;        // 3D: the z and x passes of a stage as one launch per x-z plane
+    bool fourstep = false;      // 1D long rows: x passes as four-step launches over many workgroups
     bool rtab_dirty = true;
     int nres = 0;               // active slots in the resident table
     hipGraphExec_t graph;
@@ -186,6 +193,13 @@ static hipError_t batch_step_once(Batch* b, int* owed_io, bool chain) {
             if (a && e == hipSuccess && b->d.ndim == 3) e = batch_axis<R>(b, 2, pi, pr, sc, SC_KZA);
         }
         if (e != hipSuccess) break;
+        if (b->fourstep) {
+            if (a || bb)
+                e = launch_x_fourstep<R>(nx, pr, pi, V, twx, b->ws + b->L.twsub, b->ws + b->L.twsub + 128 * 16,
+                                         b->ws + b->L.fs, rg, sc, a, bb, b->d.nyquist, b->st);
+            if (e != hipSuccess) break;
+            continue;   // 1D: no y or z passes
+        }
         if (a && bb) e = launch_x_ab<R>(nx, pr, pi, V, twx, rg, sc, b->d.nyquist, b->st, b->wpb);
         else if (a) e = launch_x_acc<R>(nx, pi, pr, V, twx, rg, sc, SC_KXA, SC_PA, b->d.nyquist, b->st, b->wpb);
         else if (bb) e = launch_x_acc<R>(nx, pr, pi, V, twx, rg, sc, SC_KXB, SC_PB, b->d.nyquist, b->st, b->wpb);
@@ -541,6 +555,7 @@ spstd_status spstd_batch_create(const spstd_batch_desc* d, void* d_workspace, si
                   !(d->flags & SPSTD_NO_RESIDENT);
     b->wpb = d->waves_per_block;
     b->planes = d->ndim == 3 && plane_ok(d->n[0], d->n[2]) && !(d->flags & SPSTD_NO_PLANES);
+    b->fourstep = d->ndim == 1 && fourstep_ok(d->n[0]) && !(d->flags & SPSTD_NO_FOURSTEP);
     // zero fields and scales, twiddles, probe slots inactive
     hipError_t e = hipSuccess;
     const size_t fb = (size_t)d->capacity * b->npts;
@@ -571,6 +586,13 @@ spstd_status spstd_batch_create(const spstd_batch_desc* d, void* d_workspace, si
         // FP64 in every precision: the kernels round each twiddle once
         std::vector<double> t = twiddles(d->n[a]);
         e = hipMemcpyAsync(b->ws + L.tw[a], t.data(), t.size() * 8, hipMemcpyHostToDevice, b->st);
+        if (e == hipSuccess) e = hipStreamSynchronize(b->st);
+    }
+    if (d->ndim == 1 && fourstep_ok(d->n[0]) && e == hipSuccess) {
+        // the four-step passes' 128-point and n/128-point tables, in turn
+        std::vector<double> t = twiddles(128), t2 = twiddles(d->n[0] / 128);
+        t.insert(t.end(), t2.begin(), t2.end());
+        e = hipMemcpyAsync(b->ws + L.twsub, t.data(), t.size() * 8, hipMemcpyHostToDevice, b->st);
         if (e == hipSuccess) e = hipStreamSynchronize(b->st);
     }
     if (e == hipSuccess) e = hipStreamSynchronize(b->st);

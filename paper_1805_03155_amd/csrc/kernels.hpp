@@ -82,6 +82,21 @@ hipError_t launch_plane_zxz(int64_t nx, int64_t ny, int64_t nz, int64_t ninst, R
                             const ScaleRef& sc, int do_a, int do_b, int nyq_zero, const void* twx, const void* twz,
                             hipStream_t st);
 
+// x passes of 1D rows of 8192 or 16384 points over many workgroups (the
+// 128-column four-step factorisation of the transform; rows_per_inst 1).
+// a, b: the A half (psi_R += T psi_I + p_A V psi_I, SC_KXA, SC_PA) and/or
+// the B half (psi_I += T psi_R + p_B V psi_R, SC_KXB, SC_PB), A first.
+// twN: the row's FP64 twiddle table (n entries); tw1: a 128-entry table;
+// tw2: an (n / 128)-entry table; scratch: fourstep_scratch_bytes bytes of
+// device memory the passes overwrite.  Pencils whose rows have zero
+// kinetic scales in the applied halves are left alone.
+bool fourstep_ok(int64_t n);
+size_t fourstep_scratch_bytes(int64_t n, int64_t nrows, size_t esz);
+template <typename R>
+hipError_t launch_x_fourstep(int64_t n, R* psiR, R* psiI, const R* V, const void* twN, const void* tw1,
+                             const void* tw2, void* scratch, const RowGeom& rg, const ScaleRef& sc, int a, int b,
+                             int nyq_zero, hipStream_t st);
+
 // Fused A and B halves along x (columns SC_KXA, SC_PA, SC_KXB, SC_PB):
 //   psi_R += T_x^A psi_I + p_A V psi_I;  then  psi_I += T_x^B psi_R + p_B V psi_R
 template <typename R>

@@ -26,6 +26,7 @@ NO_RESIDENT = 0x8    # 1D and small 2D plans/batches use the pass kernels, not a
 AUTOTUNE = 0x10      # batches: time the candidate schedules at creation, keep the fastest
 NO_MERGE = 0x20      # plans: step boundaries kept whole (neither merged nor chained)
 NO_PLANES = 0x40     # 3D batches: separate z and x passes instead of one launch per x-z plane
+NO_FOURSTEP = 0x80   # 1D batches of 8192/16384 points: one workgroup per row pair per x pass
 PASS_KINDS = ("y", "z", "xab", "x", "yba")
 MAX_PROBES = 64
 

@@ -397,9 +397,57 @@ def test_fused_planes_match_separate_passes_and_oracle(n, prec, name):
     assert fused.slot_info(1)[0] is False
 
 
+@pytest.mark.parametrize("n", [8192, 16384])
+@pytest.mark.parametrize("prec", [spstd.FP64, spstd.FP32])
+@pytest.mark.parametrize("name", ["paper", "yoshida6"])
+def test_fourstep_rows_match_one_workgroup_rows_and_oracle(n, prec, name):
+    # 1D batches of 8192- and 16384-point rows run each x pass as four-step
+    # launches (128 columns) over many workgroups; the same batch with one
+    # workgroup per row pair (SPSTD_NO_FOURSTEP) and the oracle agree.  Five
+    # slots (the last pencil holds one row), slot 1 free between active
+    # ones; 40 steps (two graph chunks and 8 eager steps); Yoshida-6 runs the
+    # single A half of its last stage (merged step boundaries) and the paper
+    # set chains its boundaries.
+    steps = 40
+    coeffs = W.COEFFS[name]
+    ws = []
+    for k in range(5):
+        w = inst((n,), seed=2100 + k, nprobes=2)
+        w.coeffs = coeffs
+        ws.append(w)
+    four = spstd.Batch((n,), coeffs, capacity=5, nprobes=2, nsteps_max=steps, precision=prec,
+                       flags=spstd.NO_RESIDENT)
+    one = spstd.Batch((n,), coeffs, capacity=5, nprobes=2, nsteps_max=steps, precision=prec,
+                      flags=spstd.NO_RESIDENT | spstd.NO_FOURSTEP)
+    dts = []
+    for k, w in enumerate(ws):
+        dt = 0.9 * oracle.stable_dt(*coeffs, w.V, w.n, w.dx)
+        dts.append(dt)
+        if k == 1:
+            continue
+        for b in (four, one):
+            b.load(k, w.dx, w.V, w.psiR, w.psiI, w.probes, dt=dt)
+    four.step(steps)
+    one.step(steps)
+    tol = 1e-13 if prec == spstd.FP64 else 2e-5
+    for k in (0, 2, 3, 4):
+        w = ws[k]
+        s1, r1, i1, c1 = four.read(k)
+        s2, r2, i2, c2 = one.read(k)
+        assert c1 == c2 == steps
+        assert rel(np.concatenate([r1, i1]), np.concatenate([r2, i2])) < tol, k
+        assert rel(s1, s2) < tol, k
+        if prec == spstd.FP64 or k == 4:
+            ro, io, so, _ = oracle.run(w.psiR, w.psiI, w.V, w.n, w.dx, *coeffs, dts[k], steps, w.probes)
+            ot = 1e-12 if prec == spstd.FP64 else 2e-5
+            assert rel(np.concatenate([r1, i1]), np.concatenate([ro, io])) <= ot, k
+            assert rel(s1, so) <= ot, k
+    assert four.slot_info(1)[0] is False
+
+
 @pytest.mark.parametrize("n,flags", [((32, 16, 64), 0), ((32, 16, 64), spstd.NO_PLANES), ((16, 16, 16), 0),
                                      ((64, 32), 0), ((64, 32), spstd.NO_RESIDENT), ((1024,), 0),
-                                     ((1024,), spstd.NO_RESIDENT)])
+                                     ((1024,), spstd.NO_RESIDENT), ((16384,), spstd.NO_RESIDENT)])
 def test_zero_nyquist_batches_against_oracle(n, flags):
     # the ZERO convention (the Nyquist bin removed) in every batch schedule:
     # fused x-z planes and separate passes (3D), the resident kernels and the
