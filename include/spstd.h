@@ -378,7 +378,16 @@ typedef struct spstd_batch_s *spstd_batch_t;
  *   capacity      number of slots (>= 1).
  *   nprobes       probe points per slot, 0..8.
  *   nsteps_max    probe samples kept per slot after sample 0.
- *   flags         SPSTD_ALLOW_UNSTABLE, SPSTD_NO_RESIDENT, SPSTD_AUTOTUNE.
+ *   flags         SPSTD_ALLOW_UNSTABLE, SPSTD_NO_RESIDENT, SPSTD_AUTOTUNE,
+ *                 SPSTD_NO_MERGE, SPSTD_NO_PLANES, SPSTD_NO_FOURSTEP.
+ *                 The pass kernels of 1D batches of 8192 or 16384 points
+ *                 run each x pass in four steps (Sec. 2, Eq. (9)-(10): the
+ *                 row's transform factored as 128 columns by n/128 rows,
+ *                 column, row and column launches over many workgroups,
+ *                 with a scratch copy of each row pair in the workspace);
+ *                 SPSTD_NO_FOURSTEP keeps one workgroup per row pair (one
+ *                 launch per pass, fewer workgroups: the better neighbour
+ *                 for other work on the device).
  *                 A 1D batch of up to 16384 points, a 2D batch of n_x,
  *                 n_y in {16, 32, 64}, or a 16^3 batch has two schedules:
  *                 the resident kernel (whole step chunks in one launch; a
@@ -393,8 +402,9 @@ typedef struct spstd_batch_s *spstd_batch_t;
  *                 (shape, precision, capacity) for the rest of the process.
  *   waves_per_block  block size of the pass kernels in 64-lane waves: 0
  *                 for the built-in choice per precision and length, or 2 or
- *                 4 (rows longer than 1024 points run one pencil per block
- *                 whatever it says).  SPSTD_AUTOTUNE overrides it.
+ *                 4 (rows longer than 1024 points run one pencil per block,
+ *                 or the four-step launches, whatever it says).
+ *                 SPSTD_AUTOTUNE overrides it.
  */
 typedef struct spstd_batch_desc {
     int ndim;

@@ -46,8 +46,13 @@ def run_instances(instances, steps, precision=spstd.FP32, coeffs=None, nprobes=1
     batches, dts = {}, {}
     for shape, idx in shapes.items():
         st = torch.cuda.Stream(device=device)
+        # long 1D rows keep one workgroup per row pair: their four-step form
+        # (five launches per x pass over many workgroups) is the faster alone
+        # but, beside the group on the shared device, falls behind it (512
+        # instances: 9.5e10 against 1.22e11 stage updates/s)
+        flags = spstd.AUTOTUNE | (spstd.NO_FOURSTEP if len(shape) == 1 else 0)
         b = spstd.Batch(shape, coeffs, capacity=len(idx), nprobes=nprobes, nsteps_max=steps + untimed,
-                        precision=precision, device=device, stream=st, flags=spstd.AUTOTUNE)
+                        precision=precision, device=device, stream=st, flags=flags)
         batches[shape] = (b, st, idx)
     gshapes = [k for k, v in batches.items()
                if group is not False and spstd.group_ok(k) and v[0].schedule()[0] == "passes"]
