@@ -164,6 +164,7 @@ static hipError_t batch_step_once(Batch* b, int* owed_io, bool chain) {
     int owed = *owed_io;
     const bool pending = owed >= 0;
     *owed_io = -1;
+    bool fs_ready = false;   // four-step scratch holds the transforms of psi_I
     for (int l = 0; l < b->d.m && e == hipSuccess; ++l) {
         const bool a = b->c[l] != 0.0, bb = b->dd[l] != 0.0;
         const ScaleRef sc{b->ws + b->L.scales, b->d.m, l};
@@ -194,9 +195,13 @@ static hipError_t batch_step_once(Batch* b, int* owed_io, bool chain) {
         }
         if (e != hipSuccess) break;
         if (b->fourstep) {
+            // a B half followed by the next stage's A half leaves that half's
+            // first transforms (of psi_I) in the scratch
+            const bool fuse = bb && l + 1 < b->d.m && b->c[l + 1] != 0.0;
             if (a || bb)
                 e = launch_x_fourstep<R>(nx, pr, pi, V, twx, b->ws + b->L.twsub, b->ws + b->L.twsub + 128 * 16,
-                                         b->ws + b->L.fs, rg, sc, a, bb, b->d.nyquist, b->st);
+                                         b->ws + b->L.fs, rg, sc, a, bb, b->d.nyquist, a && fs_ready, fuse, b->st);
+            fs_ready = fuse;
             if (e != hipSuccess) break;
             continue;   // 1D: no y or z passes
         }

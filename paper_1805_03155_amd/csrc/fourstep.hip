@@ -19,9 +19,11 @@
 //            and the update of g at n = n1 + N1 n2.
 // A fused A+B x pass runs the B half's first column launch inside the A
 // half's last (psi_R(new) of a column is in registers there), so it is
-// five launches.  Each launch has N / 16 lanes of work per pencil (eight
-// or sixteen workgroups of four waves) where the one-workgroup kernels
-// have one workgroup per pencil: the row's latency is spread over the chip.
+// five launches; likewise a B half followed by the next stage's A half
+// transforms psi_I(new) for it, which then starts at its row launch.  Each
+// launch has N / 16 lanes of work per pencil (eight or sixteen workgroups
+// of four waves) where the one-workgroup kernels have one workgroup per
+// pencil: the row's latency is spread over the chip.
 #include <hip/hip_runtime.h>
 
 #include "kernels.hpp"
@@ -222,10 +224,14 @@ __global__ __launch_bounds__(64 * kFsWaves) void k_fs_cols_inv(cpx<R>* __restric
     }
 }
 
+// s_ready: S already holds the column transforms of psi_I (left by the
+// previous pass with fuse_next), so an A half skips its first launch;
+// fuse_next: the B half's last launch also transforms psi_I(new) into S for
+// the next pass's A half.
 template <typename R, int N>
 hipError_t fs_pass(R* psiR, R* psiI, const R* V, const cpx<double>* twN, const cpx<double>* tw1,
                    const cpx<double>* tw2, cpx<R>* S, const RowGeom& rg, const ScaleRef& sc, int a, int b,
-                   int nyq_zero, hipStream_t st) {
+                   int nyq_zero, bool s_ready, bool fuse_next, hipStream_t st) {
     using SH = fs_shape<N>;
     const int64_t pencils = (rg.nrows + 1) / 2;
     const dim3 cgrid((unsigned)(pencils * SH::COL_BLOCKS)), rgrid((unsigned)(pencils * SH::ROW_BLOCKS));
@@ -234,21 +240,26 @@ hipError_t fs_pass(R* psiR, R* psiI, const R* V, const cpx<double>* twN, const c
     const int ca = a ? SC_KXA : SC_KXB, cb = (a && b) ? SC_KXB : -1;
     // A half: psi_R += T psi_I + p_A V psi_I;  B half: psi_I += T psi_R + p_B V psi_R
     const R* f = a ? psiI : psiR;
-    hipLaunchKernelGGL((k_fs_cols_fwd<R, N>), cgrid, blk, 0, st, f, S, twN, tw2, rg, sc, ca, cb);
+    if (!(a && s_ready))
+        hipLaunchKernelGGL((k_fs_cols_fwd<R, N>), cgrid, blk, 0, st, f, S, twN, tw2, rg, sc, ca, cb);
     hipLaunchKernelGGL((k_fs_rows<R, N>), rgrid, blk, 0, st, S, tw1, rg, sc, ca, cb, nyq_zero);
-    if (a && b) {
-        hipLaunchKernelGGL((k_fs_cols_inv<R, N, true>), cgrid, blk, 0, st, S, psiI, V, psiR, twN, tw2, rg, sc,
-                           (int)SC_KXA, (int)SC_PA, ca, cb);
+    if (a) {
+        // with a B half to follow, this launch also transforms psi_R(new)
+        if (b)
+            hipLaunchKernelGGL((k_fs_cols_inv<R, N, true>), cgrid, blk, 0, st, S, psiI, V, psiR, twN, tw2, rg,
+                               sc, (int)SC_KXA, (int)SC_PA, ca, cb);
+        else
+            hipLaunchKernelGGL((k_fs_cols_inv<R, N, false>), cgrid, blk, 0, st, S, psiI, V, psiR, twN, tw2, rg,
+                               sc, (int)SC_KXA, (int)SC_PA, ca, cb);
+        if (!b) return hipGetLastError();
         hipLaunchKernelGGL((k_fs_rows<R, N>), rgrid, blk, 0, st, S, tw1, rg, sc, ca, cb, nyq_zero);
-        hipLaunchKernelGGL((k_fs_cols_inv<R, N, false>), cgrid, blk, 0, st, S, psiR, V, psiI, twN, tw2, rg, sc,
-                           (int)SC_KXB, (int)SC_PB, ca, cb);
-    } else if (a) {
-        hipLaunchKernelGGL((k_fs_cols_inv<R, N, false>), cgrid, blk, 0, st, S, psiI, V, psiR, twN, tw2, rg, sc,
-                           (int)SC_KXA, (int)SC_PA, ca, cb);
-    } else {
-        hipLaunchKernelGGL((k_fs_cols_inv<R, N, false>), cgrid, blk, 0, st, S, psiR, V, psiI, twN, tw2, rg, sc,
-                           (int)SC_KXB, (int)SC_PB, ca, cb);
     }
+    if (fuse_next)
+        hipLaunchKernelGGL((k_fs_cols_inv<R, N, true>), cgrid, blk, 0, st, S, psiR, V, psiI, twN, tw2, rg, sc,
+                           (int)SC_KXB, (int)SC_PB, ca, cb);
+    else
+        hipLaunchKernelGGL((k_fs_cols_inv<R, N, false>), cgrid, blk, 0, st, S, psiR, V, psiI, twN, tw2, rg, sc,
+                           (int)SC_KXB, (int)SC_PB, ca, cb);
     return hipGetLastError();
 }
 
@@ -262,22 +273,24 @@ size_t fourstep_scratch_bytes(int64_t n, int64_t nrows, size_t esz) {
 template <typename R>
 hipError_t launch_x_fourstep(int64_t n, R* psiR, R* psiI, const R* V, const void* twN, const void* tw1,
                              const void* tw2, void* scratch, const RowGeom& rg, const ScaleRef& sc, int a, int b,
-                             int nyq_zero, hipStream_t st) {
+                             int nyq_zero, int s_ready, int fuse_next, hipStream_t st) {
     if (!fourstep_ok(n) || rg.nrows < 1 || rg.rows_per_inst != 1 || !scratch) return hipErrorInvalidValue;
     if (!a && !b) return hipSuccess;
+    if (fuse_next && !b) return hipErrorInvalidValue;   // only a B half leaves psi_I(new) in registers
     const auto* tN = (const cpx<double>*)twN;
     const auto* t1 = (const cpx<double>*)tw1;
     const auto* t2 = (const cpx<double>*)tw2;
     auto* S = (cpx<R>*)scratch;
-    if (n == 8192) return fs_pass<R, 8192>(psiR, psiI, V, tN, t1, t2, S, rg, sc, a, b, nyq_zero, st);
-    return fs_pass<R, 16384>(psiR, psiI, V, tN, t1, t2, S, rg, sc, a, b, nyq_zero, st);
+    if (n == 8192)
+        return fs_pass<R, 8192>(psiR, psiI, V, tN, t1, t2, S, rg, sc, a, b, nyq_zero, s_ready, fuse_next, st);
+    return fs_pass<R, 16384>(psiR, psiI, V, tN, t1, t2, S, rg, sc, a, b, nyq_zero, s_ready, fuse_next, st);
 }
 
 template hipError_t launch_x_fourstep<double>(int64_t, double*, double*, const double*, const void*, const void*,
                                               const void*, void*, const RowGeom&, const ScaleRef&, int, int, int,
-                                              hipStream_t);
+                                              int, int, hipStream_t);
 template hipError_t launch_x_fourstep<float>(int64_t, float*, float*, const float*, const void*, const void*,
                                              const void*, void*, const RowGeom&, const ScaleRef&, int, int, int,
-                                             hipStream_t);
+                                             int, int, hipStream_t);
 
 }  // namespace spstd

@@ -89,13 +89,16 @@ hipError_t launch_plane_zxz(int64_t nx, int64_t ny, int64_t nz, int64_t ninst, R
 // twN: the row's FP64 twiddle table (n entries); tw1: a 128-entry table;
 // tw2: an (n / 128)-entry table; scratch: fourstep_scratch_bytes bytes of
 // device memory the passes overwrite.  Pencils whose rows have zero
-// kinetic scales in the applied halves are left alone.
+// kinetic scales in the applied halves are left alone.  fuse_next (b set):
+// leave the column transforms of psi_I(new) in scratch; s_ready (a set):
+// the previous pass on the same rows left them there, with psi_I unchanged
+// since.
 bool fourstep_ok(int64_t n);
 size_t fourstep_scratch_bytes(int64_t n, int64_t nrows, size_t esz);
 template <typename R>
 hipError_t launch_x_fourstep(int64_t n, R* psiR, R* psiI, const R* V, const void* twN, const void* tw1,
                              const void* tw2, void* scratch, const RowGeom& rg, const ScaleRef& sc, int a, int b,
-                             int nyq_zero, hipStream_t st);
+                             int nyq_zero, int s_ready, int fuse_next, hipStream_t st);
 
 // Fused A and B halves along x (columns SC_KXA, SC_PA, SC_KXB, SC_PB):
 //   psi_R += T_x^A psi_I + p_A V psi_I;  then  psi_I += T_x^B psi_R + p_B V psi_R
