@@ -33,7 +33,9 @@ bool plane_ok(int64_t nx, int64_t nz) {
 template <int NX, int NZ>
 struct plane_cfg {
     static constexpr int NPL = NX * NZ;                        // points of a plane
-    static constexpr int LANES = NPL / 32;                     // lanes of a phase (either axis)
+    // square planes transform their x rows and z columns in one phase
+    static constexpr bool BOTH = NX == NZ;
+    static constexpr int LANES = BOTH ? NPL / 16 : NPL / 32;   // lanes of a phase
     static constexpr int THREADS = LANES < 64 ? 64 : LANES;    // whole waves (lane swaps)
 };
 
@@ -80,6 +82,55 @@ __device__ __forceinline__ void plane_phase(const R* f, R* g, const R* __restric
     }
 }
 
+// Both axes of one half on a square plane: g += kx T_x f + pot V f + kz T_z f.
+// The x and z terms read the same f, so lane groups q < N/2 transform the z
+// column pairs and the others the x row pairs in one call; the x lanes add
+// their terms to g first, the z lanes after a workgroup barrier.
+template <typename R, int N>
+__device__ __forceinline__ void plane_phase_both(const R* f, R* g, const R* __restrict__ V, int64_t vstride, R kx,
+                                                 R kz, R pot, int nyq_zero, const cpx<double>* __restrict__ tw) {
+    constexpr int T = N / 16, PPW = 64 / T;
+    static_assert(N == 16 || tail_swaps<N, PPW>::OK, "the last pass must run on lane swaps");
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int p = lane % PPW, j = lane / PPW;
+    const int q = wave * PPW + p;
+    const bool on = q < N;
+    const bool along_x = q >= N / 2;
+    const int qq = along_x ? q - N / 2 : q;
+    const int stride = along_x ? 1 : N;     // between a pencil's points
+    const int off = along_x ? N : 1;        // to the pencil's partner
+    const int base = along_x ? 2 * qq * N : 2 * qq;
+    cpx<R> v[1][16];
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+        const int i = base + (j + T * e) * stride;
+        v[0][e] = on ? cpx<R>{f[i], f[i + off]} : cpx<R>{(R)0, (R)0};
+    }
+    fft_pencils<R, N, false, true, true, true, 1, PPW>(v, j, nullptr, 0, tw);
+    apply_k2<R, N>(v[0], j, nyq_zero);
+    fft_pencils<R, N, true, true, true, true, 1, PPW>(v, j, nullptr, 0, tw);
+    if (on && along_x) {
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+            // element i = z * N + x of the plane; V row z starts at z * vstride
+            const int i = base + j + T * e;
+            const int z0 = i / N, x0 = i % N, z1 = z0 + 1;
+            const R v0 = V[z0 * vstride + x0], v1 = V[z1 * vstride + x0];
+            g[i] = g[i] + kx * v[0][e].x + pot * v0 * f[i];
+            g[i + N] = g[i + N] + kx * v[0][e].y + pot * v1 * f[i + N];
+        }
+    }
+    __syncthreads();
+    if (on && !along_x) {
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+            const int i = base + (j + T * e) * N;
+            g[i] = g[i] + kz * v[0][e].x;
+            g[i + 1] = g[i + 1] + kz * v[0][e].y;
+        }
+    }
+}
+
 // Block b: instance b / ny, plane y = b % ny.  do_a, do_b: which halves
 // of stage sc.l the launch applies (uniform).
 template <typename R, int NX, int NZ>
@@ -105,17 +156,30 @@ __global__ __launch_bounds__((plane_cfg<NX, NZ>::THREADS)) void k_plane_zxz(
     }
     const R* Vp = V + off;
     __syncthreads();
-    if (do_a) {
-        plane_phase<R, NZ, false, NX, NZ>(sI, sR, Vp, zstride, kza, (R)0, nyq_zero, twz);
-        __syncthreads();
-        plane_phase<R, NX, true, NX, NZ>(sI, sR, Vp, zstride, kxa, pa, nyq_zero, twx);
-        __syncthreads();
-    }
-    if (do_b) {
-        plane_phase<R, NX, true, NX, NZ>(sR, sI, Vp, zstride, kxb, pb, nyq_zero, twx);
-        __syncthreads();
-        plane_phase<R, NZ, false, NX, NZ>(sR, sI, Vp, zstride, kzb, (R)0, nyq_zero, twz);
-        __syncthreads();
+    if constexpr (C::BOTH) {
+        // the x and z transforms of a half in one phase (x and z tables of
+        // one length are the same table)
+        if (do_a) {
+            plane_phase_both<R, NX>(sI, sR, Vp, zstride, kxa, kza, pa, nyq_zero, twx);
+            __syncthreads();
+        }
+        if (do_b) {
+            plane_phase_both<R, NX>(sR, sI, Vp, zstride, kxb, kzb, pb, nyq_zero, twx);
+            __syncthreads();
+        }
+    } else {
+        if (do_a) {
+            plane_phase<R, NZ, false, NX, NZ>(sI, sR, Vp, zstride, kza, (R)0, nyq_zero, twz);
+            __syncthreads();
+            plane_phase<R, NX, true, NX, NZ>(sI, sR, Vp, zstride, kxa, pa, nyq_zero, twx);
+            __syncthreads();
+        }
+        if (do_b) {
+            plane_phase<R, NX, true, NX, NZ>(sR, sI, Vp, zstride, kxb, pb, nyq_zero, twx);
+            __syncthreads();
+            plane_phase<R, NZ, false, NX, NZ>(sR, sI, Vp, zstride, kzb, (R)0, nyq_zero, twz);
+            __syncthreads();
+        }
     }
     for (int k = threadIdx.x; k < C::NPL; k += C::THREADS) {
         const int64_t gi = off + (k / NX) * zstride + (k % NX);

@@ -354,12 +354,14 @@ def test_resident_3d_matches_pass_kernels_and_oracle(prec):
     assert res.slot_info(1)[0] is False
 
 
-@pytest.mark.parametrize("n", [(32, 32, 32), (64, 16, 32), (16, 64, 64), (32, 128, 16)])
+@pytest.mark.parametrize("n", [(32, 32, 32), (64, 16, 32), (16, 64, 64), (32, 128, 16), (64, 32, 64),
+                               (16, 32, 16)])
 @pytest.mark.parametrize("prec", [spstd.FP64, spstd.FP32])
 @pytest.mark.parametrize("name", ["paper", "yoshida6"])
 def test_fused_planes_match_separate_passes_and_oracle(n, prec, name):
     # 3D batches with x and z of 16 to 64 points run z(A), x(A+B), z(B) of a
-    # stage as one launch per x-z plane; the same batch with separate passes
+    # stage as one launch per x-z plane (square planes transform the x rows
+    # and z columns of a half together); the same batch with separate passes
     # (SPSTD_NO_PLANES) and the oracle agree.  Yoshida-6's last stage has no
     # B half (a plane launch with the A part alone).  40 steps: two graph
     # chunks and 8 eager steps; a free slot between active ones stays zero.
@@ -446,6 +448,7 @@ def test_fourstep_rows_match_one_workgroup_rows_and_oracle(n, prec, name):
 
 
 @pytest.mark.parametrize("n,flags", [((32, 16, 64), 0), ((32, 16, 64), spstd.NO_PLANES), ((16, 16, 16), 0),
+                                     ((32, 32, 32), 0),
                                      ((64, 32), 0), ((64, 32), spstd.NO_RESIDENT), ((1024,), 0),
                                      ((1024,), spstd.NO_RESIDENT), ((16384,), spstd.NO_RESIDENT)])
 def test_zero_nyquist_batches_against_oracle(n, flags):
