@@ -14,10 +14,13 @@
 // (the A or the B part alone where the stage has one half), with workgroup
 // barriers between the phases, and writes the plane back: one launch and
 // one read and write of the fields (plus V) in place of the three passes
-// z(A), x(A+B), z(B).  A lane group of N/16 lanes holds two neighbouring
-// pencils (rows 2q, 2q+1 along x; columns 2q, 2q+1 along z) as one complex
-// pencil, the pencil index fastest over the lanes, so the transform's last
-// pass runs on lane swaps (16-, 32- and 64-point pencils).
+// z(A), x(A+B), z(B).  A lane group of N/16 lanes holds two pencils half
+// the plane apart (rows q and q + NZ/2 along x; columns q and q + NX/2
+// along z) as one complex pencil, the pencil index fastest over the lanes,
+// so the transform's last pass runs on lane swaps (16-, 32- and 64-point
+// pencils).  The plane's LDS rows are NX + 1 elements apart: the lanes of a
+// phase then read different banks along either axis (with neighbouring rows
+// paired and rows NX apart, the x phases read one bank sixteen ways).
 #include <hip/hip_runtime.h>
 
 #include "kernels.hpp"
@@ -37,25 +40,34 @@ struct plane_cfg {
     static constexpr bool BOTH = NX == NZ;
     static constexpr int LANES = BOTH ? NPL / 16 : NPL / 32;   // lanes of a phase
     static constexpr int THREADS = LANES < 64 ? 64 : LANES;    // whole waves (lane swaps)
+    // LDS row stride: odd, so that the lanes of an x phase (one row each)
+    // and of a z phase (one column each) fall on different banks
+    static constexpr int S = NX + 1;
+    static constexpr int LDS = NZ * S;
 };
 
 // One phase: g += kin T f (+ pot V f along x) over the plane's pencils of
-// the axis (x rows or z columns); f and g in LDS, V the plane's potential
-// in global memory (row z at z * vstride).
+// the axis (x rows or z columns); f and g in LDS (element (z, x) at z S + x),
+// V the plane's potential in global memory (row z at z * vstride).  Lane
+// group q carries rows q and q + NZ/2 (along x) or columns q and q + NX/2
+// (along z) as one complex pencil: neighbouring lane groups read
+// neighbouring rows or columns, which the odd row stride puts on different
+// banks.
 template <typename R, int N, bool ALONG_X, int NX, int NZ>
 __device__ __forceinline__ void plane_phase(const R* f, R* g, const R* __restrict__ V, int64_t vstride, R kin,
                                             R pot, int nyq_zero, const cpx<double>* __restrict__ tw) {
     constexpr int T = N / 16, PPW = 64 / T;
+    constexpr int S = plane_cfg<NX, NZ>::S;
     constexpr int PAIRS = (ALONG_X ? NZ : NX) / 2;
     static_assert(N == 16 || tail_swaps<N, PPW>::OK, "the last pass must run on lane swaps");
     static_assert(PAIRS * T <= plane_cfg<NX, NZ>::THREADS, "one pass over the plane's pencils");
-    constexpr int STRIDE = ALONG_X ? 1 : NX;     // between a pencil's points
-    constexpr int OFF = ALONG_X ? NX : 1;        // to the pencil's partner
+    constexpr int STRIDE = ALONG_X ? 1 : S;          // between a pencil's points
+    constexpr int OFF = ALONG_X ? PAIRS * S : PAIRS; // to the pencil's partner
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int p = lane % PPW, j = lane / PPW;
     const int q = wave * PPW + p;
     const bool on = q < PAIRS;
-    const int base = ALONG_X ? 2 * q * NX : 2 * q;
+    const int base = ALONG_X ? q * S : q;
     cpx<R> v[1][16];
 #pragma unroll
     for (int e = 0; e < 16; ++e) {
@@ -70,9 +82,9 @@ __device__ __forceinline__ void plane_phase(const R* f, R* g, const R* __restric
     for (int e = 0; e < 16; ++e) {
         const int i = base + (j + T * e) * STRIDE;
         if constexpr (ALONG_X) {
-            // element i = z * NX + x of the plane; V row z starts at z * vstride
-            const int z0 = i / NX, x0 = i % NX, z1 = (i + OFF) / NX;
-            const R v0 = V[z0 * vstride + x0], v1 = V[z1 * vstride + x0];
+            // rows q and q + NZ/2 at x = j + T e
+            const int x = j + T * e, z0 = q, z1 = q + PAIRS;
+            const R v0 = V[z0 * vstride + x], v1 = V[z1 * vstride + x];
             g[i] = g[i] + kin * v[0][e].x + pot * v0 * f[i];
             g[i + OFF] = g[i + OFF] + kin * v[0][e].y + pot * v1 * f[i + OFF];
         } else {
@@ -84,22 +96,25 @@ __device__ __forceinline__ void plane_phase(const R* f, R* g, const R* __restric
 
 // Both axes of one half on a square plane: g += kx T_x f + pot V f + kz T_z f.
 // The x and z terms read the same f, so lane groups q < N/2 transform the z
-// column pairs and the others the x row pairs in one call; the x lanes add
-// their terms to g first, the z lanes after a workgroup barrier.
+// column pairs (q, q + N/2) and the others the x row pairs (q - N/2, q) in
+// one call; the x lanes add their terms to g first, the z lanes after a
+// workgroup barrier.
 template <typename R, int N>
 __device__ __forceinline__ void plane_phase_both(const R* f, R* g, const R* __restrict__ V, int64_t vstride, R kx,
                                                  R kz, R pot, int nyq_zero, const cpx<double>* __restrict__ tw) {
     constexpr int T = N / 16, PPW = 64 / T;
+    constexpr int S = plane_cfg<N, N>::S;
+    constexpr int H = N / 2;
     static_assert(N == 16 || tail_swaps<N, PPW>::OK, "the last pass must run on lane swaps");
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int p = lane % PPW, j = lane / PPW;
     const int q = wave * PPW + p;
     const bool on = q < N;
-    const bool along_x = q >= N / 2;
-    const int qq = along_x ? q - N / 2 : q;
-    const int stride = along_x ? 1 : N;     // between a pencil's points
-    const int off = along_x ? N : 1;        // to the pencil's partner
-    const int base = along_x ? 2 * qq * N : 2 * qq;
+    const bool along_x = q >= H;
+    const int qq = along_x ? q - H : q;
+    const int stride = along_x ? 1 : S;            // between a pencil's points
+    const int off = along_x ? H * S : H;           // to the pencil's partner
+    const int base = along_x ? qq * S : qq;
     cpx<R> v[1][16];
 #pragma unroll
     for (int e = 0; e < 16; ++e) {
@@ -112,21 +127,20 @@ __device__ __forceinline__ void plane_phase_both(const R* f, R* g, const R* __re
     if (on && along_x) {
 #pragma unroll
         for (int e = 0; e < 16; ++e) {
-            // element i = z * N + x of the plane; V row z starts at z * vstride
-            const int i = base + j + T * e;
-            const int z0 = i / N, x0 = i % N, z1 = z0 + 1;
-            const R v0 = V[z0 * vstride + x0], v1 = V[z1 * vstride + x0];
+            // rows qq and qq + N/2 at x = j + T e; V row z starts at z * vstride
+            const int x = j + T * e, i = base + x;
+            const R v0 = V[qq * vstride + x], v1 = V[(qq + H) * vstride + x];
             g[i] = g[i] + kx * v[0][e].x + pot * v0 * f[i];
-            g[i + N] = g[i + N] + kx * v[0][e].y + pot * v1 * f[i + N];
+            g[i + off] = g[i + off] + kx * v[0][e].y + pot * v1 * f[i + off];
         }
     }
     __syncthreads();
     if (on && !along_x) {
 #pragma unroll
         for (int e = 0; e < 16; ++e) {
-            const int i = base + (j + T * e) * N;
+            const int i = base + (j + T * e) * S;
             g[i] = g[i] + kz * v[0][e].x;
-            g[i + 1] = g[i + 1] + kz * v[0][e].y;
+            g[i + off] = g[i + off] + kz * v[0][e].y;
         }
     }
 }
@@ -138,8 +152,8 @@ __global__ __launch_bounds__((plane_cfg<NX, NZ>::THREADS)) void k_plane_zxz(
     R* __restrict__ psiR, R* __restrict__ psiI, const R* __restrict__ V, int64_t ny, ScaleRef sc, int do_a,
     int do_b, int nyq_zero, const cpx<double>* __restrict__ twx, const cpx<double>* __restrict__ twz) {
     using C = plane_cfg<NX, NZ>;
-    __shared__ R sR[C::NPL];
-    __shared__ R sI[C::NPL];
+    __shared__ R sR[C::LDS];
+    __shared__ R sI[C::LDS];
     const int64_t inst = blockIdx.x / ny, y = blockIdx.x % ny;
     const R kza = do_a ? scale_of<R>(sc, inst, SC_KZA) : (R)0, kxa = do_a ? scale_of<R>(sc, inst, SC_KXA) : (R)0;
     const R pa = do_a ? scale_of<R>(sc, inst, SC_PA) : (R)0;
@@ -150,9 +164,10 @@ __global__ __launch_bounds__((plane_cfg<NX, NZ>::THREADS)) void k_plane_zxz(
     const int64_t zstride = (int64_t)NX * ny;                       // between the plane's rows
     const int64_t off = inst * (int64_t)NZ * zstride + y * NX;      // element (z, x) at off + z * zstride + x
     for (int k = threadIdx.x; k < C::NPL; k += C::THREADS) {
-        const int64_t gi = off + (k / NX) * zstride + (k % NX);
-        sR[k] = psiR[gi];
-        sI[k] = psiI[gi];
+        const int z = k / NX, x = k % NX;
+        const int64_t gi = off + z * zstride + x;
+        sR[z * C::S + x] = psiR[gi];
+        sI[z * C::S + x] = psiI[gi];
     }
     const R* Vp = V + off;
     __syncthreads();
@@ -182,9 +197,10 @@ __global__ __launch_bounds__((plane_cfg<NX, NZ>::THREADS)) void k_plane_zxz(
         }
     }
     for (int k = threadIdx.x; k < C::NPL; k += C::THREADS) {
-        const int64_t gi = off + (k / NX) * zstride + (k % NX);
-        psiR[gi] = sR[k];
-        psiI[gi] = sI[k];
+        const int z = k / NX, x = k % NX;
+        const int64_t gi = off + z * zstride + x;
+        psiR[gi] = sR[z * C::S + x];
+        psiI[gi] = sI[z * C::S + x];
     }
 }
 
