@@ -70,12 +70,29 @@ def run_instances(instances, steps, precision=spstd.FP32, coeffs=None, nprobes=1
                             dt=0.0 if dt is None else dt[i], cfl_fraction=w.cfl_fraction,
                             hbar=w.hbar, mass=w.mass)
 
-    def advance(n, use_group):
+    def advance(n, use_group, chunk=16):
+        # resident batches step the whole run in one launch each; the
+        # graph-replayed pass batches and the group are enqueued a chunk
+        # (one step graph) at a time in turn, so that every stream has work
+        # from the start instead of the last one waiting for the host to
+        # enqueue all of the others' graphs first (512 instances, 5000
+        # steps: 1.35e11 against 1.21e11 stage updates/s)
+        looped = []
         for k, (b, _, _) in batches.items():
-            if not (use_group and k in gshapes):
+            if use_group and k in gshapes:
+                continue
+            if b.schedule()[0] == "resident":
                 b.step(n)
+            else:
+                looped.append(b)
         if use_group:
-            grp.step(n)
+            looped.append(grp)
+        done = 0
+        while done < n:
+            k = min(chunk, n - done)
+            for b in looped:
+                b.step(k)
+            done += k
 
     def timed(n, use_group):
         torch.cuda.synchronize()
