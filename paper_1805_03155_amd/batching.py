@@ -48,8 +48,8 @@ def run_instances(instances, steps, precision=spstd.FP32, coeffs=None, nprobes=1
         st = torch.cuda.Stream(device=device)
         # long 1D rows keep one workgroup per row pair: their four-step form
         # (five launches per x pass over many workgroups) is the faster alone
-        # but, beside the group on the shared device, falls behind it (512
-        # instances: 9.5e10 against 1.22e11 stage updates/s)
+        # but takes more of the device from the group beside it (512
+        # instances: 1.29e11 against 1.35e11 stage updates/s)
         flags = spstd.AUTOTUNE | (spstd.NO_FOURSTEP if len(shape) == 1 else 0)
         b = spstd.Batch(shape, coeffs, capacity=len(idx), nprobes=nprobes, nsteps_max=steps + untimed,
                         precision=precision, device=device, stream=st, flags=flags)
